@@ -1,0 +1,335 @@
+"""FP64 CPU oracle for P-Tucker's row-wise ALS (ctypes front end).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the product. It wraps the plain C file
+``ptk_oracle.c`` (double precision, loops written from the paper's
+definitions) and shares no code with the GPU library. Inputs are numpy arrays;
+float32 inputs are widened to float64 exactly.
+
+Functions and the passages they follow:
+
+* ``delta``          -- eq. "delta" (Sec. 3.2), plain core-cell loop.
+* ``predict``        -- eq. "recon2" (Sec. 2.2).
+* ``sse`` / ``loss`` -- eq. "reconfull" squared / eq. "TF_PARTIAL".
+* ``row_system``     -- eqs. "rowB", "rowC" for one row.
+* ``solve``          -- eq. "rowupdate" as a Cholesky solve.
+* ``update_rows`` / ``update_mode`` -- Alg. 3 for one mode.
+* ``fit``            -- Alg. 2 iterations (factor sweeps + error).
+* ``qr`` / ``core_update`` / ``orthogonalize`` -- Alg. 2's final QR and core
+  update (Sec. 3.1, n-mode product of Sec. 2.1).
+* ``fold_in``        -- the row update for a new row with the model fixed.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ptk_oracle.c")
+_LIB = os.path.join(_HERE, "libptk_oracle.so")
+_lib = None
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_lp = C.POINTER(C.c_int64)
+_dpp = C.POINTER(_dp)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with the host C compiler (plain -O2)."""
+    if force or not os.path.exists(_LIB) or \
+            os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC",
+                               _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load(path=None):
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    if path is None:
+        path = os.environ.get("PTK_ORACLE_LIB")   # mutation tests only
+    if path is None:
+        build()
+    lib = C.CDLL(path or _LIB)
+    sig = {
+        "ora_delta": (None, [C.c_int, _ip, _dp, _dpp, C.c_int, _dp]),
+        "ora_predict_one": (C.c_double, [C.c_int, _ip, _dp, _dpp]),
+        "ora_predict": (None, [C.c_int, _ip, _dp, _dpp, C.c_int64, _ip, _dp]),
+        "ora_sse": (C.c_double, [C.c_int, _ip, _dp, _dpp, C.c_int64, _ip, _dp]),
+        "ora_loss": (C.c_double, [C.c_int, _lp, _ip, _dp, _dpp, C.c_int64, _ip,
+                                  _dp, C.c_double]),
+        "ora_solve": (C.c_int, [C.c_int, _dp, _dp, C.c_double, _dp]),
+        "ora_row_system": (C.c_int, [C.c_int, _ip, _dp, _dpp, C.c_int64, _ip,
+                                     _dp, C.c_int, C.c_int32, _dp, _dp]),
+        "ora_update_rows": (C.c_int64, [C.c_int, _lp, _ip, _dp, _dpp, C.c_int64,
+                                        _ip, _dp, C.c_int, C.c_double, C.c_int64,
+                                        _ip, _dp]),
+        "ora_update_mode": (C.c_int64, [C.c_int, _lp, _ip, _dp, _dpp, C.c_int64,
+                                        _ip, _dp, C.c_int, C.c_double]),
+        "ora_fit": (C.c_int64, [C.c_int, _lp, _ip, _dp, _dpp, C.c_int64, _ip,
+                                _dp, C.c_double, C.c_int, _dp, _dp]),
+        "ora_qr": (C.c_int, [C.c_int64, C.c_int, _dp, _dp]),
+        "ora_core_update": (C.c_int, [C.c_int, _ip, _dp, C.c_int, _dp]),
+        "ora_orthogonalize": (C.c_int, [C.c_int, _lp, _ip, _dp, _dpp, _dp]),
+        "ora_fold_in": (C.c_int, [C.c_int, _ip, _dp, _dpp, C.c_int, C.c_int64,
+                                  _ip, _dp, C.c_double, _dp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def use_library(path):
+    """Point this module at another build of the oracle (mutation tests only).
+
+    Returns the previously loaded library handle so the caller can restore it
+    with ``restore_library``.
+    """
+    global _lib
+    prev = _lib
+    _lib = None
+    _load(path)
+    return prev
+
+
+def restore_library(prev):
+    global _lib
+    _lib = prev
+
+
+# ----------------------------------------------------------------------------
+# marshalling
+# ----------------------------------------------------------------------------
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_ip)
+
+
+def _l(a):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(_lp)
+
+
+def _ptrs(mats):
+    keep = [np.ascontiguousarray(m, dtype=np.float64) for m in mats]
+    arr = (_dp * len(keep))(*[k.ctypes.data_as(_dp) for k in keep])
+    return keep, arr
+
+
+def _shape(G, A):
+    J = np.array(G.shape, dtype=np.int32)
+    I = np.array([a.shape[0] for a in A], dtype=np.int64)
+    for a, j in zip(A, J):
+        if a.shape[1] != j:
+            raise ValueError("factor width does not match the core")
+    return I, J
+
+
+# ----------------------------------------------------------------------------
+# public functions
+# ----------------------------------------------------------------------------
+def delta(G, rows, n):
+    """delta^(n) for one entry; rows[k] is the factor row a^(k)_{i_k}."""
+    lib = _load()
+    G, Gp = _d(G)
+    J, Jp = _i(np.array(G.shape))
+    rows = [np.asarray(r, dtype=np.float64) if k != n else np.zeros(J[k])
+            for k, r in enumerate(rows)]
+    keep, rp = _ptrs(rows)
+    out = np.zeros(J[n])
+    lib.ora_delta(len(J), Jp, Gp, rp, int(n), out.ctypes.data_as(_dp))
+    return out
+
+
+def predict(G, A, idx):
+    lib = _load()
+    G, Gp = _d(G)
+    I, J = _shape(G, A)
+    J, Jp = _i(J)
+    keep, Ap = _ptrs(A)
+    idx, ip = _i(idx)
+    out = np.zeros(idx.shape[1])
+    lib.ora_predict(len(J), Jp, Gp, Ap, idx.shape[1], ip, out.ctypes.data_as(_dp))
+    return out
+
+
+def sse(G, A, idx, val):
+    lib = _load()
+    G, Gp = _d(G)
+    I, J = _shape(G, A)
+    J, Jp = _i(J)
+    keep, Ap = _ptrs(A)
+    idx, ip = _i(idx)
+    val, vp = _d(val)
+    return lib.ora_sse(len(J), Jp, Gp, Ap, idx.shape[1], ip, vp)
+
+
+def loss(G, A, idx, val, lam):
+    lib = _load()
+    G, Gp = _d(G)
+    I, J = _shape(G, A)
+    I, Ip = _l(I)
+    J, Jp = _i(J)
+    keep, Ap = _ptrs(A)
+    idx, ip = _i(idx)
+    val, vp = _d(val)
+    return lib.ora_loss(len(J), Ip, Jp, Gp, Ap, idx.shape[1], ip, vp, float(lam))
+
+
+def row_system(G, A, idx, val, n, row):
+    """(B, c) of eqs. rowB/rowC for row ``row`` of mode ``n``."""
+    lib = _load()
+    G, Gp = _d(G)
+    I, J = _shape(G, A)
+    J, Jp = _i(J)
+    keep, Ap = _ptrs(A)
+    idx, ip = _i(idx)
+    val, vp = _d(val)
+    B = np.zeros((J[n], J[n]))
+    c = np.zeros(J[n])
+    rc = lib.ora_row_system(len(J), Jp, Gp, Ap, idx.shape[1], ip, vp, int(n),
+                            int(row), B.ctypes.data_as(_dp), c.ctypes.data_as(_dp))
+    if rc:
+        raise RuntimeError("ora_row_system failed: %d" % rc)
+    return B, c
+
+
+def solve(B, c, lam):
+    lib = _load()
+    B, Bp = _d(B)
+    c, cp = _d(c)
+    a = np.zeros(c.shape[0])
+    rc = lib.ora_solve(c.shape[0], Bp, cp, float(lam), a.ctypes.data_as(_dp))
+    if rc:
+        raise np.linalg.LinAlgError("B + lambda I is not positive definite")
+    return a
+
+
+def update_rows(G, A, idx, val, n, lam, rows=None):
+    """New values of the requested rows of A^(n) (all rows when None)."""
+    lib = _load()
+    G, Gp = _d(G)
+    I, J = _shape(G, A)
+    I, Ip = _l(I)
+    J, Jp = _i(J)
+    keep, Ap = _ptrs(A)
+    idx, ip = _i(idx)
+    val, vp = _d(val)
+    if rows is None:
+        out = np.zeros((I[n], J[n]))
+        rp, nreq = None, 0
+    else:
+        rows, rp = _i(rows)
+        nreq = rows.shape[0]
+        out = np.zeros((nreq, J[n]))
+    bad = lib.ora_update_rows(len(J), Ip, Jp, Gp, Ap, idx.shape[1], ip, vp,
+                              int(n), float(lam), nreq, rp,
+                              out.ctypes.data_as(_dp))
+    if bad < 0:
+        raise RuntimeError("ora_update_rows failed: %d" % bad)
+    return out
+
+
+def update_mode(G, A, idx, val, n, lam):
+    """Alg. 3 for mode n; returns a new list of factors."""
+    A = [np.array(a, dtype=np.float64) for a in A]
+    A[n] = update_rows(G, A, idx, val, n, lam)
+    return A
+
+
+def fit(G, A, idx, val, lam, iters):
+    """Alg. 2 iterations. Returns (factors, loss after each mode, SSE per iter)."""
+    lib = _load()
+    G, Gp = _d(G)
+    I, J = _shape(G, A)
+    I, Ip = _l(I)
+    J, Jp = _i(J)
+    A = [np.array(a, dtype=np.float64) for a in A]
+    arr = (_dp * len(A))(*[a.ctypes.data_as(_dp) for a in A])
+    idx, ip = _i(idx)
+    val, vp = _d(val)
+    N = len(J)
+    L = np.zeros(iters * N)
+    S = np.zeros(iters)
+    bad = lib.ora_fit(N, Ip, Jp, Gp, arr, idx.shape[1], ip, vp, float(lam),
+                      int(iters), L.ctypes.data_as(_dp), S.ctypes.data_as(_dp))
+    if bad < 0:
+        raise RuntimeError("ora_fit failed: %d" % bad)
+    return A, L.reshape(iters, N), S
+
+
+def qr(A):
+    """Thin Householder QR with diag(R) >= 0. Returns (Q, R)."""
+    lib = _load()
+    Q = np.array(A, dtype=np.float64)
+    R = np.zeros((Q.shape[1], Q.shape[1]))
+    rc = lib.ora_qr(Q.shape[0], Q.shape[1], Q.ctypes.data_as(_dp),
+                    R.ctypes.data_as(_dp))
+    if rc:
+        raise ValueError("ora_qr failed: %d" % rc)
+    return Q, R
+
+
+def core_update(G, n, U):
+    """G x_n U with the n-mode product of Sec. 2.1."""
+    lib = _load()
+    G = np.array(G, dtype=np.float64)
+    J, Jp = _i(np.array(G.shape))
+    U, Up = _d(U)
+    rc = lib.ora_core_update(len(J), Jp, G.ctypes.data_as(_dp), int(n), Up)
+    if rc:
+        raise RuntimeError("ora_core_update failed: %d" % rc)
+    return G
+
+
+def orthogonalize(G, A):
+    """Alg. 2's final step. Returns (G', A', [R^(n)])."""
+    lib = _load()
+    G = np.array(G, dtype=np.float64)
+    I, J = _shape(G, A)
+    I, Ip = _l(I)
+    J, Jp = _i(J)
+    A = [np.array(a, dtype=np.float64) for a in A]
+    arr = (_dp * len(A))(*[a.ctypes.data_as(_dp) for a in A])
+    R = np.zeros(int(np.sum(J.astype(np.int64) ** 2)))
+    rc = lib.ora_orthogonalize(len(J), Ip, Jp, G.ctypes.data_as(_dp), arr,
+                               R.ctypes.data_as(_dp))
+    if rc:
+        raise ValueError("ora_orthogonalize failed: %d" % rc)
+    Rs, off = [], 0
+    for j in J:
+        Rs.append(R[off:off + j * j].reshape(j, j))
+        off += j * j
+    return G, A, Rs
+
+
+def fold_in(G, A, n, idx, val, lam):
+    """Row of mode n fitted to k new entries (idx [N][k]; row n ignored)."""
+    lib = _load()
+    G, Gp = _d(G)
+    I, J = _shape(G, A)
+    J, Jp = _i(J)
+    keep, Ap = _ptrs(A)
+    idx, ip = _i(idx)
+    val, vp = _d(val)
+    out = np.zeros(J[n])
+    rc = lib.ora_fold_in(len(J), Jp, Gp, Ap, int(n), idx.shape[1], ip, vp,
+                         float(lam), out.ctypes.data_as(_dp))
+    if rc:
+        raise RuntimeError("ora_fold_in failed: %d" % rc)
+    return out

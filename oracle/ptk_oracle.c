@@ -1,0 +1,447 @@
+/*
+ * FP64 CPU oracle for P-Tucker's row-wise ALS (Oh, Park, Sael, Kang,
+ * "Scalable Tucker Factorization for Sparse Tensors - Algorithms and
+ * Discoveries", arXiv 1710.02261).
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product calls, links or loads this
+ * file; only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark do. It shares no code, header, table or constant with the GPU
+ * library: every quantity is computed from its definition with plain loops in
+ * double precision, in the order the paper states it, with no blocking,
+ * fusion or re-association.
+ *
+ * Conventions: indices are 0-based (the paper counts from 1); the core G is
+ * stored in C order (last mode fastest); factor A^(n) is row-major I_n x J_n;
+ * the observed set is structure-of-arrays idx[n*nnz + e] with values val[e].
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORA_MAX_ORDER 16
+
+/* Number of cells of the core, prod_n J_n. */
+static int64_t ora_core_cells(int N, const int32_t *J)
+{
+    int64_t s = 1;
+    for (int n = 0; n < N; ++n) s *= J[n];
+    return s;
+}
+
+/* Advance a core-cell multi-index in C order (last mode fastest). */
+static void ora_next_cell(int N, const int32_t *J, int *beta)
+{
+    for (int k = N - 1; k >= 0; --k) {
+        if (++beta[k] < J[k]) return;
+        beta[k] = 0;
+    }
+}
+
+/*
+ * delta^(n)_alpha (Sec. 3.2, eq. "delta"): for every core cell beta whose
+ * n-th index is j, add G_beta times the product over k != n of a^(k)_{i_k j_k}.
+ * rows[k] points at row i_k of A^(k); rows[n] is not read. This is the
+ * plain form of Alg. 3: N-1 multiplications per (entry, cell) pair.
+ */
+void ora_delta(int N, const int32_t *J, const double *G,
+               const double *const *rows, int n, double *out)
+{
+    int beta[ORA_MAX_ORDER] = {0};
+    int64_t S = ora_core_cells(N, J);
+    for (int j = 0; j < J[n]; ++j) out[j] = 0.0;
+    for (int64_t s = 0; s < S; ++s) {
+        double p = G[s];
+        for (int k = 0; k < N; ++k)
+            if (k != n) p *= rows[k][beta[k]];
+        out[beta[n]] += p;
+        ora_next_cell(N, J, beta);
+    }
+}
+
+/* Reconstruction of one entry (Sec. 2.2, eq. "recon2"). */
+double ora_predict_one(int N, const int32_t *J, const double *G,
+                       const double *const *rows)
+{
+    int beta[ORA_MAX_ORDER] = {0};
+    int64_t S = ora_core_cells(N, J);
+    double x = 0.0;
+    for (int64_t s = 0; s < S; ++s) {
+        double p = G[s];
+        for (int k = 0; k < N; ++k) p *= rows[k][beta[k]];
+        x += p;
+        ora_next_cell(N, J, beta);
+    }
+    return x;
+}
+
+/* Gather the factor rows of entry e into rows[]. */
+static void ora_rows_of(int N, const int32_t *J, const double *const *A,
+                        const int32_t *idx, int64_t nnz, int64_t e,
+                        const double **rows)
+{
+    for (int k = 0; k < N; ++k)
+        rows[k] = A[k] + (int64_t)idx[(int64_t)k * nnz + e] * J[k];
+}
+
+/* Predictions for m cells (eq. "recon2"). */
+void ora_predict(int N, const int32_t *J, const double *G,
+                 const double *const *A, int64_t m, const int32_t *idx,
+                 double *out)
+{
+    const double *rows[ORA_MAX_ORDER];
+    for (int64_t e = 0; e < m; ++e) {
+        ora_rows_of(N, J, A, idx, m, e, rows);
+        out[e] = ora_predict_one(N, J, G, rows);
+    }
+}
+
+/*
+ * Sum of squared residuals over the observed set; the reconstruction error
+ * of eq. "reconfull" is its square root.
+ */
+double ora_sse(int N, const int32_t *J, const double *G,
+               const double *const *A, int64_t nnz, const int32_t *idx,
+               const double *val)
+{
+    const double *rows[ORA_MAX_ORDER];
+    double sse = 0.0;
+    for (int64_t e = 0; e < nnz; ++e) {
+        ora_rows_of(N, J, A, idx, nnz, e, rows);
+        double r = val[e] - ora_predict_one(N, J, G, rows);
+        sse += r * r;
+    }
+    return sse;
+}
+
+/* Loss of eq. "TF_PARTIAL": SSE + lambda * sum_n ||A^(n)||_F^2. */
+double ora_loss(int N, const int64_t *I, const int32_t *J, const double *G,
+                const double *const *A, int64_t nnz, const int32_t *idx,
+                const double *val, double lambda)
+{
+    double reg = 0.0;
+    for (int n = 0; n < N; ++n)
+        for (int64_t t = 0; t < I[n] * J[n]; ++t) reg += A[n][t] * A[n][t];
+    return ora_sse(N, J, G, A, nnz, idx, val) + lambda * reg;
+}
+
+/*
+ * Solve (B + lambda I) a = c for symmetric B by Cholesky factorisation
+ * (Golub & Van Loan, Alg. 4.2.1) and two triangular solves. This is the
+ * row update of eq. "rowupdate" written as a linear solve instead of an
+ * explicit inverse. Returns 0, or -1 if B + lambda I is not positive definite.
+ */
+int ora_solve(int Jn, const double *B, const double *c, double lambda,
+              double *a)
+{
+    double *L = (double *)calloc((size_t)Jn * Jn, sizeof(double));
+    double *y = (double *)calloc((size_t)Jn, sizeof(double));
+    if (!L || !y) { free(L); free(y); return -2; }
+    int rc = 0;
+    for (int i = 0; i < Jn && rc == 0; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            double s = B[i * Jn + j] + (i == j ? lambda : 0.0);
+            for (int k = 0; k < j; ++k) s -= L[i * Jn + k] * L[j * Jn + k];
+            if (i == j) {
+                if (!(s > 0.0)) { rc = -1; break; }
+                L[i * Jn + i] = sqrt(s);
+            } else {
+                L[i * Jn + j] = s / L[j * Jn + j];
+            }
+        }
+    }
+    if (rc == 0) {
+        for (int i = 0; i < Jn; ++i) {          /* L y = c */
+            double s = c[i];
+            for (int k = 0; k < i; ++k) s -= L[i * Jn + k] * y[k];
+            y[i] = s / L[i * Jn + i];
+        }
+        for (int i = Jn - 1; i >= 0; --i) {     /* L^T a = y */
+            double s = y[i];
+            for (int k = i + 1; k < Jn; ++k) s -= L[k * Jn + i] * a[k];
+            a[i] = s / L[i * Jn + i];
+        }
+    }
+    free(L);
+    free(y);
+    return rc;
+}
+
+/*
+ * B^(n)_i and c^(n)_i of eqs. "rowB" and "rowC" for row i of mode n, from
+ * the list of entries ents[0..cnt) whose n-th index is i.
+ */
+static void ora_row_system_list(int N, const int32_t *J, const double *G,
+                                const double *const *A, int64_t nnz,
+                                const int32_t *idx, const double *val, int n,
+                                const int64_t *ents, int64_t cnt, double *B,
+                                double *c)
+{
+    const int Jn = J[n];
+    const double *rows[ORA_MAX_ORDER];
+    double delta[256];
+    memset(B, 0, sizeof(double) * Jn * Jn);
+    memset(c, 0, sizeof(double) * Jn);
+    for (int64_t t = 0; t < cnt; ++t) {
+        int64_t e = ents[t];
+        ora_rows_of(N, J, A, idx, nnz, e, rows);
+        ora_delta(N, J, G, rows, n, delta);
+        for (int p = 0; p < Jn; ++p) {
+            for (int q = 0; q < Jn; ++q) B[p * Jn + q] += delta[p] * delta[q];
+            c[p] += val[e] * delta[p];
+        }
+    }
+}
+
+/* B and c for one row, found by scanning the whole observed set. */
+int ora_row_system(int N, const int32_t *J, const double *G,
+                   const double *const *A, int64_t nnz, const int32_t *idx,
+                   const double *val, int n, int32_t row, double *B, double *c)
+{
+    if (J[n] > 256) return -3;
+    int64_t cnt = 0;
+    for (int64_t e = 0; e < nnz; ++e)
+        if (idx[(int64_t)n * nnz + e] == row) ++cnt;
+    int64_t *ents = (int64_t *)malloc(sizeof(int64_t) * (cnt ? cnt : 1));
+    if (!ents) return -2;
+    int64_t t = 0;
+    for (int64_t e = 0; e < nnz; ++e)
+        if (idx[(int64_t)n * nnz + e] == row) ents[t++] = e;
+    ora_row_system_list(N, J, G, A, nnz, idx, val, n, ents, cnt, B, c);
+    free(ents);
+    return 0;
+}
+
+/*
+ * One pass of Alg. 3 for mode n (the rows of A^(n) are independent, Sec. 3.2):
+ * every requested row i gets a_i = c_i (B_i + lambda I)^{-1}; a row with no
+ * observed entry gets B = 0, c = 0 and hence a_i = 0.
+ *
+ * rows_req: nreq row ids, or NULL for all I_n rows in order. Results go to
+ * out (nreq x J_n, or I_n x J_n when rows_req is NULL); A is not modified.
+ * Returns the number of rows whose system was not positive definite (their
+ * output is left as zeros), or a negative code on allocation failure.
+ */
+int64_t ora_update_rows(int N, const int64_t *I, const int32_t *J,
+                        const double *G, const double *const *A, int64_t nnz,
+                        const int32_t *idx, const double *val, int n,
+                        double lambda, int64_t nreq, const int32_t *rows_req,
+                        double *out)
+{
+    const int Jn = J[n];
+    if (Jn > 256) return -3;
+    const int64_t In = I[n];
+    /* group the entries by their n-th index: counting sort, stable */
+    int64_t *start = (int64_t *)calloc((size_t)In + 1, sizeof(int64_t));
+    int64_t *ents = (int64_t *)malloc(sizeof(int64_t) * (nnz ? nnz : 1));
+    int64_t *fill = (int64_t *)calloc((size_t)In + 1, sizeof(int64_t));
+    double *B = (double *)malloc(sizeof(double) * Jn * Jn);
+    double *c = (double *)malloc(sizeof(double) * Jn);
+    if (!start || !ents || !fill || !B || !c) {
+        free(start); free(ents); free(fill); free(B); free(c);
+        return -2;
+    }
+    for (int64_t e = 0; e < nnz; ++e) start[idx[(int64_t)n * nnz + e] + 1]++;
+    for (int64_t i = 0; i < In; ++i) start[i + 1] += start[i];
+    for (int64_t e = 0; e < nnz; ++e) {
+        int32_t i = idx[(int64_t)n * nnz + e];
+        ents[start[i] + fill[i]++] = e;
+    }
+    int64_t bad = 0;
+    int64_t count = rows_req ? nreq : In;
+    for (int64_t r = 0; r < count; ++r) {
+        int64_t i = rows_req ? rows_req[r] : r;
+        double *a = out + r * Jn;
+        for (int j = 0; j < Jn; ++j) a[j] = 0.0;
+        ora_row_system_list(N, J, G, A, nnz, idx, val, n, ents + start[i],
+                            start[i + 1] - start[i], B, c);
+        if (ora_solve(Jn, B, c, lambda, a) != 0) {
+            for (int j = 0; j < Jn; ++j) a[j] = 0.0;
+            ++bad;
+        }
+    }
+    free(start); free(ents); free(fill); free(B); free(c);
+    return bad;
+}
+
+/* Alg. 3 for mode n, writing the new rows into A[n]. */
+int64_t ora_update_mode(int N, const int64_t *I, const int32_t *J,
+                        const double *G, double *const *A, int64_t nnz,
+                        const int32_t *idx, const double *val, int n,
+                        double lambda)
+{
+    double *tmp = (double *)malloc(sizeof(double) * I[n] * J[n]);
+    if (!tmp) return -2;
+    int64_t bad = ora_update_rows(N, I, J, G, (const double *const *)A, nnz,
+                                  idx, val, n, lambda, 0, NULL, tmp);
+    if (bad >= 0) memcpy(A[n], tmp, sizeof(double) * I[n] * J[n]);
+    free(tmp);
+    return bad;
+}
+
+/*
+ * Alg. 2 without the final orthogonalisation: iters times, update A^(1..N)
+ * in order (Alg. 3) and measure the error. loss_after_mode[t*N+n] receives
+ * the loss of eq. "TF_PARTIAL" after mode n of iteration t, sse[t] the sum of
+ * squared residuals after iteration t (either may be NULL).
+ */
+int64_t ora_fit(int N, const int64_t *I, const int32_t *J, const double *G,
+                double *const *A, int64_t nnz, const int32_t *idx,
+                const double *val, double lambda, int iters,
+                double *loss_after_mode, double *sse)
+{
+    int64_t bad = 0;
+    for (int t = 0; t < iters; ++t) {
+        for (int n = 0; n < N; ++n) {
+            int64_t b = ora_update_mode(N, I, J, G, A, nnz, idx, val, n, lambda);
+            if (b < 0) return b;
+            bad += b;
+            if (loss_after_mode)
+                loss_after_mode[t * N + n] =
+                    ora_loss(N, I, J, G, (const double *const *)A, nnz, idx,
+                             val, lambda);
+        }
+        if (sse)
+            sse[t] = ora_sse(N, J, G, (const double *const *)A, nnz, idx, val);
+    }
+    return bad;
+}
+
+/*
+ * Thin QR of the Im x Jn row-major matrix A by Householder reflections
+ * (Golub & Van Loan, Alg. 5.2.1), with the signs chosen so that diag(R) >= 0
+ * (Sec. 3.1: A^(n) = Q^(n) R^(n), Q column-orthonormal, R upper triangular).
+ * On return A holds Q and R (Jn x Jn, row-major) holds R. Requires Im >= Jn.
+ */
+int ora_qr(int64_t Im, int Jn, double *A, double *R)
+{
+    if (Im < Jn) return -1;
+    double *W = (double *)malloc(sizeof(double) * Im * Jn);  /* reflectors */
+    double *v = (double *)malloc(sizeof(double) * Im);
+    double *Q = (double *)calloc((size_t)Im * Jn, sizeof(double));
+    if (!W || !v || !Q) { free(W); free(v); free(Q); return -2; }
+    memcpy(W, A, sizeof(double) * Im * Jn);
+    double *vs = (double *)calloc((size_t)Im * Jn, sizeof(double));
+    if (!vs) { free(W); free(v); free(Q); return -2; }
+    for (int k = 0; k < Jn; ++k) {
+        double nx = 0.0;
+        for (int64_t i = k; i < Im; ++i) nx += W[i * Jn + k] * W[i * Jn + k];
+        nx = sqrt(nx);
+        for (int64_t i = 0; i < Im; ++i) v[i] = 0.0;
+        for (int64_t i = k; i < Im; ++i) v[i] = W[i * Jn + k];
+        double alpha = (W[(int64_t)k * Jn + k] >= 0.0) ? -nx : nx;
+        v[k] -= alpha;
+        double nv = 0.0;
+        for (int64_t i = k; i < Im; ++i) nv += v[i] * v[i];
+        if (nv > 0.0) {
+            nv = sqrt(nv);
+            for (int64_t i = k; i < Im; ++i) v[i] /= nv;
+            /* W <- (I - 2 v v^T) W on columns k.. */
+            for (int j = k; j < Jn; ++j) {
+                double d = 0.0;
+                for (int64_t i = k; i < Im; ++i) d += v[i] * W[i * Jn + j];
+                for (int64_t i = k; i < Im; ++i) W[i * Jn + j] -= 2.0 * v[i] * d;
+            }
+        }
+        for (int64_t i = 0; i < Im; ++i) vs[i * Jn + k] = v[i];
+    }
+    /* Q = H_0 H_1 ... H_{Jn-1} applied to the first Jn columns of I */
+    for (int j = 0; j < Jn; ++j) Q[(int64_t)j * Jn + j] = 1.0;
+    for (int k = Jn - 1; k >= 0; --k) {
+        for (int j = 0; j < Jn; ++j) {
+            double d = 0.0;
+            for (int64_t i = k; i < Im; ++i) d += vs[i * Jn + k] * Q[i * Jn + j];
+            for (int64_t i = k; i < Im; ++i) Q[i * Jn + j] -= 2.0 * vs[i * Jn + k] * d;
+        }
+    }
+    for (int i = 0; i < Jn; ++i)
+        for (int j = 0; j < Jn; ++j)
+            R[i * Jn + j] = (j >= i) ? W[(int64_t)i * Jn + j] : 0.0;
+    for (int i = 0; i < Jn; ++i) {
+        if (R[i * Jn + i] < 0.0) {
+            for (int j = 0; j < Jn; ++j) R[i * Jn + j] = -R[i * Jn + j];
+            for (int64_t r = 0; r < Im; ++r) Q[r * Jn + i] = -Q[r * Jn + i];
+        }
+    }
+    memcpy(A, Q, sizeof(double) * Im * Jn);
+    free(W); free(v); free(Q); free(vs);
+    return 0;
+}
+
+/*
+ * G <- G x_n U for a square U (J_n x J_n), with the n-mode product of
+ * Sec. 2.1: (G x_n U)[.., j, ..] = sum_k G[.., k, ..] U[j, k].
+ */
+int ora_core_update(int N, const int32_t *J, double *G, int n, const double *U)
+{
+    int64_t S = ora_core_cells(N, J);
+    int64_t inner = 1;
+    for (int k = n + 1; k < N; ++k) inner *= J[k];
+    double *T = (double *)malloc(sizeof(double) * S);
+    if (!T) return -2;
+    int beta[ORA_MAX_ORDER] = {0};
+    for (int64_t s = 0; s < S; ++s) {
+        double acc = 0.0;
+        int j = beta[n];
+        int64_t base = s - (int64_t)j * inner;   /* same cell with beta_n = 0 */
+        for (int k = 0; k < J[n]; ++k) acc += G[base + (int64_t)k * inner] * U[j * J[n] + k];
+        T[s] = acc;
+        ora_next_cell(N, J, beta);
+    }
+    memcpy(G, T, sizeof(double) * S);
+    free(T);
+    return 0;
+}
+
+/*
+ * Final step of Alg. 2: for n = 1..N, A^(n) = Q R, A^(n) <- Q, G <- G x_n R.
+ * R_out (optional) receives the N triangular factors, each J_n x J_n, packed.
+ */
+int ora_orthogonalize(int N, const int64_t *I, const int32_t *J, double *G,
+                      double *const *A, double *R_out)
+{
+    int64_t off = 0;
+    for (int n = 0; n < N; ++n) {
+        double *R = (double *)malloc(sizeof(double) * J[n] * J[n]);
+        if (!R) return -2;
+        int rc = ora_qr(I[n], J[n], A[n], R);
+        if (rc == 0) rc = ora_core_update(N, J, G, n, R);
+        if (rc == 0 && R_out) memcpy(R_out + off, R, sizeof(double) * J[n] * J[n]);
+        off += (int64_t)J[n] * J[n];
+        free(R);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+/*
+ * Fold-in of a new row of mode n from k observations with the model held
+ * fixed: the row update of eq. "rowupdate" over the given entries. idx is
+ * [N][k]; the n-th index array is not read.
+ */
+int ora_fold_in(int N, const int32_t *J, const double *G,
+                const double *const *A, int n, int64_t k, const int32_t *idx,
+                const double *val, double lambda, double *out)
+{
+    const int Jn = J[n];
+    if (Jn > 256) return -3;
+    double *B = (double *)malloc(sizeof(double) * Jn * Jn);
+    double *c = (double *)malloc(sizeof(double) * Jn);
+    int64_t *ents = (int64_t *)malloc(sizeof(int64_t) * (k ? k : 1));
+    int32_t *ix = (int32_t *)malloc(sizeof(int32_t) * N * (k ? k : 1));
+    if (!B || !c || !ents || !ix) {
+        free(B); free(c); free(ents); free(ix);
+        return -2;
+    }
+    for (int64_t e = 0; e < k; ++e) ents[e] = e;
+    /* the n-th index of a fold-in entry does not exist; use row 0, which
+       delta never reads */
+    memcpy(ix, idx, sizeof(int32_t) * N * k);
+    for (int64_t e = 0; e < k; ++e) ix[(int64_t)n * k + e] = 0;
+    ora_row_system_list(N, J, G, A, k, ix, val, n, ents, k, B, c);
+    for (int j = 0; j < Jn; ++j) out[j] = 0.0;
+    int rc = ora_solve(Jn, B, c, lambda, out);
+    free(ix);
+    free(B); free(c); free(ents);
+    return rc;
+}

@@ -1,0 +1,49 @@
+"""The oracle's pins catch plausible mistakes (mutation test, CPU only).
+
+Each case plants one mistake in a private copy of the oracle's C source,
+builds it, and runs the pin suite against it in a child process; the suite
+must fail. The real oracle is never modified.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "ptk_oracle.c")
+
+MUTANTS = {
+    "drop_lambda": ("s = B[i * Jn + j] + (i == j ? lambda : 0.0);",
+                    "s = B[i * Jn + j];"),
+    "sign_of_rhs": ("c[p] += val[e] * delta[p];", "c[p] -= val[e] * delta[p];"),
+    "gram_diagonal_only": ("B[p * Jn + q] += delta[p] * delta[q];",
+                           "B[p * Jn + q] += delta[p] * delta[p];"),
+    "delta_skips_last_cell": (
+        "for (int j = 0; j < J[n]; ++j) out[j] = 0.0;\n    for (int64_t s = 0; s < S; ++s)",
+        "for (int j = 0; j < J[n]; ++j) out[j] = 0.0;\n    for (int64_t s = 0; s < S - 1; ++s)"),
+    "predict_drops_last_mode": ("for (int k = 0; k < N; ++k) p *= rows[k][beta[k]];",
+                                "for (int k = 0; k < N - 1; ++k) p *= rows[k][beta[k]];"),
+    "core_update_transposed": ("* U[j * J[n] + k];", "* U[k * J[n] + j];"),
+    "qr_no_sign_fix": ("if (R[i * Jn + i] < 0.0) {", "if (R[i * Jn + i] < -1e300) {"),
+    "back_substitution_index": ("s -= L[k * Jn + i] * a[k];", "s -= L[i * Jn + k] * a[k];"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation site not found exactly once"
+    mutant = tmp_path / "mutant.c"
+    mutant.write_text(src.replace(old, new))
+    lib = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC",
+                           str(mutant), "-o", str(lib), "-lm"])
+    env = dict(os.environ, PTK_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p",
+                        "no:cacheprovider", os.path.join(ROOT, "tests",
+                                                         "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode != 0, "pins did not catch mutant %s" % name

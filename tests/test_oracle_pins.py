@@ -1,0 +1,320 @@
+"""Pins of the FP64 oracle against the paper's mathematics (CPU only).
+
+Each test checks the oracle against something other than itself: the paper's
+unfolding definition, Theorem 1 (zero row gradient), Theorem 2 (monotone
+loss), closed forms of special cases, library routines (numpy solve, lstsq,
+QR) for the cases the method reduces to, and exact recovery of a planted
+Tucker tensor. Ranks differ per mode wherever possible, so a transposed index
+or operand cannot cancel out.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import dense_ref as D
+
+RNG = np.random.default_rng(12345)
+
+
+def rand_model(dims, ranks, rng, low=-1.0, high=1.0):
+    G = rng.uniform(low, high, size=ranks)
+    A = [rng.uniform(low, high, size=(d, r)) for d, r in zip(dims, ranks)]
+    return G, A
+
+
+def rand_obs(dims, nnz, rng):
+    cells = list(itertools.product(*[range(d) for d in dims]))
+    pick = rng.choice(len(cells), size=nnz, replace=False)
+    idx = np.array([cells[p] for p in pick], dtype=np.int32).T.copy()
+    val = rng.standard_normal(nnz)
+    return idx, val
+
+
+# --------------------------------------------------------------------------
+# P1: delta against the Kronecker form on the paper's unfolding
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("ranks", [(2, 3, 4), (3, 2, 2, 4), (2, 3, 1, 2, 3)])
+def test_delta_matches_unfolding_kronecker(ranks):
+    rng = np.random.default_rng(len(ranks))
+    N = len(ranks)
+    G = rng.standard_normal(ranks)
+    rows = [rng.standard_normal(r) for r in ranks]
+    for n in range(N):
+        Gn = D.unfold(G, n)
+        # column index runs first-mode-fastest, so the Kronecker vector is
+        # kron(a^(N), ..., a^(n+1), a^(n-1), ..., a^(1))
+        kv = np.ones(1)
+        for k in range(N):
+            if k != n:
+                kv = np.kron(rows[k], kv)
+        want = Gn @ kv
+        got = oracle.delta(G, rows, n)
+        np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-13)
+
+
+def test_delta_matches_dense_partial_product():
+    rng = np.random.default_rng(7)
+    dims, ranks = (5, 4, 6), (3, 2, 4)
+    G, A = rand_model(dims, ranks, rng)
+    idx, _ = rand_obs(dims, 30, rng)
+    for n in range(3):
+        want = D.deltas(G, A, idx, n)
+        for e in range(idx.shape[1]):
+            rows = [A[k][idx[k, e]] for k in range(3)]
+            np.testing.assert_allclose(oracle.delta(G, rows, n), want[e],
+                                       rtol=1e-12, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# predictions, SSE and loss against the dense reconstruction
+# --------------------------------------------------------------------------
+def test_predict_sse_loss_match_dense():
+    rng = np.random.default_rng(8)
+    dims, ranks = (4, 5, 3, 6), (2, 3, 2, 3)
+    G, A = rand_model(dims, ranks, rng)
+    idx, val = rand_obs(dims, 50, rng)
+    X = D.full_tensor(G, A)
+    np.testing.assert_allclose(oracle.predict(G, A, idx), X[tuple(idx)],
+                               rtol=1e-12, atol=1e-13)
+    r = val - X[tuple(idx)]
+    assert oracle.sse(G, A, idx, val) == pytest.approx(r @ r, rel=1e-12)
+    lam = 0.37
+    assert oracle.loss(G, A, idx, val, lam) == pytest.approx(
+        D.loss(G, A, idx, val, lam), rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# P2: Theorem 1 -- the updated row zeroes the gradient of the loss
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("lam", [0.01, 1.0])
+def test_row_update_zero_gradient(lam):
+    rng = np.random.default_rng(9)
+    dims, ranks = (6, 5, 7), (3, 4, 2)
+    G, A = rand_model(dims, ranks, rng)
+    idx, val = rand_obs(dims, 120, rng)
+    for n in range(3):
+        An = oracle.update_mode(G, A, idx, val, n, lam)
+        # gradient of eq. TF_PARTIAL w.r.t. row i of A^(n), from dense numpy
+        X = D.full_tensor(G, An)
+        res = X[tuple(idx)] - val
+        dl = D.deltas(G, An, idx, n)
+        grad = 2.0 * lam * An[n]
+        np.add.at(grad, idx[n], 2.0 * res[:, None] * dl)
+        scale = np.abs(2.0 * lam * An[n]).max() + np.abs(dl * val[:, None]).max()
+        assert np.abs(grad).max() <= 1e-10 * scale
+
+
+def test_row_update_is_minimiser_against_perturbations():
+    rng = np.random.default_rng(10)
+    dims, ranks = (5, 6, 4), (2, 3, 3)
+    G, A = rand_model(dims, ranks, rng)
+    idx, val = rand_obs(dims, 60, rng)
+    lam = 0.05
+    An = oracle.update_mode(G, A, idx, val, 1, lam)
+    base = D.loss(G, An, idx, val, lam)
+    for _ in range(20):
+        Ap = [a.copy() for a in An]
+        Ap[1] += 1e-3 * rng.standard_normal(Ap[1].shape)
+        assert D.loss(G, Ap, idx, val, lam) > base
+
+
+# --------------------------------------------------------------------------
+# P3: Theorem 2 -- the loss never increases within the sweep
+# --------------------------------------------------------------------------
+def test_loss_monotone_over_sweeps():
+    rng = np.random.default_rng(11)
+    dims, ranks = (8, 7, 9), (3, 2, 4)
+    G = rng.random(ranks)
+    A = [rng.random((d, r)) for d, r in zip(dims, ranks)]
+    idx, val = rand_obs(dims, 200, rng)
+    lam = 0.01
+    L0 = oracle.loss(G, A, idx, val, lam)
+    Af, L, S = oracle.fit(G, A, idx, val, lam, 6)
+    seq = np.concatenate([[L0], L.ravel()])
+    assert np.all(seq[1:] <= seq[:-1] * (1 + 1e-12))
+    # the recorded SSE is that of the final factors of each iteration
+    assert S[-1] == pytest.approx(oracle.sse(G, Af, idx, val), rel=1e-12)
+    # and the loss recorded after the last mode matches the dense loss
+    assert L[-1, -1] == pytest.approx(D.loss(G, Af, idx, val, lam), rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# P4 / P5 / P6: closed forms
+# --------------------------------------------------------------------------
+def test_single_observation_row_sherman_morrison():
+    rng = np.random.default_rng(12)
+    dims, ranks = (4, 5, 6), (3, 2, 4)
+    G, A = rand_model(dims, ranks, rng)
+    idx = np.array([[2], [1], [4]], dtype=np.int32)
+    val = np.array([1.7])
+    lam = 0.3
+    for n in range(3):
+        d = D.deltas(G, A, idx, n)[0]
+        want = val[0] * d / (lam + d @ d)
+        got = oracle.update_rows(G, A, idx, val, n, lam, rows=[idx[n, 0]])[0]
+        np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-14)
+
+
+def test_empty_row_is_exactly_zero():
+    rng = np.random.default_rng(13)
+    dims, ranks = (5, 4, 3), (2, 3, 2)
+    G, A = rand_model(dims, ranks, rng)
+    idx, val = rand_obs(dims, 20, rng)
+    keep = idx[0] != 3
+    idx, val = idx[:, keep], val[keep]
+    out = oracle.update_rows(G, A, idx, val, 0, 0.01)
+    assert np.all(out[3] == 0.0)
+
+
+def test_rank_one_scalar_core_closed_form():
+    rng = np.random.default_rng(14)
+    dims = (6, 5, 4)
+    G = np.array([[[1.3]]])
+    A = [rng.standard_normal((d, 1)) for d in dims]
+    idx, val = rand_obs(dims, 40, rng)
+    lam = 0.2
+    for n in range(3):
+        got = oracle.update_rows(G, A, idx, val, n, lam)[:, 0]
+        d = G.ravel()[0] * np.prod([A[k][idx[k], 0] for k in range(3) if k != n],
+                                   axis=0)
+        num = np.bincount(idx[n], weights=val * d, minlength=dims[n])
+        den = np.bincount(idx[n], weights=d * d, minlength=dims[n]) + lam
+        np.testing.assert_allclose(got, num / den, rtol=1e-12, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# P7: order 2 with an identity core is regularised ALS matrix completion
+# --------------------------------------------------------------------------
+def test_order2_identity_core_is_matrix_completion_als():
+    rng = np.random.default_rng(15)
+    dims, J = (9, 8), 3
+    G = np.eye(J)
+    A = [rng.standard_normal((d, J)) for d in dims]
+    idx, val = rand_obs(dims, 40, rng)
+    lam = 0.1
+    for n in range(2):
+        other = 1 - n
+        got = oracle.update_rows(G, A, idx, val, n, lam)
+        for i in range(dims[n]):
+            sel = idx[n] == i
+            Bm = A[other][idx[other, sel]]
+            want = np.linalg.solve(Bm.T @ Bm + lam * np.eye(J), Bm.T @ val[sel])
+            np.testing.assert_allclose(got[i], want, rtol=1e-11, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# P8: fully observed, tiny lambda -> ordinary least squares per row
+# --------------------------------------------------------------------------
+def test_fully_observed_small_lambda_is_ols():
+    rng = np.random.default_rng(16)
+    dims, ranks = (4, 5, 3), (2, 3, 2)
+    G, A = rand_model(dims, ranks, rng)
+    idx = np.array(list(itertools.product(*[range(d) for d in dims])),
+                   dtype=np.int32).T.copy()
+    val = rng.standard_normal(idx.shape[1])
+    for n in range(3):
+        got = oracle.update_rows(G, A, idx, val, n, 1e-12)
+        dl = D.deltas(G, A, idx, n)
+        for i in range(dims[n]):
+            sel = idx[n] == i
+            want = np.linalg.lstsq(dl[sel], val[sel], rcond=None)[0]
+            np.testing.assert_allclose(got[i], want, rtol=1e-8, atol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# P9: planted exact Tucker tensor, fully observed, planted core given
+# --------------------------------------------------------------------------
+def test_planted_exact_tucker_recovered():
+    rng = np.random.default_rng(17)
+    dims, ranks = (12, 11, 10), (3, 2, 4)
+    Gs = rng.standard_normal(ranks)
+    As = [rng.standard_normal((d, r)) for d, r in zip(dims, ranks)]
+    X = D.full_tensor(Gs, As)
+    idx = np.array(list(itertools.product(*[range(d) for d in dims])),
+                   dtype=np.int32).T.copy()
+    val = X[tuple(idx)]
+    A0 = [a + 0.1 * rng.standard_normal(a.shape) for a in As]
+    # with the core fixed, rescalings of the factors whose product is 1 leave
+    # the model unchanged; ALS converges linearly (about 2 % per sweep here)
+    Af, L, S = oracle.fit(Gs, A0, idx, val, 1e-12, 800)
+    assert S[-1] / (val @ val) < 1e-10
+    assert np.all(np.diff(S) <= 1e-12 * S[:-1])
+
+
+# --------------------------------------------------------------------------
+# P10: final QR and core update
+# --------------------------------------------------------------------------
+def test_qr_properties_and_library_agreement():
+    rng = np.random.default_rng(18)
+    A = rng.standard_normal((40, 6))
+    Q, R = oracle.qr(A)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(6), atol=1e-12)
+    assert np.all(np.tril(R, -1) == 0.0)
+    assert np.all(np.diag(R) >= 0.0)
+    np.testing.assert_allclose(Q @ R, A, atol=1e-12)
+    Qn, Rn = np.linalg.qr(A)
+    s = np.sign(np.diag(Rn))
+    np.testing.assert_allclose(Q, Qn * s, atol=1e-12)
+    np.testing.assert_allclose(R, Rn * s[:, None], atol=1e-12)
+
+
+def test_core_update_matches_n_mode_product_definition():
+    rng = np.random.default_rng(19)
+    G = rng.standard_normal((2, 3, 4))
+    for n in range(3):
+        U = rng.standard_normal((G.shape[n], G.shape[n]))
+        got = oracle.core_update(G, n, U)
+        # definition: (G x_n U)[.., j, ..] = sum_k G[.., k, ..] U[j, k]
+        want = np.moveaxis(np.tensordot(U, G, axes=([1], [n])), 0, n)
+        np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-13)
+
+
+def test_orthogonalize_preserves_predictions():
+    rng = np.random.default_rng(20)
+    dims, ranks = (9, 8, 7, 6), (3, 2, 4, 2)
+    G, A = rand_model(dims, ranks, rng)
+    X0 = D.full_tensor(G, A)
+    G2, A2, Rs = oracle.orthogonalize(G, A)
+    for a in A2:
+        np.testing.assert_allclose(a.T @ a, np.eye(a.shape[1]), atol=1e-12)
+    np.testing.assert_allclose(D.full_tensor(G2, A2), X0, rtol=1e-11, atol=1e-11)
+
+
+# --------------------------------------------------------------------------
+# P11: order of the observed set does not matter
+# --------------------------------------------------------------------------
+def test_invariant_to_coo_order():
+    rng = np.random.default_rng(21)
+    dims, ranks = (7, 6, 5), (3, 2, 3)
+    G, A = rand_model(dims, ranks, rng)
+    idx, val = rand_obs(dims, 90, rng)
+    p = rng.permutation(idx.shape[1])
+    for n in range(3):
+        a = oracle.update_rows(G, A, idx, val, n, 0.01)
+        b = oracle.update_rows(G, A, idx[:, p], val[p], n, 0.01)
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# P12: fold-in of an existing row with all its entries equals its update
+# --------------------------------------------------------------------------
+def test_fold_in_equals_row_update():
+    rng = np.random.default_rng(22)
+    dims, ranks = (6, 7, 5), (2, 3, 4)
+    G, A = rand_model(dims, ranks, rng)
+    idx, val = rand_obs(dims, 80, rng)
+    for n in range(3):
+        rows = oracle.update_rows(G, A, idx, val, n, 0.02)
+        i = int(np.bincount(idx[n]).argmax())
+        sel = idx[n] == i
+        sub = idx[:, sel].copy()
+        sub[n] = 0        # the fold-in row has no index of its own
+        got = oracle.fold_in(G, A, n, sub, val[sel], 0.02)
+        np.testing.assert_allclose(got, rows[i], rtol=1e-12, atol=1e-14)
+
+
+def test_solve_rejects_non_positive_definite():
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.solve(-np.eye(3), np.ones(3), 0.01)
