@@ -1,0 +1,182 @@
+/*
+ * ptucker.h -- C ABI of the MI355X (gfx950) row-wise sparse Tucker ALS library.
+ *
+ * The calls follow the problem statement of P-Tucker (Oh, Park, Sael, Kang,
+ * arXiv 1710.02261): Def. "Sparse Tucker Factorization" (Sec. 2.2), the
+ * inputs and outputs of Alg. 2 (Sec. 3.1) and Alg. 3 (Sec. 3.2). A user
+ * hands over the observed entries as COO indices and values, the core G, the
+ * factor matrices A^(n), the regularisation lambda and the ranks J_n.
+ *
+ * Conventions shared by every call
+ *  - Indices are 0-based (the paper counts from 1).
+ *  - Pointers are DEVICE pointers (memory of the device that was current when
+ *    the context was created) unless the parameter name ends in "_host".
+ *  - The observed set is structure-of-arrays: idx[n * nnz + e] is the mode-n
+ *    index of entry e, val[e] its value (float32).
+ *  - The core G is float32 in C order (J_1 x ... x J_N, last mode fastest).
+ *    Factor A^(n) is float32 row-major I_n x J_n (row i is contiguous).
+ *  - All device work is ordered on the HIP stream given to ptk_create. Calls
+ *    that return host values synchronise that stream before returning.
+ *  - Every call returns a ptk_status; no exception crosses the ABI. The text
+ *    of the last failure is available from ptk_last_error(ctx).
+ *  - A context is not thread-safe: one thread at a time may call into it.
+ */
+#ifndef PTUCKER_H
+#define PTUCKER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ptk_status {
+    PTK_OK = 0,
+    PTK_E_INVALID = 1,      /* bad argument or out-of-range input data      */
+    PTK_E_NOMEM = 2,        /* device or host allocation failed             */
+    PTK_E_UNSUPPORTED = 3,  /* shape outside what the library supports      */
+    PTK_E_NOT_PD = 4,       /* a J x J system was not positive definite     */
+    PTK_E_HIP = 5,          /* a HIP runtime call or kernel launch failed   */
+    PTK_E_STATE = 6         /* call order violated (e.g. no observed set)   */
+} ptk_status;
+
+typedef struct ptk_ctx ptk_ctx;
+
+/* Arithmetic of the delta / Gram kernels (the solve and the QR are FP64). */
+typedef enum ptk_precision {
+    PTK_PREC_FP64_ACC = 0,  /* fp32 data, fp64 delta and Gram arithmetic    */
+    PTK_PREC_FP32 = 1       /* fp32 delta arithmetic, fp64 Gram sums        */
+} ptk_precision;
+
+typedef struct ptk_options {
+    int32_t precision;      /* ptk_precision                                 */
+    int32_t chunk_nnz;      /* entries per wavefront work range; 0 = auto    */
+    int32_t fuse_error;     /* 1: error pass fused into the last mode        */
+    int32_t profile;        /* 1: time every kernel launch with HIP events   */
+} ptk_options;
+
+/*
+ * Create a context for an N-order tensor of size dims_host[0..N) with core
+ * ranks ranks_host[0..N), bound to the device that is current and to
+ * hip_stream (a hipStream_t; NULL means the null stream).
+ * Limits: 2 <= N <= 10, 1 <= J_n <= 32, 1 <= I_n < 2^31, prod J_n <= 2^20.
+ * Returns PTK_E_INVALID for out-of-range arguments. *out owns all library
+ * device memory of the context; release it with ptk_destroy.
+ */
+ptk_status ptk_create(ptk_ctx **out, int32_t N, const int64_t *dims_host,
+                      const int32_t *ranks_host, void *hip_stream);
+
+/* Release the context and all device memory it owns. NULL is accepted. */
+ptk_status ptk_destroy(ptk_ctx *ctx);
+
+/* Message of the last failed call on ctx (owned by ctx; never NULL). */
+const char *ptk_last_error(const ptk_ctx *ctx);
+
+/* Set options (see ptk_options). PTK_E_INVALID for unknown values. */
+ptk_status ptk_set_options(ptk_ctx *ctx, const ptk_options *opt_host);
+
+/*
+ * Hand over the observed set Omega (Sec. 2.2): nnz entries, idx [N][nnz]
+ * int32 and val [nnz] float32, both device memory that the library only
+ * reads during this call. Builds, for every mode n, the grouping of entries
+ * by their mode-n index (the sets Omega^(n)_i of Table 2) as a CSR copy in
+ * library memory, and the per-wavefront work ranges. Synchronises the stream.
+ * Errors: PTK_E_INVALID if any index is outside [0, I_n) or any value is not
+ * finite (the message gives the count); PTK_E_NOMEM. nnz = 0 is valid.
+ * Duplicate cells are accepted and act as separate observations.
+ */
+ptk_status ptk_set_observed(ptk_ctx *ctx, int64_t nnz, const int32_t *idx,
+                            const float *val);
+
+/*
+ * Bind the model: core (device, float32, C order, prod J_n values) and the
+ * N factor pointers in factors_host[0..N) (each device float32 I_n x J_n).
+ * The caller keeps ownership and must keep the buffers alive while bound.
+ * Later calls read them and update the factors in place; the core is only
+ * written by ptk_orthogonalize. The core may be changed by the caller
+ * between calls (the library re-reads it at the start of every call).
+ */
+ptk_status ptk_bind_model(ptk_ctx *ctx, float *core, float *const *factors_host);
+
+/*
+ * One pass of Alg. 3 for mode n (0-based): every row i of A^(n) becomes the
+ * solution of (B_i + lambda I) a_i = c_i (eq. "rowupdate"), where B_i and
+ * c_i sum delta delta^T and x delta (eqs. "rowB", "rowC", "delta") over the
+ * entries of row i. A row with no entry becomes 0. Requires lambda > 0
+ * (PTK_E_INVALID otherwise). PTK_E_NOT_PD if some system could not be
+ * factorised (those rows are left unchanged; the count is in the message).
+ */
+ptk_status ptk_update_mode(ptk_ctx *ctx, int32_t n, double lambda);
+
+/*
+ * iters iterations of Alg. 2 (lines 3-4): modes 0..N-1 in order, then the
+ * reconstruction error. sse_host[t] / loss_host[t] (either may be NULL)
+ * receive, after iteration t, sum over Omega of (x - x_hat)^2 (the square of
+ * eq. "reconfull") and the loss of eq. "TF_PARTIAL".
+ */
+ptk_status ptk_iterate(ptk_ctx *ctx, int32_t iters, double lambda,
+                       double *sse_host, double *loss_host);
+
+/*
+ * Reconstruction error of the bound model on Omega (eq. "reconfull"):
+ * *sse_host = sum (x - x_hat)^2, *rmse_host = sqrt(sse / nnz),
+ * *loss_host = sse + lambda * sum_n ||A^(n)||_F^2 (eq. "TF_PARTIAL").
+ * Any output pointer may be NULL.
+ */
+ptk_status ptk_recon_error(ptk_ctx *ctx, double lambda, double *sse_host,
+                           double *rmse_host, double *loss_host);
+
+/*
+ * Final step of Alg. 2 (Sec. 3.1): for n = 0..N-1, A^(n) = Q R (thin QR,
+ * diag(R) > 0), A^(n) <- Q, G <- G x_n R. Writes the bound factors and core.
+ * PTK_E_NOT_PD if some A^(n) does not have full column rank.
+ */
+ptk_status ptk_orthogonalize(ptk_ctx *ctx);
+
+/*
+ * Predictions x_hat (eq. "recon2") for m cells: idx [N][m] int32 (device),
+ * out [m] float32 (device, caller-owned). Stream-ordered; does not
+ * synchronise. PTK_E_INVALID for m < 0. Indices are not range-checked here:
+ * the caller guarantees 0 <= idx[n*m+e] < I_n.
+ */
+ptk_status ptk_predict(ptk_ctx *ctx, int64_t m, const int32_t *idx, float *out);
+
+/*
+ * Fold-in (eq. "rowupdate" for a row that is not in the model): the row of
+ * mode n that best fits k observations with G and the other factors held
+ * fixed. idx [N][k] int32 device (the mode-n array is not read), val [k]
+ * float32 device, row_out [J_n] float32 device. k = 0 gives a zero row.
+ * Stream-ordered; does not synchronise.
+ */
+ptk_status ptk_fold_in(ptk_ctx *ctx, int32_t n, int64_t k, const int32_t *idx,
+                       const float *val, double lambda, float *row_out);
+
+/*
+ * Inspection of intermediate results (eqs. "delta", "rowB", "rowC").
+ * ptk_delta: delta^(n) for m cells, idx [N][m] device, out [m][J_n] float32
+ * device. ptk_row_systems: B_i and c_i of every row of mode n for the bound
+ * model, written as float64 to B_out [I_n][J_n][J_n] and c_out [I_n][J_n]
+ * (device; rows with no entry are zero). Both synchronise the stream.
+ */
+ptk_status ptk_delta(ptk_ctx *ctx, int32_t n, int64_t m, const int32_t *idx,
+                     float *out);
+ptk_status ptk_row_systems(ptk_ctx *ctx, int32_t n, double *B_out,
+                           double *c_out);
+
+/*
+ * Per-kernel timing collected while options.profile = 1: for each kernel
+ * family k < *count_host, names_host[k] (static strings), calls_host[k] and
+ * ms_host[k] (summed HIP-event durations on the context's stream). *count_host
+ * is in/out: capacity on entry, number of families on return.
+ * ptk_reset_timers clears the totals.
+ */
+ptk_status ptk_kernel_times(ptk_ctx *ctx, int32_t *count_host,
+                            const char **names_host, int64_t *calls_host,
+                            double *ms_host);
+ptk_status ptk_reset_timers(ptk_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTUCKER_H */

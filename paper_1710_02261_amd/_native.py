@@ -1,0 +1,245 @@
+"""ctypes binding of include/ptucker.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libptucker.so")
+_lib = None
+
+PTK_OK = 0
+PREC_FP64_ACC = 0
+PREC_FP32 = 1
+_STATUS = {0: "PTK_OK", 1: "PTK_E_INVALID", 2: "PTK_E_NOMEM",
+           3: "PTK_E_UNSUPPORTED", 4: "PTK_E_NOT_PD", 5: "PTK_E_HIP",
+           6: "PTK_E_STATE"}
+
+_vp = C.c_void_p
+_i32 = C.c_int32
+_i64 = C.c_int64
+_dbl = C.c_double
+
+
+class _Options(C.Structure):
+    _fields_ = [("precision", _i32), ("chunk_nnz", _i32), ("fuse_error", _i32),
+                ("profile", _i32)]
+
+
+class PtkError(RuntimeError):
+    def __init__(self, status, message):
+        self.status = status
+        self.name = _STATUS.get(status, str(status))
+        super().__init__("%s: %s" % (self.name, message))
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError("libptucker.so is not built; run "
+                          "`python -m paper_1710_02261_amd.build` first")
+    lib = C.CDLL(_LIB_PATH)
+    sigs = {
+        "ptk_create": [C.POINTER(_vp), _i32, C.POINTER(_i64), C.POINTER(_i32), _vp],
+        "ptk_destroy": [_vp],
+        "ptk_set_options": [_vp, C.POINTER(_Options)],
+        "ptk_set_observed": [_vp, _i64, _vp, _vp],
+        "ptk_bind_model": [_vp, _vp, C.POINTER(_vp)],
+        "ptk_update_mode": [_vp, _i32, _dbl],
+        "ptk_iterate": [_vp, _i32, _dbl, C.POINTER(_dbl), C.POINTER(_dbl)],
+        "ptk_recon_error": [_vp, _dbl, C.POINTER(_dbl), C.POINTER(_dbl),
+                            C.POINTER(_dbl)],
+        "ptk_orthogonalize": [_vp],
+        "ptk_predict": [_vp, _i64, _vp, _vp],
+        "ptk_fold_in": [_vp, _i32, _i64, _vp, _vp, _dbl, _vp],
+        "ptk_delta": [_vp, _i32, _i64, _vp, _vp],
+        "ptk_row_systems": [_vp, _i32, _vp, _vp],
+        "ptk_kernel_times": [_vp, C.POINTER(_i32), C.POINTER(C.c_char_p),
+                             C.POINTER(_i64), C.POINTER(_dbl)],
+        "ptk_reset_timers": [_vp],
+    }
+    for name, args in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.ptk_last_error.argtypes = [_vp]
+    lib.ptk_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return _vp(t.data_ptr())
+
+
+class Context:
+    """One ptk_ctx: an N-order tensor shape, core ranks and a HIP stream."""
+
+    def __init__(self, dims, ranks, stream=None):
+        torch = _torch()
+        self._lib = load_library()
+        self.dims = tuple(int(d) for d in dims)
+        self.ranks = tuple(int(r) for r in ranks)
+        self.N = len(self.dims)
+        if len(self.ranks) != self.N:
+            raise ValueError("dims and ranks differ in length")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = _vp()
+        d = (_i64 * self.N)(*self.dims)
+        r = (_i32 * self.N)(*self.ranks)
+        st = self._lib.ptk_create(C.byref(h), self.N, d, r, _vp(stream.cuda_stream))
+        if st != PTK_OK:
+            raise PtkError(st, "ptk_create(%s, %s)" % (self.dims, self.ranks))
+        self._h = h
+        self._keep = []
+
+    # -- plumbing ----------------------------------------------------------
+    def _check(self, st):
+        if st != PTK_OK:
+            msg = self._lib.ptk_last_error(self._h)
+            raise PtkError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ptk_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- C ABI calls ---------------------------------------------------------
+    def set_options(self, precision=PREC_FP64_ACC, chunk_nnz=0, fuse_error=1,
+                    profile=0):
+        o = _Options(precision, chunk_nnz, fuse_error, profile)
+        self._check(self._lib.ptk_set_options(self._h, C.byref(o)))
+
+    def set_observed(self, idx, val):
+        torch = _torch()
+        if idx.dim() != 2 or idx.shape[0] != self.N:
+            raise ValueError("idx must be [N, nnz]")
+        nnz = int(idx.shape[1])
+        if tuple(val.shape) != (nnz,):
+            raise ValueError("val must be [nnz]")
+        self._check(self._lib.ptk_set_observed(
+            self._h, nnz, _dev_ptr(idx, torch.int32, "idx"),
+            _dev_ptr(val, torch.float32, "val")))
+        self.nnz = nnz
+
+    def bind_model(self, core, factors):
+        torch = _torch()
+        if tuple(core.shape) != self.ranks:
+            raise ValueError("core shape %s != ranks %s" % (tuple(core.shape), self.ranks))
+        if len(factors) != self.N:
+            raise ValueError("need one factor per mode")
+        ptrs = (_vp * self.N)()
+        for n, f in enumerate(factors):
+            if tuple(f.shape) != (self.dims[n], self.ranks[n]):
+                raise ValueError("factor %d has shape %s" % (n, tuple(f.shape)))
+            ptrs[n] = _dev_ptr(f, torch.float32, "factor %d" % n)
+        self._check(self._lib.ptk_bind_model(
+            self._h, _dev_ptr(core, torch.float32, "core"), ptrs))
+        self._keep = [core, *factors]
+
+    def update_mode(self, n, lam):
+        self._check(self._lib.ptk_update_mode(self._h, int(n), float(lam)))
+
+    def iterate(self, iters, lam):
+        sse = np.zeros(max(iters, 1))
+        loss = np.zeros(max(iters, 1))
+        self._check(self._lib.ptk_iterate(
+            self._h, int(iters), float(lam),
+            sse.ctypes.data_as(C.POINTER(_dbl)), loss.ctypes.data_as(C.POINTER(_dbl))))
+        return sse[:iters], loss[:iters]
+
+    def recon_error(self, lam=0.0):
+        s, r, l = _dbl(), _dbl(), _dbl()
+        self._check(self._lib.ptk_recon_error(self._h, float(lam), C.byref(s),
+                                              C.byref(r), C.byref(l)))
+        return s.value, r.value, l.value
+
+    def orthogonalize(self):
+        self._check(self._lib.ptk_orthogonalize(self._h))
+
+    def predict(self, idx, out=None):
+        torch = _torch()
+        m = int(idx.shape[1])
+        if out is None:
+            out = torch.empty(m, dtype=torch.float32, device=idx.device)
+        self._check(self._lib.ptk_predict(self._h, m, _dev_ptr(idx, torch.int32, "idx"),
+                                          _dev_ptr(out, torch.float32, "out")))
+        return out
+
+    def fold_in(self, n, idx, val, lam, out=None):
+        torch = _torch()
+        k = int(idx.shape[1])
+        if out is None:
+            out = torch.empty(self.ranks[n], dtype=torch.float32, device=idx.device)
+        iptr = _dev_ptr(idx, torch.int32, "idx") if k else _vp(0)
+        vptr = _dev_ptr(val, torch.float32, "val") if k else _vp(0)
+        self._check(self._lib.ptk_fold_in(self._h, int(n), k, iptr, vptr, float(lam),
+                                          _dev_ptr(out, torch.float32, "out")))
+        return out
+
+    def delta(self, n, idx):
+        torch = _torch()
+        m = int(idx.shape[1])
+        out = torch.empty((m, self.ranks[n]), dtype=torch.float32, device=idx.device)
+        self._check(self._lib.ptk_delta(self._h, int(n), m,
+                                        _dev_ptr(idx, torch.int32, "idx"),
+                                        _dev_ptr(out, torch.float32, "out")))
+        return out
+
+    def row_systems(self, n):
+        torch = _torch()
+        I, J = self.dims[n], self.ranks[n]
+        dev = self._keep[0].device
+        B = torch.empty((I, J, J), dtype=torch.float64, device=dev)
+        c = torch.empty((I, J), dtype=torch.float64, device=dev)
+        self._check(self._lib.ptk_row_systems(self._h, int(n),
+                                              _dev_ptr(B, torch.float64, "B"),
+                                              _dev_ptr(c, torch.float64, "c")))
+        return B, c
+
+    def kernel_times(self):
+        cnt = _i32(64)
+        names = (C.c_char_p * 64)()
+        calls = (_i64 * 64)()
+        ms = (_dbl * 64)()
+        self._check(self._lib.ptk_kernel_times(self._h, C.byref(cnt), names, calls, ms))
+        return {names[k].decode(): (int(calls[k]), float(ms[k]))
+                for k in range(min(cnt.value, 64))}
+
+    def reset_timers(self):
+        self._check(self._lib.ptk_reset_timers(self._h))

@@ -1,0 +1,812 @@
+// C ABI of the row-wise sparse Tucker ALS library (include/ptucker.h).
+//
+// Host orchestration only: argument checks, device buffers, the per-mode CSR
+// build, the work-range split, and the launch order of Alg. 2 / Alg. 3.
+// Every arithmetic step runs in the HIP kernels of this directory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ptk_internal.h"
+
+using namespace ptk;
+
+namespace {
+
+constexpr int kRedBlocks = 1024;   // blocks of the error / norm reductions
+
+struct ModeData {
+    int64_t *rowptr = nullptr;
+    int32_t *rows = nullptr;
+    int32_t *oidx = nullptr;     // [N-1][nnz]
+    float *vals = nullptr;
+    int64_t chunk = 0, nchunks = 0;
+    int32_t *split = nullptr;    // [nsplit][3]
+    int32_t nsplit = 0;
+    bool fast = false;
+};
+
+struct Timed {
+    const char *name;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct ptk_ctx {
+    Shape s{};
+    hipStream_t st = nullptr;
+    int device = 0;
+    int num_cu = 256;
+    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0};
+    int64_t nnz = -1;
+    ModeData md[kMaxN];
+    float *core = nullptr;
+    float *fac[kMaxN] = {};
+    void *gp[kMaxN] = {};        // permuted cores of the row-system kernels
+    double *gpe = nullptr;       // fp64 permuted core of the per-entry kernels
+    int gpe_mode = -1;
+    int64_t core_cells = 1;
+    double *bbuf = nullptr;
+    double *part = nullptr;
+    float *dcache = nullptr;
+    double *red = nullptr;       // [kRedBlocks * (N + 1)] partials + scalars
+    int32_t *bad = nullptr;
+    double *host = nullptr;      // pinned results
+    size_t host_cap = 0;
+    void *qr_work = nullptr;
+    size_t qr_cap = 0;
+    double *fold_bbuf = nullptr, *fold_part = nullptr;
+    int64_t *fold_rowptr = nullptr;
+    int32_t *fold_split = nullptr;
+    int64_t fold_part_chunks = 0;
+    std::string err;
+    std::vector<Timed> pending;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, std::pair<int64_t, double>> totals;
+};
+
+namespace {
+
+ptk_status fail(ptk_ctx *c, ptk_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return s;
+}
+
+#define HIPCHK(ctx, x)                                                          \
+    do {                                                                        \
+        hipError_t e_ = (x);                                                    \
+        if (e_ != hipSuccess)                                                   \
+            return fail(ctx, PTK_E_HIP, "%s failed: %s", #x,                    \
+                        hipGetErrorString(e_));                                 \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void **)p, count * sizeof(T));
+}
+
+void dfree(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+hipEvent_t get_event(ptk_ctx *c) {
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+// Launch through fn, bracketed by events when profiling.
+template <typename F>
+hipError_t timed(ptk_ctx *c, const char *name, F fn) {
+    if (!c->opt.profile) return fn();
+    Timed t{name, get_event(c), get_event(c)};
+    (void)hipEventRecord(t.a, c->st);
+    hipError_t e = fn();
+    (void)hipEventRecord(t.b, c->st);
+    c->pending.push_back(t);
+    return e;
+}
+
+void collect_timers(ptk_ctx *c) {
+    if (c->pending.empty()) return;
+    (void)hipStreamSynchronize(c->st);
+    for (auto &t : c->pending) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, t.a, t.b);
+        auto &tot = c->totals[t.name];
+        tot.first += 1;
+        tot.second += ms;
+        c->pool.push_back(t.a);
+        c->pool.push_back(t.b);
+    }
+    c->pending.clear();
+}
+
+void free_modes(ptk_ctx *c) {
+    for (int n = 0; n < kMaxN; ++n) {
+        ModeData &m = c->md[n];
+        dfree(m.rowptr);
+        dfree(m.rows);
+        dfree(m.oidx);
+        dfree(m.vals);
+        dfree(m.split);
+        m = ModeData();
+    }
+    dfree(c->bbuf);
+    dfree(c->part);
+    dfree(c->dcache);
+    c->bbuf = c->part = nullptr;
+    c->dcache = nullptr;
+    c->nnz = -1;
+}
+
+Arith arith_of(const ptk_ctx *c, int n) {
+    if (!c->md[n].fast) return kArithF64;
+    return c->opt.precision == PTK_PREC_FP32 ? kArithF32 : kArithF64;
+}
+
+bool equal_ranks(const Shape &s) {
+    for (int k = 1; k < s.N; ++k)
+        if (s.ranks[k] != s.ranks[0]) return false;
+    return true;
+}
+
+ptk_status need_model(ptk_ctx *c) {
+    if (c->nnz < 0) return fail(c, PTK_E_STATE, "no observed set (ptk_set_observed)");
+    if (!c->core) return fail(c, PTK_E_STATE, "no model bound (ptk_bind_model)");
+    return PTK_OK;
+}
+
+hipError_t permute(ptk_ctx *c, int n) {
+    return timed(c, "permute_core", [&] {
+        return launch_permute_core(c->core, c->gp[n], c->s, n, arith_of(c, n), c->st);
+    });
+}
+
+// The per-entry kernels (error, predict, delta) always read an fp64 core.
+hipError_t permute_entries(ptk_ctx *c, int n) {
+    return timed(c, "permute_core", [&] {
+        return launch_permute_core(c->core, c->gpe, c->s, n, kArithF64, c->st);
+    });
+}
+
+// Arguments of the delta kernels for mode n over an entry list whose
+// other-mode index arrays are other[t] (t over the modes k != n in order).
+template <typename Args>
+void fill_common(const ptk_ctx *c, int n, Args &a, const int32_t *const *other) {
+    a.gp = c->gp[n];
+    int t = 0, off = 0;
+    for (int k = 0; k < c->s.N; ++k) {
+        if (k == n) continue;
+        a.fac[t] = c->fac[k];
+        a.oidx[t] = other[t];
+        a.jk[t] = c->s.ranks[k];
+        a.aoff[t] = off;
+        off += c->s.ranks[k];
+        ++t;
+    }
+    a.nother = c->s.N - 1;
+    a.jn = c->s.ranks[n];
+}
+
+GramArgs gram_args(const ptk_ctx *c, int n, float *dcache) {
+    const ModeData &m = c->md[n];
+    GramArgs a{};
+    const int32_t *other[kMaxN];
+    for (int t = 0; t < c->s.N - 1; ++t) other[t] = m.oidx + (int64_t)t * c->nnz;
+    fill_common(c, n, a, other);
+    a.E = sys_entries(c->s.ranks[n]);
+    a.rows = m.rows;
+    a.val = m.vals;
+    a.rowptr = m.rowptr;
+    a.nnz = c->nnz;
+    a.chunk = m.chunk;
+    a.bbuf = c->bbuf;
+    a.part = c->part;
+    a.dcache = dcache;
+    return a;
+}
+
+// B_i, c_i for every row of mode n into bbuf (delta + Gram kernel, merge).
+ptk_status systems(ptk_ctx *c, int n, float *dcache) {
+    const ModeData &m = c->md[n];
+    GramArgs a = gram_args(c, n, dcache);
+    HIPCHK(c, timed(c, "gram", [&] {
+        return launch_gram(a, c->s, n, arith_of(c, n), m.nchunks, m.fast, c->st);
+    }));
+    HIPCHK(c, timed(c, "merge", [&] {
+        return launch_merge(c->part, m.split, m.nsplit, a.E, c->bbuf, c->st);
+    }));
+    return PTK_OK;
+}
+
+ptk_status update_mode_impl(ptk_ctx *c, int n, double lambda, float *dcache) {
+    ptk_status s = systems(c, n, dcache);
+    if (s != PTK_OK) return s;
+    const ModeData &m = c->md[n];
+    HIPCHK(c, timed(c, "solve", [&] {
+        return launch_solve(c->bbuf, m.rowptr, c->s.dims[n], c->s.ranks[n], lambda,
+                            c->fac[n], c->bad, c->st);
+    }));
+    return PTK_OK;
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_f64(double *p, double v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t zero_bad(ptk_ctx *c) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, c->bad, 0, (int64_t)1);
+    return hipGetLastError();
+}
+
+ptk_status ensure_host(ptk_ctx *c, size_t doubles) {
+    if (doubles <= c->host_cap) return PTK_OK;
+    if (c->host) (void)hipHostFree(c->host);
+    c->host = nullptr;
+    c->host_cap = 0;
+    HIPCHK(c, hipHostMalloc((void **)&c->host, doubles * sizeof(double)));
+    c->host_cap = doubles;
+    return PTK_OK;
+}
+
+__global__ void k_fill_f64(double *p, double v, int64_t n);
+
+// sum over n of ||A^(n)||_F^2 into *out (device).
+hipError_t factor_norms(ptk_ctx *c, double *partial, double *out) {
+    for (int n = 0; n < c->s.N; ++n) {
+        hipError_t e = launch_sumsq(c->fac[n], c->s.dims[n] * c->s.ranks[n],
+                                    partial + (int64_t)n * kRedBlocks, kRedBlocks,
+                                    c->st);
+        if (e != hipSuccess) return e;
+    }
+    return launch_reduce(partial, c->s.N * kRedBlocks, out, c->st);
+}
+
+// SSE of the bound model over Omega via the per-entry kernel on mode 0.
+hipError_t sse_direct(ptk_ctx *c, double *partial, double *out) {
+    const ModeData &m = c->md[0];
+    EntryArgs a{};
+    const int32_t *other[kMaxN];
+    for (int t = 0; t < c->s.N - 1; ++t) other[t] = m.oidx + (int64_t)t * c->nnz;
+    fill_common(c, 0, a, other);
+    a.gp = c->gpe;
+    a.own_idx = m.rows;
+    a.own = c->fac[0];
+    a.val = m.vals;
+    a.m = c->nnz;
+    a.partial = partial;
+    hipError_t e = permute_entries(c, 0);
+    if (e != hipSuccess) return e;
+    if (c->nnz == 0) {
+        hipLaunchKernelGGL(k_fill_f64, dim3(kRedBlocks / 256), dim3(256), 0, c->st,
+                           partial, 0.0, (int64_t)kRedBlocks);
+        e = hipGetLastError();
+    } else {
+        e = launch_entries(a, c->s, 0, kOutSSE, m.fast, kRedBlocks, c->st);
+    }
+    if (e != hipSuccess) return e;
+    return launch_reduce(partial, kRedBlocks, out, c->st);
+}
+
+ptk_status check_bad(ptk_ctx *c, const char *what) {
+    int32_t bad = 0;
+    HIPCHK(c, hipMemcpyAsync(&bad, c->bad, sizeof bad, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (bad > 0)
+        return fail(c, PTK_E_NOT_PD, "%s: %d system(s) not positive definite", what,
+                    bad);
+    return PTK_OK;
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+extern "C" {
+
+ptk_status ptk_create(ptk_ctx **out, int32_t N, const int64_t *dims_host,
+                      const int32_t *ranks_host, void *hip_stream) {
+    if (!out) return PTK_E_INVALID;
+    *out = nullptr;
+    if (N < 2 || N > kMaxN || !dims_host || !ranks_host) return PTK_E_INVALID;
+    int64_t cells = 1;
+    for (int n = 0; n < N; ++n) {
+        if (dims_host[n] < 1 || dims_host[n] >= (int64_t(1) << 31)) return PTK_E_INVALID;
+        if (ranks_host[n] < 1 || ranks_host[n] > kMaxJ) return PTK_E_INVALID;
+        cells *= ranks_host[n];
+        if (cells > kMaxCore) return PTK_E_INVALID;
+    }
+    ptk_ctx *c = new (std::nothrow) ptk_ctx();
+    if (!c) return PTK_E_NOMEM;
+    c->s.N = N;
+    for (int n = 0; n < N; ++n) {
+        c->s.dims[n] = dims_host[n];
+        c->s.ranks[n] = ranks_host[n];
+    }
+    c->core_cells = cells;
+    c->st = (hipStream_t)hip_stream;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount,
+                                  c->device);
+    // generic kernels keep the other factor rows in LDS: bound their size
+    for (int n = 0; n < N && e == hipSuccess; ++n) {
+        int sumj = 0;
+        for (int k = 0; k < N; ++k)
+            if (k != n) sumj += ranks_host[k];
+        const size_t lds = (size_t)sumj * kWave * 4 + (ranks_host[n] + 1) * 65 * 8;
+        if (lds > 64 * 1024) {
+            delete c;
+            return PTK_E_UNSUPPORTED;
+        }
+    }
+    for (int n = 0; n < N && e == hipSuccess; ++n)
+        e = hipMalloc(&c->gp[n], (size_t)(cells + 64) * sizeof(double));
+    if (e == hipSuccess) e = dalloc(&c->gpe, (size_t)(cells + 64));
+    if (e == hipSuccess) e = dalloc(&c->red, (size_t)kRedBlocks * (N + 1) + 64);
+    if (e == hipSuccess) e = dalloc(&c->bad, 1);
+    if (e != hipSuccess) {
+        ptk_destroy(c);
+        return e == hipErrorOutOfMemory ? PTK_E_NOMEM : PTK_E_HIP;
+    }
+    *out = c;
+    return PTK_OK;
+}
+
+ptk_status ptk_destroy(ptk_ctx *c) {
+    if (!c) return PTK_OK;
+    if (c->st) (void)hipStreamSynchronize(c->st);
+    else (void)hipDeviceSynchronize();
+    free_modes(c);
+    for (int n = 0; n < kMaxN; ++n) dfree(c->gp[n]);
+    dfree(c->gpe);
+    dfree(c->red);
+    dfree(c->bad);
+    dfree(c->qr_work);
+    dfree(c->fold_bbuf);
+    dfree(c->fold_part);
+    dfree(c->fold_rowptr);
+    dfree(c->fold_split);
+    if (c->host) (void)hipHostFree(c->host);
+    for (auto &t : c->pending) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto e : c->pool) (void)hipEventDestroy(e);
+    delete c;
+    return PTK_OK;
+}
+
+const char *ptk_last_error(const ptk_ctx *c) {
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+ptk_status ptk_set_options(ptk_ctx *c, const ptk_options *o) {
+    if (!c || !o) return PTK_E_INVALID;
+    if (o->precision != PTK_PREC_FP64_ACC && o->precision != PTK_PREC_FP32)
+        return fail(c, PTK_E_INVALID, "unknown precision %d", o->precision);
+    if (o->chunk_nnz < 0 || (o->chunk_nnz % kWave) != 0)
+        return fail(c, PTK_E_INVALID, "chunk_nnz must be a multiple of 64");
+    const bool rechunk = o->chunk_nnz != c->opt.chunk_nnz;
+    const bool recache = o->fuse_error != c->opt.fuse_error;
+    if ((rechunk || recache) && c->nnz >= 0)
+        return fail(c, PTK_E_STATE,
+                    "chunk_nnz / fuse_error must be set before ptk_set_observed");
+    c->opt = *o;
+    return PTK_OK;
+}
+
+ptk_status ptk_set_observed(ptk_ctx *c, int64_t nnz, const int32_t *idx,
+                            const float *val) {
+    if (!c) return PTK_E_INVALID;
+    if (nnz < 0 || nnz >= (int64_t(1) << 31))
+        return fail(c, PTK_E_INVALID, "nnz out of range");
+    if (nnz > 0 && (!idx || !val)) return fail(c, PTK_E_INVALID, "null input");
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    free_modes(c);
+    const Shape &s = c->s;
+    const int N = s.N;
+
+    // validate indices and values on the device
+    if (nnz > 0) {
+        unsigned long long *dbad = nullptr;
+        HIPCHK(c, dalloc(&dbad, 2));
+        hipError_t e = hipMemsetAsync(dbad, 0, 2 * sizeof(unsigned long long), c->st);
+        if (e == hipSuccess) e = launch_validate(idx, val, nnz, s, dbad, c->st);
+        unsigned long long hb[2] = {0, 0};
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hb, dbad, sizeof hb, hipMemcpyDeviceToHost, c->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+        dfree(dbad);
+        HIPCHK(c, e);
+        if (hb[0] || hb[1])
+            return fail(c, PTK_E_INVALID,
+                        "%llu index(es) out of range, %llu non-finite value(s)", hb[0],
+                        hb[1]);
+    }
+
+    // per-mode CSR
+    void *work = nullptr;
+    HIPCHK(c, hipMalloc(&work, sort_workspace_bytes(nnz)));
+    const bool eq = equal_ranks(s);
+    for (int n = 0; n < N; ++n) {
+        ModeData &m = c->md[n];
+        hipError_t e = dalloc(&m.rowptr, s.dims[n] + 1);
+        if (e == hipSuccess) e = dalloc(&m.rows, nnz + 64);
+        if (e == hipSuccess) e = dalloc(&m.oidx, (size_t)(N - 1) * nnz + 64);
+        if (e == hipSuccess) e = dalloc(&m.vals, nnz + 64);
+        if (e == hipSuccess)
+            e = build_mode_csr(idx, val, nnz, s, n, work, m.rowptr, m.rows, m.oidx,
+                               m.vals, c->st);
+        if (e != hipSuccess) {
+            dfree(work);
+            free_modes(c);
+            return fail(c, e == hipErrorOutOfMemory ? PTK_E_NOMEM : PTK_E_HIP,
+                        "CSR build of mode %d: %s", n, hipGetErrorString(e));
+        }
+        m.fast = eq && fast_available(N, s.ranks[n], kArithF64);
+    }
+    hipError_t e = hipStreamSynchronize(c->st);
+    dfree(work);
+    if (e != hipSuccess) {
+        free_modes(c);
+        HIPCHK(c, e);
+    }
+    c->nnz = nnz;
+
+    // work ranges and rows that cross them
+    int64_t bbuf_elems = 0, part_elems = 0;
+    for (int n = 0; n < N; ++n) {
+        ModeData &m = c->md[n];
+        const int E = sys_entries(s.ranks[n]);
+        int64_t chunk = c->opt.chunk_nnz;
+        if (chunk <= 0) {
+            const int bpc = gram_blocks_per_cu(s, n, arith_of(c, n), m.fast);
+            const int64_t waves = (int64_t)c->num_cu * std::max(1, bpc);
+            chunk = round_up((nnz + waves - 1) / std::max<int64_t>(waves, 1), kWave);
+            chunk = std::max<int64_t>(chunk, kWave);
+        }
+        m.chunk = chunk;
+        m.nchunks = (nnz + chunk - 1) / chunk;
+        std::vector<int64_t> rp(s.dims[n] + 1);
+        HIPCHK(c, hipMemcpy(rp.data(), m.rowptr, rp.size() * 8, hipMemcpyDeviceToHost));
+        std::vector<int32_t> split;
+        for (int64_t r = 0; r < s.dims[n]; ++r) {
+            if (rp[r] == rp[r + 1]) continue;
+            const int64_t c0 = rp[r] / chunk, c1 = (rp[r + 1] - 1) / chunk;
+            if (c0 != c1) {
+                split.push_back((int32_t)r);
+                split.push_back((int32_t)c0);
+                split.push_back((int32_t)c1);
+            }
+        }
+        m.nsplit = (int32_t)(split.size() / 3);
+        if (m.nsplit > 0) {
+            HIPCHK(c, dalloc(&m.split, split.size()));
+            HIPCHK(c, hipMemcpy(m.split, split.data(), split.size() * 4,
+                                hipMemcpyHostToDevice));
+        }
+        bbuf_elems = std::max(bbuf_elems, s.dims[n] * E);
+        part_elems = std::max(part_elems, m.nchunks * 2 * E);
+    }
+    HIPCHK(c, dalloc(&c->bbuf, bbuf_elems));
+    HIPCHK(c, dalloc(&c->part, part_elems));
+    if (c->opt.fuse_error)
+        HIPCHK(c, dalloc(&c->dcache, (size_t)nnz * s.ranks[N - 1] + 64));
+    return PTK_OK;
+}
+
+ptk_status ptk_bind_model(ptk_ctx *c, float *core, float *const *factors_host) {
+    if (!c || !core || !factors_host) return fail(c, PTK_E_INVALID, "null model");
+    for (int n = 0; n < c->s.N; ++n)
+        if (!factors_host[n]) return fail(c, PTK_E_INVALID, "null factor %d", n);
+    c->core = core;
+    for (int n = 0; n < c->s.N; ++n) c->fac[n] = factors_host[n];
+    return PTK_OK;
+}
+
+ptk_status ptk_update_mode(ptk_ctx *c, int32_t n, double lambda) {
+    if (!c) return PTK_E_INVALID;
+    if (n < 0 || n >= c->s.N) return fail(c, PTK_E_INVALID, "mode %d out of range", n);
+    if (!(lambda > 0.0) || !std::isfinite(lambda))
+        return fail(c, PTK_E_INVALID, "lambda must be > 0");
+    ptk_status s = need_model(c);
+    if (s != PTK_OK) return s;
+    HIPCHK(c, permute(c, n));
+    HIPCHK(c, zero_bad(c));
+    s = update_mode_impl(c, n, lambda, nullptr);
+    if (s != PTK_OK) return s;
+    return check_bad(c, "ptk_update_mode");
+}
+
+ptk_status ptk_iterate(ptk_ctx *c, int32_t iters, double lambda, double *sse_host,
+                       double *loss_host) {
+    if (!c) return PTK_E_INVALID;
+    if (iters < 0) return fail(c, PTK_E_INVALID, "iters < 0");
+    if (!(lambda > 0.0) || !std::isfinite(lambda))
+        return fail(c, PTK_E_INVALID, "lambda must be > 0");
+    ptk_status s = need_model(c);
+    if (s != PTK_OK) return s;
+    if (iters == 0) return PTK_OK;
+    s = ensure_host(c, 2 * (size_t)iters);
+    if (s != PTK_OK) return s;
+    const int N = c->s.N;
+    for (int n = 0; n < N; ++n) HIPCHK(c, permute(c, n));
+    HIPCHK(c, zero_bad(c));
+    double *partial = c->red;
+    double *scal = c->red + (int64_t)kRedBlocks * N;    // 2 doubles
+    const bool fuse = c->dcache != nullptr;
+    for (int t = 0; t < iters; ++t) {
+        for (int n = 0; n < N; ++n) {
+            s = update_mode_impl(c, n, lambda, (fuse && n == N - 1) ? c->dcache : nullptr);
+            if (s != PTK_OK) return s;
+        }
+        HIPCHK(c, timed(c, "error", [&]() -> hipError_t {
+            if (fuse) {
+                const ModeData &m = c->md[N - 1];
+                hipError_t e = launch_sse_cached(c->dcache, m.rows, m.vals, c->fac[N - 1],
+                                                 c->s.ranks[N - 1], c->nnz, partial,
+                                                 kRedBlocks, c->st);
+                if (e != hipSuccess) return e;
+                return launch_reduce(partial, kRedBlocks, scal, c->st);
+            }
+            return sse_direct(c, partial, scal);
+        }));
+        HIPCHK(c, timed(c, "norms", [&] { return factor_norms(c, partial, scal + 1); }));
+        HIPCHK(c, hipMemcpyAsync(c->host + 2 * t, scal, 2 * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->st));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    for (int t = 0; t < iters; ++t) {
+        if (sse_host) sse_host[t] = c->host[2 * t];
+        if (loss_host) loss_host[t] = c->host[2 * t] + lambda * c->host[2 * t + 1];
+    }
+    return check_bad(c, "ptk_iterate");
+}
+
+ptk_status ptk_recon_error(ptk_ctx *c, double lambda, double *sse_host,
+                           double *rmse_host, double *loss_host) {
+    if (!c) return PTK_E_INVALID;
+    ptk_status s = need_model(c);
+    if (s != PTK_OK) return s;
+    s = ensure_host(c, 2);
+    if (s != PTK_OK) return s;
+    double *partial = c->red;
+    double *scal = c->red + (int64_t)kRedBlocks * c->s.N;
+    HIPCHK(c, timed(c, "error", [&] { return sse_direct(c, partial, scal); }));
+    HIPCHK(c, timed(c, "norms", [&] { return factor_norms(c, partial, scal + 1); }));
+    HIPCHK(c, hipMemcpyAsync(c->host, scal, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                             c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    const double sse = c->host[0];
+    if (sse_host) *sse_host = sse;
+    if (rmse_host) *rmse_host = c->nnz > 0 ? std::sqrt(sse / (double)c->nnz) : 0.0;
+    if (loss_host) *loss_host = sse + lambda * c->host[1];
+    return PTK_OK;
+}
+
+ptk_status ptk_orthogonalize(ptk_ctx *c) {
+    if (!c) return PTK_E_INVALID;
+    if (!c->core) return fail(c, PTK_E_STATE, "no model bound (ptk_bind_model)");
+    const Shape &s = c->s;
+    for (int n = 0; n < s.N; ++n)
+        if (s.dims[n] < s.ranks[n])
+            return fail(c, PTK_E_INVALID, "mode %d has fewer rows than its rank", n);
+    size_t need = (size_t)kMaxN * kMaxJ * kMaxJ * 8 + 2 * (size_t)c->core_cells * 8 + 256;
+    size_t qr = 0;
+    for (int n = 0; n < s.N; ++n) qr = std::max(qr, qr_workspace_bytes(s.dims[n], s.ranks[n]));
+    need += qr;
+    if (need > c->qr_cap) {
+        dfree(c->qr_work);
+        c->qr_work = nullptr;
+        c->qr_cap = 0;
+        HIPCHK(c, hipMalloc(&c->qr_work, need));
+        c->qr_cap = need;
+    }
+    double *Rs = (double *)c->qr_work;
+    char *qrw = (char *)c->qr_work + (size_t)kMaxN * kMaxJ * kMaxJ * 8 +
+                2 * (size_t)c->core_cells * 8 + 256;
+    HIPCHK(c, zero_bad(c));
+    for (int n = 0; n < s.N; ++n)
+        HIPCHK(c, timed(c, "qr", [&] {
+            return launch_cholqr2(c->fac[n], s.dims[n], s.ranks[n], qrw,
+                                  Rs + (size_t)n * kMaxJ * kMaxJ, c->bad, c->st);
+        }));
+    HIPCHK(c, timed(c, "core_update", [&] {
+        return launch_core_mode_product(c->core, c->core, s, 0, Rs, c->st);
+    }));
+    return check_bad(c, "ptk_orthogonalize");
+}
+
+ptk_status ptk_predict(ptk_ctx *c, int64_t m, const int32_t *idx, float *out) {
+    if (!c) return PTK_E_INVALID;
+    if (m < 0) return fail(c, PTK_E_INVALID, "m < 0");
+    if (!c->core) return fail(c, PTK_E_STATE, "no model bound (ptk_bind_model)");
+    if (m == 0) return PTK_OK;
+    if (!idx || !out) return fail(c, PTK_E_INVALID, "null buffer");
+    HIPCHK(c, permute_entries(c, 0));
+    EntryArgs a{};
+    const int32_t *other[kMaxN];
+    for (int k = 1; k < c->s.N; ++k) other[k - 1] = idx + (int64_t)k * m;
+    fill_common(c, 0, a, other);
+    a.gp = c->gpe;
+    a.own_idx = idx;
+    a.own = c->fac[0];
+    a.m = m;
+    a.out = out;
+    const bool fast = equal_ranks(c->s) && fast_available(c->s.N, c->s.ranks[0], kArithF64);
+    const int64_t blocks = std::min<int64_t>((m + kWave - 1) / kWave, (int64_t)c->num_cu * 16);
+    HIPCHK(c, timed(c, "predict", [&] {
+        return launch_entries(a, c->s, 0, kOutPredict, fast, blocks, c->st);
+    }));
+    return PTK_OK;
+}
+
+ptk_status ptk_delta(ptk_ctx *c, int32_t n, int64_t m, const int32_t *idx, float *out) {
+    if (!c) return PTK_E_INVALID;
+    if (n < 0 || n >= c->s.N) return fail(c, PTK_E_INVALID, "mode %d out of range", n);
+    if (m < 0) return fail(c, PTK_E_INVALID, "m < 0");
+    if (!c->core) return fail(c, PTK_E_STATE, "no model bound (ptk_bind_model)");
+    if (m == 0) return PTK_OK;
+    HIPCHK(c, permute_entries(c, n));
+    EntryArgs a{};
+    const int32_t *other[kMaxN];
+    int t = 0;
+    for (int k = 0; k < c->s.N; ++k)
+        if (k != n) other[t++] = idx + (int64_t)k * m;
+    fill_common(c, n, a, other);
+    a.gp = c->gpe;
+    a.own_idx = idx + (int64_t)n * m;
+    a.own = c->fac[n];
+    a.m = m;
+    a.out = out;
+    const bool fast = equal_ranks(c->s) && fast_available(c->s.N, c->s.ranks[n], kArithF64);
+    const int64_t blocks = std::min<int64_t>((m + kWave - 1) / kWave, (int64_t)c->num_cu * 16);
+    HIPCHK(c, launch_entries(a, c->s, n, kOutDelta, fast, blocks, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    return PTK_OK;
+}
+
+ptk_status ptk_row_systems(ptk_ctx *c, int32_t n, double *B_out, double *c_out) {
+    if (!c) return PTK_E_INVALID;
+    if (n < 0 || n >= c->s.N) return fail(c, PTK_E_INVALID, "mode %d out of range", n);
+    ptk_status s = need_model(c);
+    if (s != PTK_OK) return s;
+    if (!B_out || !c_out) return fail(c, PTK_E_INVALID, "null output");
+    HIPCHK(c, permute(c, n));
+    s = systems(c, n, nullptr);
+    if (s != PTK_OK) return s;
+    HIPCHK(c, launch_expand_systems(c->bbuf, c->md[n].rowptr, c->s.dims[n],
+                                    c->s.ranks[n], B_out, c_out, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    return PTK_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+__global__ void k_fold_setup(int64_t *rowptr, int32_t *split, int64_t k,
+                             int32_t nchunks) {
+    if (threadIdx.x == 0) {
+        rowptr[0] = 0;
+        rowptr[1] = k;
+        split[0] = 0;
+        split[1] = 0;
+        split[2] = nchunks - 1;
+    }
+}
+
+constexpr int64_t kFoldMaxChunks = 1024;
+
+}  // namespace
+
+extern "C" ptk_status ptk_fold_in(ptk_ctx *c, int32_t n, int64_t k, const int32_t *idx,
+                                  const float *val, double lambda, float *row_out) {
+    if (!c) return PTK_E_INVALID;
+    if (n < 0 || n >= c->s.N) return fail(c, PTK_E_INVALID, "mode %d out of range", n);
+    if (k < 0 || k >= (int64_t(1) << 31)) return fail(c, PTK_E_INVALID, "k out of range");
+    if (!(lambda > 0.0) || !std::isfinite(lambda))
+        return fail(c, PTK_E_INVALID, "lambda must be > 0");
+    if (!c->core) return fail(c, PTK_E_STATE, "no model bound (ptk_bind_model)");
+    if (!row_out || (k > 0 && (!idx || !val)))
+        return fail(c, PTK_E_INVALID, "null buffer");
+    const int J = c->s.ranks[n];
+    const int E = sys_entries(J);
+    if (!c->fold_bbuf) {
+        HIPCHK(c, dalloc(&c->fold_bbuf, (size_t)sys_entries(kMaxJ)));
+        HIPCHK(c, dalloc(&c->fold_part, (size_t)kFoldMaxChunks * 2 * sys_entries(kMaxJ)));
+        HIPCHK(c, dalloc(&c->fold_rowptr, 2));
+        HIPCHK(c, dalloc(&c->fold_split, 3));
+    }
+    int64_t chunk = round_up((k + c->num_cu * 4 - 1) / (c->num_cu * 4), kWave);
+    chunk = std::max<int64_t>(chunk, 4 * kWave);
+    while ((k + chunk - 1) / chunk > kFoldMaxChunks) chunk *= 2;
+    const int64_t nchunks = (k + chunk - 1) / chunk;
+    hipLaunchKernelGGL(k_fold_setup, dim3(1), dim3(64), 0, c->st, c->fold_rowptr,
+                       c->fold_split, k, (int32_t)std::max<int64_t>(nchunks, 1));
+    HIPCHK(c, hipGetLastError());
+    GramArgs a{};
+    const int32_t *other[kMaxN];
+    int t = 0;
+    for (int q = 0; q < c->s.N; ++q)
+        if (q != n) other[t++] = idx + (int64_t)q * k;
+    fill_common(c, n, a, other);
+    a.E = E;
+    a.rows = nullptr;
+    a.val = val;
+    a.rowptr = c->fold_rowptr;
+    a.nnz = k;
+    a.chunk = chunk;
+    a.bbuf = c->fold_bbuf;
+    a.part = c->fold_part;
+    a.dcache = nullptr;
+    const bool fast = equal_ranks(c->s) && fast_available(c->s.N, J, kArithF64);
+    const Arith ar = (fast && c->opt.precision == PTK_PREC_FP32) ? kArithF32 : kArithF64;
+    HIPCHK(c, timed(c, "permute_core", [&] {
+        return launch_permute_core(c->core, c->gp[n], c->s, n, ar, c->st);
+    }));
+    HIPCHK(c, timed(c, "fold_gram", [&] {
+        return launch_gram(a, c->s, n, ar, nchunks, fast, c->st);
+    }));
+    if (nchunks > 1)
+        HIPCHK(c, launch_merge(c->fold_part, c->fold_split, 1, E, c->fold_bbuf, c->st));
+    HIPCHK(c, timed(c, "fold_solve", [&] {
+        return launch_solve(c->fold_bbuf, c->fold_rowptr, 1, J, lambda, row_out,
+                            c->bad, c->st);
+    }));
+    return PTK_OK;
+}
+
+extern "C" ptk_status ptk_kernel_times(ptk_ctx *c, int32_t *count, const char **names,
+                                       int64_t *calls, double *ms) {
+    if (!c || !count) return PTK_E_INVALID;
+    collect_timers(c);
+    int32_t cap = *count, k = 0;
+    for (auto &kv : c->totals) {
+        if (k < cap) {
+            if (names) names[k] = kv.first.c_str();
+            if (calls) calls[k] = kv.second.first;
+            if (ms) ms[k] = kv.second.second;
+        }
+        ++k;
+    }
+    *count = k;
+    return PTK_OK;
+}
+
+extern "C" ptk_status ptk_reset_timers(ptk_ctx *c) {
+    if (!c) return PTK_E_INVALID;
+    collect_timers(c);
+    c->totals.clear();
+    return PTK_OK;
+}

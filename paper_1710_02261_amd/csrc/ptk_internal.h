@@ -1,0 +1,139 @@
+// Internal declarations of the gfx950 sparse Tucker ALS library.
+//
+// Layout of the library's device data (per context):
+//  * per mode n, a CSR copy of the observed set grouped by the mode-n index
+//    (the sets Omega^(n)_i of Table 2): rowptr[I_n+1] (int64), rows[nnz]
+//    (the mode-n index of every entry in grouped order, int32), oidx[N-1][nnz]
+//    (the other modes' indices, int32, modes in increasing order) and
+//    val[nnz] (float32);
+//  * per mode n, the core permuted so that the mode-n index is fastest and
+//    the other modes keep their order: gp[n][m_1..m_{N-1}][j_n], in the
+//    arithmetic type of the delta kernels;
+//  * a row-system buffer bbuf[I_n][E] (float64) with E = J(J+1)/2 + J: the
+//    upper triangle of B_i row by row followed by c_i;
+//  * per work range, two partial row systems (the range's first row when it
+//    began in an earlier range, its last row when it continues past the end).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ptucker.h"
+
+namespace ptk {
+
+constexpr int kMaxN = 10;
+constexpr int kMaxJ = 32;
+constexpr int kWave = 64;
+constexpr int64_t kMaxCore = int64_t(1) << 20;
+
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// Entries of the packed row system for rank J: upper triangle + rhs.
+__host__ __device__ constexpr inline int sys_entries(int J) {
+    return J * (J + 1) / 2 + J;
+}
+// Position of B(p, q), p <= q, in the packed upper triangle (row by row).
+__host__ __device__ inline int tri_pos(int p, int q, int J) {
+    return p * J - (p * (p - 1)) / 2 + (q - p);
+}
+
+// Arguments of the delta / Gram kernels for one mode.
+struct GramArgs {
+    const void *gp;                   // permuted core of mode n (float or double)
+    const float *fac[kMaxN];          // factors of the other modes, mode order
+    const int32_t *oidx[kMaxN];       // other-mode index arrays, same order
+    int32_t jk[kMaxN];                // ranks of the other modes
+    int32_t aoff[kMaxN];              // prefix sums of jk (LDS row offsets)
+    int32_t nother;                   // N - 1
+    int32_t jn;                       // rank of mode n
+    int32_t E;                        // sys_entries(jn)
+    const int32_t *rows;              // mode-n index per entry, or null (all 0)
+    const float *val;                 // values in grouped order
+    const int64_t *rowptr;            // CSR row pointers of mode n
+    int64_t nnz;
+    int64_t chunk;                    // entries per work range (multiple of 64)
+    double *bbuf;                     // complete rows
+    double *part;                     // [nchunks][2][E]
+    float *dcache;                    // [nnz][jn] delta of this mode, or null
+};
+
+// Arguments of the per-entry kernels (predict, error, delta inspection).
+struct EntryArgs {
+    const void *gp;
+    const float *fac[kMaxN];
+    const int32_t *oidx[kMaxN];
+    int32_t jk[kMaxN];
+    int32_t aoff[kMaxN];
+    int32_t nother;
+    int32_t jn;
+    const int32_t *own_idx;           // index of the entry in mode n
+    const float *own;                 // factor A^(n)
+    const float *val;                 // values (error mode)
+    int64_t m;                        // number of entries
+    float *out;                       // predictions [m] or deltas [m][jn]
+    double *partial;                  // per-block partial sums (error mode)
+};
+
+enum EntryOut { kOutDelta = 0, kOutPredict = 1, kOutSSE = 2 };
+
+// ---------------------------------------------------------------------------
+// kernel launchers (ptk_kernels.hip, ptk_sort.hip, ptk_solve.hip)
+// ---------------------------------------------------------------------------
+struct Shape {
+    int N;
+    int64_t dims[kMaxN];
+    int32_t ranks[kMaxN];
+};
+
+// delta precision of the row-system kernels
+enum Arith { kArithF64 = 0, kArithF32 = 1 };
+
+// Is there a compiled fast kernel for this (N, J) with equal ranks?
+bool fast_available(int N, int J, Arith ar);
+
+hipError_t launch_permute_core(const float *G, void *gp, const Shape &s, int n,
+                               Arith ar, hipStream_t st);
+hipError_t launch_gram(const GramArgs &a, const Shape &s, int n, Arith ar,
+                       int64_t nchunks, bool fast, hipStream_t st);
+int gram_blocks_per_cu(const Shape &s, int n, Arith ar, bool fast);
+hipError_t launch_merge(const double *part, const int32_t *split, int32_t nsplit,
+                        int E, double *bbuf, hipStream_t st);
+hipError_t launch_solve(const double *bbuf, const int64_t *rowptr, int64_t I,
+                        int J, double lambda, float *A, int32_t *bad,
+                        hipStream_t st);
+hipError_t launch_entries(const EntryArgs &a, const Shape &s, int n, int kind,
+                          bool fast, int64_t nblocks, hipStream_t st);
+hipError_t launch_sse_cached(const float *dcache, const int32_t *rows,
+                             const float *val, const float *A, int J,
+                             int64_t nnz, double *partial, int nblocks,
+                             hipStream_t st);
+hipError_t launch_sumsq(const float *x, int64_t n, double *partial, int nblocks,
+                        hipStream_t st);
+hipError_t launch_reduce(const double *partial, int n, double *out,
+                         hipStream_t st);
+hipError_t launch_expand_systems(const double *bbuf, const int64_t *rowptr,
+                                 int64_t I, int J, double *B, double *c,
+                                 hipStream_t st);
+hipError_t launch_validate(const int32_t *idx, const float *val, int64_t nnz,
+                           const Shape &s, unsigned long long *bad,
+                           hipStream_t st);
+
+// sort / CSR build (ptk_sort.hip)
+size_t sort_workspace_bytes(int64_t nnz);
+hipError_t build_mode_csr(const int32_t *idx, const float *val, int64_t nnz,
+                          const Shape &s, int n, void *work, int64_t *rowptr,
+                          int32_t *rows, int32_t *oidx, float *vals,
+                          hipStream_t st);
+
+// finalisation (ptk_finalize.hip)
+size_t qr_workspace_bytes(int64_t I, int J);
+hipError_t launch_cholqr2(float *A, int64_t I, int J, void *work, double *R,
+                          int32_t *bad, hipStream_t st);
+hipError_t launch_core_mode_product(const float *G, float *Gout, const Shape &s,
+                                    int n, const double *R, hipStream_t st);
+
+}  // namespace ptk

@@ -1,0 +1,106 @@
+// Row solves of the row-wise ALS (Sec. 3.2, eq. "rowupdate"), FP64.
+//
+// a_i = c_i (B_i + lambda I)^{-1} is computed as the solution of the
+// symmetric positive definite system (B_i + lambda I) a_i^T = c_i^T by a
+// Cholesky factorisation and two triangular solves (Golub & Van Loan,
+// Alg. 4.2.1) instead of the explicit inverse of Alg. 3. One thread owns one
+// row; its packed system lives in LDS, one column per thread.
+#include "ptk_internal.h"
+
+namespace ptk {
+
+// Merge the partial systems of rows that cross work-range boundaries:
+// split[3*s + {0,1,2}] = (row, first range, last range). The first range
+// holds the row's head in its tail slot, every later range its head slot.
+__global__ __launch_bounds__(kWave) void k_merge(const double *__restrict__ part,
+                                                 const int32_t *__restrict__ split,
+                                                 int E, double *__restrict__ bbuf) {
+    const int s = blockIdx.x;
+    const int row = split[3 * s + 0];
+    const int c0 = split[3 * s + 1];
+    const int c1 = split[3 * s + 2];
+    for (int e = threadIdx.x; e < E; e += kWave) {
+        double acc = part[((int64_t)c0 * 2 + 1) * E + e];
+        for (int c = c0 + 1; c <= c1; ++c) acc += part[((int64_t)c * 2 + 0) * E + e];
+        bbuf[(int64_t)row * E + e] = acc;
+    }
+}
+
+hipError_t launch_merge(const double *part, const int32_t *split, int32_t nsplit,
+                        int E, double *bbuf, hipStream_t st) {
+    if (nsplit <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_merge, dim3(nsplit), dim3(kWave), 0, st, part, split, E,
+                       bbuf);
+    return hipGetLastError();
+}
+
+// Packed Cholesky in place: L(i, j), j <= i, overwrites B(j, i).
+__global__ void k_solve(const double *__restrict__ bbuf,
+                        const int64_t *__restrict__ rowptr, int64_t I, int J,
+                        double lambda, float *__restrict__ A,
+                        int32_t *__restrict__ bad) {
+    extern __shared__ double s_sys[];
+    const int bs = blockDim.x;
+    const int64_t i = (int64_t)blockIdx.x * bs + threadIdx.x;
+    if (i >= I) return;
+    float *arow = A + i * J;
+    if (rowptr[i] == rowptr[i + 1]) {      // no entry: B = 0, c = 0 -> a = 0
+        for (int p = 0; p < J; ++p) arow[p] = 0.0f;
+        return;
+    }
+    const int T = J * (J + 1) / 2;
+    const int E = T + J;
+    double *m = s_sys + threadIdx.x;       // entry k at m[k * bs]
+    const double *src = bbuf + i * E;
+    for (int k = 0; k < E; ++k) m[k * bs] = src[k];
+    for (int p = 0; p < J; ++p) m[tri_pos(p, p, J) * bs] += lambda;
+
+    bool ok = true;
+    for (int r = 0; r < J && ok; ++r) {
+        for (int c = 0; c <= r; ++c) {
+            double s = m[tri_pos(c, r, J) * bs];
+            for (int k = 0; k < c; ++k)
+                s -= m[tri_pos(k, r, J) * bs] * m[tri_pos(k, c, J) * bs];
+            if (c == r) {
+                if (!(s > 0.0)) {
+                    ok = false;
+                    break;
+                }
+                m[tri_pos(r, r, J) * bs] = sqrt(s);
+            } else {
+                m[tri_pos(c, r, J) * bs] = s / m[tri_pos(c, c, J) * bs];
+            }
+        }
+    }
+    if (!ok) {
+        atomicAdd(bad, 1);
+        return;                            // row left unchanged
+    }
+    double *y = m + T * bs;                // rhs c, overwritten by y then a
+    for (int r = 0; r < J; ++r) {          // L y = c
+        double s = y[r * bs];
+        for (int k = 0; k < r; ++k) s -= m[tri_pos(k, r, J) * bs] * y[k * bs];
+        y[r * bs] = s / m[tri_pos(r, r, J) * bs];
+    }
+    for (int r = J - 1; r >= 0; --r) {     // L^T a = y
+        double s = y[r * bs];
+        for (int k = r + 1; k < J; ++k) s -= m[tri_pos(r, k, J) * bs] * y[k * bs];
+        y[r * bs] = s / m[tri_pos(r, r, J) * bs];
+    }
+    for (int p = 0; p < J; ++p) arow[p] = (float)y[p * bs];
+}
+
+hipError_t launch_solve(const double *bbuf, const int64_t *rowptr, int64_t I,
+                        int J, double lambda, float *A, int32_t *bad,
+                        hipStream_t st) {
+    if (I <= 0) return hipSuccess;
+    const int E = sys_entries(J);
+    int bs = 64;
+    while (bs > 8 && (size_t)E * bs * 8 > 64 * 1024) bs /= 2;
+    const size_t lds = (size_t)E * bs * 8;
+    hipLaunchKernelGGL(k_solve, dim3((unsigned)((I + bs - 1) / bs)), dim3(bs), lds,
+                       st, bbuf, rowptr, I, J, lambda, A, bad);
+    return hipGetLastError();
+}
+
+}  // namespace ptk

@@ -1,0 +1,300 @@
+// Mode-n grouping of the observed entries (the sets Omega^(n)_i of Table 2,
+// which Alg. 3 visits row by row).
+//
+// The entries are ordered by their mode-n index with a stable least-
+// significant-digit radix sort (8-bit digits): per pass, every tile of 4096
+// entries counts its digits, one exclusive scan over (digit, tile) gives each
+// tile's output offsets, and each tile scatters its entries in input order,
+// ranking equal digits inside a wavefront with ballots. Stability makes the
+// order inside a row, and hence every later floating-point sum, independent of
+// the launch. The other modes' indices and the values are then gathered into
+// the grouped order and the row pointers are read off the sorted keys.
+#include "ptk_internal.h"
+
+namespace ptk {
+
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kRsThreads * kRsItems;   // 4096
+constexpr int kRsDigits = 256;
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;  // 2048
+
+// --------------------------------------------------------------------------
+// exclusive scan of int32 (counts < 2^31)
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t v) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int32_t t = __shfl_up(v, off, kWave);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan of v over the block (kScanThreads threads); *total receives
+// the block sum.
+__device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t *s_w,
+                                                   int32_t *total) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    const int32_t incl = wave_incl_scan(v);
+    if (lane == kWave - 1) s_w[w] = incl;
+    __syncthreads();
+    int32_t off = 0, tot = 0;
+    for (int k = 0; k < kScanThreads / kWave; ++k) {
+        if (k < w) off += s_w[k];
+        tot += s_w[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(
+    const int32_t *__restrict__ in, int64_t n, int32_t *__restrict__ bsum) {
+    __shared__ int32_t s_w[kScanThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) v += in[base + k];
+    int32_t tot;
+    block_excl_scan(v, s_w, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(
+    const int32_t *in, int32_t *out, int64_t n, const int32_t *__restrict__ boff) {
+    __shared__ int32_t s_w[kScanThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int32_t x[kScanItems];
+    int32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        x[k] = (base + k < n) ? in[base + k] : 0;
+        v += x[k];
+    }
+    int32_t tot;
+    int32_t run = block_excl_scan(v, s_w, &tot) + (boff ? boff[blockIdx.x] : 0);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += x[k];
+    }
+}
+
+static int64_t scan_work_elems(int64_t n) {
+    int64_t w = 0;
+    while (n > kScanTile) {
+        n = (n + kScanTile - 1) / kScanTile;
+        w += n;
+    }
+    return w + 1;
+}
+
+// out may alias in.
+static hipError_t scan_exclusive(const int32_t *in, int32_t *out, int64_t n,
+                                 int32_t *work, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb == 1) {
+        hipLaunchKernelGGL(k_scan_down, dim3(1), dim3(kScanThreads), 0, st, in,
+                           out, n, (const int32_t *)nullptr);
+        return hipGetLastError();
+    }
+    int32_t *bsum = work;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0,
+                       st, in, n, bsum);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = scan_exclusive(bsum, bsum, nb, work + nb, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, st,
+                       in, out, n, (const int32_t *)bsum);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// radix sort passes
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kRsThreads) void k_radix_hist(
+    const int32_t *__restrict__ keys, int64_t n, int shift,
+    int32_t *__restrict__ hist, int64_t ntiles) {
+    __shared__ int32_t h[kRsDigits];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+#pragma unroll
+    for (int k = 0; k < kRsItems; ++k) {
+        const int64_t pos = base + k * kRsThreads + threadIdx.x;
+        if (pos < n) atomicAdd(&h[(keys[pos] >> shift) & (kRsDigits - 1)], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kRsThreads) void k_radix_scatter(
+    const int32_t *__restrict__ kin, const int32_t *__restrict__ vin,
+    int32_t *__restrict__ kout, int32_t *__restrict__ vout, int64_t n, int shift,
+    const int32_t *__restrict__ offs, int64_t ntiles) {
+    constexpr int kWaves = kRsThreads / kWave;
+    __shared__ int32_t s_base[kRsDigits];
+    __shared__ int32_t s_cnt[kWaves][kRsDigits];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int w = tid / kWave;
+    s_base[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) s_cnt[k][tid] = 0;
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int k = 0; k < kRsItems; ++k) {
+        const int64_t pos = base + k * kRsThreads + tid;
+        const bool valid = pos < n;
+        const int32_t key = valid ? kin[pos] : 0;
+        const int dig = (key >> shift) & (kRsDigits - 1);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (dig >> b) & 1;
+            const uint64_t m = __ballot(valid && bit);
+            peers &= bit ? m : ~m;
+        }
+        const int wrank = __popcll(peers & lt);
+        if (valid && wrank == 0) s_cnt[w][dig] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            int32_t r = s_base[dig] + wrank;
+            for (int q = 0; q < w; ++q) r += s_cnt[q][dig];
+            kout[r] = key;
+            vout[r] = vin ? vin[pos] : (int32_t)pos;
+        }
+        __syncthreads();
+        int32_t add = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) {
+            add += s_cnt[q][tid];
+            s_cnt[q][tid] = 0;
+        }
+        s_base[tid] += add;
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------------------
+// gather into grouped order; row pointers from the sorted keys
+// --------------------------------------------------------------------------
+struct GatherArgs {
+    const int32_t *idx;
+    const float *val;
+    const int32_t *perm;
+    int32_t *oidx;     // [N-1][nnz]
+    float *vals;
+    int64_t nnz;
+    int32_t N, n;
+};
+
+__global__ void k_gather(GatherArgs g) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < g.nnz;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = g.perm[p];
+        int t = 0;
+        for (int k = 0; k < g.N; ++k) {
+            if (k == g.n) continue;
+            g.oidx[(int64_t)t * g.nnz + p] = g.idx[(int64_t)k * g.nnz + e];
+            ++t;
+        }
+        g.vals[p] = g.val[e];
+    }
+}
+
+__global__ void k_rowptr(const int32_t *__restrict__ keys, int64_t nnz, int64_t I,
+                         int64_t *__restrict__ rowptr) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > nnz) return;
+    const int64_t kp = (p < nnz) ? keys[p] : I;
+    const int64_t kprev = (p == 0) ? -1 : keys[p - 1];
+    for (int64_t r = kprev + 1; r <= kp; ++r) rowptr[r] = p;
+}
+
+static int64_t n_tiles(int64_t nnz) { return (nnz + kRsTile - 1) / kRsTile; }
+
+size_t sort_workspace_bytes(int64_t nnz) {
+    const int64_t nt = n_tiles(nnz > 0 ? nnz : 1);
+    const int64_t hist = nt * kRsDigits;
+    size_t b = 0;
+    b += 4 * (size_t)(nnz + 64) * 4;              // keys A/B, vals A/B
+    b += (size_t)(hist + 64) * 4;                 // histogram / offsets
+    b += (size_t)(scan_work_elems(hist) + 64) * 4;
+    return b;
+}
+
+hipError_t build_mode_csr(const int32_t *idx, const float *val, int64_t nnz,
+                          const Shape &s, int n, void *work, int64_t *rowptr,
+                          int32_t *rows, int32_t *oidx, float *vals,
+                          hipStream_t st) {
+    const int64_t I = s.dims[n];
+    if (nnz == 0) {
+        hipLaunchKernelGGL(k_rowptr, dim3(1), dim3(64), 0, st, rows, (int64_t)0, I,
+                           rowptr);
+        return hipGetLastError();
+    }
+    const int64_t nt = n_tiles(nnz);
+    const int64_t hist_n = nt * kRsDigits;
+    int32_t *keyA = (int32_t *)work;
+    int32_t *keyB = keyA + nnz + 64;
+    int32_t *valA = keyB + nnz + 64;
+    int32_t *valB = valA + nnz + 64;
+    int32_t *hist = valB + nnz + 64;
+    int32_t *swork = hist + hist_n + 64;
+
+    int bits = 0;
+    while ((int64_t(1) << bits) < I) ++bits;
+    const int passes = bits <= 8 ? 1 : (bits + 7) / 8;
+
+    const int32_t *kin = idx + (int64_t)n * nnz;
+    const int32_t *vin = nullptr;
+    int32_t *kout = keyA, *vout = valA;
+    hipError_t e = hipSuccess;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nt), dim3(kRsThreads), 0, st,
+                           kin, nnz, shift, hist, nt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = scan_exclusive(hist, hist, hist_n, swork, st)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nt), dim3(kRsThreads), 0,
+                           st, kin, vin, kout, vout, nnz, shift, hist, nt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        kin = kout;
+        vin = vout;
+        kout = (kout == keyA) ? keyB : keyA;
+        vout = (vout == valA) ? valB : valA;
+    }
+    // kin / vin hold the sorted keys and the permutation
+    if ((e = hipMemcpyAsync(rows, kin, nnz * 4, hipMemcpyDeviceToDevice, st)) !=
+        hipSuccess)
+        return e;
+    GatherArgs g;
+    g.idx = idx;
+    g.val = val;
+    g.perm = vin;
+    g.oidx = oidx;
+    g.vals = vals;
+    g.nnz = nnz;
+    g.N = s.N;
+    g.n = n;
+    int64_t blocks = (nnz + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)blocks), dim3(256), 0, st, g);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rowptr, dim3((unsigned)((nnz + 1 + 255) / 256)), dim3(256),
+                       0, st, rows, nnz, I, rowptr);
+    return hipGetLastError();
+}
+
+}  // namespace ptk

@@ -1,0 +1,312 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Every case feeds identical inputs (the same float32 values widened exactly
+for the oracle) to both sides. Tolerances:
+
+* delta, predictions: 1e-6 relative (fp64 arithmetic, fp32 output);
+* row systems B_i, c_i: 1e-10 relative (fp64 on both sides);
+* one mode update (eq. "rowupdate"): per-row ||a_gpu - a_ora|| / ||a_ora||
+  <= 1e-5, rows with no entry exactly 0;
+* error and loss: 1e-9 relative; ALS trajectory (SSE per iteration) 1e-4.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import context, f64, log, row_rel_err, to_device
+
+pytestmark = pytest.mark.gpu
+
+FAST = [
+    ((50, 40, 30), (5, 5, 5), 3000),
+    ((30, 25, 20, 15), (10, 10, 10, 10), 2500),
+    ((60, 50, 40), (16, 16, 16), 4001),
+    ((12, 11, 10, 9, 8), (8, 8, 8, 8, 8), 3333),
+    ((40, 30, 35), (8, 8, 8), 2100),
+    ((20, 18, 16, 14), (5, 5, 5, 5), 1999),
+]
+GENERIC = [
+    ((40, 30, 20), (3, 2, 4), 2000),
+    ((9, 8, 7, 6), (2, 3, 4, 5), 1500),
+    ((5, 5, 4, 4, 3, 3), (2, 2, 2, 2, 2, 3), 1200),
+    ((30, 20, 25), (20, 3, 4), 1700),
+]
+
+
+def ids(cases):
+    return ["x".join(map(str, r)) + "_%d" % z for _, r, z in cases]
+
+
+def problem(dims, ranks, nnz, seed=0, skew=None):
+    return synth.make_small(dims, ranks, nnz, seed=seed, skew=skew)
+
+
+def oracle_inputs(p, fac=None):
+    G = p.core.astype(np.float64)
+    A = [a.astype(np.float64) for a in (fac if fac is not None else p.factors)]
+    return G, A, p.val.astype(np.float64)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1710_02261_amd as ptk
+    ptk.load_library()
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dims,ranks,nnz", FAST + GENERIC, ids=ids(FAST + GENERIC))
+def test_delta_matches_oracle(dims, ranks, nnz):
+    import torch
+    p = problem(dims, ranks, nnz, seed=1)
+    log("delta", dims, ranks, nnz)
+    ctx, idx, val, core, fac = context(p)
+    G, A, _ = oracle_inputs(p)
+    sel = np.arange(0, nnz, max(1, nnz // 97))
+    for n in range(len(dims)):
+        got = f64(ctx.delta(n, idx))
+        for e in sel:
+            rows = [A[k][p.idx[k, e]] for k in range(len(dims))]
+            want = oracle.delta(G, rows, n)
+            np.testing.assert_allclose(got[e], want, rtol=1e-6,
+                                       atol=1e-6 * np.abs(want).max())
+    ctx.close()
+
+
+@pytest.mark.parametrize("dims,ranks,nnz", FAST + GENERIC, ids=ids(FAST + GENERIC))
+def test_row_systems_match_oracle(dims, ranks, nnz):
+    p = problem(dims, ranks, nnz, seed=2)
+    log("systems", dims, ranks, nnz)
+    ctx, *_ = context(p, chunk_nnz=128)
+    G, A, val = oracle_inputs(p)
+    for n in range(len(dims)):
+        B, c = ctx.row_systems(n)
+        B, c = f64(B), f64(c)
+        counts = np.bincount(p.idx[n], minlength=dims[n])
+        rows = list(np.argsort(-counts)[:3]) + list(range(0, dims[n], max(1, dims[n] // 7)))
+        for i in rows:
+            Bo, co = oracle.row_system(G, A, p.idx, val, n, int(i))
+            scale = max(np.abs(Bo).max(), 1e-300)
+            assert np.abs(B[i] - Bo).max() <= 1e-10 * scale, (n, i)
+            assert np.abs(c[i] - co).max() <= 1e-10 * max(np.abs(co).max(), 1e-300)
+    ctx.close()
+
+
+def _check_update(p, chunk_nnz=0, precision=0, tol=1e-5):
+    ctx, idx, val, core, fac = context(p, chunk_nnz=chunk_nnz, precision=precision)
+    G, A, v = oracle_inputs(p)
+    worst = 0.0
+    for n in range(p.N):
+        before = [f.clone() for f in fac]
+        ctx.update_mode(n, p.lam)
+        got = f64(fac[n])
+        want = oracle.update_rows(G, A, p.idx, v, n, p.lam)
+        empty = np.bincount(p.idx[n], minlength=p.dims[n]) == 0
+        assert np.all(got[empty] == 0.0)
+        err = row_rel_err(got[~empty], want[~empty])
+        worst = max(worst, float(err.max()) if err.size else 0.0)
+        assert err.max() <= tol, (n, err.max())
+        # restore the pre-update state so every mode starts from the same model
+        for f, b in zip(fac, before):
+            f.copy_(b)
+    ctx.close()
+    return worst
+
+
+@pytest.mark.parametrize("dims,ranks,nnz", FAST + GENERIC, ids=ids(FAST + GENERIC))
+def test_update_mode_matches_oracle(dims, ranks, nnz):
+    p = problem(dims, ranks, nnz, seed=3)
+    log("update", dims, ranks, nnz, "worst", _check_update(p))
+
+
+@pytest.mark.parametrize("chunk", [64, 192, 1024])
+def test_update_with_rows_split_across_ranges(chunk):
+    # skewed indices: head rows span many work ranges and need the merge
+    p = problem((80, 70, 60), (5, 5, 5), 6000, seed=4, skew=1.2)
+    log("split", chunk, "worst", _check_update(p, chunk_nnz=chunk))
+    p = problem((80, 70, 60), (3, 2, 4), 6000, seed=5, skew=1.2)
+    log("split generic", chunk, "worst", _check_update(p, chunk_nnz=chunk))
+
+
+def test_update_fp32_arithmetic_stated_tolerance():
+    """fp32 delta arithmetic (PTK_PREC_FP32): per-row error reported, <= 1e-3."""
+    for dims, ranks, nnz in FAST[:4]:
+        p = problem(dims, ranks, nnz, seed=6)
+        w = _check_update(p, precision=1, tol=1e-3)
+        log("fp32 arithmetic", dims, ranks, "worst per-row rel err", w)
+
+
+def test_empty_rows_and_empty_observed_set():
+    import torch
+    import paper_1710_02261_amd as ptk
+    p = problem((30, 20, 10), (5, 5, 5), 40, seed=7)   # many empty rows
+    _check_update(p)
+    # nnz = 0: every row becomes zero, error is zero
+    ctx = ptk.Context(p.dims, p.ranks)
+    idx = torch.zeros((3, 0), dtype=torch.int32, device="cuda")
+    val = torch.zeros((0,), dtype=torch.float32, device="cuda")
+    ctx.set_observed(idx, val)
+    _, _, core, fac = to_device(p)
+    ctx.bind_model(core, fac)
+    sse, loss = ctx.iterate(2, 0.01)
+    assert np.all(sse == 0.0)
+    for f in fac:
+        assert torch.count_nonzero(f).item() == 0
+    ctx.close()
+
+
+def test_iterate_trajectory_c1_matches_oracle():
+    p = synth.make_c1()
+    ctx, idx, val, core, fac = context(p)
+    G, A, v = oracle_inputs(p)
+    sse, loss = ctx.iterate(p.iters, p.lam)
+    Af, L, S = oracle.fit(G, A, p.idx, v, p.lam, p.iters)
+    log("c1 sse gpu", sse, "oracle", S)
+    np.testing.assert_allclose(sse, S, rtol=1e-4)
+    np.testing.assert_allclose(loss, L[:, -1], rtol=1e-4)
+    for n in range(3):
+        err = row_rel_err(f64(fac[n]), Af[n])
+        assert np.median(err) < 1e-4
+    ctx.close()
+
+
+def test_iterate_unfused_error_matches_fused():
+    p = problem((40, 35, 30, 25), (5, 5, 5, 5), 5000, seed=8)
+    c1, _, _, _, fac1 = context(p, fuse_error=1)
+    c2, _, _, _, fac2 = context(p, fuse_error=0)
+    s1, l1 = c1.iterate(3, p.lam)
+    s2, l2 = c2.iterate(3, p.lam)
+    np.testing.assert_allclose(s1, s2, rtol=1e-9)
+    np.testing.assert_allclose(l1, l2, rtol=1e-9)
+    c1.close()
+    c2.close()
+
+
+@pytest.mark.parametrize("dims,ranks,nnz", [FAST[1], GENERIC[1]], ids=ids([FAST[1], GENERIC[1]]))
+def test_recon_error_and_predict_match_oracle(dims, ranks, nnz):
+    p = problem(dims, ranks, nnz, seed=9)
+    ctx, idx, val, core, fac = context(p)
+    G, A, v = oracle_inputs(p)
+    sse, rmse, loss = ctx.recon_error(0.3)
+    want = oracle.sse(G, A, p.idx, v)
+    assert sse == pytest.approx(want, rel=1e-9)
+    assert rmse == pytest.approx(np.sqrt(want / nnz), rel=1e-9)
+    assert loss == pytest.approx(oracle.loss(G, A, p.idx, v, 0.3), rel=1e-9)
+    got = f64(ctx.predict(idx))
+    np.testing.assert_allclose(got, oracle.predict(G, A, p.idx), rtol=1e-6,
+                               atol=1e-6 * np.abs(got).max())
+    ctx.close()
+
+
+@pytest.mark.parametrize("dims,ranks", [((50, 40, 30), (5, 5, 5)),
+                                        ((30, 25, 20, 15), (2, 3, 4, 5))])
+def test_orthogonalize_matches_oracle(dims, ranks):
+    import torch
+    p = problem(dims, ranks, 1000, seed=10)
+    ctx, idx, val, core, fac = context(p)
+    before = f64(ctx.predict(idx))
+    ctx.orthogonalize()
+    G, A, _ = oracle_inputs(p)
+    Go, Ao, Rs = oracle.orthogonalize(G, A)
+    for n in range(p.N):
+        Q = f64(fac[n])
+        np.testing.assert_allclose(Q.T @ Q, np.eye(ranks[n]), atol=2e-6)
+        np.testing.assert_allclose(Q, Ao[n], atol=2e-6)
+    np.testing.assert_allclose(f64(core), Go, rtol=1e-5, atol=1e-5 * np.abs(Go).max())
+    after = f64(ctx.predict(idx))
+    np.testing.assert_allclose(after, before, rtol=1e-5, atol=1e-5 * np.abs(before).max())
+    ctx.close()
+
+
+@pytest.mark.parametrize("k", [0, 1, 7, 300, 70000])
+def test_fold_in_matches_oracle(k):
+    import torch
+    import paper_1710_02261_amd as ptk
+    p = problem((200, 150, 100), (5, 5, 5), 3000, seed=11)
+    _, _, core, fac = to_device(p)
+    ctx = ptk.Context(p.dims, p.ranks)
+    ctx.bind_model(core, fac)
+    rng = np.random.default_rng(k)
+    idx = np.stack([np.zeros(k, np.int64), rng.integers(0, 150, k),
+                    rng.integers(0, 100, k)]).astype(np.int32)
+    val = rng.standard_normal(k).astype(np.float32)
+    got = f64(ctx.fold_in(0, torch.from_numpy(idx).cuda(), torch.from_numpy(val).cuda(),
+                          0.05))
+    torch.cuda.synchronize()
+    G, A, _ = oracle_inputs(p)
+    want = oracle.fold_in(G, A, 0, idx, val.astype(np.float64), 0.05)
+    if k == 0:
+        assert np.all(got == 0.0)
+    else:
+        assert np.linalg.norm(got - want) <= 1e-5 * np.linalg.norm(want)
+    ctx.close()
+
+
+def test_fold_in_of_existing_row_equals_its_update():
+    import torch
+    p = problem((60, 50, 40), (5, 5, 5), 4000, seed=12)
+    ctx, idx, val, core, fac = context(p)
+    i = int(np.bincount(p.idx[0]).argmax())
+    sel = p.idx[0] == i
+    sub = torch.from_numpy(np.ascontiguousarray(p.idx[:, sel])).cuda()
+    sv = torch.from_numpy(np.ascontiguousarray(p.val[sel])).cuda()
+    row = f64(ctx.fold_in(0, sub, sv, p.lam))
+    ctx.update_mode(0, p.lam)
+    np.testing.assert_allclose(row, f64(fac[0])[i], rtol=1e-6, atol=1e-7)
+    ctx.close()
+
+
+def test_deterministic_runs():
+    import torch
+    p = problem((80, 70, 60), (5, 5, 5), 6000, seed=13, skew=1.1)
+    outs = []
+    for _ in range(2):
+        ctx, idx, val, core, fac = context(p)
+        sse, _ = ctx.iterate(2, p.lam)
+        outs.append((sse, [f.cpu().numpy().copy() for f in fac]))
+        ctx.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    for a, b in zip(outs[0][1], outs[1][1]):
+        assert np.array_equal(a, b)
+
+
+def test_invariant_to_coo_order():
+    p = problem((50, 40, 30), (5, 5, 5), 3000, seed=14)
+    perm = np.random.default_rng(0).permutation(p.nnz)
+    q = synth.Problem(p.name, p.dims, p.ranks, np.ascontiguousarray(p.idx[:, perm]),
+                      np.ascontiguousarray(p.val[perm]), p.core, p.factors, p.lam)
+    c1, _, _, _, f1 = context(p)
+    c2, _, _, _, f2 = context(q)
+    c1.update_mode(1, p.lam)
+    c2.update_mode(1, p.lam)
+    np.testing.assert_allclose(f64(f1[1]), f64(f2[1]), rtol=1e-6, atol=1e-7)
+    c1.close()
+    c2.close()
+
+
+def test_error_statuses():
+    import torch
+    import paper_1710_02261_amd as ptk
+    p = problem((20, 20, 20), (5, 5, 5), 500, seed=15)
+    idx, val, core, fac = to_device(p)
+    ctx = ptk.Context(p.dims, p.ranks)
+    with pytest.raises(ptk.PtkError, match="PTK_E_STATE"):
+        ctx.update_mode(0, 0.01)
+    bad = idx.clone()
+    bad[1, 7] = 20
+    with pytest.raises(ptk.PtkError, match="PTK_E_INVALID"):
+        ctx.set_observed(bad, val)
+    nanv = val.clone()
+    nanv[3] = float("nan")
+    with pytest.raises(ptk.PtkError, match="PTK_E_INVALID"):
+        ctx.set_observed(idx, nanv)
+    ctx.set_observed(idx, val)
+    ctx.bind_model(core, fac)
+    with pytest.raises(ptk.PtkError, match="PTK_E_INVALID"):
+        ctx.update_mode(0, 0.0)
+    with pytest.raises(ptk.PtkError, match="PTK_E_INVALID"):
+        ctx.update_mode(3, 0.01)
+    ctx.update_mode(0, 0.01)          # still usable after the errors
+    ctx.close()
