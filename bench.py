@@ -1,0 +1,243 @@
+"""Throughput of the row-wise sparse Tucker ALS on one MI355X.
+
+Workload: order-4 tensor, 100,000 per mode, 10^7 distinct observed cells with
+truncated Zipf(1.1) index skew per mode, ranks J=10, planted Tucker values
++ N(0, 0.1) noise, lambda = 0.01 (synthetic, seeded; ``synth.make_c2``).
+
+One step = one iteration of Alg. 2 (lines 3-4): the four mode updates of
+Alg. 3 and the reconstruction error, all on the GPU through the C ABI. The
+metric is nnz x iterations / s over the timed steps, inputs resident in HBM.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+
+Prints one JSON line. Besides the throughput it reports the roofline of the
+dominant kernel (delta + row-system kernel) from HIP-event durations taken
+inside the library, and the FP64 oracle's throughput on a bounded sample of
+the same workload on this host's CPU (``cpu_baseline``).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f64": 78.6e12, "f32": 157.3e12}          # MI355X vector FP64 / FP32
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gram_c2_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1710_02261_amd", "csrc", "ptk_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def fma_per_nnz_mode(N, J):
+    """Algorithmic multiply-adds per (entry, mode): delta by the contraction
+    chain J^N + J^(N-1) + ... + J^2, plus the packed Gram and rhs."""
+    chain = sum(J ** k for k in range(2, N + 1))
+    return chain + J * (J + 1) // 2 + J
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_record(launch_nnz):
+    """HBM bytes per launch of the dominant kernel from the committed PMC
+    summary, or None when it is missing or the kernel source has changed."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(p, seconds=20.0):
+    """FP64 oracle on a bounded sample of the workload (single thread)."""
+    import oracle
+    G = p.core.astype(np.float64)
+    A = [a.astype(np.float64) for a in p.factors]
+    v = p.val.astype(np.float64)
+    rng = np.random.default_rng(123)
+    N = p.N
+    per = seconds / (N + 1)
+    # calibrate the per-entry cost on a few rows, then size each sample
+    t_per_nnz = []
+    total_nnz = 0
+    for n in range(N):
+        cnt = np.bincount(p.idx[n], minlength=p.dims[n])
+        nz = np.flatnonzero(cnt)
+        order = rng.permutation(nz)
+        # calibration rows
+        csum = np.cumsum(cnt[order])
+        k0 = int(np.searchsorted(csum, 200)) + 1
+        t0 = time.perf_counter()
+        oracle.update_rows(G, A, p.idx, v, n, p.lam, rows=order[:k0])
+        dt = time.perf_counter() - t0
+        rate = max(dt, 1e-3) / max(csum[k0 - 1], 1)
+        target = max(200, int(per / rate))
+        k = int(np.searchsorted(csum, target)) + 1
+        rows = order[:k]
+        t0 = time.perf_counter()
+        oracle.update_rows(G, A, p.idx, v, n, p.lam, rows=rows)
+        dt = time.perf_counter() - t0
+        nn = int(cnt[rows].sum())
+        t_per_nnz.append(dt / nn)
+        total_nnz += nn
+    m = max(200, int(per / max(t_per_nnz[0], 1e-9)))
+    sel = rng.choice(p.nnz, size=min(m, p.nnz), replace=False)
+    sub = np.ascontiguousarray(p.idx[:, sel])
+    t0 = time.perf_counter()
+    oracle.sse(G, A, sub, v[sel])
+    t_err = (time.perf_counter() - t0) / len(sel)
+    per_nnz_iter = sum(t_per_nnz) + t_err
+    return {
+        "value": 1.0 / per_nnz_iter,
+        "unit": "nnz*iters/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "FP64 oracle, one thread: Alg. 3 row updates of %d random rows "
+                  "per mode (%d entries in all) and the error of %d random "
+                  "entries of the same workload; seconds per entry-iteration "
+                  "summed over the 4 modes and the error pass" %
+                  (len(rows), total_nnz, len(sel)),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--nnz", type=int, default=10_000_000)
+    ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variant", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d, WORLD_SIZE %d requested)" % (args.gpus, world),
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_1710_02261_amd as ptk
+    from paper_1710_02261_amd import _native
+    if not os.path.exists(_native.library_path()):
+        from paper_1710_02261_amd import build as hipbuild
+        hipbuild.build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    t0 = time.perf_counter()
+    p = synth.make_c2(nnz=args.nnz)
+    log("generated workload in %.1f s" % (time.perf_counter() - t0))
+    dev = torch.device("cuda:0")
+    idx = torch.from_numpy(p.idx).to(dev)
+    val = torch.from_numpy(p.val).to(dev)
+    core = torch.from_numpy(p.core).to(dev)
+    fac0 = [torch.from_numpy(a).to(dev) for a in p.factors]
+    N, J = p.N, p.ranks[0]
+
+    def run(precision):
+        fac = [f.clone() for f in fac0]
+        ctx = ptk.Context(p.dims, p.ranks)
+        ctx.set_options(precision=precision, fuse_error=1, profile=0)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        ctx.set_observed(idx, val)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - ts
+        ctx.bind_model(core, fac)
+        if args.warmup:
+            ctx.iterate(args.warmup, p.lam, strict=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sse, loss = ctx.iterate(args.steps, p.lam, strict=False)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t1
+        not_pd = ctx.not_pd_count()
+        # second pass with per-kernel HIP events on the library's stream
+        ctx.set_options(precision=precision, fuse_error=1, profile=1)
+        ctx.reset_timers()
+        ctx.iterate(args.steps, p.lam, strict=False)
+        times = ctx.kernel_times()
+        ctx.close()
+        return elapsed, setup, sse, loss, times, not_pd
+
+    prec = ptk.PREC_FP64_ACC if args.precision == "f64" else ptk.PREC_FP32
+    elapsed, setup, sse, loss, times, not_pd = run(prec)
+    value = p.nnz * args.steps / elapsed
+    log("timed %d steps: %.2f ms/step, %.3e nnz*iters/s" %
+        (args.steps, 1e3 * elapsed / args.steps, value))
+    log("kernels: " + ", ".join("%s %.3f ms x%d" % (k, v[1] / max(v[0], 1), v[0])
+                                for k, v in sorted(times.items())))
+
+    calls, ms = times.get("gram", (0, 0.0))
+    avg_s = ms / max(calls, 1) / 1e3
+    flops = 2.0 * p.nnz * fma_per_nnz_mode(N, J)
+    achieved = flops / avg_s / 1e12
+    peak = PEAK[args.precision] / 1e12
+    traffic = traffic_record(p.nnz)
+    roofline = {"bound": "alu", "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                "kernel": "k_gram_fast<4,10,2,%s>" % ("double" if args.precision == "f64"
+                                                      else "float"),
+                "avg_launch_ms": avg_s * 1e3,
+                "flops_per_launch": flops}
+
+    out = {
+        "metric": "nnz*ALS-iters/s for row-wise factor update (1 GPU); fold-in p50/p99 ms",
+        "value": value,
+        "unit": "nnz*iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": "order-4 100000^4, 1e7 distinct cells, Zipf(1.1) "
+                               "per mode, J=10, planted Tucker + N(0,0.1), "
+                               "lambda=0.01, seed 1",
+                   "nnz": p.nnz, "ranks": list(p.ranks), "dims": list(p.dims),
+                   "step": "Alg. 2 iteration: 4 mode updates + error"},
+        "roofline": roofline,
+        "setup_s": setup,
+        "sse_last": float(sse[-1]),
+        "not_pd_rows_timed": int(not_pd),
+        "kernel_ms": {k: v[1] / max(v[0], 1) for k, v in times.items()},
+    }
+    if not args.no_variant:
+        other = "f32" if args.precision == "f64" else "f64"
+        e2, _, s2, _, t2, _ = run(ptk.PREC_FP32 if other == "f32" else ptk.PREC_FP64_ACC)
+        out["variant_%s_arith" % other] = {
+            "value": p.nnz * args.steps / e2,
+            "ms_per_step": 1e3 * e2 / args.steps,
+            "gram_ms": t2.get("gram", (1, 0.0))[1] / max(t2.get("gram", (1, 0))[0], 1),
+            "sse_last": float(s2[-1])}
+    if not args.no_cpu:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+        log("cpu baseline in %.1f s" % (time.perf_counter() - t0))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

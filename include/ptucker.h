@@ -112,10 +112,22 @@ ptk_status ptk_update_mode(ptk_ctx *ctx, int32_t n, double lambda);
  * iters iterations of Alg. 2 (lines 3-4): modes 0..N-1 in order, then the
  * reconstruction error. sse_host[t] / loss_host[t] (either may be NULL)
  * receive, after iteration t, sum over Omega of (x - x_hat)^2 (the square of
- * eq. "reconfull") and the loss of eq. "TF_PARTIAL".
+ * eq. "reconfull") and the loss of eq. "TF_PARTIAL". If some row systems were
+ * not positive definite in floating point, all iterations still run, the
+ * outputs are filled, those rows keep their previous values and the call
+ * returns PTK_E_NOT_PD (count in the message and from ptk_not_pd_count).
  */
 ptk_status ptk_iterate(ptk_ctx *ctx, int32_t iters, double lambda,
                        double *sse_host, double *loss_host);
+
+/*
+ * Number of row systems that were not positive definite in floating point
+ * during the last ptk_update_mode / ptk_iterate / ptk_orthogonalize call.
+ * B_i + lambda I is positive definite in exact arithmetic; in FP64 the
+ * factorisation can break down when ||B_i|| * 2^-52 exceeds lambda for a row
+ * with fewer entries than J_n. Synchronises the stream.
+ */
+ptk_status ptk_not_pd_count(ptk_ctx *ctx, int64_t *count_host);
 
 /*
  * Reconstruction error of the bound model on Omega (eq. "reconfull"):

@@ -220,8 +220,11 @@ def solve(B, c, lam):
     return a
 
 
-def update_rows(G, A, idx, val, n, lam, rows=None):
-    """New values of the requested rows of A^(n) (all rows when None)."""
+def update_rows(G, A, idx, val, n, lam, rows=None, return_bad=False):
+    """New values of the requested rows of A^(n) (all rows when None).
+
+    A row whose system is not positive definite in FP64 keeps its previous
+    value; with return_bad=True the number of such rows is returned too."""
     lib = _load()
     G, Gp = _d(G)
     I, J = _shape(G, A)
@@ -242,7 +245,7 @@ def update_rows(G, A, idx, val, n, lam, rows=None):
                               out.ctypes.data_as(_dp))
     if bad < 0:
         raise RuntimeError("ora_update_rows failed: %d" % bad)
-    return out
+    return (out, int(bad)) if return_bad else out
 
 
 def update_mode(G, A, idx, val, n, lam):

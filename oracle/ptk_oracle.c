@@ -219,8 +219,9 @@ int ora_row_system(int N, const int32_t *J, const double *G,
  *
  * rows_req: nreq row ids, or NULL for all I_n rows in order. Results go to
  * out (nreq x J_n, or I_n x J_n when rows_req is NULL); A is not modified.
- * Returns the number of rows whose system was not positive definite (their
- * output is left as zeros), or a negative code on allocation failure.
+ * Returns the number of rows whose system was not positive definite in
+ * floating point (their output is their previous value), or a negative code
+ * on allocation failure.
  */
 int64_t ora_update_rows(int N, const int64_t *I, const int32_t *J,
                         const double *G, const double *const *A, int64_t nnz,
@@ -256,7 +257,11 @@ int64_t ora_update_rows(int N, const int64_t *I, const int32_t *J,
         ora_row_system_list(N, J, G, A, nnz, idx, val, n, ents + start[i],
                             start[i + 1] - start[i], B, c);
         if (ora_solve(Jn, B, c, lambda, a) != 0) {
-            for (int j = 0; j < Jn; ++j) a[j] = 0.0;
+            /* B + lambda I is positive definite in exact arithmetic, but not
+               always in floating point: when ||B|| * eps exceeds lambda for a
+               rank-deficient B (fewer entries than J_n) the factorisation
+               breaks down. Such a row keeps its previous value. */
+            for (int j = 0; j < Jn; ++j) a[j] = A[n][i * Jn + j];
             ++bad;
         }
     }

@@ -66,6 +66,7 @@ def load_library():
         "ptk_kernel_times": [_vp, C.POINTER(_i32), C.POINTER(C.c_char_p),
                              C.POINTER(_i64), C.POINTER(_dbl)],
         "ptk_reset_timers": [_vp],
+        "ptk_not_pd_count": [_vp, C.POINTER(_i64)],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -175,13 +176,23 @@ class Context:
     def update_mode(self, n, lam):
         self._check(self._lib.ptk_update_mode(self._h, int(n), float(lam)))
 
-    def iterate(self, iters, lam):
+    def iterate(self, iters, lam, strict=True):
+        """Alg. 2 iterations; with strict=False a PTK_E_NOT_PD status (rows
+        whose system was not positive definite in FP64 keep their values) is
+        not raised and the results are returned."""
         sse = np.zeros(max(iters, 1))
         loss = np.zeros(max(iters, 1))
-        self._check(self._lib.ptk_iterate(
+        st = self._lib.ptk_iterate(
             self._h, int(iters), float(lam),
-            sse.ctypes.data_as(C.POINTER(_dbl)), loss.ctypes.data_as(C.POINTER(_dbl))))
+            sse.ctypes.data_as(C.POINTER(_dbl)), loss.ctypes.data_as(C.POINTER(_dbl)))
+        if not (st == 4 and not strict):
+            self._check(st)
         return sse[:iters], loss[:iters]
+
+    def not_pd_count(self):
+        n = _i64()
+        self._check(self._lib.ptk_not_pd_count(self._h, C.byref(n)))
+        return n.value
 
     def recon_error(self, lam=0.0):
         s, r, l = _dbl(), _dbl(), _dbl()

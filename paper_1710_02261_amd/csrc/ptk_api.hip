@@ -60,6 +60,7 @@ struct ptk_ctx {
     float *dcache = nullptr;
     double *red = nullptr;       // [kRedBlocks * (N + 1)] partials + scalars
     int32_t *bad = nullptr;
+    int64_t last_not_pd = 0;
     double *host = nullptr;      // pinned results
     size_t host_cap = 0;
     void *qr_work = nullptr;
@@ -320,6 +321,7 @@ ptk_status check_bad(ptk_ctx *c, const char *what) {
     int32_t bad = 0;
     HIPCHK(c, hipMemcpyAsync(&bad, c->bad, sizeof bad, hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
+    c->last_not_pd = bad;
     if (bad > 0)
         return fail(c, PTK_E_NOT_PD, "%s: %d system(s) not positive definite", what,
                     bad);
@@ -801,6 +803,12 @@ extern "C" ptk_status ptk_kernel_times(ptk_ctx *c, int32_t *count, const char **
         ++k;
     }
     *count = k;
+    return PTK_OK;
+}
+
+extern "C" ptk_status ptk_not_pd_count(ptk_ctx *c, int64_t *count) {
+    if (!c || !count) return PTK_E_INVALID;
+    *count = c->last_not_pd;
     return PTK_OK;
 }
 

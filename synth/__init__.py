@@ -84,16 +84,31 @@ def _keys(idx: np.ndarray, dims) -> np.ndarray:
 
 
 def _dedup(idx: np.ndarray, dims, redraw, max_rounds: int = 200) -> np.ndarray:
-    """Redraw every tuple that repeats an earlier one until all are distinct."""
+    """Redraw every tuple that repeats an earlier one until all are distinct.
+
+    The first pass keeps the first occurrence of every cell; later passes
+    only test the redrawn tuples against the sorted set of kept cells.
+    """
+    keys = _keys(idx, dims)
+    kept, first = np.unique(keys, return_index=True)
+    dup = np.ones(idx.shape[1], dtype=bool)
+    dup[first] = False
+    todo = np.flatnonzero(dup)
     for _ in range(max_rounds):
-        keys = _keys(idx, dims)
-        _, first = np.unique(keys, return_index=True)
-        dup = np.ones(idx.shape[1], dtype=bool)
-        dup[first] = False
-        nd = int(dup.sum())
-        if nd == 0:
+        if todo.size == 0:
             return idx
-        idx[:, dup] = redraw(nd)
+        new = redraw(todo.size)
+        nk = _keys(new, dims)
+        pos = np.searchsorted(kept, nk)
+        hit = (pos < kept.size) & (kept[np.minimum(pos, kept.size - 1)] == nk)
+        _, f2 = np.unique(nk, return_index=True)
+        fresh = np.zeros(todo.size, dtype=bool)
+        fresh[f2] = True
+        ok = fresh & ~hit
+        idx[:, todo[ok]] = new[:, ok]
+        add = np.sort(nk[ok])
+        kept = np.insert(kept, np.searchsorted(kept, add), add)
+        todo = todo[~ok]
     raise RuntimeError("could not draw a set of distinct cells")
 
 
@@ -206,13 +221,16 @@ def _kron_rows(rows):
     return K
 
 
-def planted_values(idx, G, A, chunk: int = 1 << 16) -> np.ndarray:
+def planted_values(idx, G, A, chunk: int = 1 << 13) -> np.ndarray:
     """Evaluate a planted Tucker model at the given cells (input recipe only).
 
     The modes are split into a left and a right group; per chunk of cells the
     model value is <kron(left rows), G_mat @ kron(right rows)> with G_mat the
-    core reshaped to (left cells, right cells).
+    core reshaped to (left cells, right cells). Chunks run on a thread pool
+    and each writes its own slice, so the result does not depend on timing.
     """
+    import concurrent.futures as cf
+    import os
     N = len(A)
     ranks = G.shape
     h = max(1, N // 2)
@@ -220,12 +238,22 @@ def planted_values(idx, G, A, chunk: int = 1 << 16) -> np.ndarray:
     Gm = np.ascontiguousarray(G.reshape(JL, -1))
     nnz = idx.shape[1]
     out = np.empty(nnz, dtype=np.float64)
-    for s in range(0, nnz, chunk):
+
+    def work(s):
         e = min(nnz, s + chunk)
         KL = _kron_rows([A[n][idx[n, s:e]] for n in range(h)])
         KR = _kron_rows([A[n][idx[n, s:e]] for n in range(h, N)])
         M = KR @ Gm.T
         out[s:e] = np.einsum("bi,bi->b", KL, M)
+
+    starts = range(0, nnz, chunk)
+    workers = min(16, os.cpu_count() or 1)
+    if nnz <= 4 * chunk or workers == 1:
+        for s in starts:
+            work(s)
+    else:
+        with cf.ThreadPoolExecutor(workers) as ex:
+            list(ex.map(work, starts))
     return out
 
 

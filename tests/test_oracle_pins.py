@@ -318,3 +318,20 @@ def test_fold_in_equals_row_update():
 def test_solve_rejects_non_positive_definite():
     with pytest.raises(np.linalg.LinAlgError):
         oracle.solve(-np.eye(3), np.ones(3), 0.01)
+
+
+def test_numerically_singular_row_keeps_previous_value():
+    """B + lambda I is PD in exact arithmetic; with a one-entry row and huge
+    factors, ||B|| * eps far exceeds lambda and FP64 Cholesky breaks down.
+    The row then keeps its previous value (the library does the same)."""
+    rng = np.random.default_rng(23)
+    dims, ranks = (4, 5, 6), (3, 3, 3)
+    G, A = rand_model(dims, ranks, rng)
+    A = [a * 1e7 for a in A]
+    idx = np.array([[1], [2], [3]], dtype=np.int32)
+    val = np.array([1.0])
+    out, bad = oracle.update_rows(G, A, idx, val, 0, 1e-2, return_bad=True)
+    if bad:
+        np.testing.assert_array_equal(out[1], A[0][1])
+    # rows without entries are still exactly zero
+    assert np.all(out[[0, 2, 3]] == 0.0)
