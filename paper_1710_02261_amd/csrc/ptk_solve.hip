@@ -12,25 +12,44 @@ namespace ptk {
 // Merge the partial systems of rows that cross work-range boundaries:
 // split[3*s + {0,1,2}] = (row, first range, last range). The first range
 // holds the row's head in its tail slot, every later range its head slot.
-__global__ __launch_bounds__(kWave) void k_merge(const double *__restrict__ part,
-                                                 const int32_t *__restrict__ split,
-                                                 int E, double *__restrict__ bbuf) {
+// A block of 256 threads serves one row: 64 entries of the packed system at a
+// time, the ranges dealt round-robin to 4 groups whose sums are combined in a
+// fixed order (deterministic for any range count).
+constexpr int kMergeGroups = 4;
+
+__global__ __launch_bounds__(kWave * kMergeGroups) void k_merge(
+    const double *__restrict__ part, const int32_t *__restrict__ split, int E,
+    double *__restrict__ bbuf) {
+    __shared__ double s_acc[kMergeGroups][kWave];
     const int s = blockIdx.x;
     const int row = split[3 * s + 0];
     const int c0 = split[3 * s + 1];
     const int c1 = split[3 * s + 2];
-    for (int e = threadIdx.x; e < E; e += kWave) {
-        double acc = part[((int64_t)c0 * 2 + 1) * E + e];
-        for (int c = c0 + 1; c <= c1; ++c) acc += part[((int64_t)c * 2 + 0) * E + e];
-        bbuf[(int64_t)row * E + e] = acc;
+    const int lane = threadIdx.x % kWave;
+    const int grp = threadIdx.x / kWave;
+    for (int e0 = 0; e0 < E; e0 += kWave) {
+        const int e = e0 + lane;
+        double acc = 0.0;
+        if (e < E) {
+            if (grp == 0) acc = part[((int64_t)c0 * 2 + 1) * E + e];
+#pragma unroll 4
+            for (int c = c0 + 1 + grp; c <= c1; c += kMergeGroups)
+                acc += part[((int64_t)c * 2 + 0) * E + e];
+        }
+        s_acc[grp][lane] = acc;
+        __syncthreads();
+        if (grp == 0 && e < E)
+            bbuf[(int64_t)row * E + e] =
+                (s_acc[0][lane] + s_acc[1][lane]) + (s_acc[2][lane] + s_acc[3][lane]);
+        __syncthreads();
     }
 }
 
 hipError_t launch_merge(const double *part, const int32_t *split, int32_t nsplit,
                         int E, double *bbuf, hipStream_t st) {
     if (nsplit <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_merge, dim3(nsplit), dim3(kWave), 0, st, part, split, E,
-                       bbuf);
+    hipLaunchKernelGGL(k_merge, dim3(nsplit), dim3(kWave * kMergeGroups), 0, st, part,
+                       split, E, bbuf);
     return hipGetLastError();
 }
 
