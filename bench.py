@@ -29,7 +29,6 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"f64": 78.6e12, "f32": 157.3e12}          # MI355X vector FP64 / FP32
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gram_c2_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1710_02261_amd", "csrc", "ptk_kernels.hip")
 
@@ -115,14 +114,28 @@ def cpu_baseline(p, seconds=20.0):
     }
 
 
+WORKLOADS = {
+    "c2": ("order-4 100000^4, 1e7 distinct cells, Zipf(1.1) per mode, J=10, "
+           "planted Tucker + N(0,0.1), lambda=0.01, seed 1"),
+    "c3": ("rating tensor 480000x18000x2000, 1e8 distinct cells, users Zipf(0.6), "
+           "items Zipf(0.9), days uniform, ratings 1..5, J=16, lambda=0.01, seed 2"),
+    "c4": ("order-5 10000^5, 5e7 distinct cells, lognormal(3,2) row weights per mode "
+           "(1..1e5 per row), J=8, planted rank 4 + N(0,0.1), lambda=0.01, seed 3"),
+}
+PREC_NAMES = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
+PREC_DTYPE = {"f64": "f64", "f32": "f32", "bf16": "bf16", "bf16x3": "bf16"}
+PREC_PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15, "bf16x3": 2.5e15}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--nnz", type=int, default=10_000_000)
-    ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2")
+    ap.add_argument("--nnz", type=int, default=0, help="override the entry count")
+    ap.add_argument("--precision", choices=sorted(PREC_NAMES), default="f64")
+    ap.add_argument("--cpu-seconds", type=float, default=40.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variant", action="store_true")
     args = ap.parse_args()
@@ -144,8 +157,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
     t0 = time.perf_counter()
-    p = synth.make_c2(nnz=args.nnz)
-    log("generated workload in %.1f s" % (time.perf_counter() - t0))
+    kw = {"nnz": args.nnz} if args.nnz else {}
+    p = synth.make(args.workload, **kw)
+    log("generated %s (%d entries) in %.1f s" % (args.workload, p.nnz,
+                                                time.perf_counter() - t0))
     dev = torch.device("cuda:0")
     idx = torch.from_numpy(p.idx).to(dev)
     val = torch.from_numpy(p.val).to(dev)
@@ -153,10 +168,10 @@ def main():
     fac0 = [torch.from_numpy(a).to(dev) for a in p.factors]
     N, J = p.N, p.ranks[0]
 
-    def run(precision):
+    def run(prec):
         fac = [f.clone() for f in fac0]
         ctx = ptk.Context(p.dims, p.ranks)
-        ctx.set_options(precision=precision, fuse_error=1, profile=0)
+        ctx.set_options(precision=PREC_NAMES[prec], fuse_error=1, profile=0)
         torch.cuda.synchronize()
         ts = time.perf_counter()
         ctx.set_observed(idx, val)
@@ -171,68 +186,92 @@ def main():
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t1
         not_pd = ctx.not_pd_count()
+        # the model's error by a direct FP64 pass over all entries (untimed)
+        _, rmse_direct, _ = ctx.recon_error(p.lam)
         # second pass with per-kernel HIP events on the library's stream
-        ctx.set_options(precision=precision, fuse_error=1, profile=1)
+        ctx.set_options(precision=PREC_NAMES[prec], fuse_error=1, profile=1)
         ctx.reset_timers()
         ctx.iterate(args.steps, p.lam, strict=False)
         times = ctx.kernel_times()
         ctx.close()
-        return elapsed, setup, sse, loss, times, not_pd
+        gname = "gram_mfma" if prec.startswith("bf16") else "gram"
+        calls, ms = times.get(gname, (0, 0.0))
+        return {"elapsed": elapsed, "setup": setup, "sse": sse, "times": times,
+                "not_pd": not_pd, "gram_ms": ms / max(calls, 1),
+                "value": p.nnz * args.steps / elapsed,
+                "rmse": float(rmse_direct),
+                "rmse_fused": float(np.sqrt(max(sse[-1], 0.0) / p.nnz))}
 
-    prec = ptk.PREC_FP64_ACC if args.precision == "f64" else ptk.PREC_FP32
-    elapsed, setup, sse, loss, times, not_pd = run(prec)
-    value = p.nnz * args.steps / elapsed
-    log("timed %d steps: %.2f ms/step, %.3e nnz*iters/s" %
-        (args.steps, 1e3 * elapsed / args.steps, value))
+    main_prec = args.precision
+    r = run(main_prec)
+    log("%s: %.2f ms/step, %.3e nnz*iters/s" % (main_prec, 1e3 * r["elapsed"] / args.steps,
+                                                  r["value"]))
     log("kernels: " + ", ".join("%s %.3f ms x%d" % (k, v[1] / max(v[0], 1), v[0])
-                                for k, v in sorted(times.items())))
+                                for k, v in sorted(r["times"].items())))
 
-    calls, ms = times.get("gram", (0, 0.0))
-    avg_s = ms / max(calls, 1) / 1e3
-    flops = 2.0 * p.nnz * fma_per_nnz_mode(N, J)
+    avg_s = r["gram_ms"] / 1e3
+    if main_prec.startswith("bf16"):
+        # matrix-core work per entry and mode: stage 1 J^N (+2x for the split
+        # products), Gram J^2 (+2x); the VALU part is not counted here
+        mult = 3 if main_prec == "bf16x3" else 1
+        flops = 2.0 * p.nnz * mult * (J ** N + J * J)
+        bound, unit = "mfma", "TFLOP/s"
+    else:
+        flops = 2.0 * p.nnz * fma_per_nnz_mode(N, J)
+        bound, unit = "alu", "TFLOP/s"
     achieved = flops / avg_s / 1e12
-    peak = PEAK[args.precision] / 1e12
-    traffic = traffic_record(p.nnz)
-    roofline = {"bound": "alu", "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-                "kernel": "k_gram_fast<4,10,2,%s>" % ("double" if args.precision == "f64"
-                                                      else "float"),
-                "avg_launch_ms": avg_s * 1e3,
-                "flops_per_launch": flops}
+    peak = PREC_PEAK[main_prec] / 1e12
+    traffic = traffic_record(p.nnz) if args.workload == "c2" and main_prec == "f64" else None
+    kname = {"f64": "k_gram_fast<%d,%d,U,double>" % (N, J),
+             "f32": "k_gram_fast<%d,%d,U,float>" % (N, J),
+             "bf16": "k_gram_mfma<%d,%d,1>" % (N, J),
+             "bf16x3": "k_gram_mfma<%d,%d,3>" % (N, J)}[main_prec]
+    roofline = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": traffic, "kernel": kname,
+                "avg_launch_ms": r["gram_ms"], "flops_per_launch": flops}
 
     out = {
         "metric": "nnz*ALS-iters/s for row-wise factor update (1 GPU); fold-in p50/p99 ms",
-        "value": value,
+        "value": r["value"],
         "unit": "nnz*iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": 1e3 * r["elapsed"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.precision,
+        "dtype": PREC_DTYPE[main_prec],
         "data": "synthetic",
-        "config": {"workload": "order-4 100000^4, 1e7 distinct cells, Zipf(1.1) "
-                               "per mode, J=10, planted Tucker + N(0,0.1), "
-                               "lambda=0.01, seed 1",
+        "config": {"workload": WORKLOADS[args.workload],
                    "nnz": p.nnz, "ranks": list(p.ranks), "dims": list(p.dims),
-                   "step": "Alg. 2 iteration: 4 mode updates + error"},
+                   "step": "Alg. 2 iteration: %d mode updates + error" % N},
         "roofline": roofline,
-        "setup_s": setup,
-        "sse_last": float(sse[-1]),
-        "not_pd_rows_timed": int(not_pd),
-        "kernel_ms": {k: v[1] / max(v[0], 1) for k, v in times.items()},
+        "setup_s": r["setup"],
+        "rmse_after": r["rmse"],
+        "rmse_after_fused": r["rmse_fused"],
+        "not_pd_rows_timed": int(r["not_pd"]),
+        "kernel_ms": {k: v[1] / max(v[0], 1) for k, v in r["times"].items()},
     }
     if not args.no_variant:
-        other = "f32" if args.precision == "f64" else "f64"
-        e2, _, s2, _, t2, _ = run(ptk.PREC_FP32 if other == "f32" else ptk.PREC_FP64_ACC)
-        out["variant_%s_arith" % other] = {
-            "value": p.nnz * args.steps / e2,
-            "ms_per_step": 1e3 * e2 / args.steps,
-            "gram_ms": t2.get("gram", (1, 0.0))[1] / max(t2.get("gram", (1, 0))[0], 1),
-            "sse_last": float(s2[-1])}
-    if not args.no_cpu:
+        variants = {}
+        for prec in PREC_NAMES:
+            if prec == main_prec:
+                continue
+            if prec.startswith("bf16") and not (N in (3, 4) and J in (8, 10, 16)
+                                                and len(set(p.ranks)) == 1):
+                continue
+            v = run(prec)
+            variants[prec] = {"value": v["value"], "ms_per_step": 1e3 * v["elapsed"] / args.steps,
+                              "gram_ms": v["gram_ms"], "rmse_after": v["rmse"],
+                              "rmse_rel_to_main": v["rmse"] / r["rmse"] - 1.0}
+            log("%s: %.2f ms/step, rmse %.6g (main %.6g)" % (
+                prec, variants[prec]["ms_per_step"], v["rmse"], r["rmse"]))
+        out["variants"] = variants
+        out["variants_note"] = ("same workload, init and iteration count; rmse_after = "
+                                "sqrt(SSE/nnz) by a direct FP64 pass after warmup+steps "
+                                "iterations")
+    if not args.no_cpu and args.workload == "c2":
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
         log("cpu baseline in %.1f s" % (time.perf_counter() - t0))

@@ -45,13 +45,21 @@ typedef struct ptk_ctx ptk_ctx;
 /* Arithmetic of the delta / Gram kernels (the solve and the QR are FP64). */
 typedef enum ptk_precision {
     PTK_PREC_FP64_ACC = 0,  /* fp32 data, fp64 delta and Gram arithmetic    */
-    PTK_PREC_FP32 = 1       /* fp32 delta arithmetic, fp64 Gram sums        */
+    PTK_PREC_FP32 = 1,      /* fp32 delta arithmetic, fp64 Gram sums        */
+    PTK_PREC_BF16 = 2,      /* bf16 delta and Gram on the matrix cores with
+                               fp32 accumulation; equal ranks only, (N, J) in
+                               {(3,8),(3,10),(3,16),(4,8),(4,10)}           */
+    PTK_PREC_BF16X3 = 3     /* as PTK_PREC_BF16 with every operand split into
+                               two bf16 parts (hi + lo) and three products:
+                               about 16 significant bits                    */
 } ptk_precision;
 
 typedef struct ptk_options {
     int32_t precision;      /* ptk_precision                                 */
     int32_t chunk_nnz;      /* entries per wavefront work range; 0 = auto    */
-    int32_t fuse_error;     /* 1: error pass fused into the last mode        */
+    int32_t fuse_error;     /* 1: error of ptk_iterate from the last mode's
+                               row systems (sum x^2 - 2 a^T c + a^T B a per
+                               row); 0: a separate pass over all entries     */
     int32_t profile;        /* 1: time every kernel launch with HIP events   */
 } ptk_options;
 
@@ -72,7 +80,10 @@ ptk_status ptk_destroy(ptk_ctx *ctx);
 /* Message of the last failed call on ctx (owned by ctx; never NULL). */
 const char *ptk_last_error(const ptk_ctx *ctx);
 
-/* Set options (see ptk_options). PTK_E_INVALID for unknown values. */
+/* Set options (see ptk_options). PTK_E_INVALID for unknown values,
+ * PTK_E_UNSUPPORTED for the BF16 forms on a shape without a matrix-core
+ * kernel, PTK_E_STATE when chunk_nnz or a change to or from a BF16 form comes
+ * after ptk_set_observed (they shape its work split). */
 ptk_status ptk_set_options(ptk_ctx *ctx, const ptk_options *opt_host);
 
 /*

@@ -13,6 +13,8 @@ _lib = None
 PTK_OK = 0
 PREC_FP64_ACC = 0
 PREC_FP32 = 1
+PREC_BF16 = 2
+PREC_BF16X3 = 3
 _STATUS = {0: "PTK_OK", 1: "PTK_E_INVALID", 2: "PTK_E_NOMEM",
            3: "PTK_E_UNSUPPORTED", 4: "PTK_E_NOT_PD", 5: "PTK_E_HIP",
            6: "PTK_E_STATE"}

@@ -22,6 +22,7 @@ using namespace ptk;
 namespace {
 
 constexpr int kRedBlocks = 1024;   // blocks of the error / norm reductions
+constexpr int kSseBlocks = 8192;   // single-wave blocks of the direct error pass
 
 struct ModeData {
     int64_t *rowptr = nullptr;
@@ -32,6 +33,11 @@ struct ModeData {
     int32_t *split = nullptr;    // [nsplit][3]
     int32_t nsplit = 0;
     bool fast = false;
+    // BF16 matrix-core form: blocks of <= 32 entries of one row
+    bool bf16 = false;
+    int split_bf16 = 1;          // 1: bf16 operands; 3: hi/lo split products
+    int32_t *blk_row = nullptr, *blk_start = nullptr, *blk_cnt = nullptr;
+    int64_t nblk = 0, blk_per_wave = 0, nwaves = 0;
 };
 
 struct Timed {
@@ -52,13 +58,15 @@ struct ptk_ctx {
     float *core = nullptr;
     float *fac[kMaxN] = {};
     void *gp[kMaxN] = {};        // permuted cores of the row-system kernels
+    void *frag[kMaxN] = {};      // bf16 core fragments of the matrix-core kernel
     double *gpe = nullptr;       // fp64 permuted core of the per-entry kernels
     int gpe_mode = -1;
     int64_t core_cells = 1;
     double *bbuf = nullptr;
     double *part = nullptr;
-    float *dcache = nullptr;
     double *red = nullptr;       // [kRedBlocks * (N + 1)] partials + scalars
+    double *xsq = nullptr;       // sum of x^2 over Omega (device, 1 double)
+    double *scal = nullptr;      // [2] error and factor norms of one iteration
     int32_t *bad = nullptr;
     int64_t last_not_pd = 0;
     double *host = nullptr;      // pinned results
@@ -152,13 +160,14 @@ void free_modes(ptk_ctx *c) {
         dfree(m.oidx);
         dfree(m.vals);
         dfree(m.split);
+        dfree(m.blk_row);
+        dfree(m.blk_start);
+        dfree(m.blk_cnt);
         m = ModeData();
     }
     dfree(c->bbuf);
     dfree(c->part);
-    dfree(c->dcache);
     c->bbuf = c->part = nullptr;
-    c->dcache = nullptr;
     c->nnz = -1;
 }
 
@@ -180,6 +189,10 @@ ptk_status need_model(ptk_ctx *c) {
 }
 
 hipError_t permute(ptk_ctx *c, int n) {
+    if (c->md[n].bf16)
+        return timed(c, "permute_core", [&] {
+            return launch_mfma_frags(c->core, c->frag[n], c->s, n, c->st);
+        });
     return timed(c, "permute_core", [&] {
         return launch_permute_core(c->core, c->gp[n], c->s, n, arith_of(c, n), c->st);
     });
@@ -211,7 +224,7 @@ void fill_common(const ptk_ctx *c, int n, Args &a, const int32_t *const *other) 
     a.jn = c->s.ranks[n];
 }
 
-GramArgs gram_args(const ptk_ctx *c, int n, float *dcache) {
+GramArgs gram_args(const ptk_ctx *c, int n) {
     const ModeData &m = c->md[n];
     GramArgs a{};
     const int32_t *other[kMaxN];
@@ -225,14 +238,48 @@ GramArgs gram_args(const ptk_ctx *c, int n, float *dcache) {
     a.chunk = m.chunk;
     a.bbuf = c->bbuf;
     a.part = c->part;
-    a.dcache = dcache;
+    return a;
+}
+
+MfmaArgs mfma_args(const ptk_ctx *c, int n) {
+    const ModeData &m = c->md[n];
+    MfmaArgs a{};
+    a.frag = c->frag[n];
+    int t = 0;
+    for (int k = 0; k < c->s.N; ++k) {
+        if (k == n) continue;
+        a.fac[t] = c->fac[k];
+        a.oidx[t] = m.oidx + (int64_t)t * c->nnz;
+        ++t;
+    }
+    a.val = m.vals;
+    a.rowptr = m.rowptr;
+    a.blk_row = m.blk_row;
+    a.blk_start = m.blk_start;
+    a.blk_cnt = m.blk_cnt;
+    a.nblk = m.nblk;
+    a.blk_per_wave = m.blk_per_wave;
+    a.E = sys_entries(c->s.ranks[n]);
+    a.bbuf = c->bbuf;
+    a.part = c->part;
     return a;
 }
 
 // B_i, c_i for every row of mode n into bbuf (delta + Gram kernel, merge).
-ptk_status systems(ptk_ctx *c, int n, float *dcache) {
+ptk_status systems(ptk_ctx *c, int n) {
     const ModeData &m = c->md[n];
-    GramArgs a = gram_args(c, n, dcache);
+    if (m.bf16) {
+        MfmaArgs a = mfma_args(c, n);
+        HIPCHK(c, timed(c, "gram_mfma", [&] {
+            return launch_gram_mfma(a, c->s.N, c->s.ranks[n], m.split_bf16, m.nwaves,
+                                    c->st);
+        }));
+        HIPCHK(c, timed(c, "merge", [&] {
+            return launch_merge(c->part, m.split, m.nsplit, a.E, c->bbuf, c->st);
+        }));
+        return PTK_OK;
+    }
+    GramArgs a = gram_args(c, n);
     HIPCHK(c, timed(c, "gram", [&] {
         return launch_gram(a, c->s, n, arith_of(c, n), m.nchunks, m.fast, c->st);
     }));
@@ -242,8 +289,8 @@ ptk_status systems(ptk_ctx *c, int n, float *dcache) {
     return PTK_OK;
 }
 
-ptk_status update_mode_impl(ptk_ctx *c, int n, double lambda, float *dcache) {
-    ptk_status s = systems(c, n, dcache);
+ptk_status update_mode_impl(ptk_ctx *c, int n, double lambda) {
+    ptk_status s = systems(c, n);
     if (s != PTK_OK) return s;
     const ModeData &m = c->md[n];
     HIPCHK(c, timed(c, "solve", [&] {
@@ -261,6 +308,11 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
 __global__ void k_fill_f64(double *p, double v, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// partial[n] = *x (appends one term to a list of partial sums)
+__global__ void k_add_scalar(double *partial, int n, const double *x) {
+    if (threadIdx.x == 0) partial[n] = *x;
 }
 
 hipError_t zero_bad(ptk_ctx *c) {
@@ -306,15 +358,17 @@ hipError_t sse_direct(ptk_ctx *c, double *partial, double *out) {
     a.partial = partial;
     hipError_t e = permute_entries(c, 0);
     if (e != hipSuccess) return e;
+    const int64_t nb = std::max<int64_t>(
+        1, std::min<int64_t>(kSseBlocks, (c->nnz + kWave - 1) / kWave));
     if (c->nnz == 0) {
-        hipLaunchKernelGGL(k_fill_f64, dim3(kRedBlocks / 256), dim3(256), 0, c->st,
-                           partial, 0.0, (int64_t)kRedBlocks);
+        hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, partial, 0.0,
+                           (int64_t)1);
         e = hipGetLastError();
     } else {
-        e = launch_entries(a, c->s, 0, kOutSSE, m.fast, kRedBlocks, c->st);
+        e = launch_entries(a, c->s, 0, kOutSSE, m.fast, nb, c->st);
     }
     if (e != hipSuccess) return e;
-    return launch_reduce(partial, kRedBlocks, out, c->st);
+    return launch_reduce(partial, (int)nb, out, c->st);
 }
 
 ptk_status check_bad(ptk_ctx *c, const char *what) {
@@ -373,8 +427,11 @@ ptk_status ptk_create(ptk_ctx **out, int32_t N, const int64_t *dims_host,
     for (int n = 0; n < N && e == hipSuccess; ++n)
         e = hipMalloc(&c->gp[n], (size_t)(cells + 64) * sizeof(double));
     if (e == hipSuccess) e = dalloc(&c->gpe, (size_t)(cells + 64));
-    if (e == hipSuccess) e = dalloc(&c->red, (size_t)kRedBlocks * (N + 1) + 64);
+    if (e == hipSuccess)
+        e = dalloc(&c->red, std::max<size_t>((size_t)kRedBlocks * (N + 1), kSseBlocks + 2) + 64);
     if (e == hipSuccess) e = dalloc(&c->bad, 1);
+    if (e == hipSuccess) e = dalloc(&c->xsq, 1);
+    if (e == hipSuccess) e = dalloc(&c->scal, 4);
     if (e != hipSuccess) {
         ptk_destroy(c);
         return e == hipErrorOutOfMemory ? PTK_E_NOMEM : PTK_E_HIP;
@@ -388,10 +445,15 @@ ptk_status ptk_destroy(ptk_ctx *c) {
     if (c->st) (void)hipStreamSynchronize(c->st);
     else (void)hipDeviceSynchronize();
     free_modes(c);
-    for (int n = 0; n < kMaxN; ++n) dfree(c->gp[n]);
+    for (int n = 0; n < kMaxN; ++n) {
+        dfree(c->gp[n]);
+        dfree(c->frag[n]);
+    }
     dfree(c->gpe);
     dfree(c->red);
     dfree(c->bad);
+    dfree(c->xsq);
+    dfree(c->scal);
     dfree(c->qr_work);
     dfree(c->fold_bbuf);
     dfree(c->fold_part);
@@ -414,15 +476,21 @@ const char *ptk_last_error(const ptk_ctx *c) {
 
 ptk_status ptk_set_options(ptk_ctx *c, const ptk_options *o) {
     if (!c || !o) return PTK_E_INVALID;
-    if (o->precision != PTK_PREC_FP64_ACC && o->precision != PTK_PREC_FP32)
+    if (o->precision < PTK_PREC_FP64_ACC || o->precision > PTK_PREC_BF16X3)
         return fail(c, PTK_E_INVALID, "unknown precision %d", o->precision);
+    const bool bf_new = o->precision == PTK_PREC_BF16 || o->precision == PTK_PREC_BF16X3;
+    const bool bf_old =
+        c->opt.precision == PTK_PREC_BF16 || c->opt.precision == PTK_PREC_BF16X3;
+    if (bf_new && !(equal_ranks(c->s) && mfma_available(c->s.N, c->s.ranks[0])))
+        return fail(c, PTK_E_UNSUPPORTED, "no matrix-core kernel for this shape");
+    const bool rebf = bf_new != bf_old || (bf_new && o->precision != c->opt.precision);
+    if (rebf && c->nnz >= 0)
+        return fail(c, PTK_E_STATE, "BF16 form must be chosen before ptk_set_observed");
     if (o->chunk_nnz < 0 || (o->chunk_nnz % kWave) != 0)
         return fail(c, PTK_E_INVALID, "chunk_nnz must be a multiple of 64");
     const bool rechunk = o->chunk_nnz != c->opt.chunk_nnz;
-    const bool recache = o->fuse_error != c->opt.fuse_error;
-    if ((rechunk || recache) && c->nnz >= 0)
-        return fail(c, PTK_E_STATE,
-                    "chunk_nnz / fuse_error must be set before ptk_set_observed");
+    if (rechunk && c->nnz >= 0)
+        return fail(c, PTK_E_STATE, "chunk_nnz must be set before ptk_set_observed");
     c->opt = *o;
     return PTK_OK;
 }
@@ -502,13 +570,52 @@ ptk_status ptk_set_observed(ptk_ctx *c, int64_t nnz, const int32_t *idx,
         std::vector<int64_t> rp(s.dims[n] + 1);
         HIPCHK(c, hipMemcpy(rp.data(), m.rowptr, rp.size() * 8, hipMemcpyDeviceToHost));
         std::vector<int32_t> split;
-        for (int64_t r = 0; r < s.dims[n]; ++r) {
-            if (rp[r] == rp[r + 1]) continue;
-            const int64_t c0 = rp[r] / chunk, c1 = (rp[r + 1] - 1) / chunk;
-            if (c0 != c1) {
-                split.push_back((int32_t)r);
-                split.push_back((int32_t)c0);
-                split.push_back((int32_t)c1);
+        if (c->opt.precision == PTK_PREC_BF16 || c->opt.precision == PTK_PREC_BF16X3) {
+            // blocks of <= 32 entries of one row; equal runs of blocks per wave
+            m.bf16 = true;
+            m.split_bf16 = c->opt.precision == PTK_PREC_BF16X3 ? 3 : 1;
+            std::vector<int32_t> br, bst, bc, first(s.dims[n], -1), last(s.dims[n], -1);
+            for (int64_t r = 0; r < s.dims[n]; ++r)
+                for (int64_t q = rp[r]; q < rp[r + 1]; q += 32) {
+                    if (first[r] < 0) first[r] = (int32_t)br.size();
+                    last[r] = (int32_t)br.size();
+                    br.push_back((int32_t)r);
+                    bst.push_back((int32_t)q);
+                    bc.push_back((int32_t)std::min<int64_t>(32, rp[r + 1] - q));
+                }
+            m.nblk = (int64_t)br.size();
+            const int64_t waves =
+                (int64_t)c->num_cu * mfma_waves_per_cu(N, s.ranks[n], m.split_bf16);
+            m.blk_per_wave = std::max<int64_t>(1, (m.nblk + waves - 1) / waves);
+            m.nwaves = (m.nblk + m.blk_per_wave - 1) / m.blk_per_wave;
+            for (int64_t r = 0; r < s.dims[n]; ++r) {
+                if (first[r] < 0) continue;
+                const int64_t w0 = first[r] / m.blk_per_wave, w1 = last[r] / m.blk_per_wave;
+                if (w0 != w1) {
+                    split.push_back((int32_t)r);
+                    split.push_back((int32_t)w0);
+                    split.push_back((int32_t)w1);
+                }
+            }
+            HIPCHK(c, dalloc(&m.blk_row, br.size()));
+            HIPCHK(c, dalloc(&m.blk_start, bst.size()));
+            HIPCHK(c, dalloc(&m.blk_cnt, bc.size()));
+            if (m.nblk) {
+                HIPCHK(c, hipMemcpy(m.blk_row, br.data(), br.size() * 4, hipMemcpyHostToDevice));
+                HIPCHK(c, hipMemcpy(m.blk_start, bst.data(), bst.size() * 4, hipMemcpyHostToDevice));
+                HIPCHK(c, hipMemcpy(m.blk_cnt, bc.data(), bc.size() * 4, hipMemcpyHostToDevice));
+            }
+            if (!c->frag[n])
+                HIPCHK(c, hipMalloc(&c->frag[n], 2 * (size_t)mfma_tiles(N, s.ranks[n]) * kWave * 8));
+        } else {
+            for (int64_t r = 0; r < s.dims[n]; ++r) {
+                if (rp[r] == rp[r + 1]) continue;
+                const int64_t c0 = rp[r] / chunk, c1 = (rp[r + 1] - 1) / chunk;
+                if (c0 != c1) {
+                    split.push_back((int32_t)r);
+                    split.push_back((int32_t)c0);
+                    split.push_back((int32_t)c1);
+                }
             }
         }
         m.nsplit = (int32_t)(split.size() / 3);
@@ -518,12 +625,19 @@ ptk_status ptk_set_observed(ptk_ctx *c, int64_t nnz, const int32_t *idx,
                                 hipMemcpyHostToDevice));
         }
         bbuf_elems = std::max(bbuf_elems, s.dims[n] * E);
-        part_elems = std::max(part_elems, m.nchunks * 2 * E);
+        part_elems = std::max(part_elems, (m.bf16 ? m.nwaves : m.nchunks) * 2 * E);
     }
     HIPCHK(c, dalloc(&c->bbuf, bbuf_elems));
     HIPCHK(c, dalloc(&c->part, part_elems));
-    if (c->opt.fuse_error)
-        HIPCHK(c, dalloc(&c->dcache, (size_t)nnz * s.ranks[N - 1] + 64));
+    // sum of x^2 for the error identity of the fused pass
+    if (nnz > 0) {
+        HIPCHK(c, launch_sumsq(c->md[0].vals, nnz, c->red, kRedBlocks, c->st));
+        HIPCHK(c, launch_reduce(c->red, kRedBlocks, c->xsq, c->st));
+    } else {
+        hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, c->xsq, 0.0, (int64_t)1);
+        HIPCHK(c, hipGetLastError());
+    }
+    HIPCHK(c, hipStreamSynchronize(c->st));
     return PTK_OK;
 }
 
@@ -545,7 +659,7 @@ ptk_status ptk_update_mode(ptk_ctx *c, int32_t n, double lambda) {
     if (s != PTK_OK) return s;
     HIPCHK(c, permute(c, n));
     HIPCHK(c, zero_bad(c));
-    s = update_mode_impl(c, n, lambda, nullptr);
+    s = update_mode_impl(c, n, lambda);
     if (s != PTK_OK) return s;
     return check_bad(c, "ptk_update_mode");
 }
@@ -565,21 +679,25 @@ ptk_status ptk_iterate(ptk_ctx *c, int32_t iters, double lambda, double *sse_hos
     for (int n = 0; n < N; ++n) HIPCHK(c, permute(c, n));
     HIPCHK(c, zero_bad(c));
     double *partial = c->red;
-    double *scal = c->red + (int64_t)kRedBlocks * N;    // 2 doubles
-    const bool fuse = c->dcache != nullptr;
+    double *scal = c->scal;
+    const bool fuse = c->opt.fuse_error != 0;
     for (int t = 0; t < iters; ++t) {
         for (int n = 0; n < N; ++n) {
-            s = update_mode_impl(c, n, lambda, (fuse && n == N - 1) ? c->dcache : nullptr);
+            s = update_mode_impl(c, n, lambda);
             if (s != PTK_OK) return s;
         }
         HIPCHK(c, timed(c, "error", [&]() -> hipError_t {
             if (fuse) {
+                // from the last mode's row systems, still in bbuf
                 const ModeData &m = c->md[N - 1];
-                hipError_t e = launch_sse_cached(c->dcache, m.rows, m.vals, c->fac[N - 1],
-                                                 c->s.ranks[N - 1], c->nnz, partial,
-                                                 kRedBlocks, c->st);
+                hipError_t e = launch_row_sse(c->bbuf, m.rowptr, c->fac[N - 1],
+                                              c->s.dims[N - 1], c->s.ranks[N - 1],
+                                              partial, kRedBlocks, c->st);
                 if (e != hipSuccess) return e;
-                return launch_reduce(partial, kRedBlocks, scal, c->st);
+                hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, c->st, partial,
+                                   kRedBlocks, c->xsq);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+                return launch_reduce(partial, kRedBlocks + 1, scal, c->st);
             }
             return sse_direct(c, partial, scal);
         }));
@@ -603,7 +721,7 @@ ptk_status ptk_recon_error(ptk_ctx *c, double lambda, double *sse_host,
     s = ensure_host(c, 2);
     if (s != PTK_OK) return s;
     double *partial = c->red;
-    double *scal = c->red + (int64_t)kRedBlocks * c->s.N;
+    double *scal = c->scal;
     HIPCHK(c, timed(c, "error", [&] { return sse_direct(c, partial, scal); }));
     HIPCHK(c, timed(c, "norms", [&] { return factor_norms(c, partial, scal + 1); }));
     HIPCHK(c, hipMemcpyAsync(c->host, scal, 2 * sizeof(double), hipMemcpyDeviceToHost,
@@ -705,7 +823,7 @@ ptk_status ptk_row_systems(ptk_ctx *c, int32_t n, double *B_out, double *c_out) 
     if (s != PTK_OK) return s;
     if (!B_out || !c_out) return fail(c, PTK_E_INVALID, "null output");
     HIPCHK(c, permute(c, n));
-    s = systems(c, n, nullptr);
+    s = systems(c, n);
     if (s != PTK_OK) return s;
     HIPCHK(c, launch_expand_systems(c->bbuf, c->md[n].rowptr, c->s.dims[n],
                                     c->s.ranks[n], B_out, c_out, c->st));
@@ -771,7 +889,6 @@ extern "C" ptk_status ptk_fold_in(ptk_ctx *c, int32_t n, int64_t k, const int32_
     a.chunk = chunk;
     a.bbuf = c->fold_bbuf;
     a.part = c->fold_part;
-    a.dcache = nullptr;
     const bool fast = equal_ranks(c->s) && fast_available(c->s.N, J, kArithF64);
     const Arith ar = (fast && c->opt.precision == PTK_PREC_FP32) ? kArithF32 : kArithF64;
     HIPCHK(c, timed(c, "permute_core", [&] {

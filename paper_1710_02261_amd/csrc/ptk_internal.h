@@ -58,7 +58,6 @@ struct GramArgs {
     int64_t chunk;                    // entries per work range (multiple of 64)
     double *bbuf;                     // complete rows
     double *part;                     // [nchunks][2][E]
-    float *dcache;                    // [nnz][jn] delta of this mode, or null
 };
 
 // Arguments of the per-entry kernels (predict, error, delta inspection).
@@ -79,6 +78,25 @@ struct EntryArgs {
 };
 
 enum EntryOut { kOutDelta = 0, kOutPredict = 1, kOutSSE = 2 };
+
+// Arguments of the BF16 matrix-core row-system kernel (ptk_mfma.hip). The
+// entries of mode n are cut into blocks of at most 32 entries that never span
+// two rows; blk_* describe them in grouped order.
+struct MfmaArgs {
+    const void *frag;                 // bf16 core fragments [tiles][64][4]
+    const float *fac[kMaxN];          // factors of the other modes, mode order
+    const int32_t *oidx[kMaxN];       // other-mode index arrays, same order
+    const float *val;
+    const int64_t *rowptr;
+    const int32_t *blk_row;
+    const int32_t *blk_start;
+    const int32_t *blk_cnt;
+    int64_t nblk;
+    int64_t blk_per_wave;
+    int32_t E;
+    double *bbuf;
+    double *part;                     // [waves][2][E]
+};
 
 // ---------------------------------------------------------------------------
 // kernel launchers (ptk_kernels.hip, ptk_sort.hip, ptk_solve.hip)
@@ -105,12 +123,11 @@ hipError_t launch_merge(const double *part, const int32_t *split, int32_t nsplit
 hipError_t launch_solve(const double *bbuf, const int64_t *rowptr, int64_t I,
                         int J, double lambda, float *A, int32_t *bad,
                         hipStream_t st);
+hipError_t launch_row_sse(const double *bbuf, const int64_t *rowptr, const float *A,
+                          int64_t I, int J, double *partial, int nblocks,
+                          hipStream_t st);
 hipError_t launch_entries(const EntryArgs &a, const Shape &s, int n, int kind,
                           bool fast, int64_t nblocks, hipStream_t st);
-hipError_t launch_sse_cached(const float *dcache, const int32_t *rows,
-                             const float *val, const float *A, int J,
-                             int64_t nnz, double *partial, int nblocks,
-                             hipStream_t st);
 hipError_t launch_sumsq(const float *x, int64_t n, double *partial, int nblocks,
                         hipStream_t st);
 hipError_t launch_reduce(const double *partial, int n, double *out,
@@ -121,6 +138,15 @@ hipError_t launch_expand_systems(const double *bbuf, const int64_t *rowptr,
 hipError_t launch_validate(const int32_t *idx, const float *val, int64_t nnz,
                            const Shape &s, unsigned long long *bad,
                            hipStream_t st);
+
+// BF16 matrix-core form (ptk_mfma.hip)
+bool mfma_available(int N, int J);
+int64_t mfma_tiles(int N, int J);
+int mfma_waves_per_cu(int N, int J, int split);
+hipError_t launch_mfma_frags(const float *G, void *frag, const Shape &s, int n,
+                             hipStream_t st);
+hipError_t launch_gram_mfma(const MfmaArgs &a, int N, int J, int split, int64_t nwaves,
+                            hipStream_t st);
 
 // sort / CSR build (ptk_sort.hip)
 size_t sort_workspace_bytes(int64_t nnz);

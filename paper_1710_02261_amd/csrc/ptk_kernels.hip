@@ -337,10 +337,6 @@ __global__ __launch_bounds__(kWave) void k_gram_fast(GramArgs a) {
         __syncthreads();
         double d[J];
         delta_fast<NO, J, U, T>(a.gp, s_aout, lane, ain, d);
-        if (a.dcache && valid) {
-#pragma unroll
-            for (int j = 0; j < J; ++j) a.dcache[pos * J + j] = (float)d[j];
-        }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < J; ++j) s_dl[j * kDlStride + lane] = d[j];
@@ -382,11 +378,6 @@ __global__ __launch_bounds__(kWave) void k_gram_generic(GramArgs a) {
         __syncthreads();
         double d[JMAX];
         delta_generic<JMAX>(a, s_arow, lane, d);
-        if (a.dcache && valid) {
-#pragma unroll
-            for (int j = 0; j < JMAX; ++j)
-                if (j < J) a.dcache[pos * J + j] = (float)d[j];
-        }
 #pragma unroll
         for (int j = 0; j < JMAX; ++j)
             if (j < J) s_dl[j * kDlStride + lane] = d[j];
@@ -624,43 +615,6 @@ hipError_t launch_entries(const EntryArgs &a, const Shape &s, int n, int kind,
             hipLaunchKernelGGL(k_entries_generic<32>, grid, block, lds, st, a, kind);
             break;
     }
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// error pass fused with the last mode: x_hat = <a^(N)_{i_N}, delta^(N)>
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_sse_cached(const float *__restrict__ dc,
-                                                    const int32_t *__restrict__ rows,
-                                                    const float *__restrict__ val,
-                                                    const float *__restrict__ A,
-                                                    int J, int64_t nnz,
-                                                    double *__restrict__ partial) {
-    __shared__ double s_part[4];
-    double sse = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const float *r = A + (int64_t)rows[e] * J;
-        const float *d = dc + e * J;
-        double xh = 0.0;
-        for (int j = 0; j < J; ++j) xh = __builtin_fma((double)r[j], (double)d[j], xh);
-        const double res = (double)val[e] - xh;
-        sse = __builtin_fma(res, res, sse);
-    }
-    sse = block_reduce_sum(sse, nullptr);
-    const int w = threadIdx.x / kWave;
-    if ((threadIdx.x % kWave) == 0) s_part[w] = sse;
-    __syncthreads();
-    if (threadIdx.x == 0)
-        partial[blockIdx.x] = ((s_part[0] + s_part[1]) + (s_part[2] + s_part[3]));
-}
-
-hipError_t launch_sse_cached(const float *dcache, const int32_t *rows,
-                             const float *val, const float *A, int J,
-                             int64_t nnz, double *partial, int nblocks,
-                             hipStream_t st) {
-    hipLaunchKernelGGL(k_sse_cached, dim3(nblocks), dim3(256), 0, st, dcache, rows,
-                       val, A, J, nnz, partial);
     return hipGetLastError();
 }
 

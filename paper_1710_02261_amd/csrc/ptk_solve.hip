@@ -122,4 +122,49 @@ hipError_t launch_solve(const double *bbuf, const int64_t *rowptr, int64_t I,
     return hipGetLastError();
 }
 
+// Error of the last mode's update from its row systems: for the entries of
+// row i, sum (x - a_i^T delta)^2 = sum x^2 - 2 a_i^T c_i + a_i^T B_i a_i, so
+// the squared error of eq. "reconfull" after the sweep is
+//     sum_Omega x^2 + sum_i (a_i^T B_i a_i - 2 a_i^T c_i)
+// with a_i the stored (float32) row. Per-block partial sums, FP64.
+__global__ __launch_bounds__(256) void k_row_sse(const double *__restrict__ bbuf,
+                                                 const int64_t *__restrict__ rowptr,
+                                                 const float *__restrict__ A,
+                                                 int64_t I, int J,
+                                                 double *__restrict__ partial) {
+    __shared__ double s_part[256 / kWave];
+    const int T = J * (J + 1) / 2;
+    const int E = T + J;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (rowptr[i] == rowptr[i + 1]) continue;
+        const double *sys = bbuf + i * E;
+        const float *a = A + i * J;
+        double q = 0.0;
+        for (int p = 0; p < J; ++p) {
+            const double ap = (double)a[p];
+            double r = 0.0;
+            for (int qq = p + 1; qq < J; ++qq)
+                r = __builtin_fma(sys[tri_pos(p, qq, J)], (double)a[qq], r);
+            q += ap * (sys[tri_pos(p, p, J)] * ap + 2.0 * r - 2.0 * sys[T + p]);
+        }
+        acc += q;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, kWave);
+    if ((threadIdx.x % kWave) == 0) s_part[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
+}
+
+hipError_t launch_row_sse(const double *bbuf, const int64_t *rowptr, const float *A,
+                          int64_t I, int J, double *partial, int nblocks,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_row_sse, dim3(nblocks), dim3(256), 0, st, bbuf, rowptr, A, I, J,
+                       partial);
+    return hipGetLastError();
+}
+
 }  // namespace ptk
