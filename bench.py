@@ -138,6 +138,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=40.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variant", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default work-range sizes")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch kernels one by one instead of replaying a graph")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -168,16 +172,24 @@ def main():
     fac0 = [torch.from_numpy(a).to(dev) for a in p.factors]
     N, J = p.N, p.ranks[0]
 
+    use_graph = 0 if args.no_graph else 1
+
     def run(prec):
         fac = [f.clone() for f in fac0]
         ctx = ptk.Context(p.dims, p.ranks)
-        ctx.set_options(precision=PREC_NAMES[prec], fuse_error=1, profile=0)
+        ctx.set_options(precision=PREC_NAMES[prec], fuse_error=1, profile=0,
+                        use_graph=use_graph)
         torch.cuda.synchronize()
         ts = time.perf_counter()
         ctx.set_observed(idx, val)
         torch.cuda.synchronize()
         setup = time.perf_counter() - ts
         ctx.bind_model(core, fac)
+        work, tune_s = None, 0.0
+        if not args.no_autotune:
+            ts = time.perf_counter()
+            work = ctx.autotune(None)
+            tune_s = time.perf_counter() - ts
         if args.warmup:
             ctx.iterate(args.warmup, p.lam, strict=False)
         torch.cuda.synchronize()
@@ -189,7 +201,8 @@ def main():
         # the model's error by a direct FP64 pass over all entries (untimed)
         _, rmse_direct, _ = ctx.recon_error(p.lam)
         # second pass with per-kernel HIP events on the library's stream
-        ctx.set_options(precision=PREC_NAMES[prec], fuse_error=1, profile=1)
+        ctx.set_options(precision=PREC_NAMES[prec], fuse_error=1, profile=1,
+                        use_graph=use_graph)
         ctx.reset_timers()
         ctx.iterate(args.steps, p.lam, strict=False)
         times = ctx.kernel_times()
@@ -199,7 +212,7 @@ def main():
         return {"elapsed": elapsed, "setup": setup, "sse": sse, "times": times,
                 "not_pd": not_pd, "gram_ms": ms / max(calls, 1),
                 "value": p.nnz * args.steps / elapsed,
-                "rmse": float(rmse_direct),
+                "rmse": float(rmse_direct), "work": work, "tune_s": tune_s,
                 "rmse_fused": float(np.sqrt(max(sse[-1], 0.0) / p.nnz))}
 
     main_prec = args.precision
@@ -248,6 +261,8 @@ def main():
                    "step": "Alg. 2 iteration: %d mode updates + error" % N},
         "roofline": roofline,
         "setup_s": r["setup"],
+        "autotune": {"work_per_mode": r["work"], "seconds": r["tune_s"]},
+        "graph": bool(use_graph),
         "rmse_after": r["rmse"],
         "rmse_after_fused": r["rmse_fused"],
         "not_pd_rows_timed": int(r["not_pd"]),

@@ -60,7 +60,11 @@ typedef struct ptk_options {
     int32_t fuse_error;     /* 1: error of ptk_iterate from the last mode's
                                row systems (sum x^2 - 2 a^T c + a^T B a per
                                row); 0: a separate pass over all entries     */
-    int32_t profile;        /* 1: time every kernel launch with HIP events   */
+    int32_t profile;        /* 1: time every kernel launch with HIP events
+                               (kernels are then launched one by one)        */
+    int32_t use_graph;      /* 1: ptk_iterate replays one captured graph per
+                               iteration (re-captured when lambda, options,
+                               the observed set or the bound model change)   */
 } ptk_options;
 
 /*
@@ -139,6 +143,20 @@ ptk_status ptk_iterate(ptk_ctx *ctx, int32_t iters, double lambda,
  * with fewer entries than J_n. Synchronises the stream.
  */
 ptk_status ptk_not_pd_count(ptk_ctx *ctx, int64_t *count_host);
+
+/*
+ * Autotuner of the batching form (the GPU counterpart of the dynamic row
+ * schedule of Sec. 3.4). For every mode it times the row-system kernels
+ * (delta, Gram, merge) of the bound model on the observed set for several
+ * sizes of the per-wavefront work ranges (entries per range for the FP64 /
+ * FP32 forms, 32-entry blocks per range for the BF16 forms) and keeps the
+ * fastest; the model is not modified. cache_path (host string, may be NULL)
+ * names a text file of "key value" lines keyed by order, ranks, precision,
+ * entry count, mode size and the mode's row-length histogram: a hit is
+ * applied without timing, a new result is appended. work_host (NULL or N
+ * entries) receives the chosen sizes. Synchronises the stream.
+ */
+ptk_status ptk_autotune(ptk_ctx *ctx, const char *cache_path, int64_t *work_host);
 
 /*
  * Reconstruction error of the bound model on Omega (eq. "reconfull"):

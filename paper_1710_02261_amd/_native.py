@@ -27,7 +27,7 @@ _dbl = C.c_double
 
 class _Options(C.Structure):
     _fields_ = [("precision", _i32), ("chunk_nnz", _i32), ("fuse_error", _i32),
-                ("profile", _i32)]
+                ("profile", _i32), ("use_graph", _i32)]
 
 
 class PtkError(RuntimeError):
@@ -69,6 +69,7 @@ def load_library():
                              C.POINTER(_i64), C.POINTER(_dbl)],
         "ptk_reset_timers": [_vp],
         "ptk_not_pd_count": [_vp, C.POINTER(_i64)],
+        "ptk_autotune": [_vp, C.c_char_p, C.POINTER(_i64)],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -144,8 +145,8 @@ class Context:
 
     # -- C ABI calls ---------------------------------------------------------
     def set_options(self, precision=PREC_FP64_ACC, chunk_nnz=0, fuse_error=1,
-                    profile=0):
-        o = _Options(precision, chunk_nnz, fuse_error, profile)
+                    profile=0, use_graph=1):
+        o = _Options(precision, chunk_nnz, fuse_error, profile, use_graph)
         self._check(self._lib.ptk_set_options(self._h, C.byref(o)))
 
     def set_observed(self, idx, val):
@@ -190,6 +191,13 @@ class Context:
         if not (st == 4 and not strict):
             self._check(st)
         return sse[:iters], loss[:iters]
+
+    def autotune(self, cache_path=None):
+        """Time work-range sizes per mode, keep the fastest; returns them."""
+        out = (_i64 * self.N)()
+        path = cache_path.encode() if cache_path else None
+        self._check(self._lib.ptk_autotune(self._h, path, out))
+        return [int(v) for v in out]
 
     def not_pd_count(self):
         n = _i64()

@@ -38,6 +38,10 @@ struct ModeData {
     int split_bf16 = 1;          // 1: bf16 operands; 3: hi/lo split products
     int32_t *blk_row = nullptr, *blk_start = nullptr, *blk_cnt = nullptr;
     int64_t nblk = 0, blk_per_wave = 0, nwaves = 0;
+    // host copies used to recompute the work split (autotuner)
+    std::vector<int64_t> rp_host;
+    std::vector<int32_t> first_blk, last_blk;
+    int64_t part_elems = 0;
 };
 
 struct Timed {
@@ -52,7 +56,7 @@ struct ptk_ctx {
     hipStream_t st = nullptr;
     int device = 0;
     int num_cu = 256;
-    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0};
+    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1};
     int64_t nnz = -1;
     ModeData md[kMaxN];
     float *core = nullptr;
@@ -64,9 +68,19 @@ struct ptk_ctx {
     int64_t core_cells = 1;
     double *bbuf = nullptr;
     double *part = nullptr;
+    int64_t part_cap = 0;
     double *red = nullptr;       // [kRedBlocks * (N + 1)] partials + scalars
     double *xsq = nullptr;       // sum of x^2 over Omega (device, 1 double)
     double *scal = nullptr;      // [2] error and factor norms of one iteration
+    double *dres = nullptr;      // [2 * dres_cap] per-iteration results
+    int64_t dres_cap = 0;
+    int32_t *iter_ctr = nullptr; // device iteration counter for dres
+    uint64_t epoch = 1;          // bumped whenever captured launch arguments change
+    hipStream_t gstream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    uint64_t g_epoch = 0;
+    double g_lambda = 0.0;
+    int g_fuse = -1;
     int32_t *bad = nullptr;
     int64_t last_not_pd = 0;
     double *host = nullptr;      // pinned results
@@ -168,6 +182,7 @@ void free_modes(ptk_ctx *c) {
     dfree(c->bbuf);
     dfree(c->part);
     c->bbuf = c->part = nullptr;
+    c->part_cap = 0;
     c->nnz = -1;
 }
 
@@ -310,6 +325,16 @@ __global__ void k_fill_f64(double *p, double v, int64_t n) {
     if (i < n) p[i] = v;
 }
 
+// dres[2k .. 2k+1] = scal[0..1] with k = (*ctr)++ (one thread; stream-ordered)
+__global__ void k_store_iter(const double *scal, double *dres, int32_t *ctr) {
+    if (threadIdx.x == 0) {
+        const int k = *ctr;
+        dres[2 * k] = scal[0];
+        dres[2 * k + 1] = scal[1];
+        *ctr = k + 1;
+    }
+}
+
 // partial[n] = *x (appends one term to a list of partial sums)
 __global__ void k_add_scalar(double *partial, int n, const double *x) {
     if (threadIdx.x == 0) partial[n] = *x;
@@ -384,6 +409,148 @@ ptk_status check_bad(ptk_ctx *c, const char *what) {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// Default work per wavefront: one round of resident wavefronts covers the mode.
+int64_t default_work(const ptk_ctx *c, int n) {
+    const ModeData &m = c->md[n];
+    if (m.bf16) {
+        const int64_t waves = (int64_t)c->num_cu *
+                              mfma_waves_per_cu(c->s.N, c->s.ranks[n], m.split_bf16);
+        return std::max<int64_t>(1, (m.nblk + waves - 1) / std::max<int64_t>(waves, 1));
+    }
+    const int bpc = gram_blocks_per_cu(c->s, n, arith_of(c, n), m.fast);
+    const int64_t waves = (int64_t)c->num_cu * std::max(1, bpc);
+    int64_t chunk = round_up((c->nnz + waves - 1) / std::max<int64_t>(waves, 1), kWave);
+    return std::max<int64_t>(chunk, kWave);
+}
+
+// Cut mode n into wavefront work ranges of `work` entries (FP64/FP32 path,
+// a multiple of 64) or `work` blocks (BF16 path); 0 picks the default. Lists
+// the rows that cross ranges for the merge and grows the partial buffer.
+ptk_status configure_ranges(ptk_ctx *c, int n, int64_t work) {
+    ModeData &m = c->md[n];
+    const int E = sys_entries(c->s.ranks[n]);
+    if (work <= 0) work = default_work(c, n);
+    const std::vector<int64_t> &rp = m.rp_host;
+    std::vector<int32_t> split;
+    int64_t ranges;
+    if (m.bf16) {
+        m.blk_per_wave = work;
+        m.nwaves = (m.nblk + work - 1) / work;
+        ranges = m.nwaves;
+        for (int64_t r = 0; r < c->s.dims[n]; ++r) {
+            if (m.first_blk[r] < 0) continue;
+            const int64_t w0 = m.first_blk[r] / work, w1 = m.last_blk[r] / work;
+            if (w0 != w1) {
+                split.push_back((int32_t)r);
+                split.push_back((int32_t)w0);
+                split.push_back((int32_t)w1);
+            }
+        }
+    } else {
+        work = round_up(work, kWave);
+        m.chunk = work;
+        m.nchunks = (c->nnz + work - 1) / work;
+        ranges = m.nchunks;
+        for (int64_t r = 0; r < c->s.dims[n]; ++r) {
+            if (rp[r] == rp[r + 1]) continue;
+            const int64_t c0 = rp[r] / work, c1 = (rp[r + 1] - 1) / work;
+            if (c0 != c1) {
+                split.push_back((int32_t)r);
+                split.push_back((int32_t)c0);
+                split.push_back((int32_t)c1);
+            }
+        }
+    }
+    dfree(m.split);
+    m.split = nullptr;
+    m.nsplit = (int32_t)(split.size() / 3);
+    if (m.nsplit > 0) {
+        HIPCHK(c, dalloc(&m.split, split.size()));
+        HIPCHK(c, hipMemcpy(m.split, split.data(), split.size() * 4, hipMemcpyHostToDevice));
+    }
+    const int64_t need = ranges * 2 * E;
+    if (need > c->part_cap) {
+        dfree(c->part);
+        c->part = nullptr;
+        c->part_cap = 0;
+        HIPCHK(c, dalloc(&c->part, need));
+        c->part_cap = need;
+    }
+    c->epoch++;
+    return PTK_OK;
+}
+
+// One iteration of Alg. 2 (lines 3-4) as stream-ordered kernels only: the
+// N mode updates, the error and the factor norms, stored to dres through the
+// device counter. Contains no memset, copy or synchronisation, so it can be
+// captured into a graph and replayed.
+ptk_status iteration_body(ptk_ctx *c, double lambda) {
+    const int N = c->s.N;
+    double *partial = c->red;
+    double *scal = c->scal;
+    for (int n = 0; n < N; ++n) {
+        ptk_status s = update_mode_impl(c, n, lambda);
+        if (s != PTK_OK) return s;
+    }
+    HIPCHK(c, timed(c, "error", [&]() -> hipError_t {
+        if (c->opt.fuse_error) {
+            // from the last mode's row systems, still in bbuf
+            const ModeData &m = c->md[N - 1];
+            hipError_t e = launch_row_sse(c->bbuf, m.rowptr, c->fac[N - 1],
+                                          c->s.dims[N - 1], c->s.ranks[N - 1], partial,
+                                          kRedBlocks, c->st);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, c->st, partial,
+                               kRedBlocks, c->xsq);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            return launch_reduce(partial, kRedBlocks + 1, scal, c->st);
+        }
+        return sse_direct(c, partial, scal);
+    }));
+    HIPCHK(c, timed(c, "norms", [&] { return factor_norms(c, partial, scal + 1); }));
+    hipLaunchKernelGGL(k_store_iter, dim3(1), dim3(64), 0, c->st, scal, c->dres,
+                       c->iter_ctr);
+    HIPCHK(c, hipGetLastError());
+    return PTK_OK;
+}
+
+// Capture iteration_body into a graph on a private stream (capture needs a
+// stream other than the null stream); replayed on the context's stream.
+ptk_status ensure_iteration_graph(ptk_ctx *c, double lambda) {
+    const int fuse = c->opt.fuse_error ? 1 : 0;
+    if (c->gexec && c->g_epoch == c->epoch && c->g_lambda == lambda && c->g_fuse == fuse)
+        return PTK_OK;
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    if (!c->gstream) HIPCHK(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+    hipStream_t user = c->st;
+    c->st = c->gstream;
+    hipError_t e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal);
+    ptk_status s = PTK_OK;
+    if (e == hipSuccess) s = iteration_body(c, lambda);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->gstream, &g);
+    c->st = user;
+    if (e != hipSuccess) return fail(c, PTK_E_HIP, "graph capture: %s", hipGetErrorString(e));
+    if (s != PTK_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+    }
+    if (e2 != hipSuccess) return fail(c, PTK_E_HIP, "graph capture: %s", hipGetErrorString(e2));
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->gexec = nullptr;
+        return fail(c, PTK_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    c->g_epoch = c->epoch;
+    c->g_lambda = lambda;
+    c->g_fuse = fuse;
+    return PTK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -432,6 +599,7 @@ ptk_status ptk_create(ptk_ctx **out, int32_t N, const int64_t *dims_host,
     if (e == hipSuccess) e = dalloc(&c->bad, 1);
     if (e == hipSuccess) e = dalloc(&c->xsq, 1);
     if (e == hipSuccess) e = dalloc(&c->scal, 4);
+    if (e == hipSuccess) e = dalloc(&c->iter_ctr, 1);
     if (e != hipSuccess) {
         ptk_destroy(c);
         return e == hipErrorOutOfMemory ? PTK_E_NOMEM : PTK_E_HIP;
@@ -454,6 +622,10 @@ ptk_status ptk_destroy(ptk_ctx *c) {
     dfree(c->bad);
     dfree(c->xsq);
     dfree(c->scal);
+    dfree(c->dres);
+    dfree(c->iter_ctr);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
     dfree(c->qr_work);
     dfree(c->fold_bbuf);
     dfree(c->fold_part);
@@ -492,6 +664,7 @@ ptk_status ptk_set_options(ptk_ctx *c, const ptk_options *o) {
     if (rechunk && c->nnz >= 0)
         return fail(c, PTK_E_STATE, "chunk_nnz must be set before ptk_set_observed");
     c->opt = *o;
+    c->epoch++;
     return PTK_OK;
 }
 
@@ -503,6 +676,7 @@ ptk_status ptk_set_observed(ptk_ctx *c, int64_t nnz, const int32_t *idx,
     if (nnz > 0 && (!idx || !val)) return fail(c, PTK_E_INVALID, "null input");
     HIPCHK(c, hipStreamSynchronize(c->st));
     free_modes(c);
+    c->epoch++;
     const Shape &s = c->s;
     const int N = s.N;
 
@@ -554,49 +728,30 @@ ptk_status ptk_set_observed(ptk_ctx *c, int64_t nnz, const int32_t *idx,
     c->nnz = nnz;
 
     // work ranges and rows that cross them
-    int64_t bbuf_elems = 0, part_elems = 0;
+    int64_t bbuf_elems = 0;
     for (int n = 0; n < N; ++n) {
         ModeData &m = c->md[n];
         const int E = sys_entries(s.ranks[n]);
-        int64_t chunk = c->opt.chunk_nnz;
-        if (chunk <= 0) {
-            const int bpc = gram_blocks_per_cu(s, n, arith_of(c, n), m.fast);
-            const int64_t waves = (int64_t)c->num_cu * std::max(1, bpc);
-            chunk = round_up((nnz + waves - 1) / std::max<int64_t>(waves, 1), kWave);
-            chunk = std::max<int64_t>(chunk, kWave);
-        }
-        m.chunk = chunk;
-        m.nchunks = (nnz + chunk - 1) / chunk;
-        std::vector<int64_t> rp(s.dims[n] + 1);
-        HIPCHK(c, hipMemcpy(rp.data(), m.rowptr, rp.size() * 8, hipMemcpyDeviceToHost));
-        std::vector<int32_t> split;
+        m.rp_host.resize(s.dims[n] + 1);
+        HIPCHK(c, hipMemcpy(m.rp_host.data(), m.rowptr, m.rp_host.size() * 8,
+                            hipMemcpyDeviceToHost));
+        const std::vector<int64_t> &rp = m.rp_host;
         if (c->opt.precision == PTK_PREC_BF16 || c->opt.precision == PTK_PREC_BF16X3) {
-            // blocks of <= 32 entries of one row; equal runs of blocks per wave
+            // blocks of <= 32 entries of one row
             m.bf16 = true;
             m.split_bf16 = c->opt.precision == PTK_PREC_BF16X3 ? 3 : 1;
-            std::vector<int32_t> br, bst, bc, first(s.dims[n], -1), last(s.dims[n], -1);
+            std::vector<int32_t> br, bst, bc;
+            m.first_blk.assign(s.dims[n], -1);
+            m.last_blk.assign(s.dims[n], -1);
             for (int64_t r = 0; r < s.dims[n]; ++r)
                 for (int64_t q = rp[r]; q < rp[r + 1]; q += 32) {
-                    if (first[r] < 0) first[r] = (int32_t)br.size();
-                    last[r] = (int32_t)br.size();
+                    if (m.first_blk[r] < 0) m.first_blk[r] = (int32_t)br.size();
+                    m.last_blk[r] = (int32_t)br.size();
                     br.push_back((int32_t)r);
                     bst.push_back((int32_t)q);
                     bc.push_back((int32_t)std::min<int64_t>(32, rp[r + 1] - q));
                 }
             m.nblk = (int64_t)br.size();
-            const int64_t waves =
-                (int64_t)c->num_cu * mfma_waves_per_cu(N, s.ranks[n], m.split_bf16);
-            m.blk_per_wave = std::max<int64_t>(1, (m.nblk + waves - 1) / waves);
-            m.nwaves = (m.nblk + m.blk_per_wave - 1) / m.blk_per_wave;
-            for (int64_t r = 0; r < s.dims[n]; ++r) {
-                if (first[r] < 0) continue;
-                const int64_t w0 = first[r] / m.blk_per_wave, w1 = last[r] / m.blk_per_wave;
-                if (w0 != w1) {
-                    split.push_back((int32_t)r);
-                    split.push_back((int32_t)w0);
-                    split.push_back((int32_t)w1);
-                }
-            }
             HIPCHK(c, dalloc(&m.blk_row, br.size()));
             HIPCHK(c, dalloc(&m.blk_start, bst.size()));
             HIPCHK(c, dalloc(&m.blk_cnt, bc.size()));
@@ -607,28 +762,13 @@ ptk_status ptk_set_observed(ptk_ctx *c, int64_t nnz, const int32_t *idx,
             }
             if (!c->frag[n])
                 HIPCHK(c, hipMalloc(&c->frag[n], 2 * (size_t)mfma_tiles(N, s.ranks[n]) * kWave * 8));
-        } else {
-            for (int64_t r = 0; r < s.dims[n]; ++r) {
-                if (rp[r] == rp[r + 1]) continue;
-                const int64_t c0 = rp[r] / chunk, c1 = (rp[r + 1] - 1) / chunk;
-                if (c0 != c1) {
-                    split.push_back((int32_t)r);
-                    split.push_back((int32_t)c0);
-                    split.push_back((int32_t)c1);
-                }
-            }
         }
-        m.nsplit = (int32_t)(split.size() / 3);
-        if (m.nsplit > 0) {
-            HIPCHK(c, dalloc(&m.split, split.size()));
-            HIPCHK(c, hipMemcpy(m.split, split.data(), split.size() * 4,
-                                hipMemcpyHostToDevice));
-        }
+        ptk_status st = configure_ranges(c, n, c->opt.chunk_nnz > 0 && !m.bf16
+                                                   ? c->opt.chunk_nnz : 0);
+        if (st != PTK_OK) return st;
         bbuf_elems = std::max(bbuf_elems, s.dims[n] * E);
-        part_elems = std::max(part_elems, (m.bf16 ? m.nwaves : m.nchunks) * 2 * E);
     }
     HIPCHK(c, dalloc(&c->bbuf, bbuf_elems));
-    HIPCHK(c, dalloc(&c->part, part_elems));
     // sum of x^2 for the error identity of the fused pass
     if (nnz > 0) {
         HIPCHK(c, launch_sumsq(c->md[0].vals, nnz, c->red, kRedBlocks, c->st));
@@ -647,6 +787,7 @@ ptk_status ptk_bind_model(ptk_ctx *c, float *core, float *const *factors_host) {
         if (!factors_host[n]) return fail(c, PTK_E_INVALID, "null factor %d", n);
     c->core = core;
     for (int n = 0; n < c->s.N; ++n) c->fac[n] = factors_host[n];
+    c->epoch++;
     return PTK_OK;
 }
 
@@ -675,36 +816,32 @@ ptk_status ptk_iterate(ptk_ctx *c, int32_t iters, double lambda, double *sse_hos
     if (iters == 0) return PTK_OK;
     s = ensure_host(c, 2 * (size_t)iters);
     if (s != PTK_OK) return s;
+    if (c->dres_cap < iters) {
+        dfree(c->dres);
+        c->dres = nullptr;
+        c->dres_cap = 0;
+        HIPCHK(c, dalloc(&c->dres, 2 * (size_t)iters));
+        c->dres_cap = iters;
+        c->epoch++;
+    }
     const int N = c->s.N;
     for (int n = 0; n < N; ++n) HIPCHK(c, permute(c, n));
     HIPCHK(c, zero_bad(c));
-    double *partial = c->red;
-    double *scal = c->scal;
-    const bool fuse = c->opt.fuse_error != 0;
-    for (int t = 0; t < iters; ++t) {
-        for (int n = 0; n < N; ++n) {
-            s = update_mode_impl(c, n, lambda);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, c->iter_ctr, 0, (int64_t)1);
+    HIPCHK(c, hipGetLastError());
+    const bool use_graph = c->opt.use_graph && !c->opt.profile;
+    if (use_graph) {
+        s = ensure_iteration_graph(c, lambda);
+        if (s != PTK_OK) return s;
+        for (int t = 0; t < iters; ++t) HIPCHK(c, hipGraphLaunch(c->gexec, c->st));
+    } else {
+        for (int t = 0; t < iters; ++t) {
+            s = iteration_body(c, lambda);
             if (s != PTK_OK) return s;
         }
-        HIPCHK(c, timed(c, "error", [&]() -> hipError_t {
-            if (fuse) {
-                // from the last mode's row systems, still in bbuf
-                const ModeData &m = c->md[N - 1];
-                hipError_t e = launch_row_sse(c->bbuf, m.rowptr, c->fac[N - 1],
-                                              c->s.dims[N - 1], c->s.ranks[N - 1],
-                                              partial, kRedBlocks, c->st);
-                if (e != hipSuccess) return e;
-                hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, c->st, partial,
-                                   kRedBlocks, c->xsq);
-                if ((e = hipGetLastError()) != hipSuccess) return e;
-                return launch_reduce(partial, kRedBlocks + 1, scal, c->st);
-            }
-            return sse_direct(c, partial, scal);
-        }));
-        HIPCHK(c, timed(c, "norms", [&] { return factor_norms(c, partial, scal + 1); }));
-        HIPCHK(c, hipMemcpyAsync(c->host + 2 * t, scal, 2 * sizeof(double),
-                                 hipMemcpyDeviceToHost, c->st));
     }
+    HIPCHK(c, hipMemcpyAsync(c->host, c->dres, 2 * sizeof(double) * iters,
+                             hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
     for (int t = 0; t < iters; ++t) {
         if (sse_host) sse_host[t] = c->host[2 * t];
@@ -921,6 +1058,109 @@ extern "C" ptk_status ptk_kernel_times(ptk_ctx *c, int32_t *count, const char **
     }
     *count = k;
     return PTK_OK;
+}
+
+namespace {
+
+// Key of the autotuner cache: shape, arithmetic and the row-length
+// histogram (rows per power-of-two length class) of the mode.
+std::string tune_key(const ptk_ctx *c, int n) {
+    const ModeData &m = c->md[n];
+    int64_t bins[40] = {0};
+    for (size_t r = 0; r + 1 < m.rp_host.size(); ++r) {
+        const int64_t len = m.rp_host[r + 1] - m.rp_host[r];
+        int b = 0;
+        while ((int64_t(1) << b) <= len && b < 39) ++b;
+        ++bins[b];
+    }
+    char buf[128];
+    snprintf(buf, sizeof buf, "N=%d,J=%d,n=%d,prec=%d,nnz=%lld,I=%lld,hist=", c->s.N,
+             c->s.ranks[n], n, c->opt.precision, (long long)c->nnz,
+             (long long)c->s.dims[n]);
+    std::string k = buf;
+    for (int b = 0; b < 40; ++b) {
+        if (b) k += ':';
+        k += std::to_string(bins[b]);
+    }
+    return k;
+}
+
+bool tune_lookup(const char *path, const std::string &key, int64_t *value) {
+    if (!path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool hit = false;
+    while (fgets(line, sizeof line, f)) {
+        char *sp = strchr(line, ' ');
+        if (!sp) continue;
+        *sp = 0;
+        if (key == line) {
+            *value = strtoll(sp + 1, nullptr, 10);
+            hit = true;        // the last entry for a key wins
+        }
+    }
+    fclose(f);
+    return hit && *value > 0;
+}
+
+void tune_store(const char *path, const std::string &key, int64_t value) {
+    if (!path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %lld\n", key.c_str(), (long long)value);
+    fclose(f);
+}
+
+}  // namespace
+
+extern "C" ptk_status ptk_autotune(ptk_ctx *c, const char *cache_path, int64_t *work_host) {
+    if (!c) return PTK_E_INVALID;
+    ptk_status s = need_model(c);
+    if (s != PTK_OK) return s;
+    hipEvent_t e0 = get_event(c), e1 = get_event(c);
+    const int saved_profile = c->opt.profile;
+    c->opt.profile = 0;
+    for (int n = 0; n < c->s.N && s == PTK_OK; ++n) {
+        ModeData &m = c->md[n];
+        const std::string key = tune_key(c, n);
+        int64_t best = 0;
+        if (!tune_lookup(cache_path, key, &best)) {
+            const int64_t base = default_work(c, n);
+            const double mult[] = {0.125, 0.25, 0.5, 1.0, 2.0};
+            double best_ms = 1e300;
+            HIPCHK(c, permute(c, n));
+            for (double f : mult) {
+                int64_t w = (int64_t)(base * f);
+                w = m.bf16 ? std::max<int64_t>(w, 1) : std::max<int64_t>(round_up(w, kWave), kWave);
+                if ((s = configure_ranges(c, n, w)) != PTK_OK) break;
+                if ((s = systems(c, n)) != PTK_OK) break;          // warm-up
+                double ms_min = 1e300;
+                for (int rep = 0; rep < 3 && s == PTK_OK; ++rep) {
+                    HIPCHK(c, hipEventRecord(e0, c->st));
+                    s = systems(c, n);
+                    HIPCHK(c, hipEventRecord(e1, c->st));
+                    HIPCHK(c, hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+                    ms_min = std::min(ms_min, (double)ms);
+                }
+                if (s != PTK_OK) break;
+                if (ms_min < best_ms) {
+                    best_ms = ms_min;
+                    best = m.bf16 ? m.blk_per_wave : m.chunk;
+                }
+            }
+            if (s != PTK_OK) break;
+            tune_store(cache_path, key, best);
+        }
+        s = configure_ranges(c, n, best);
+        if (work_host) work_host[n] = m.bf16 ? m.blk_per_wave : m.chunk;
+    }
+    c->opt.profile = saved_profile;
+    c->pool.push_back(e0);
+    c->pool.push_back(e1);
+    return s;
 }
 
 extern "C" ptk_status ptk_not_pd_count(ptk_ctx *c, int64_t *count) {
