@@ -37,7 +37,8 @@ typedef enum ptk_status {
     PTK_E_UNSUPPORTED = 3,  /* shape outside what the library supports      */
     PTK_E_NOT_PD = 4,       /* a J x J system was not positive definite     */
     PTK_E_HIP = 5,          /* a HIP runtime call or kernel launch failed   */
-    PTK_E_STATE = 6         /* call order violated (e.g. no observed set)   */
+    PTK_E_STATE = 6,        /* call order violated (e.g. no observed set)   */
+    PTK_E_BUSY = 7          /* queue full, or a wait timed out              */
 } ptk_status;
 
 typedef struct ptk_ctx ptk_ctx;
@@ -215,6 +216,81 @@ ptk_status ptk_kernel_times(ptk_ctx *ctx, int32_t *count_host,
                             const char **names_host, int64_t *calls_host,
                             double *ms_host);
 ptk_status ptk_reset_timers(ptk_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Serving: a continuous-batching request loop on a bound model.
+ *
+ * Fold-in requests (the row update of eq. "rowupdate" for a new row of mode
+ * n, with G and the factors fixed) and prediction requests (eq. "recon2" for
+ * missing entries) are copied at submit, queued, and served by a library
+ * thread in batches. Up to `slots` batches are in flight at once, each on its
+ * own stream with its own part of the device-memory budget; requests are
+ * admitted first-in first-out as a slot's memory frees up, so requests that
+ * arrive while others run on the GPU start as soon as a slot is idle. Every
+ * request's result is bitwise the same whether it is served alone or in a
+ * mix. While a server runs on a context, the caller must not change the
+ * bound model or call into the context.
+ * ------------------------------------------------------------------------ */
+typedef struct ptk_server ptk_server;
+
+typedef struct ptk_server_opts {
+    int64_t mem_budget_bytes;   /* device bytes for in-flight batches, split
+                                   evenly over the slots; 0 = 512 MiB        */
+    int32_t slots;              /* batches in flight; 0 = 2                  */
+    int32_t max_batch_requests; /* requests per batch; 0 = 4096              */
+    int32_t queue_capacity;     /* queued requests before PTK_E_BUSY; 0 = 2^20 */
+    double lambda;              /* regularisation of the fold-in solves (> 0) */
+} ptk_server_opts;
+
+typedef struct ptk_server_stats {
+    int64_t batches;            /* batches completed                        */
+    int64_t requests;           /* requests completed                       */
+    int64_t max_batch_requests; /* largest batch                            */
+    int64_t max_in_flight;      /* most batches on the GPU at the same time  */
+    int64_t queued;             /* requests waiting now                     */
+} ptk_server_stats;
+
+/* Start a server on ctx (which must have a bound model). *out owns the
+ * thread, streams, device arenas and pinned staging memory.
+ * PTK_E_INVALID for bad options (lambda <= 0, budget too small). */
+ptk_status ptk_server_create(ptk_server **out, ptk_ctx *ctx,
+                             const ptk_server_opts *opts_host);
+
+/* Queue a fold-in of mode n from k observations: idx_host [N][k] (the mode-n
+ * array is not read), val_host [k], both host memory copied before return.
+ * *ticket identifies the request. PTK_E_INVALID for out-of-range indices or
+ * non-finite values (nothing is queued), PTK_E_NOMEM if the request alone
+ * exceeds a slot's memory, PTK_E_BUSY if the queue is full. */
+ptk_status ptk_server_submit_foldin(ptk_server *srv, int32_t n, int64_t k,
+                                    const int32_t *idx_host,
+                                    const float *val_host, uint64_t *ticket);
+
+/* Queue predictions of m cells: idx_host [N][m] host memory, copied. Errors
+ * as for fold-in. */
+ptk_status ptk_server_submit_predict(ptk_server *srv, int64_t m,
+                                     const int32_t *idx_host, uint64_t *ticket);
+
+/* Non-blocking: *done = 1 when the request has finished; then up to cap
+ * floats of its result (J_n for a fold-in, m for predictions) are copied to
+ * out_host, *req_status receives its own status (PTK_OK, PTK_E_NOT_PD for a
+ * fold-in whose system was not positive definite in FP64, PTK_E_HIP), the
+ * submit-to-completion time goes to *latency_ms (may be NULL) and the ticket
+ * is released. */
+ptk_status ptk_server_poll(ptk_server *srv, uint64_t ticket, float *out_host,
+                           int64_t cap, int32_t *done, ptk_status *req_status,
+                           double *latency_ms);
+
+/* As ptk_server_poll, but blocks up to timeout_s seconds (PTK_E_BUSY on
+ * timeout, the ticket stays valid). */
+ptk_status ptk_server_wait(ptk_server *srv, uint64_t ticket, float *out_host,
+                           int64_t cap, double timeout_s, ptk_status *req_status,
+                           double *latency_ms);
+
+ptk_status ptk_server_get_stats(ptk_server *srv, ptk_server_stats *out_host);
+const char *ptk_server_last_error(const ptk_server *srv);
+
+/* Finish every submitted request, stop the thread, free everything. */
+ptk_status ptk_server_destroy(ptk_server *srv);
 
 #ifdef __cplusplus
 }

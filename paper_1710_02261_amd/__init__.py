@@ -8,9 +8,9 @@ failing status. There is no CPU fallback: importing the binding fails when the
 library has not been built.
 """
 from ._native import (  # noqa: F401
-    Context, PtkError, PREC_FP64_ACC, PREC_FP32, PREC_BF16, PREC_BF16X3, library_path,
+    Context, PtkError, Server, PREC_FP64_ACC, PREC_FP32, PREC_BF16, PREC_BF16X3, library_path,
     load_library,
 )
 
-__all__ = ["Context", "PtkError", "PREC_FP64_ACC", "PREC_FP32", "PREC_BF16", "PREC_BF16X3",
+__all__ = ["Context", "PtkError", "Server", "PREC_FP64_ACC", "PREC_FP32", "PREC_BF16", "PREC_BF16X3",
            "library_path", "load_library"]

@@ -264,3 +264,120 @@ class Context:
 
     def reset_timers(self):
         self._check(self._lib.ptk_reset_timers(self._h))
+
+
+class _ServerOpts(C.Structure):
+    _fields_ = [("mem_budget_bytes", _i64), ("slots", _i32),
+                ("max_batch_requests", _i32), ("queue_capacity", _i32),
+                ("lambda_", _dbl)]
+
+
+class _ServerStats(C.Structure):
+    _fields_ = [("batches", _i64), ("requests", _i64), ("max_batch_requests", _i64),
+                ("max_in_flight", _i64), ("queued", _i64)]
+
+
+def _host_i32(a, rows):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    if a.ndim != 2 or a.shape[0] != rows:
+        raise ValueError("idx must be [N, count]")
+    return a
+
+
+class Server:
+    """ptk_server: continuous-batching fold-in / prediction loop on a context."""
+
+    def __init__(self, ctx, lam, mem_budget_bytes=0, slots=0, max_batch_requests=0,
+                 queue_capacity=0):
+        lib = load_library()
+        if not getattr(lib, "_server_sigs", False):
+            u64p = C.POINTER(C.c_uint64)
+            for name, args in {
+                "ptk_server_create": [C.POINTER(_vp), _vp, C.POINTER(_ServerOpts)],
+                "ptk_server_submit_foldin": [_vp, _i32, _i64, _vp, _vp, u64p],
+                "ptk_server_submit_predict": [_vp, _i64, _vp, u64p],
+                "ptk_server_poll": [_vp, C.c_uint64, _vp, _i64, C.POINTER(_i32),
+                                    C.POINTER(C.c_int), C.POINTER(_dbl)],
+                "ptk_server_wait": [_vp, C.c_uint64, _vp, _i64, _dbl, C.POINTER(C.c_int),
+                                    C.POINTER(_dbl)],
+                "ptk_server_get_stats": [_vp, C.POINTER(_ServerStats)],
+                "ptk_server_destroy": [_vp],
+            }.items():
+                f = getattr(lib, name)
+                f.argtypes = args
+                f.restype = C.c_int
+            lib.ptk_server_last_error.argtypes = [_vp]
+            lib.ptk_server_last_error.restype = C.c_char_p
+            lib._server_sigs = True
+        self._lib = lib
+        self.ctx = ctx
+        self.N = ctx.N
+        o = _ServerOpts(int(mem_budget_bytes), int(slots), int(max_batch_requests),
+                        int(queue_capacity), float(lam))
+        h = _vp()
+        st = lib.ptk_server_create(C.byref(h), ctx._h, C.byref(o))
+        if st != PTK_OK:
+            raise PtkError(st, "ptk_server_create")
+        self._h = h
+
+    def _check(self, st):
+        if st != PTK_OK:
+            msg = self._lib.ptk_server_last_error(self._h)
+            raise PtkError(st, msg.decode() if msg else "")
+
+    def submit_foldin(self, n, idx, val):
+        idx = _host_i32(idx, self.N)
+        val = np.ascontiguousarray(val, dtype=np.float32)
+        t = C.c_uint64()
+        self._check(self._lib.ptk_server_submit_foldin(
+            self._h, int(n), int(idx.shape[1]), idx.ctypes.data_as(_vp),
+            val.ctypes.data_as(_vp), C.byref(t)))
+        return t.value
+
+    def submit_predict(self, idx):
+        idx = _host_i32(idx, self.N)
+        t = C.c_uint64()
+        self._check(self._lib.ptk_server_submit_predict(
+            self._h, int(idx.shape[1]), idx.ctypes.data_as(_vp), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket, size):
+        out = np.zeros(max(int(size), 1), dtype=np.float32)
+        done, st, lat = _i32(), C.c_int(), _dbl()
+        self._check(self._lib.ptk_server_poll(self._h, ticket, out.ctypes.data_as(_vp),
+                                              int(size), C.byref(done), C.byref(st),
+                                              C.byref(lat)))
+        if not done.value:
+            return False, None, None, None
+        return True, out[:size], st.value, lat.value
+
+    def wait(self, ticket, size, timeout=60.0):
+        """Blocks until the request finishes: (result, status, latency_ms)."""
+        out = np.zeros(max(int(size), 1), dtype=np.float32)
+        st, lat = C.c_int(), _dbl()
+        self._check(self._lib.ptk_server_wait(self._h, ticket, out.ctypes.data_as(_vp),
+                                              int(size), float(timeout), C.byref(st),
+                                              C.byref(lat)))
+        return out[:size], st.value, lat.value
+
+    def stats(self):
+        s = _ServerStats()
+        self._check(self._lib.ptk_server_get_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in _ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ptk_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -15,87 +15,10 @@
 #include <string>
 #include <vector>
 
+#include "ptk_context.h"
 #include "ptk_internal.h"
 
 using namespace ptk;
-
-namespace {
-
-constexpr int kRedBlocks = 1024;   // blocks of the error / norm reductions
-constexpr int kSseBlocks = 8192;   // single-wave blocks of the direct error pass
-
-struct ModeData {
-    int64_t *rowptr = nullptr;
-    int32_t *rows = nullptr;
-    int32_t *oidx = nullptr;     // [N-1][nnz]
-    float *vals = nullptr;
-    int64_t chunk = 0, nchunks = 0;
-    int32_t *split = nullptr;    // [nsplit][3]
-    int32_t nsplit = 0;
-    bool fast = false;
-    // BF16 matrix-core form: blocks of <= 32 entries of one row
-    bool bf16 = false;
-    int split_bf16 = 1;          // 1: bf16 operands; 3: hi/lo split products
-    int32_t *blk_row = nullptr, *blk_start = nullptr, *blk_cnt = nullptr;
-    int64_t nblk = 0, blk_per_wave = 0, nwaves = 0;
-    // host copies used to recompute the work split (autotuner)
-    std::vector<int64_t> rp_host;
-    std::vector<int32_t> first_blk, last_blk;
-    int64_t part_elems = 0;
-};
-
-struct Timed {
-    const char *name;
-    hipEvent_t a, b;
-};
-
-}  // namespace
-
-struct ptk_ctx {
-    Shape s{};
-    hipStream_t st = nullptr;
-    int device = 0;
-    int num_cu = 256;
-    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1};
-    int64_t nnz = -1;
-    ModeData md[kMaxN];
-    float *core = nullptr;
-    float *fac[kMaxN] = {};
-    void *gp[kMaxN] = {};        // permuted cores of the row-system kernels
-    void *frag[kMaxN] = {};      // bf16 core fragments of the matrix-core kernel
-    double *gpe = nullptr;       // fp64 permuted core of the per-entry kernels
-    int gpe_mode = -1;
-    int64_t core_cells = 1;
-    double *bbuf = nullptr;
-    double *part = nullptr;
-    int64_t part_cap = 0;
-    double *red = nullptr;       // [kRedBlocks * (N + 1)] partials + scalars
-    double *xsq = nullptr;       // sum of x^2 over Omega (device, 1 double)
-    double *scal = nullptr;      // [2] error and factor norms of one iteration
-    double *dres = nullptr;      // [2 * dres_cap] per-iteration results
-    int64_t dres_cap = 0;
-    int32_t *iter_ctr = nullptr; // device iteration counter for dres
-    uint64_t epoch = 1;          // bumped whenever captured launch arguments change
-    hipStream_t gstream = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    uint64_t g_epoch = 0;
-    double g_lambda = 0.0;
-    int g_fuse = -1;
-    int32_t *bad = nullptr;
-    int64_t last_not_pd = 0;
-    double *host = nullptr;      // pinned results
-    size_t host_cap = 0;
-    void *qr_work = nullptr;
-    size_t qr_cap = 0;
-    double *fold_bbuf = nullptr, *fold_part = nullptr;
-    int64_t *fold_rowptr = nullptr;
-    int32_t *fold_split = nullptr;
-    int64_t fold_part_chunks = 0;
-    std::string err;
-    std::vector<Timed> pending;
-    std::vector<hipEvent_t> pool;
-    std::map<std::string, std::pair<int64_t, double>> totals;
-};
 
 namespace {
 
@@ -245,6 +168,7 @@ GramArgs gram_args(const ptk_ctx *c, int n) {
     const int32_t *other[kMaxN];
     for (int t = 0; t < c->s.N - 1; ++t) other[t] = m.oidx + (int64_t)t * c->nnz;
     fill_common(c, n, a, other);
+    a.skip_row = -1;
     a.E = sys_entries(c->s.ranks[n]);
     a.rows = m.rows;
     a.val = m.vals;
@@ -1018,6 +942,7 @@ extern "C" ptk_status ptk_fold_in(ptk_ctx *c, int32_t n, int64_t k, const int32_
     for (int q = 0; q < c->s.N; ++q)
         if (q != n) other[t++] = idx + (int64_t)q * k;
     fill_common(c, n, a, other);
+    a.skip_row = -1;
     a.E = E;
     a.rows = nullptr;
     a.val = val;

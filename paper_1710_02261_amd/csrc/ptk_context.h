@@ -1,0 +1,93 @@
+// Context of the C ABI (shared by ptk_api.hip and ptk_server.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "ptk_internal.h"
+
+namespace ptk {
+
+constexpr int kRedBlocks = 1024;   // blocks of the error / norm reductions
+constexpr int kSseBlocks = 8192;   // single-wave blocks of the direct error pass
+
+struct ModeData {
+    int64_t *rowptr = nullptr;
+    int32_t *rows = nullptr;
+    int32_t *oidx = nullptr;     // [N-1][nnz]
+    float *vals = nullptr;
+    int64_t chunk = 0, nchunks = 0;
+    int32_t *split = nullptr;    // [nsplit][3]
+    int32_t nsplit = 0;
+    bool fast = false;
+    // BF16 matrix-core form: blocks of <= 32 entries of one row
+    bool bf16 = false;
+    int split_bf16 = 1;          // 1: bf16 operands; 3: hi/lo split products
+    int32_t *blk_row = nullptr, *blk_start = nullptr, *blk_cnt = nullptr;
+    int64_t nblk = 0, blk_per_wave = 0, nwaves = 0;
+    // host copies used to recompute the work split (autotuner)
+    std::vector<int64_t> rp_host;
+    std::vector<int32_t> first_blk, last_blk;
+    int64_t part_elems = 0;
+};
+
+struct Timed {
+    const char *name;
+    hipEvent_t a, b;
+};
+
+}  // namespace ptk
+
+struct ptk_ctx {
+    using ModeData = ptk::ModeData;
+    using Timed = ptk::Timed;
+    using Shape = ptk::Shape;
+
+    Shape s{};
+    hipStream_t st = nullptr;
+    int device = 0;
+    int num_cu = 256;
+    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1};
+    int64_t nnz = -1;
+    ModeData md[ptk::kMaxN];
+    float *core = nullptr;
+    float *fac[ptk::kMaxN] = {};
+    void *gp[ptk::kMaxN] = {};        // permuted cores of the row-system kernels
+    void *frag[ptk::kMaxN] = {};      // bf16 core fragments of the matrix-core kernel
+    double *gpe = nullptr;       // fp64 permuted core of the per-entry kernels
+    int gpe_mode = -1;
+    int64_t core_cells = 1;
+    double *bbuf = nullptr;
+    double *part = nullptr;
+    int64_t part_cap = 0;
+    double *red = nullptr;       // [kRedBlocks * (N + 1)] partials + scalars
+    double *xsq = nullptr;       // sum of x^2 over Omega (device, 1 double)
+    double *scal = nullptr;      // [2] error and factor norms of one iteration
+    double *dres = nullptr;      // [2 * dres_cap] per-iteration results
+    int64_t dres_cap = 0;
+    int32_t *iter_ctr = nullptr; // device iteration counter for dres
+    uint64_t epoch = 1;          // bumped whenever captured launch arguments change
+    hipStream_t gstream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    uint64_t g_epoch = 0;
+    double g_lambda = 0.0;
+    int g_fuse = -1;
+    int32_t *bad = nullptr;
+    int64_t last_not_pd = 0;
+    double *host = nullptr;      // pinned results
+    size_t host_cap = 0;
+    void *qr_work = nullptr;
+    size_t qr_cap = 0;
+    double *fold_bbuf = nullptr, *fold_part = nullptr;
+    int64_t *fold_rowptr = nullptr;
+    int32_t *fold_split = nullptr;
+    int64_t fold_part_chunks = 0;
+    std::string err;
+    std::vector<Timed> pending;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, std::pair<int64_t, double>> totals;
+};
+

@@ -52,6 +52,7 @@ struct GramArgs {
     int32_t jn;                       // rank of mode n
     int32_t E;                        // sys_entries(jn)
     const int32_t *rows;              // mode-n index per entry, or null (all 0)
+    int32_t skip_row;                 // row id whose sums are discarded (padding), or -1
     const float *val;                 // values in grouped order
     const int64_t *rowptr;            // CSR row pointers of mode n
     int64_t nnz;

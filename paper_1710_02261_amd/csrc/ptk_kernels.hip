@@ -273,6 +273,7 @@ template <int EPL>
 __device__ __forceinline__ void flush_row(const GramArgs &a, SysLane<EPL> &sl,
                                           int cur, int64_t chunk, int64_t cs,
                                           int64_t ce) {
+    if (cur == a.skip_row) return;     // padding entries of a request batch
     const int64_t r0 = a.rowptr[cur], r1 = a.rowptr[cur + 1];
     double *dst;
     if (r0 < cs)
