@@ -127,12 +127,145 @@ PREC_DTYPE = {"f64": "f64", "f32": "f32", "bf16": "bf16", "bf16x3": "bf16"}
 PREC_PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15, "bf16x3": 2.5e15}
 
 
+def serving(args):
+    """Serving workload: continuous-batching server vs per-request calls."""
+    import queue
+    import threading
+
+    import torch
+    import synth
+    import paper_1710_02261_amd as ptk
+
+    sys.setswitchinterval(1e-4)
+    t0 = time.perf_counter()
+    G, A, reqs = synth.make_c5(n_foldin=args.requests)
+    dims, J = (100_000, 50_000, 1_000), 16
+    log("generated %d requests in %.1f s" % (len(reqs), time.perf_counter() - t0))
+    dev = torch.device("cuda:0")
+    core = torch.from_numpy(G).to(dev)
+    fac = [torch.from_numpy(a).to(dev) for a in A]
+    ctx = ptk.Context(dims, (J, J, J))
+    ctx.bind_model(core, fac)
+    ctx.orthogonalize()                       # orthonormal factors, rotated core
+    torch.cuda.synchronize()
+    lam = 0.01
+    sizes = [J if r[0] == "f" else r[2].shape[1] for r in reqs]
+    kinds = np.array([r[0] == "f" for r in reqs])
+
+    def submit(srv, r):
+        return srv.submit_foldin(0, r[2], r[3]) if r[0] == "f" else srv.submit_predict(r[2])
+
+    def run_server(rate):
+        srv = ptk.Server(ctx, lam, slots=args.slots, max_batch_requests=args.max_batch)
+        for r in reqs[:50]:                    # warm-up
+            srv.wait(submit(srv, r), J if r[0] == "f" else r[2].shape[1])
+        q = queue.Queue()
+        lag = np.zeros(len(reqs))
+        rng = np.random.default_rng(7)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, len(reqs))) if rate else None
+
+        def gen():
+            start = time.perf_counter()
+            for i, r in enumerate(reqs):
+                if arrivals is not None:
+                    while True:
+                        now = time.perf_counter() - start
+                        if now >= arrivals[i]:
+                            break
+                        if arrivals[i] - now > 2e-4:
+                            time.sleep(0)
+                    lag[i] = (time.perf_counter() - start) - arrivals[i]
+                q.put((i, submit(srv, r)))
+
+        lat = np.zeros(len(reqs))
+        th = threading.Thread(target=gen)
+        tstart = time.perf_counter()
+        th.start()
+        for _ in range(len(reqs)):
+            i, t = q.get()
+            out, st, ms = srv.wait(t, sizes[i], timeout=600.0)
+            if st != 0:
+                raise RuntimeError("request %d failed with status %d" % (i, st))
+            lat[i] = ms
+        elapsed = time.perf_counter() - tstart
+        th.join()
+        stats = srv.stats()
+        srv.close()
+        return elapsed, lat, lag, stats
+
+    def pct(x, q):
+        return float(np.percentile(x, q)) if len(x) else None
+
+    # saturation: the whole stream submitted as fast as possible
+    el, lat, lag, st = run_server(None)
+    sat = len(reqs) / el
+    log("saturation: %.0f requests/s (%d batches, max %d in flight)" % (
+        sat, st["batches"], st["max_in_flight"]))
+    loads = {}
+    for frac in args.loads:
+        rate = frac * sat
+        el2, lat2, lag2, st2 = run_server(rate)
+        loads["%d%%" % round(100 * frac)] = {
+            "offered_req_s": rate, "achieved_req_s": len(reqs) / el2,
+            "foldin_p50_ms": pct(lat2[kinds], 50), "foldin_p99_ms": pct(lat2[kinds], 99),
+            "predict_p50_ms": pct(lat2[~kinds], 50), "predict_p99_ms": pct(lat2[~kinds], 99),
+            "generator_lag_p99_ms": 1e3 * pct(lag2, 99), "batches": st2["batches"],
+            "max_in_flight": st2["max_in_flight"]}
+        log("load %.0f%%: fold-in p50 %.3f ms p99 %.3f ms" % (
+            100 * frac, loads["%d%%" % round(100 * frac)]["foldin_p50_ms"],
+            loads["%d%%" % round(100 * frac)]["foldin_p99_ms"]))
+    # per-request plain calls (synchronous, one at a time) on a prefix
+    nplain = min(args.plain_requests, len(reqs))
+    plat = np.zeros(nplain)
+    tp = time.perf_counter()
+    for i in range(nplain):
+        r = reqs[i]
+        t1 = time.perf_counter()
+        idx = torch.from_numpy(r[2]).to(dev)
+        if r[0] == "f":
+            val = torch.from_numpy(r[3]).to(dev)
+            ctx.fold_in(0, idx, val, lam).cpu()
+        else:
+            ctx.predict(idx).cpu()
+        plat[i] = 1e3 * (time.perf_counter() - t1)
+    plain_el = time.perf_counter() - tp
+    pk = kinds[:nplain]
+    out = {
+        "metric": "serving: fold-in / prediction requests per second; p50/p99 ms",
+        "value": sat, "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
+        "data": "synthetic", "dtype": "f64",
+        "config": {"workload": "order-3 model 100000x50000x1000, J=16, orthogonalised "
+                               "planted N(0,1); %d fold-ins of mode 0 (k ~ lognormal(ln 50, "
+                               "1.2) in [5, 5000]) and one prediction batch (1e3..1e5 "
+                               "cells, log-uniform) per 20 fold-ins; Poisson arrivals"
+                               % args.requests,
+                   "requests": len(reqs), "foldins": int(kinds.sum()),
+                   "slots": args.slots, "max_batch_requests": args.max_batch},
+        "saturation": {"req_s": sat, "foldin_p50_ms": pct(lat[kinds], 50),
+                       "foldin_p99_ms": pct(lat[kinds], 99), "batches": st["batches"],
+                       "max_in_flight": st["max_in_flight"]},
+        "poisson": loads,
+        "plain_per_request": {"requests": nplain, "req_s": nplain / plain_el,
+                              "foldin_p50_ms": pct(plat[pk], 50),
+                              "foldin_p99_ms": pct(plat[pk], 99),
+                              "predict_p50_ms": pct(plat[~pk], 50),
+                              "predict_p99_ms": pct(plat[~pk], 99)},
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["c5"], default="c2")
+    ap.add_argument("--requests", type=int, default=100_000, help="c5: fold-ins")
+    ap.add_argument("--slots", type=int, default=2)
+    ap.add_argument("--max-batch", type=int, default=1024)
+    ap.add_argument("--loads", type=float, nargs="*", default=[0.25, 0.5, 0.75, 0.9])
+    ap.add_argument("--plain-requests", type=int, default=10_000)
     ap.add_argument("--nnz", type=int, default=0, help="override the entry count")
     ap.add_argument("--precision", choices=sorted(PREC_NAMES), default="f64")
     ap.add_argument("--cpu-seconds", type=float, default=40.0)
@@ -159,6 +292,9 @@ def main():
         from paper_1710_02261_amd import build as hipbuild
         hipbuild.build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "c5":
+        serving(args)
+        return
 
     t0 = time.perf_counter()
     kw = {"nnz": args.nnz} if args.nnz else {}

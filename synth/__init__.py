@@ -321,6 +321,43 @@ def make_c4(seed=3, nnz=50_000_000, I=10_000):
                             planted_ranks=(4,) * 5)
 
 
+def make_c5(seed=4, n_foldin=100_000, pred_every=20, dims=(100_000, 50_000, 1_000),
+            J=16):
+    """Serving workload: a planted order-3 model and a request stream.
+
+    Fold-in requests (new rows of mode 0): k ~ lognormal(ln 50, 1.2) clipped
+    to [5, 5000], entries at uniform (i_2, i_3), values of the planted model
+    with a fresh N(0,1) row + N(0, 0.1) noise. After every `pred_every`
+    fold-ins one prediction batch of log-uniform size in [1e3, 1e5] uniform
+    cells. Returns (core, factors, requests); a request is
+    ("f", mode, idx [N][k] int32, val float32) or ("p", None, idx [N][m], None).
+    """
+    rng = np.random.default_rng(seed)
+    ranks = (J,) * 3
+    G, A = planted_model(rng, dims, ranks)
+    k = np.clip(np.rint(rng.lognormal(math.log(50.0), 1.2, n_foldin)), 5, 5000).astype(np.int64)
+    tot = int(k.sum())
+    owner = np.repeat(np.arange(n_foldin, dtype=np.int32), k)
+    i2 = rng.integers(0, dims[1], tot, dtype=np.int64).astype(np.int32)
+    i3 = rng.integers(0, dims[2], tot, dtype=np.int64).astype(np.int32)
+    Anew = rng.standard_normal((n_foldin, J))
+    x = planted_values(np.stack([owner, i2, i3]), G, [Anew, A[1], A[2]])
+    x += math.sqrt(0.1) * rng.standard_normal(tot)
+    x = x.astype(np.float32)
+    reqs = []
+    off = np.concatenate([[0], np.cumsum(k)])
+    for r in range(n_foldin):
+        a, b = off[r], off[r + 1]
+        idx = np.stack([np.zeros(b - a, np.int32), i2[a:b], i3[a:b]])
+        reqs.append(("f", 0, idx, x[a:b]))
+        if (r + 1) % pred_every == 0:
+            m = int(round(10 ** rng.uniform(3, 5)))
+            pidx = np.stack([rng.integers(0, d, m, dtype=np.int64).astype(np.int32)
+                             for d in dims])
+            reqs.append(("p", None, pidx, None))
+    return (G.astype(np.float32), [a.astype(np.float32) for a in A], reqs)
+
+
 CONFIGS = {"c1": make_c1, "c2": make_c2, "c3": make_c3, "c4": make_c4}
 
 
