@@ -271,6 +271,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=40.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variant", action="store_true")
+    ap.add_argument("--pair-cache", action="store_true",
+                    help="main run with the per-entry pair cache")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default work-range sizes")
     ap.add_argument("--no-graph", action="store_true",
@@ -310,11 +312,11 @@ def main():
 
     use_graph = 0 if args.no_graph else 1
 
-    def run(prec):
+    def run(prec, cache=0):
         fac = [f.clone() for f in fac0]
         ctx = ptk.Context(p.dims, p.ranks)
         ctx.set_options(precision=PREC_NAMES[prec], fuse_error=1, profile=0,
-                        use_graph=use_graph)
+                        use_graph=use_graph, pair_cache=cache)
         torch.cuda.synchronize()
         ts = time.perf_counter()
         ctx.set_observed(idx, val)
@@ -338,12 +340,13 @@ def main():
         _, rmse_direct, _ = ctx.recon_error(p.lam)
         # second pass with per-kernel HIP events on the library's stream
         ctx.set_options(precision=PREC_NAMES[prec], fuse_error=1, profile=1,
-                        use_graph=use_graph)
+                        use_graph=use_graph, pair_cache=cache)
         ctx.reset_timers()
         ctx.iterate(args.steps, p.lam, strict=False)
         times = ctx.kernel_times()
         ctx.close()
-        gname = "gram_mfma" if prec.startswith("bf16") else "gram"
+        gname = ("gram_mfma" if prec.startswith("bf16")
+                 else "gram_cache_write" if cache else "gram")
         calls, ms = times.get(gname, (0, 0.0))
         return {"elapsed": elapsed, "setup": setup, "sse": sse, "times": times,
                 "not_pd": not_pd, "gram_ms": ms / max(calls, 1),
@@ -352,7 +355,12 @@ def main():
                 "rmse_fused": float(np.sqrt(max(sse[-1], 0.0) / p.nnz))}
 
     main_prec = args.precision
-    r = run(main_prec)
+    cache_shapes = {3: (3, 4, 5, 8, 10, 16), 4: (3, 5, 8, 10), 5: (3, 5, 8)}
+    cache_ok = (len(set(p.ranks)) == 1 and not main_prec.startswith("bf16")
+                and J in cache_shapes.get(N, ()))
+    if args.pair_cache and not cache_ok:
+        raise SystemExit("bench.py: no pair-cache kernel for this workload and precision")
+    r = run(main_prec, 1 if args.pair_cache else 0)
     log("%s: %.2f ms/step, %.3e nnz*iters/s" % (main_prec, 1e3 * r["elapsed"] / args.steps,
                                                   r["value"]))
     log("kernels: " + ", ".join("%s %.3f ms x%d" % (k, v[1] / max(v[0], 1), v[0])
@@ -375,6 +383,10 @@ def main():
              "f32": "k_gram_fast<%d,%d,U,float>" % (N, J),
              "bf16": "k_gram_mfma<%d,%d,1>" % (N, J),
              "bf16x3": "k_gram_mfma<%d,%d,3>" % (N, J)}[main_prec]
+    if args.pair_cache:
+        kname = "k_gram_cache_write<%d,%d,%s>" % (N, J, "double" if main_prec == "f64"
+                                                   else "float")
+        traffic = None
     roofline = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak, "traffic": traffic, "kernel": kname,
                 "avg_launch_ms": r["gram_ms"], "flops_per_launch": flops}
@@ -399,6 +411,7 @@ def main():
         "setup_s": r["setup"],
         "autotune": {"work_per_mode": r["work"], "seconds": r["tune_s"]},
         "graph": bool(use_graph),
+        "pair_cache": bool(args.pair_cache),
         "rmse_after": r["rmse"],
         "rmse_after_fused": r["rmse_fused"],
         "not_pd_rows_timed": int(r["not_pd"]),
@@ -406,6 +419,18 @@ def main():
     }
     if not args.no_variant:
         variants = {}
+        if cache_ok:
+            other = 0 if args.pair_cache else 1
+            v = run(main_prec, other)
+            name = main_prec + ("" if other == 0 else "+pair_cache")
+            variants[name] = {"value": v["value"],
+                              "ms_per_step": 1e3 * v["elapsed"] / args.steps,
+                              "rmse_after": v["rmse"],
+                              "rmse_rel_to_main": v["rmse"] / r["rmse"] - 1.0,
+                              "kernel_ms": {k: t[1] / max(t[0], 1)
+                                            for k, t in v["times"].items()}}
+            log("%s: %.2f ms/step, rmse %.6g (main %.6g)" % (
+                name, variants[name]["ms_per_step"], v["rmse"], r["rmse"]))
         for prec in PREC_NAMES:
             if prec == main_prec:
                 continue

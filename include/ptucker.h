@@ -66,6 +66,22 @@ typedef struct ptk_options {
     int32_t use_graph;      /* 1: ptk_iterate replays one captured graph per
                                iteration (re-captured when lambda, options,
                                the observed set or the bound model change)   */
+    int32_t pair_cache;     /* 1: per-entry partial-product cache inside
+                               ptk_iterate (the Cache variant of Alg. 3 in a
+                               reduced form). Modes are paired (0,1), (2,3),
+                               ...: while mode 2k is updated, every entry
+                               stores G contracted with all modes except 2k
+                               and 2k+1 (J*J doubles), and mode 2k+1 then
+                               forms its deltas from that table and the new
+                               mode-2k row instead of from G. Same result up
+                               to rounding. Needs equal ranks, PTK_PREC_FP64_ACC
+                               or PTK_PREC_FP32, (N, J) in {3} x {3,4,5,8,10,16},
+                               {4} x {3,5,8,10} or {5} x {3,5,8} (else
+                               PTK_E_UNSUPPORTED), and (nnz + 1) * R * 8 bytes
+                               of device memory, R = J*J rounded up to even
+                               (PTK_E_NOMEM from ptk_set_observed). Chosen
+                               before ptk_set_observed. ptk_update_mode,
+                               ptk_row_systems and fold-in never use it.      */
 } ptk_options;
 
 /*
@@ -87,8 +103,9 @@ const char *ptk_last_error(const ptk_ctx *ctx);
 
 /* Set options (see ptk_options). PTK_E_INVALID for unknown values,
  * PTK_E_UNSUPPORTED for the BF16 forms on a shape without a matrix-core
- * kernel, PTK_E_STATE when chunk_nnz or a change to or from a BF16 form comes
- * after ptk_set_observed (they shape its work split). */
+ * kernel or pair_cache where it is not available, PTK_E_STATE when chunk_nnz,
+ * pair_cache or a change to or from a BF16 form comes after ptk_set_observed
+ * (they shape what it builds). */
 ptk_status ptk_set_options(ptk_ctx *ctx, const ptk_options *opt_host);
 
 /*

@@ -96,6 +96,7 @@ void free_modes(ptk_ctx *c) {
         dfree(m.rows);
         dfree(m.oidx);
         dfree(m.vals);
+        dfree(m.cmap);
         dfree(m.split);
         dfree(m.blk_row);
         dfree(m.blk_start);
@@ -104,6 +105,8 @@ void free_modes(ptk_ctx *c) {
     }
     dfree(c->bbuf);
     dfree(c->part);
+    dfree(c->pcache);
+    c->pcache = nullptr;
     c->bbuf = c->part = nullptr;
     c->part_cap = 0;
     c->nnz = -1;
@@ -120,19 +123,29 @@ bool equal_ranks(const Shape &s) {
     return true;
 }
 
+// Role of mode n in the pair cache of a full sweep: 1 writes it (modes 2k
+// with a partner 2k+1), 2 reads it (modes 2k+1), 0 neither.
+int cache_role(const ptk_ctx *c, int n) {
+    if (!c->opt.pair_cache) return 0;
+    if (n % 2 == 1) return 2;
+    return n + 1 < c->s.N ? 1 : 0;
+}
+
 ptk_status need_model(ptk_ctx *c) {
     if (c->nnz < 0) return fail(c, PTK_E_STATE, "no observed set (ptk_set_observed)");
     if (!c->core) return fail(c, PTK_E_STATE, "no model bound (ptk_bind_model)");
     return PTK_OK;
 }
 
-hipError_t permute(ptk_ctx *c, int n) {
+// A pair-cache writer (role 1) needs its partner as the leading other mode.
+hipError_t permute(ptk_ctx *c, int n, int role = 0) {
     if (c->md[n].bf16)
         return timed(c, "permute_core", [&] {
             return launch_mfma_frags(c->core, c->frag[n], c->s, n, c->st);
         });
     return timed(c, "permute_core", [&] {
-        return launch_permute_core(c->core, c->gp[n], c->s, n, arith_of(c, n), c->st);
+        return launch_permute_core(c->core, c->gp[n], c->s, n, arith_of(c, n), c->st,
+                                   role == 1 ? n + 1 : -1);
     });
 }
 
@@ -180,6 +193,28 @@ GramArgs gram_args(const ptk_ctx *c, int n) {
     return a;
 }
 
+// Pair-cache arguments. Writer n: other-mode slots reordered so that the
+// partner n+1 (slot n of the ascending list) leads, as in its permuted core.
+// Reader n: the partner n-1 is slot n-1 of the ascending list.
+GramArgs cache_args(const ptk_ctx *c, int n, int role) {
+    GramArgs a = gram_args(c, n);
+    a.cache = c->pcache;
+    if (role == 1) {
+        const float *f = a.fac[n];
+        const int32_t *o = a.oidx[n];
+        for (int t = n; t > 0; --t) {
+            a.fac[t] = a.fac[t - 1];
+            a.oidx[t] = a.oidx[t - 1];
+        }
+        a.fac[0] = f;
+        a.oidx[0] = o;
+    } else {
+        a.cmap = c->md[n].cmap;
+        a.cslot = n - 1;
+    }
+    return a;
+}
+
 MfmaArgs mfma_args(const ptk_ctx *c, int n) {
     const ModeData &m = c->md[n];
     MfmaArgs a{};
@@ -205,13 +240,23 @@ MfmaArgs mfma_args(const ptk_ctx *c, int n) {
 }
 
 // B_i, c_i for every row of mode n into bbuf (delta + Gram kernel, merge).
-ptk_status systems(ptk_ctx *c, int n) {
+ptk_status systems(ptk_ctx *c, int n, int role = 0) {
     const ModeData &m = c->md[n];
     if (m.bf16) {
         MfmaArgs a = mfma_args(c, n);
         HIPCHK(c, timed(c, "gram_mfma", [&] {
             return launch_gram_mfma(a, c->s.N, c->s.ranks[n], m.split_bf16, m.nwaves,
                                     c->st);
+        }));
+        HIPCHK(c, timed(c, "merge", [&] {
+            return launch_merge(c->part, m.split, m.nsplit, a.E, c->bbuf, c->st);
+        }));
+        return PTK_OK;
+    }
+    if (role) {
+        GramArgs a = cache_args(c, n, role);
+        HIPCHK(c, timed(c, role == 1 ? "gram_cache_write" : "gram_cache_read", [&] {
+            return launch_gram_cache(a, c->s, n, arith_of(c, n), m.nchunks, role, c->st);
         }));
         HIPCHK(c, timed(c, "merge", [&] {
             return launch_merge(c->part, m.split, m.nsplit, a.E, c->bbuf, c->st);
@@ -228,8 +273,8 @@ ptk_status systems(ptk_ctx *c, int n) {
     return PTK_OK;
 }
 
-ptk_status update_mode_impl(ptk_ctx *c, int n, double lambda) {
-    ptk_status s = systems(c, n);
+ptk_status update_mode_impl(ptk_ctx *c, int n, double lambda, int role = 0) {
+    ptk_status s = systems(c, n, role);
     if (s != PTK_OK) return s;
     const ModeData &m = c->md[n];
     HIPCHK(c, timed(c, "solve", [&] {
@@ -341,7 +386,9 @@ int64_t default_work(const ptk_ctx *c, int n) {
                               mfma_waves_per_cu(c->s.N, c->s.ranks[n], m.split_bf16);
         return std::max<int64_t>(1, (m.nblk + waves - 1) / std::max<int64_t>(waves, 1));
     }
-    const int bpc = gram_blocks_per_cu(c->s, n, arith_of(c, n), m.fast);
+    const int role = cache_role(c, n);
+    const int bpc = role ? gram_cache_blocks_per_cu(c->s, n, arith_of(c, n), role)
+                         : gram_blocks_per_cu(c->s, n, arith_of(c, n), m.fast);
     const int64_t waves = (int64_t)c->num_cu * std::max(1, bpc);
     int64_t chunk = round_up((c->nnz + waves - 1) / std::max<int64_t>(waves, 1), kWave);
     return std::max<int64_t>(chunk, kWave);
@@ -413,7 +460,7 @@ ptk_status iteration_body(ptk_ctx *c, double lambda) {
     double *partial = c->red;
     double *scal = c->scal;
     for (int n = 0; n < N; ++n) {
-        ptk_status s = update_mode_impl(c, n, lambda);
+        ptk_status s = update_mode_impl(c, n, lambda, cache_role(c, n));
         if (s != PTK_OK) return s;
     }
     HIPCHK(c, timed(c, "error", [&]() -> hipError_t {
@@ -587,6 +634,14 @@ ptk_status ptk_set_options(ptk_ctx *c, const ptk_options *o) {
     const bool rechunk = o->chunk_nnz != c->opt.chunk_nnz;
     if (rechunk && c->nnz >= 0)
         return fail(c, PTK_E_STATE, "chunk_nnz must be set before ptk_set_observed");
+    if (o->pair_cache != 0 && o->pair_cache != 1)
+        return fail(c, PTK_E_INVALID, "pair_cache must be 0 or 1");
+    if (o->pair_cache &&
+        (bf_new || !equal_ranks(c->s) || !cache_available(c->s.N, c->s.ranks[0])))
+        return fail(c, PTK_E_UNSUPPORTED,
+                    "no pair-cache kernel for this shape and precision");
+    if (o->pair_cache != c->opt.pair_cache && c->nnz >= 0)
+        return fail(c, PTK_E_STATE, "pair_cache must be set before ptk_set_observed");
     c->opt = *o;
     c->epoch++;
     return PTK_OK;
@@ -622,21 +677,40 @@ ptk_status ptk_set_observed(ptk_ctx *c, int64_t nnz, const int32_t *idx,
                         hb[1]);
     }
 
-    // per-mode CSR
+    // per-mode CSR; with the pair cache also the position map from each
+    // reader's grouping to its writer's (perm: grouped position -> entry)
     void *work = nullptr;
     HIPCHK(c, hipMalloc(&work, sort_workspace_bytes(nnz)));
+    int32_t *perm = nullptr, *inv = nullptr;
+    if (c->opt.pair_cache && nnz > 0) {
+        hipError_t e = dalloc(&perm, nnz);
+        if (e == hipSuccess) e = dalloc(&inv, nnz);
+        if (e != hipSuccess) {
+            dfree(work);
+            dfree(perm);
+            return fail(c, PTK_E_NOMEM, "pair-cache position maps");
+        }
+    }
     const bool eq = equal_ranks(s);
     for (int n = 0; n < N; ++n) {
         ModeData &m = c->md[n];
+        const int role = cache_role(c, n);
         hipError_t e = dalloc(&m.rowptr, s.dims[n] + 1);
         if (e == hipSuccess) e = dalloc(&m.rows, nnz + 64);
         if (e == hipSuccess) e = dalloc(&m.oidx, (size_t)(N - 1) * nnz + 64);
         if (e == hipSuccess) e = dalloc(&m.vals, nnz + 64);
+        if (e == hipSuccess && role == 2) e = dalloc(&m.cmap, nnz + 64);
         if (e == hipSuccess)
             e = build_mode_csr(idx, val, nnz, s, n, work, m.rowptr, m.rows, m.oidx,
-                               m.vals, c->st);
+                               m.vals, c->st, role && nnz > 0 ? perm : nullptr);
+        if (e == hipSuccess && role == 1 && nnz > 0)
+            e = launch_invert_perm(perm, nnz, inv, c->st);
+        if (e == hipSuccess && role == 2 && nnz > 0)
+            e = launch_compose_perm(inv, perm, nnz, m.cmap, c->st);
         if (e != hipSuccess) {
             dfree(work);
+            dfree(perm);
+            dfree(inv);
             free_modes(c);
             return fail(c, e == hipErrorOutOfMemory ? PTK_E_NOMEM : PTK_E_HIP,
                         "CSR build of mode %d: %s", n, hipGetErrorString(e));
@@ -645,9 +719,19 @@ ptk_status ptk_set_observed(ptk_ctx *c, int64_t nnz, const int32_t *idx,
     }
     hipError_t e = hipStreamSynchronize(c->st);
     dfree(work);
+    dfree(perm);
+    dfree(inv);
     if (e != hipSuccess) {
         free_modes(c);
         HIPCHK(c, e);
+    }
+    if (c->opt.pair_cache) {
+        const int64_t rec = cache_record_doubles(s.ranks[0]);
+        if (dalloc(&c->pcache, (size_t)(nnz + 1) * rec) != hipSuccess) {
+            free_modes(c);
+            return fail(c, PTK_E_NOMEM, "pair cache: %.2f GB of device memory",
+                        (nnz + 1) * rec * 8e-9);
+        }
     }
     c->nnz = nnz;
 
@@ -749,7 +833,7 @@ ptk_status ptk_iterate(ptk_ctx *c, int32_t iters, double lambda, double *sse_hos
         c->epoch++;
     }
     const int N = c->s.N;
-    for (int n = 0; n < N; ++n) HIPCHK(c, permute(c, n));
+    for (int n = 0; n < N; ++n) HIPCHK(c, permute(c, n, cache_role(c, n)));
     HIPCHK(c, zero_bad(c));
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, c->iter_ctr, 0, (int64_t)1);
     HIPCHK(c, hipGetLastError());
@@ -999,9 +1083,9 @@ std::string tune_key(const ptk_ctx *c, int n) {
         ++bins[b];
     }
     char buf[128];
-    snprintf(buf, sizeof buf, "N=%d,J=%d,n=%d,prec=%d,nnz=%lld,I=%lld,hist=", c->s.N,
-             c->s.ranks[n], n, c->opt.precision, (long long)c->nnz,
-             (long long)c->s.dims[n]);
+    snprintf(buf, sizeof buf, "N=%d,J=%d,n=%d,prec=%d,cache=%d,nnz=%lld,I=%lld,hist=",
+             c->s.N, c->s.ranks[n], n, c->opt.precision, cache_role(c, n),
+             (long long)c->nnz, (long long)c->s.dims[n]);
     std::string k = buf;
     for (int b = 0; b < 40; ++b) {
         if (b) k += ':';
@@ -1054,16 +1138,17 @@ extern "C" ptk_status ptk_autotune(ptk_ctx *c, const char *cache_path, int64_t *
             const int64_t base = default_work(c, n);
             const double mult[] = {0.125, 0.25, 0.5, 1.0, 2.0};
             double best_ms = 1e300;
-            HIPCHK(c, permute(c, n));
+            const int role = cache_role(c, n);
+            HIPCHK(c, permute(c, n, role));
             for (double f : mult) {
                 int64_t w = (int64_t)(base * f);
                 w = m.bf16 ? std::max<int64_t>(w, 1) : std::max<int64_t>(round_up(w, kWave), kWave);
                 if ((s = configure_ranges(c, n, w)) != PTK_OK) break;
-                if ((s = systems(c, n)) != PTK_OK) break;          // warm-up
+                if ((s = systems(c, n, role)) != PTK_OK) break;    // warm-up
                 double ms_min = 1e300;
                 for (int rep = 0; rep < 3 && s == PTK_OK; ++rep) {
                     HIPCHK(c, hipEventRecord(e0, c->st));
-                    s = systems(c, n);
+                    s = systems(c, n, role);
                     HIPCHK(c, hipEventRecord(e1, c->st));
                     HIPCHK(c, hipEventSynchronize(e1));
                     float ms = 0.f;

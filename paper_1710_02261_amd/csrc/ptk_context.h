@@ -19,6 +19,7 @@ struct ModeData {
     int32_t *rows = nullptr;
     int32_t *oidx = nullptr;     // [N-1][nnz]
     float *vals = nullptr;
+    int32_t *cmap = nullptr;     // pair-cache reader: own position -> writer's
     int64_t chunk = 0, nchunks = 0;
     int32_t *split = nullptr;    // [nsplit][3]
     int32_t nsplit = 0;
@@ -50,7 +51,7 @@ struct ptk_ctx {
     hipStream_t st = nullptr;
     int device = 0;
     int num_cu = 256;
-    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1};
+    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1, 0};
     int64_t nnz = -1;
     ModeData md[ptk::kMaxN];
     float *core = nullptr;
@@ -62,6 +63,7 @@ struct ptk_ctx {
     int64_t core_cells = 1;
     double *bbuf = nullptr;
     double *part = nullptr;
+    double *pcache = nullptr;    // pair cache [nnz + 1][J][J]
     int64_t part_cap = 0;
     double *red = nullptr;       // [kRedBlocks * (N + 1)] partials + scalars
     double *xsq = nullptr;       // sum of x^2 over Omega (device, 1 double)

@@ -59,6 +59,15 @@ struct GramArgs {
     int64_t chunk;                    // entries per work range (multiple of 64)
     double *bbuf;                     // complete rows
     double *part;                     // [nchunks][2][E]
+    // per-entry partial-product cache (pairs of modes n, p), records of
+    // cache_record_doubles(J) doubles:
+    // writer (mode n): cache[pos][m_p][j_n] = G contracted with all modes but
+    //   n and p, the partner p being the first of the other modes;
+    // reader (mode p): delta_p[m] = sum_j a^(n)_{i_n}[j] cache[cmap[pos]][m][j],
+    //   a^(n) being other-mode slot cslot.
+    double *cache;
+    const int32_t *cmap;
+    int32_t cslot;
 };
 
 // Arguments of the per-entry kernels (predict, error, delta inspection).
@@ -114,10 +123,18 @@ enum Arith { kArithF64 = 0, kArithF32 = 1 };
 // Is there a compiled fast kernel for this (N, J) with equal ranks?
 bool fast_available(int N, int J, Arith ar);
 
+// gp[others][j_n] <- G. The other modes are in ascending order, or, with
+// lead >= 0, lead first and the rest ascending.
 hipError_t launch_permute_core(const float *G, void *gp, const Shape &s, int n,
-                               Arith ar, hipStream_t st);
+                               Arith ar, hipStream_t st, int lead = -1);
 hipError_t launch_gram(const GramArgs &a, const Shape &s, int n, Arith ar,
                        int64_t nchunks, bool fast, hipStream_t st);
+// cache_mode 1 = write the pair cache, 2 = read it (see GramArgs)
+bool cache_available(int N, int J);
+int cache_record_doubles(int J);    // doubles per entry record of the pair cache
+hipError_t launch_gram_cache(const GramArgs &a, const Shape &s, int n, Arith ar,
+                             int64_t nchunks, int cache_mode, hipStream_t st);
+int gram_cache_blocks_per_cu(const Shape &s, int n, Arith ar, int cache_mode);
 int gram_blocks_per_cu(const Shape &s, int n, Arith ar, bool fast);
 hipError_t launch_merge(const double *part, const int32_t *split, int32_t nsplit,
                         int E, double *bbuf, hipStream_t st);
@@ -154,7 +171,13 @@ size_t sort_workspace_bytes(int64_t nnz);
 hipError_t build_mode_csr(const int32_t *idx, const float *val, int64_t nnz,
                           const Shape &s, int n, void *work, int64_t *rowptr,
                           int32_t *rows, int32_t *oidx, float *vals,
-                          hipStream_t st);
+                          hipStream_t st, int32_t *perm_out = nullptr);
+// inv[perm[i]] = i
+hipError_t launch_invert_perm(const int32_t *perm, int64_t nnz, int32_t *inv,
+                              hipStream_t st);
+// out[i] = inv[perm[i]]
+hipError_t launch_compose_perm(const int32_t *inv, const int32_t *perm, int64_t nnz,
+                               int32_t *out, hipStream_t st);
 
 // finalisation (ptk_finalize.hip)
 size_t qr_workspace_bytes(int64_t I, int J);

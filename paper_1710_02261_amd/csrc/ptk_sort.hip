@@ -236,7 +236,7 @@ size_t sort_workspace_bytes(int64_t nnz) {
 hipError_t build_mode_csr(const int32_t *idx, const float *val, int64_t nnz,
                           const Shape &s, int n, void *work, int64_t *rowptr,
                           int32_t *rows, int32_t *oidx, float *vals,
-                          hipStream_t st) {
+                          hipStream_t st, int32_t *perm_out) {
     const int64_t I = s.dims[n];
     if (nnz == 0) {
         hipLaunchKernelGGL(k_rowptr, dim3(1), dim3(64), 0, st, rows, (int64_t)0, I,
@@ -279,6 +279,10 @@ hipError_t build_mode_csr(const int32_t *idx, const float *val, int64_t nnz,
     if ((e = hipMemcpyAsync(rows, kin, nnz * 4, hipMemcpyDeviceToDevice, st)) !=
         hipSuccess)
         return e;
+    if (perm_out &&
+        (e = hipMemcpyAsync(perm_out, vin, nnz * 4, hipMemcpyDeviceToDevice, st)) !=
+            hipSuccess)
+        return e;
     GatherArgs g;
     g.idx = idx;
     g.val = val;
@@ -294,6 +298,45 @@ hipError_t build_mode_csr(const int32_t *idx, const float *val, int64_t nnz,
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rowptr, dim3((unsigned)((nnz + 1 + 255) / 256)), dim3(256),
                        0, st, rows, nnz, I, rowptr);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// permutation helpers (position maps between the groupings of two modes)
+// ---------------------------------------------------------------------------
+__global__ void k_invert_perm(const int32_t *__restrict__ perm, int64_t nnz,
+                              int32_t *__restrict__ inv) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += stride)
+        inv[perm[i]] = (int32_t)i;
+}
+
+__global__ void k_compose_perm(const int32_t *__restrict__ inv,
+                               const int32_t *__restrict__ perm, int64_t nnz,
+                               int32_t *__restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += stride)
+        out[i] = inv[perm[i]];
+}
+
+static unsigned perm_blocks(int64_t nnz) {
+    int64_t b = (nnz + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
+}
+
+hipError_t launch_invert_perm(const int32_t *perm, int64_t nnz, int32_t *inv,
+                              hipStream_t st) {
+    if (nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_invert_perm, dim3(perm_blocks(nnz)), dim3(256), 0, st, perm,
+                       nnz, inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_compose_perm(const int32_t *inv, const int32_t *perm, int64_t nnz,
+                               int32_t *out, hipStream_t st) {
+    if (nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compose_perm, dim3(perm_blocks(nnz)), dim3(256), 0, st, inv,
+                       perm, nnz, out);
     return hipGetLastError();
 }
 
