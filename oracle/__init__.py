@@ -15,6 +15,9 @@ Functions and the passages they follow:
 * ``solve``          -- eq. "rowupdate" as a Cholesky solve.
 * ``update_rows`` / ``update_mode`` -- Alg. 3 for one mode.
 * ``fit``            -- Alg. 2 iterations (factor sweeps + error).
+* ``fit_cached``     -- the same with the Cache variant of Alg. 3 (Sec. 3.3):
+  table Pres, delta by division, rescale after each mode, plain products
+  where a factor element is zero.
 * ``qr`` / ``core_update`` / ``orthogonalize`` -- Alg. 2's final QR and core
   update (Sec. 3.1, n-mode product of Sec. 2.1).
 * ``fold_in``        -- the row update for a new row with the model fixed.
@@ -75,6 +78,8 @@ def _load(path=None):
                                         _ip, _dp, C.c_int, C.c_double]),
         "ora_fit": (C.c_int64, [C.c_int, _lp, _ip, _dp, _dpp, C.c_int64, _ip,
                                 _dp, C.c_double, C.c_int, _dp, _dp]),
+        "ora_fit_cached": (C.c_int64, [C.c_int, _lp, _ip, _dp, _dpp, C.c_int64,
+                                       _ip, _dp, C.c_double, C.c_int, _dp]),
         "ora_qr": (C.c_int, [C.c_int64, C.c_int, _dp, _dp]),
         "ora_core_update": (C.c_int, [C.c_int, _ip, _dp, C.c_int, _dp]),
         "ora_orthogonalize": (C.c_int, [C.c_int, _lp, _ip, _dp, _dpp, _dp]),
@@ -274,6 +279,25 @@ def fit(G, A, idx, val, lam, iters):
     if bad < 0:
         raise RuntimeError("ora_fit failed: %d" % bad)
     return A, L.reshape(iters, N), S
+
+
+def fit_cached(G, A, idx, val, lam, iters):
+    """Alg. 2 iterations with the Cache variant. Returns (factors, SSE per iter)."""
+    lib = _load()
+    G, Gp = _d(G)
+    I, J = _shape(G, A)
+    I, Ip = _l(I)
+    J, Jp = _i(J)
+    A = [np.array(a, dtype=np.float64) for a in A]
+    arr = (_dp * len(A))(*[a.ctypes.data_as(_dp) for a in A])
+    idx, ip = _i(idx)
+    val, vp = _d(val)
+    S = np.zeros(iters)
+    bad = lib.ora_fit_cached(len(J), Ip, Jp, Gp, arr, idx.shape[1], ip, vp, float(lam),
+                             int(iters), S.ctypes.data_as(_dp))
+    if bad < 0:
+        raise RuntimeError("ora_fit_cached failed: %d" % bad)
+    return A, S
 
 
 def qr(A):

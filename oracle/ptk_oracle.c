@@ -450,3 +450,124 @@ int ora_fold_in(int N, const int32_t *J, const double *G,
     free(B); free(c); free(ents);
     return rc;
 }
+
+/*
+ * The Cache variant of Alg. 3 (Sec. 3.3): a table Pres with one value per
+ * (entry alpha, core cell beta), Pres[alpha][beta] = G_beta times the product
+ * over ALL modes k of a^(k)_{i_k beta_k}. The delta of mode n then divides
+ * the n-th factor back out, Pres / a^(n)_{i_n beta_n}, and after mode n is
+ * updated every value is rescaled by new / old of that same factor element.
+ * Where the factor element is exactly zero the division is impossible and
+ * the plain product is formed instead (for delta: G_beta times the product
+ * over k != n; for the rescale: the full product with the new row), as the
+ * paper prescribes for that case. Meant for small cases: |Omega| * |G|
+ * doubles.
+ */
+static double ora_cell_product(int N, const int32_t *J, const double *G,
+                               const double *const *rows, const int *beta,
+                               int64_t s, int skip)
+{
+    double p = G[s];
+    for (int k = 0; k < N; ++k)
+        if (k != skip) p *= rows[k][beta[k]];
+    return p;
+}
+
+/* One mode of the Cache variant: new rows of A^(n) from Pres, then the
+   rescale of Pres. Returns the number of rows whose system was not positive
+   definite (they keep their previous value), or a negative code. */
+static int64_t ora_update_mode_cached(int N, const int64_t *I, const int32_t *J,
+                                      const double *G, double *const *A,
+                                      int64_t nnz, const int32_t *idx,
+                                      const double *val, int n, double lambda,
+                                      double *Pres)
+{
+    const int Jn = J[n];
+    const int64_t In = I[n];
+    const int64_t S = ora_core_cells(N, J);
+    double *anew = (double *)malloc(sizeof(double) * In * Jn);
+    double *B = (double *)calloc((size_t)In * Jn * Jn, sizeof(double));
+    double *c = (double *)calloc((size_t)In * Jn, sizeof(double));
+    double delta[256];
+    if (!anew || !B || !c || Jn > 256) {
+        free(anew); free(B); free(c);
+        return Jn > 256 ? -3 : -2;
+    }
+    const double *rows[ORA_MAX_ORDER];
+    /* B_i and c_i of every row from the deltas of its entries */
+    for (int64_t e = 0; e < nnz; ++e) {
+        ora_rows_of(N, J, (const double *const *)A, idx, nnz, e, rows);
+        const int64_t i = idx[(int64_t)n * nnz + e];
+        int beta[ORA_MAX_ORDER] = {0};
+        for (int j = 0; j < Jn; ++j) delta[j] = 0.0;
+        for (int64_t s = 0; s < S; ++s) {
+            const double an = rows[n][beta[n]];
+            delta[beta[n]] += an != 0.0 ? Pres[e * S + s] / an
+                                        : ora_cell_product(N, J, G, rows, beta, s, n);
+            ora_next_cell(N, J, beta);
+        }
+        for (int p = 0; p < Jn; ++p) {
+            for (int q = 0; q < Jn; ++q) B[(i * Jn + p) * Jn + q] += delta[p] * delta[q];
+            c[i * Jn + p] += val[e] * delta[p];
+        }
+    }
+    int64_t bad = 0;
+    for (int64_t i = 0; i < In; ++i) {
+        double *a = anew + i * Jn;
+        if (ora_solve(Jn, B + i * Jn * Jn, c + i * Jn, lambda, a) != 0) {
+            for (int j = 0; j < Jn; ++j) a[j] = A[n][i * Jn + j];
+            ++bad;
+        }
+    }
+    /* rescale Pres: old -> new value of the n-th factor element */
+    for (int64_t e = 0; e < nnz; ++e) {
+        const int64_t i = idx[(int64_t)n * nnz + e];
+        ora_rows_of(N, J, (const double *const *)A, idx, nnz, e, rows);
+        const double *old_row = rows[n];
+        rows[n] = anew + i * Jn;
+        int beta[ORA_MAX_ORDER] = {0};
+        for (int64_t s = 0; s < S; ++s) {
+            const double ao = old_row[beta[n]];
+            Pres[e * S + s] = ao != 0.0 ? Pres[e * S + s] / ao * rows[n][beta[n]]
+                                        : ora_cell_product(N, J, G, rows, beta, s, -1);
+            ora_next_cell(N, J, beta);
+        }
+    }
+    memcpy(A[n], anew, sizeof(double) * In * Jn);
+    free(anew); free(B); free(c);
+    return bad;
+}
+
+/* Alg. 2 iterations with the Cache variant of Alg. 3: Pres is built once
+   (Alg. 3, before the mode loop) and rescaled after every mode; sse[t] is
+   the sum of squared residuals after iteration t (may be NULL). */
+int64_t ora_fit_cached(int N, const int64_t *I, const int32_t *J, const double *G,
+                       double *const *A, int64_t nnz, const int32_t *idx,
+                       const double *val, double lambda, int iters, double *sse)
+{
+    const int64_t S = ora_core_cells(N, J);
+    double *Pres = (double *)malloc(sizeof(double) * (nnz ? nnz : 1) * S);
+    if (!Pres) return -2;
+    const double *rows[ORA_MAX_ORDER];
+    for (int64_t e = 0; e < nnz; ++e) {
+        ora_rows_of(N, J, (const double *const *)A, idx, nnz, e, rows);
+        int beta[ORA_MAX_ORDER] = {0};
+        for (int64_t s = 0; s < S; ++s) {
+            Pres[e * S + s] = ora_cell_product(N, J, G, rows, beta, s, -1);
+            ora_next_cell(N, J, beta);
+        }
+    }
+    int64_t bad = 0;
+    for (int t = 0; t < iters; ++t) {
+        for (int n = 0; n < N; ++n) {
+            int64_t b = ora_update_mode_cached(N, I, J, G, A, nnz, idx, val, n,
+                                               lambda, Pres);
+            if (b < 0) { free(Pres); return b; }
+            bad += b;
+        }
+        if (sse)
+            sse[t] = ora_sse(N, J, G, (const double *const *)A, nnz, idx, val);
+    }
+    free(Pres);
+    return bad;
+}

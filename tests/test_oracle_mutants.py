@@ -27,6 +27,10 @@ MUTANTS = {
     "core_update_transposed": ("* U[j * J[n] + k];", "* U[k * J[n] + j];"),
     "qr_no_sign_fix": ("if (R[i * Jn + i] < 0.0) {", "if (R[i * Jn + i] < -1e300) {"),
     "back_substitution_index": ("s -= L[k * Jn + i] * a[k];", "s -= L[i * Jn + k] * a[k];"),
+    "cache_no_zero_fallback": ("delta[beta[n]] += an != 0.0 ? Pres[e * S + s] / an",
+                               "delta[beta[n]] += 1 ? Pres[e * S + s] / an"),
+    "cache_no_rescale": ("Pres[e * S + s] / ao * rows[n][beta[n]]",
+                         "Pres[e * S + s]"),
 }
 
 

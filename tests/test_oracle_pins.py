@@ -335,3 +335,37 @@ def test_numerically_singular_row_keeps_previous_value():
         np.testing.assert_array_equal(out[1], A[0][1])
     # rows without entries are still exactly zero
     assert np.all(out[[0, 2, 3]] == 0.0)
+
+
+# --------------------------------------------------------------------------
+# P13: the Cache variant (table Pres, delta by division, rescale after each
+# mode) is the plain update in exact arithmetic, also where a factor element
+# is exactly zero and the variant falls back to the plain product
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dims,ranks", [((6, 5, 4), (2, 3, 4)),
+                                        ((4, 5, 3, 4), (3, 2, 2, 3))])
+def test_cache_variant_equals_plain_sweeps(dims, ranks):
+    rng = np.random.default_rng(sum(ranks))
+    G, A = rand_model(dims, ranks, rng)
+    idx, val = rand_obs(dims, int(0.4 * np.prod(dims)), rng)
+    Ap, _, Sp = oracle.fit(G, A, idx, val, 0.1, 3)
+    Ac, Sc = oracle.fit_cached(G, A, idx, val, 0.1, 3)
+    for a, b in zip(Ac, Ap):
+        np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(Sc, Sp, rtol=1e-9)
+
+
+def test_cache_variant_zero_factor_elements():
+    dims, ranks = (6, 5, 4), (3, 2, 4)
+    rng = np.random.default_rng(77)
+    G, A = rand_model(dims, ranks, rng)
+    for a in A:
+        a[rng.random(a.shape) < 0.35] = 0.0      # divisions by these are impossible
+    A[1][:, 1] = 0.0
+    idx, val = rand_obs(dims, 60, rng)
+    Ap, _, Sp = oracle.fit(G, A, idx, val, 0.1, 2)
+    Ac, Sc = oracle.fit_cached(G, A, idx, val, 0.1, 2)
+    for a, b in zip(Ac, Ap):
+        assert np.all(np.isfinite(a))
+        np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(Sc, Sp, rtol=1e-9)
