@@ -19,23 +19,9 @@
 // one wavefront each. Rows wholly inside a range are written to bbuf; the
 // pieces of rows that cross range boundaries go to two partial slots per
 // range and are merged in range order afterwards (deterministic).
-#include "ptk_internal.h"
+#include "ptk_device.h"
 
 namespace ptk {
-
-template <typename T>
-using cptr = const __attribute__((address_space(4))) T *;
-
-template <typename T>
-__device__ __forceinline__ T fma_t(T a, T b, T c);
-template <>
-__device__ __forceinline__ float fma_t<float>(float a, float b, float c) {
-    return __builtin_fmaf(a, b, c);
-}
-template <>
-__device__ __forceinline__ double fma_t<double>(double a, double b, double c) {
-    return __builtin_fma(a, b, c);
-}
 
 // ---------------------------------------------------------------------------
 // core permutation: gp[others in mode order][j_n] <- G (C order)
@@ -89,81 +75,6 @@ hipError_t launch_permute_core(const float *G, void *gp, const Shape &s, int n,
         hipLaunchKernelGGL(k_permute_core<float>, grid, dim3(256), 0, st, G,
                            (float *)gp, p);
     return hipGetLastError();
-}
-
-// unrolled (VGPR-resident) other modes of the fast kernels
-constexpr int fast_depth(int N, int J) {
-    return (N - 1 <= 1) ? 1 : ((J >= 12) ? 1 : 2);
-}
-
-// ---------------------------------------------------------------------------
-// fast delta: equal ranks J, N-1 other modes, the last U of them unrolled
-// ---------------------------------------------------------------------------
-template <int J, int U, int L, typename T>
-__device__ __forceinline__ void inner_accum(cptr<T> g, T w, const T (&ain)[U][J],
-                                            T (&acc)[J]) {
-    if constexpr (L == U) {
-#pragma unroll
-        for (int j = 0; j < J; ++j) acc[j] = fma_t<T>(g[j], w, acc[j]);
-    } else {
-        constexpr int st = ipow(J, U - L);
-#pragma unroll
-        for (int m = 0; m < J; ++m)
-            inner_accum<J, U, L + 1, T>(g + m * st, w * ain[L][m], ain, acc);
-    }
-}
-
-// aout: lane-private LDS rows of the leading NO-U other modes, [k][j][64].
-template <int NO, int J, int U, typename T>
-__device__ __forceinline__ void delta_fast(const void *gp_raw, const float *aout,
-                                           int lane, const T (&ain)[U][J],
-                                           double (&out)[J]) {
-    constexpr int NOUT = NO - U;
-    constexpr int OUTER = ipow(J, NOUT);
-    constexpr int BLOCK = ipow(J, U) * J;
-    cptr<T> gp = (cptr<T>)gp_raw;
-#pragma unroll
-    for (int j = 0; j < J; ++j) out[j] = 0.0;
-    for (int o = 0; o < OUTER; ++o) {
-        T w = (T)1;
-        int t = o;
-#pragma unroll
-        for (int k = NOUT - 1; k >= 0; --k) {
-            const int d = t % J;
-            t /= J;
-            w *= (T)aout[(k * J + d) * kWave + lane];
-        }
-        if constexpr (sizeof(T) == 8) {
-            inner_accum<J, U, 0, T>(gp + (int64_t)o * BLOCK, w, ain, out);
-        } else {
-            T acc[J];
-#pragma unroll
-            for (int j = 0; j < J; ++j) acc[j] = (T)0;
-            inner_accum<J, U, 0, T>(gp + (int64_t)o * BLOCK, w, ain, acc);
-#pragma unroll
-            for (int j = 0; j < J; ++j) out[j] += (double)acc[j];
-        }
-    }
-}
-
-// Load the other-mode rows of one entry: leading modes to LDS, last U to VGPRs.
-template <int NO, int J, int U, typename T, typename Args>
-__device__ __forceinline__ void load_rows_fast(const Args &a, int64_t pos,
-                                               bool valid, float *aout, int lane,
-                                               T (&ain)[U][J]) {
-    constexpr int NOUT = NO - U;
-#pragma unroll
-    for (int k = 0; k < NO; ++k) {
-        const int32_t i = valid ? a.oidx[k][pos] : 0;
-        const float *r = a.fac[k] + (int64_t)i * J;
-        if (k < NOUT) {
-#pragma unroll
-            for (int j = 0; j < J; ++j) aout[(k * J + j) * kWave + lane] = r[j];
-        } else {
-#pragma unroll
-            for (int j = 0; j < J; ++j) ain[k - NOUT][j] = (T)r[j];
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -224,95 +135,6 @@ __device__ __forceinline__ void delta_generic(const Args &a, const float *arow,
 }
 
 // ---------------------------------------------------------------------------
-// row-system sweep over one tile of deltas in LDS
-// ---------------------------------------------------------------------------
-// s_dl layout: [j][65] doubles, row J holds the values x (stride 65 keeps the
-// per-lane writes and the per-entry reads free of bank conflicts).
-constexpr int kDlStride = kWave + 1;
-
-template <int EPL>
-struct SysLane {
-    int p[EPL], q[EPL];
-    int e[EPL];
-    double acc[EPL];
-
-    __device__ void init(int lane, int J) {
-        const int T = J * (J + 1) / 2;
-        const int E = T + J;
-#pragma unroll
-        for (int t = 0; t < EPL; ++t) {
-            int ee = lane + kWave * t;
-            e[t] = ee < E ? ee : -1;
-            int pp = 0, qq = 0;
-            if (ee < T) {
-                // invert tri_pos: row pp holds J - pp entries
-                int r = ee;
-                while (r >= J - pp) {
-                    r -= J - pp;
-                    ++pp;
-                }
-                qq = pp + r;
-            } else if (ee < E) {
-                pp = ee - T;
-                qq = J;      // the value row
-            }
-            p[t] = pp;
-            q[t] = qq;
-            acc[t] = 0.0;
-        }
-    }
-    __device__ __forceinline__ void zero() {
-#pragma unroll
-        for (int t = 0; t < EPL; ++t) acc[t] = 0.0;
-    }
-    __device__ __forceinline__ void add(const double *s_dl, int b) {
-#pragma unroll
-        for (int t = 0; t < EPL; ++t)
-            if (e[t] >= 0)
-                acc[t] = __builtin_fma(s_dl[p[t] * kDlStride + b],
-                                       s_dl[q[t] * kDlStride + b], acc[t]);
-    }
-    __device__ __forceinline__ void store(double *dst) const {
-#pragma unroll
-        for (int t = 0; t < EPL; ++t)
-            if (e[t] >= 0) dst[e[t]] = acc[t];
-    }
-};
-
-template <int EPL>
-__device__ __forceinline__ void flush_row(const GramArgs &a, SysLane<EPL> &sl,
-                                          int cur, int64_t chunk, int64_t cs,
-                                          int64_t ce) {
-    if (cur == a.skip_row) return;     // padding entries of a request batch
-    const int64_t r0 = a.rowptr[cur], r1 = a.rowptr[cur + 1];
-    double *dst;
-    if (r0 < cs)
-        dst = a.part + (chunk * 2 + 0) * a.E;
-    else if (r1 > ce)
-        dst = a.part + (chunk * 2 + 1) * a.E;
-    else
-        dst = a.bbuf + (int64_t)cur * a.E;
-    sl.store(dst);
-}
-
-// Sweep the nb deltas of a tile into the open row systems.
-template <int EPL>
-__device__ __forceinline__ void sweep_tile(const GramArgs &a, SysLane<EPL> &sl,
-                                           const double *s_dl, const int *s_row,
-                                           int nb, int &cur, int64_t chunk,
-                                           int64_t cs, int64_t ce) {
-    for (int b = 0; b < nb; ++b) {
-        const int r = __builtin_amdgcn_readfirstlane(s_row[b]);
-        if (r != cur) {
-            if (cur >= 0) flush_row<EPL>(a, sl, cur, chunk, cs, ce);
-            cur = r;
-            sl.zero();
-        }
-        sl.add(s_dl, b);
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Gram kernels
 // ---------------------------------------------------------------------------
 template <int N, int J, int U, typename T>
@@ -349,213 +171,6 @@ __global__ __launch_bounds__(kWave) void k_gram_fast(GramArgs a) {
         double d[J];
         delta_fast<NO, J, U, T>(a.gp, s_aout, lane, ain, d);
         __syncthreads();
-#pragma unroll
-        for (int j = 0; j < J; ++j) s_dl[j * kDlStride + lane] = d[j];
-        s_dl[J * kDlStride + lane] = (double)x;
-        s_row[lane] = row;
-        __syncthreads();
-        sweep_tile<EPL>(a, sl, s_dl, s_row, nb, cur, chunk, cs, ce);
-        __syncthreads();
-    }
-    if (cur >= 0) flush_row<EPL>(a, sl, cur, chunk, cs, ce);
-}
-
-// ---------------------------------------------------------------------------
-// pair cache: writer and reader kernels
-// ---------------------------------------------------------------------------
-// One record per entry: T[m_p][j_n] (J*J doubles, padded to an even count so
-// that records are 16-byte aligned), i.e. G contracted with the rows of every
-// mode except n (the writer) and its partner p.
-constexpr int cache_record(int J) { return (J * J + 1) / 2 * 2; }
-
-// Writer delta: the partner p is the leading other mode (outer loop over
-// m_p), then NO-1-U runtime levels, then U unrolled levels. The sum over all
-// but the partner, for one m_p, is T[m_p][:]; it is stored, and weighted by
-// a^(p)[m_p] into delta.
-template <int NO, int J, int U, typename T>
-__device__ __forceinline__ void delta_fast_store(const void *gp_raw, const float *aout,
-                                                 const float *ones, int lane,
-                                                 const T (&ain)[U][J],
-                                                 double (&out)[J], double *tdst) {
-    constexpr int NMID = NO - 1 - U;
-    constexpr int MID = ipow(J, NMID);
-    constexpr int BLOCK = ipow(J, U) * J;
-    cptr<T> gp = (cptr<T>)gp_raw;
-#pragma unroll
-    for (int j = 0; j < J; ++j) out[j] = 0.0;
-#pragma unroll 1
-    for (int o = 0; o < J; ++o) {
-        T acc[J];
-#pragma unroll
-        for (int j = 0; j < J; ++j) acc[j] = (T)0;
-#pragma unroll 1
-        for (int mo = 0; mo < MID; ++mo) {
-            // unit weight read from LDS at index o: the J^U inner weight
-            // products (the same for every o when NMID = 0) are then not
-            // hoisted out of the loop into registers
-            T w = (T)ones[o];
-            int t = mo;
-#pragma unroll
-            for (int k = NMID; k >= 1; --k) {
-                const int d = t % J;
-                t /= J;
-                w *= (T)aout[(k * J + d) * kWave + lane];
-            }
-            inner_accum<J, U, 0, T>(gp + ((int64_t)o * MID + mo) * BLOCK, w, ain, acc);
-        }
-        const double wp = (double)aout[o * kWave + lane];
-        // unconditional store (no lane branch inside the loop: a branch here
-        // forces the scalar-loaded core values to be spilled)
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            tdst[o * J + j] = (double)acc[j];
-            out[j] = __builtin_fma(wp, (double)acc[j], out[j]);
-        }
-    }
-}
-
-constexpr int cache_depth(int N, int J) {
-    return fast_depth(N, J) < N - 2 ? fast_depth(N, J) : N - 2;
-}
-
-template <int N, int J, typename T>
-__global__ __launch_bounds__(kWave) void k_gram_cache_write(GramArgs a) {
-    constexpr int NO = N - 1;
-    constexpr int U = cache_depth(N, J);
-    constexpr int NOUT = NO - U;
-    constexpr int RS = cache_record(J);
-    constexpr int E = sys_entries(J);
-    constexpr int EPL = (E + kWave - 1) / kWave;
-    constexpr int AOUT = NOUT * J * kWave;                         // floats
-    constexpr int DL = (J + 1) * kDlStride;                        // doubles
-    constexpr int LDS_BYTES = (AOUT * 4 > DL * 8) ? AOUT * 4 : DL * 8;
-    __shared__ __attribute__((aligned(16))) unsigned char s_raw[LDS_BYTES];
-    __shared__ int s_row[kWave];
-    __shared__ float s_ones[J];
-    float *s_aout = (float *)s_raw;
-    double *s_dl = (double *)s_raw;
-    const int lane = threadIdx.x;
-    const int64_t chunk = blockIdx.x;
-    const int64_t cs = chunk * a.chunk;
-    const int64_t ce = min(cs + a.chunk, a.nnz);
-    if (lane < J) s_ones[lane] = 1.0f;
-    SysLane<EPL> sl;
-    sl.init(lane, J);
-    int cur = -1;
-    for (int64_t base = cs; base < ce; base += kWave) {
-        const int64_t pos = base + lane;
-        const bool valid = pos < ce;
-        const int nb = (int)min((int64_t)kWave, ce - base);
-        const int row = valid ? a.rows[pos] : 0;
-        const float x = valid ? a.val[pos] : 0.0f;
-        T ain[U][J];
-        load_rows_fast<NO, J, U, T>(a, pos, valid, s_aout, lane, ain);
-        __syncthreads();
-        double d[J];
-        // lanes past the range write the spare record at index nnz
-        delta_fast_store<NO, J, U, T>(a.gp, s_aout, s_ones, lane, ain, d,
-                                      a.cache + (valid ? pos : a.nnz) * RS);
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < J; ++j) s_dl[j * kDlStride + lane] = d[j];
-        s_dl[J * kDlStride + lane] = (double)x;
-        s_row[lane] = row;
-        __syncthreads();
-        sweep_tile<EPL>(a, sl, s_dl, s_row, nb, cur, chunk, cs, ce);
-        __syncthreads();
-    }
-    if (cur >= 0) flush_row<EPL>(a, sl, cur, chunk, cs, ce);
-}
-
-// Reader: delta^(p)[m] = sum_j a^(n)_{i_n}[j] T[m][j] with T written by the
-// partner's update (same sweep, so the other modes have not changed since).
-// Records sit at random writer positions: the wavefront loads them whole,
-// one record per load instruction (full cache lines), eight in flight, into
-// LDS, NR records per pass; each lane then reads its own record from LDS.
-constexpr int cache_pass_records(int J) {
-    return (64 * (cache_record(J) + 1) * 8 <= 32768)   ? 64
-           : (32 * (cache_record(J) + 1) * 8 <= 32768) ? 32
-           : (16 * (cache_record(J) + 1) * 8 <= 32768) ? 16
-                                                       : 8;
-}
-
-template <int J>
-__global__ __launch_bounds__(kWave) void k_gram_cache_read(GramArgs a) {
-    constexpr int E = sys_entries(J);
-    constexpr int EPL = (E + kWave - 1) / kWave;
-    constexpr int RS = cache_record(J);
-    constexpr int S = RS + 1;                 // odd LDS stride (in doubles)
-    constexpr int NP = RS / 2;                // 16-byte pieces of a record
-    constexpr int NR = cache_pass_records(J);
-    __shared__ double s_dl[(J + 1) * kDlStride];
-    __shared__ int s_row[kWave];
-    __shared__ double s_t[NR * S];
-    const int lane = threadIdx.x;
-    const int64_t chunk = blockIdx.x;
-    const int64_t cs = chunk * a.chunk;
-    const int64_t ce = min(cs + a.chunk, a.nnz);
-    SysLane<EPL> sl;
-    sl.init(lane, J);
-    int cur = -1;
-    for (int64_t base = cs; base < ce; base += kWave) {
-        const int64_t pos = base + lane;
-        const bool valid = pos < ce;
-        const int nb = (int)min((int64_t)kWave, ce - base);
-        const int row = valid ? a.rows[pos] : 0;
-        const float x = valid ? a.val[pos] : 0.0f;
-        const int32_t q = valid ? a.cmap[pos] : 0;
-        double av[J];
-        {
-            const int32_t in = valid ? a.oidx[a.cslot][pos] : 0;
-            const float *an = a.fac[a.cslot] + (int64_t)in * J;
-#pragma unroll
-            for (int j = 0; j < J; ++j) av[j] = valid ? (double)an[j] : 0.0;
-        }
-        double d[J];
-#pragma unroll
-        for (int m = 0; m < J; ++m) d[m] = 0.0;
-        for (int h = 0; h < kWave; h += NR) {
-            if (h >= nb) break;                            // wave-uniform
-            for (int e0 = 0; e0 < NR; e0 += 8) {
-                double2 v[8][(NP + kWave - 1) / kWave];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int e = h + e0 + u;
-                    const int64_t qe = __shfl(q, e);
-#pragma unroll
-                    for (int r = 0; r < (NP + kWave - 1) / kWave; ++r) {
-                        const int k = lane + r * kWave;
-                        v[u][r] = make_double2(0.0, 0.0);
-                        if (e < nb && k < NP)
-                            v[u][r] = *(const double2 *)(a.cache + qe * RS + 2 * k);
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-#pragma unroll
-                    for (int r = 0; r < (NP + kWave - 1) / kWave; ++r) {
-                        const int k = lane + r * kWave;
-                        if (k < NP) {
-                            s_t[(e0 + u) * S + 2 * k] = v[u][r].x;
-                            s_t[(e0 + u) * S + 2 * k + 1] = v[u][r].y;
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-            const int me = lane - h;
-            if (me >= 0 && me < NR && valid) {
-                const double *t = s_t + me * S;
-#pragma unroll
-                for (int m = 0; m < J; ++m) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int j = 0; j < J; ++j) acc = __builtin_fma(av[j], t[m * J + j], acc);
-                    d[m] = acc;
-                }
-            }
-            __syncthreads();
-        }
 #pragma unroll
         for (int j = 0; j < J; ++j) s_dl[j * kDlStride + lane] = d[j];
         s_dl[J * kDlStride + lane] = (double)x;
@@ -720,15 +335,6 @@ static int generic_jmax(int jn) {
     return jn <= 4 ? 4 : jn <= 8 ? 8 : jn <= 16 ? 16 : 32;
 }
 
-template <typename K>
-static int blocks_per_cu(K kernel, size_t dyn) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kWave, dyn) !=
-        hipSuccess)
-        return 8;
-    return nb > 0 ? nb : 1;
-}
-
 int gram_blocks_per_cu(const Shape &s, int n, Arith ar, bool fast) {
     const int J = s.ranks[n];
     if (fast) {
@@ -794,73 +400,6 @@ hipError_t launch_gram(const GramArgs &a, const Shape &s, int n, Arith ar,
             break;
     }
     return hipGetLastError();
-}
-
-#define PTK_CACHE_SHAPES(X) \
-    X(3, 3) X(3, 4) X(3, 5) X(3, 8) X(3, 10) X(3, 16) \
-    X(4, 3) X(4, 5) X(4, 8) X(4, 10) \
-    X(5, 3) X(5, 5) X(5, 8)
-
-int cache_record_doubles(int J) { return cache_record(J); }
-
-bool cache_available(int N, int J) {
-#define PTK_X(n_, j_) if (N == n_ && J == j_) return true;
-    PTK_CACHE_SHAPES(PTK_X)
-#undef PTK_X
-    return false;
-}
-
-int gram_cache_blocks_per_cu(const Shape &s, int n, Arith ar, int cm) {
-    const int J = s.ranks[n];
-    if (cm == 2) {
-        switch (J) {
-            case 3: return blocks_per_cu(k_gram_cache_read<3>, 0);
-            case 4: return blocks_per_cu(k_gram_cache_read<4>, 0);
-            case 5: return blocks_per_cu(k_gram_cache_read<5>, 0);
-            case 8: return blocks_per_cu(k_gram_cache_read<8>, 0);
-            case 10: return blocks_per_cu(k_gram_cache_read<10>, 0);
-            default: return blocks_per_cu(k_gram_cache_read<16>, 0);
-        }
-    }
-#define PTK_X(n_, j_)                                                             \
-    if (s.N == n_ && J == j_)                                                     \
-        return ar == kArithF64 ? blocks_per_cu(k_gram_cache_write<n_, j_, double>, 0) \
-                               : blocks_per_cu(k_gram_cache_write<n_, j_, float>, 0);
-    PTK_CACHE_SHAPES(PTK_X)
-#undef PTK_X
-    return 1;
-}
-
-hipError_t launch_gram_cache(const GramArgs &a, const Shape &s, int n, Arith ar,
-                             int64_t nchunks, int cm, hipStream_t st) {
-    if (nchunks <= 0) return hipSuccess;
-    dim3 grid((unsigned)nchunks), block(kWave);
-    const int J = s.ranks[n];
-    if (cm == 2) {
-        switch (J) {
-            case 3: hipLaunchKernelGGL(k_gram_cache_read<3>, grid, block, 0, st, a); break;
-            case 4: hipLaunchKernelGGL(k_gram_cache_read<4>, grid, block, 0, st, a); break;
-            case 5: hipLaunchKernelGGL(k_gram_cache_read<5>, grid, block, 0, st, a); break;
-            case 8: hipLaunchKernelGGL(k_gram_cache_read<8>, grid, block, 0, st, a); break;
-            case 10: hipLaunchKernelGGL(k_gram_cache_read<10>, grid, block, 0, st, a); break;
-            case 16: hipLaunchKernelGGL(k_gram_cache_read<16>, grid, block, 0, st, a); break;
-            default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
-#define PTK_X(n_, j_)                                                                \
-    if (s.N == n_ && J == j_) {                                                      \
-        if (ar == kArithF64)                                                         \
-            hipLaunchKernelGGL((k_gram_cache_write<n_, j_, double>), grid, block, 0,  \
-                               st, a);                                              \
-        else                                                                         \
-            hipLaunchKernelGGL((k_gram_cache_write<n_, j_, float>), grid, block, 0,   \
-                               st, a);                                              \
-        return hipGetLastError();                                                    \
-    }
-    PTK_CACHE_SHAPES(PTK_X)
-#undef PTK_X
-    return hipErrorInvalidValue;
 }
 
 hipError_t launch_entries(const EntryArgs &a, const Shape &s, int n, int kind,
