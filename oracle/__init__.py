@@ -15,6 +15,9 @@ Functions and the passages they follow:
 * ``solve``          -- eq. "rowupdate" as a Cholesky solve.
 * ``update_rows`` / ``update_mode`` -- Alg. 3 for one mode.
 * ``fit``            -- Alg. 2 iterations (factor sweeps + error).
+* ``partial_error`` / ``truncate`` / ``fit_approx`` -- the Approx variant
+  (Alg. 4, eq. "recon_partial"): per-cell partial reconstruction error,
+  removal of the top floor(p |G|) cells, Alg. 2 with the removal.
 * ``fit_cached``     -- the same with the Cache variant of Alg. 3 (Sec. 3.3):
   table Pres, delta by division, rescale after each mode, plain products
   where a factor element is zero.
@@ -80,6 +83,12 @@ def _load(path=None):
                                 _dp, C.c_double, C.c_int, _dp, _dp]),
         "ora_fit_cached": (C.c_int64, [C.c_int, _lp, _ip, _dp, _dpp, C.c_int64,
                                        _ip, _dp, C.c_double, C.c_int, _dp]),
+        "ora_partial_error": (C.c_int, [C.c_int, _ip, _dp, _dpp, C.c_int64, _ip,
+                                        _dp, _dp]),
+        "ora_truncate": (C.c_int64, [C.c_int, _ip, _dp, _dp, C.c_double]),
+        "ora_fit_approx": (C.c_int64, [C.c_int, _lp, _ip, _dp, _dpp, C.c_int64,
+                                       _ip, _dp, C.c_double, C.c_int, C.c_double,
+                                       _dp, _lp]),
         "ora_qr": (C.c_int, [C.c_int64, C.c_int, _dp, _dp]),
         "ora_core_update": (C.c_int, [C.c_int, _ip, _dp, C.c_int, _dp]),
         "ora_orthogonalize": (C.c_int, [C.c_int, _lp, _ip, _dp, _dpp, _dp]),
@@ -298,6 +307,58 @@ def fit_cached(G, A, idx, val, lam, iters):
     if bad < 0:
         raise RuntimeError("ora_fit_cached failed: %d" % bad)
     return A, S
+
+
+def partial_error(G, A, idx, val):
+    """R(beta) of eq. "recon_partial" for every core cell (shape of G)."""
+    lib = _load()
+    G, Gp = _d(G)
+    I, J = _shape(G, A)
+    J, Jp = _i(J)
+    A = [np.ascontiguousarray(a, dtype=np.float64) for a in A]
+    arr = (_dp * len(A))(*[a.ctypes.data_as(_dp) for a in A])
+    idx, ip = _i(idx)
+    val, vp = _d(val)
+    R = np.zeros(G.shape)
+    rc = lib.ora_partial_error(len(J), Jp, Gp, arr, idx.shape[1], ip, vp,
+                               R.ctypes.data_as(_dp))
+    if rc:
+        raise RuntimeError("ora_partial_error failed: %d" % rc)
+    return R
+
+
+def truncate(G, R, p):
+    """Alg. 4's removal on a copy of G. Returns (G', number removed)."""
+    lib = _load()
+    G = np.array(G, dtype=np.float64)
+    J, Jp = _i(np.array(G.shape))
+    R, Rp = _d(R)
+    k = lib.ora_truncate(len(J), Jp, G.ctypes.data_as(_dp), Rp, float(p))
+    if k < 0:
+        raise RuntimeError("ora_truncate failed: %d" % k)
+    return G, int(k)
+
+
+def fit_approx(G, A, idx, val, lam, iters, p):
+    """Alg. 2 with Alg. 4 each iteration. Returns (G, factors, SSE per iter
+    (before the removal), non-zero core cells left after each iteration)."""
+    lib = _load()
+    G = np.array(G, dtype=np.float64)
+    I, J = _shape(G, A)
+    I, Ip = _l(I)
+    J, Jp = _i(J)
+    A = [np.array(a, dtype=np.float64) for a in A]
+    arr = (_dp * len(A))(*[a.ctypes.data_as(_dp) for a in A])
+    idx, ip = _i(idx)
+    val, vp = _d(val)
+    S = np.zeros(iters)
+    C_ = np.zeros(iters, dtype=np.int64)
+    bad = lib.ora_fit_approx(len(J), Ip, Jp, G.ctypes.data_as(_dp), arr, idx.shape[1],
+                             ip, vp, float(lam), int(iters), float(p),
+                             S.ctypes.data_as(_dp), C_.ctypes.data_as(_lp))
+    if bad < 0:
+        raise RuntimeError("ora_fit_approx failed: %d" % bad)
+    return G, A, S, C_
 
 
 def qr(A):

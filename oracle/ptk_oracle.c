@@ -571,3 +571,104 @@ int64_t ora_fit_cached(int N, const int64_t *I, const int32_t *J, const double *
     free(Pres);
     return bad;
 }
+
+/*
+ * The Approx variant (Alg. 4, Sec. 3.3): the partial reconstruction error of
+ * every core cell beta (eq. "recon_partial", first form): the sum over the
+ * observed entries of the squared residual of the model minus the squared
+ * residual of the model without the cell's term,
+ *     R(beta) = sum_alpha (x - xhat)^2 - (x - (xhat - t))^2,
+ *     t = G_beta prod_n a^(n)_{i_n beta_n}.
+ * A high R(beta) means that removing the cell lowers the error.
+ */
+int ora_partial_error(int N, const int32_t *J, const double *G,
+                      const double *const *A, int64_t nnz, const int32_t *idx,
+                      const double *val, double *R)
+{
+    const int64_t S = ora_core_cells(N, J);
+    double *xhat = (double *)malloc(sizeof(double) * (nnz ? nnz : 1));
+    if (!xhat) return -2;
+    const double *rows[ORA_MAX_ORDER];
+    for (int64_t e = 0; e < nnz; ++e) {
+        ora_rows_of(N, J, A, idx, nnz, e, rows);
+        xhat[e] = ora_predict_one(N, J, G, rows);
+    }
+    int beta[ORA_MAX_ORDER] = {0};
+    for (int64_t s = 0; s < S; ++s) {
+        double r = 0.0;
+        for (int64_t e = 0; e < nnz; ++e) {
+            ora_rows_of(N, J, A, idx, nnz, e, rows);
+            const double t = ora_cell_product(N, J, G, rows, beta, s, -1);
+            const double with = val[e] - xhat[e];
+            const double without = val[e] - (xhat[e] - t);
+            r += with * with - without * without;
+        }
+        R[s] = r;
+        ora_next_cell(N, J, beta);
+    }
+    free(xhat);
+    return 0;
+}
+
+/*
+ * Alg. 4's removal: among the cells of G that are not zero (the entries of
+ * the core), the floor(p * count) cells with the largest R(beta) are set to
+ * zero; equal R values are taken in increasing cell order. Returns the
+ * number of cells removed.
+ */
+static const double *ora_sort_R;
+static int ora_cmp_desc(const void *pa, const void *pb)
+{
+    const int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
+    if (ora_sort_R[a] > ora_sort_R[b]) return -1;
+    if (ora_sort_R[a] < ora_sort_R[b]) return 1;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+int64_t ora_truncate(int N, const int32_t *J, double *G, const double *R, double p)
+{
+    const int64_t S = ora_core_cells(N, J);
+    int64_t *cells = (int64_t *)malloc(sizeof(int64_t) * S);
+    if (!cells) return -2;
+    int64_t nz = 0;
+    for (int64_t s = 0; s < S; ++s)
+        if (G[s] != 0.0) cells[nz++] = s;
+    const int64_t k = (int64_t)floor(p * (double)nz);
+    ora_sort_R = R;
+    qsort(cells, (size_t)nz, sizeof(int64_t), ora_cmp_desc);
+    for (int64_t t = 0; t < k; ++t) G[cells[t]] = 0.0;
+    free(cells);
+    return k;
+}
+
+/* Alg. 2 with the Approx variant: each iteration updates the factors (Alg. 3),
+   measures the error (sse[t], before the removal) and removes cells of G by
+   Alg. 4 (core_nnz[t] = non-zero cells left). G is updated in place. */
+int64_t ora_fit_approx(int N, const int64_t *I, const int32_t *J, double *G,
+                       double *const *A, int64_t nnz, const int32_t *idx,
+                       const double *val, double lambda, int iters, double p,
+                       double *sse, int64_t *core_nnz)
+{
+    const int64_t S = ora_core_cells(N, J);
+    double *R = (double *)malloc(sizeof(double) * S);
+    if (!R) return -2;
+    int64_t bad = 0;
+    for (int t = 0; t < iters; ++t) {
+        for (int n = 0; n < N; ++n) {
+            int64_t b = ora_update_mode(N, I, J, G, A, nnz, idx, val, n, lambda);
+            if (b < 0) { free(R); return b; }
+            bad += b;
+        }
+        if (sse) sse[t] = ora_sse(N, J, G, (const double *const *)A, nnz, idx, val);
+        int rc = ora_partial_error(N, J, G, (const double *const *)A, nnz, idx, val, R);
+        if (rc) { free(R); return rc; }
+        if (ora_truncate(N, J, G, R, p) < 0) { free(R); return -2; }
+        if (core_nnz) {
+            int64_t c = 0;
+            for (int64_t s = 0; s < S; ++s) c += G[s] != 0.0;
+            core_nnz[t] = c;
+        }
+    }
+    free(R);
+    return bad;
+}

@@ -31,6 +31,11 @@ MUTANTS = {
                                "delta[beta[n]] += 1 ? Pres[e * S + s] / an"),
     "cache_no_rescale": ("Pres[e * S + s] / ao * rows[n][beta[n]]",
                          "Pres[e * S + s]"),
+    "approx_error_sign": ("r += with * with - without * without;",
+                          "r += without * without - with * with;"),
+    "approx_count_ceil": ("(int64_t)floor(p * (double)nz)", "(int64_t)ceil(p * (double)nz)"),
+    "approx_ties_reversed": ("return a < b ? -1 : (a > b ? 1 : 0);",
+                             "return a > b ? -1 : (a < b ? 1 : 0);"),
 }
 
 

@@ -369,3 +369,83 @@ def test_cache_variant_zero_factor_elements():
         assert np.all(np.isfinite(a))
         np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-12)
     np.testing.assert_allclose(Sc, Sp, rtol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# P14: the Approx variant (Alg. 4). R(beta) is the drop of the SSE when the
+# cell is removed: checked against dense reconstructions of the model with
+# and without each cell. The removal takes the top floor(p |G|) cells.
+# --------------------------------------------------------------------------
+def _dense_sse(G, A, idx, val):
+    X = D.full_tensor(G, A)
+    return float(np.sum((val - X[tuple(idx)]) ** 2))
+
+
+@pytest.mark.parametrize("dims,ranks", [((5, 4, 6), (2, 3, 2)), ((4, 3, 3, 4), (2, 2, 3, 2))])
+def test_partial_error_is_sse_drop_without_the_cell(dims, ranks):
+    rng = np.random.default_rng(len(dims) + 30)
+    G, A = rand_model(dims, ranks, rng)
+    idx, val = rand_obs(dims, int(0.5 * np.prod(dims)), rng)
+    R = oracle.partial_error(G, A, idx, val)
+    base = _dense_sse(G, A, idx, val)
+    for cell in itertools.product(*[range(r) for r in ranks]):
+        G2 = G.copy()
+        G2[cell] = 0.0
+        np.testing.assert_allclose(R[cell], base - _dense_sse(G2, A, idx, val),
+                                   rtol=1e-9, atol=1e-9 * base)
+
+
+def test_truncate_removes_top_cells_with_index_ties():
+    rng = np.random.default_rng(41)
+    G = rng.standard_normal((3, 4, 5))
+    G[0, 1, 2] = 0.0                                  # not an entry of the core
+    R = rng.standard_normal(G.shape)
+    R[2, 0, 1], R[1, 2, 3], R[0, 3, 3] = 20.0, 21.0, 22.0
+    R[2, 3, 4] = R[1, 1, 1] = R[0, 0, 0] = R[2, 2, 2] = 10.0   # four-way tie
+    R[0, 1, 2] = 100.0                                # largest, but already zero
+    G2, k = oracle.truncate(G, R, 0.1)
+    nz = int(np.count_nonzero(G))
+    assert k == int(np.floor(0.1 * nz)) == 5
+    order = sorted((c for c in np.ndindex(G.shape) if G[c] != 0.0),
+                   key=lambda c: (-R[c], np.ravel_multi_index(c, G.shape)))
+    removed = set(order[:k])
+    for c in np.ndindex(G.shape):
+        assert G2[c] == (0.0 if (c in removed or G[c] == 0.0) else G[c])
+    # the cut falls inside the tie: the two lowest cell indices go
+    assert {(0, 0, 0), (1, 1, 1)} <= removed
+    assert G2[2, 2, 2] != 0.0 and G2[2, 3, 4] != 0.0
+
+
+def test_fit_approx_removal_schedule_and_errors():
+    dims, ranks = (6, 5, 4), (3, 2, 3)
+    rng = np.random.default_rng(43)
+    G, A = rand_model(dims, ranks, rng)
+    idx, val = rand_obs(dims, 70, rng)
+    Gt, At, S, C = oracle.fit_approx(G, A, idx, val, 0.1, 4, 0.2)
+    n = G.size
+    for t in range(4):
+        n -= int(np.floor(0.2 * n))
+        assert C[t] == n
+    assert np.count_nonzero(Gt) == C[-1]
+    # replay: each iteration's SSE is that of the plain sweep from the
+    # previous state, before the removal
+    Gr, Ar = G.copy(), [a.copy() for a in A]
+    for t in range(4):
+        Ar, _, s = oracle.fit(Gr, Ar, idx, val, 0.1, 1)
+        np.testing.assert_allclose(S[t], s[0], rtol=1e-12)
+        R = oracle.partial_error(Gr, Ar, idx, val)
+        Gr, _ = oracle.truncate(Gr, R, 0.2)
+    np.testing.assert_array_equal(Gr, Gt)
+
+
+def test_fit_approx_with_no_removal_is_plain_fit():
+    dims, ranks = (5, 6, 4), (2, 3, 2)
+    rng = np.random.default_rng(44)
+    G, A = rand_model(dims, ranks, rng)
+    idx, val = rand_obs(dims, 50, rng)
+    Gt, At, S, C = oracle.fit_approx(G, A, idx, val, 0.1, 3, 0.01)   # floor(0.12) = 0
+    Ap, _, Sp = oracle.fit(G, A, idx, val, 0.1, 3)
+    np.testing.assert_array_equal(Gt, G)
+    for a, b in zip(At, Ap):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(S, Sp)
