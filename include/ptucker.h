@@ -82,6 +82,18 @@ typedef struct ptk_options {
                                (PTK_E_NOMEM from ptk_set_observed). Chosen
                                before ptk_set_observed. ptk_update_mode,
                                ptk_row_systems and fold-in never use it.      */
+    double approx_rate;     /* p of the Approx variant (Alg. 4, Sec. 3.3),
+                               0 <= p < 1; 0 turns it off. After the error of
+                               every ptk_iterate iteration, the floor(p * nz)
+                               non-zero cells of the core with the largest
+                               partial reconstruction error (eq.
+                               "recon_partial") are set to zero in the bound
+                               core (nz = its non-zero cells; equal values in
+                               increasing cell order). The error and loss
+                               reported for the iteration are those before the
+                               removal. Equal ranks and (N, J) in {3} x
+                               {3,4,5,8,10,16}, {4} x {3,5,8,10} or {5} x
+                               {3,5,8} (else PTK_E_UNSUPPORTED).             */
 } ptk_options;
 
 /*
@@ -221,6 +233,19 @@ ptk_status ptk_delta(ptk_ctx *ctx, int32_t n, int64_t m, const int32_t *idx,
                      float *out);
 ptk_status ptk_row_systems(ptk_ctx *ctx, int32_t n, double *B_out,
                            double *c_out);
+
+/*
+ * Approx variant (Alg. 4, Sec. 3.3) on the bound model, outside ptk_iterate.
+ * ptk_partial_error: R(beta) of eq. "recon_partial" for every core cell,
+ * R_out [J_1]...[J_N] float64 device (C order), 0 for cells that are zero in
+ * the core. ptk_truncate: one removal with rate p (0 <= p < 1) as in
+ * ptk_options.approx_rate, applied to the bound core; *removed_host receives
+ * the number of cells set to zero. Both synchronise the stream. Errors:
+ * PTK_E_INVALID, PTK_E_STATE (no observed set or model), PTK_E_UNSUPPORTED
+ * (shape without the Approx kernels).
+ */
+ptk_status ptk_partial_error(ptk_ctx *ctx, double *R_out);
+ptk_status ptk_truncate(ptk_ctx *ctx, double p, int32_t *removed_host);
 
 /*
  * Per-kernel timing collected while options.profile = 1: for each kernel

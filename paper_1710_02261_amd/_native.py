@@ -27,7 +27,8 @@ _dbl = C.c_double
 
 class _Options(C.Structure):
     _fields_ = [("precision", _i32), ("chunk_nnz", _i32), ("fuse_error", _i32),
-                ("profile", _i32), ("use_graph", _i32), ("pair_cache", _i32)]
+                ("profile", _i32), ("use_graph", _i32), ("pair_cache", _i32),
+                ("approx_rate", _dbl)]
 
 
 class PtkError(RuntimeError):
@@ -70,6 +71,8 @@ def load_library():
         "ptk_reset_timers": [_vp],
         "ptk_not_pd_count": [_vp, C.POINTER(_i64)],
         "ptk_autotune": [_vp, C.c_char_p, C.POINTER(_i64)],
+        "ptk_partial_error": [_vp, _vp],
+        "ptk_truncate": [_vp, _dbl, C.POINTER(_i32)],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -145,8 +148,9 @@ class Context:
 
     # -- C ABI calls ---------------------------------------------------------
     def set_options(self, precision=PREC_FP64_ACC, chunk_nnz=0, fuse_error=1,
-                    profile=0, use_graph=1, pair_cache=0):
-        o = _Options(precision, chunk_nnz, fuse_error, profile, use_graph, pair_cache)
+                    profile=0, use_graph=1, pair_cache=0, approx_rate=0.0):
+        o = _Options(precision, chunk_nnz, fuse_error, profile, use_graph, pair_cache,
+                     float(approx_rate))
         self._check(self._lib.ptk_set_options(self._h, C.byref(o)))
 
     def set_observed(self, idx, val):
@@ -252,6 +256,20 @@ class Context:
                                               _dev_ptr(B, torch.float64, "B"),
                                               _dev_ptr(c, torch.float64, "c")))
         return B, c
+
+    def partial_error(self):
+        """R(beta) of eq. "recon_partial" for every core cell (float64, device)."""
+        torch = _torch()
+        dev = self._keep[0].device
+        R = torch.empty(self.ranks, dtype=torch.float64, device=dev)
+        self._check(self._lib.ptk_partial_error(self._h, _dev_ptr(R, torch.float64, "R")))
+        return R
+
+    def truncate(self, p):
+        """One removal of Alg. 4 on the bound core; returns the cells removed."""
+        k = _i32(0)
+        self._check(self._lib.ptk_truncate(self._h, float(p), C.byref(k)))
+        return int(k.value)
 
     def kernel_times(self):
         cnt = _i32(64)

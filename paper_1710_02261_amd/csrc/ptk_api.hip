@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "ptk_approx.h"
 #include "ptk_context.h"
 #include "ptk_internal.h"
 
@@ -107,6 +108,13 @@ void free_modes(ptk_ctx *c) {
     dfree(c->part);
     dfree(c->pcache);
     c->pcache = nullptr;
+    dfree(c->ap_resid);
+    dfree(c->ap_part);
+    dfree(c->ap_R);
+    dfree(c->ap_removed);
+    c->ap_resid = c->ap_part = c->ap_R = nullptr;
+    c->ap_removed = nullptr;
+    c->ap_slices = 0;
     c->bbuf = c->part = nullptr;
     c->part_cap = 0;
     c->nnz = -1;
@@ -451,6 +459,64 @@ ptk_status configure_ranges(ptk_ctx *c, int n, int64_t work) {
     return PTK_OK;
 }
 
+// Buffers of the Approx variant, sized for the observed set (not inside a
+// graph capture).
+ptk_status ensure_approx(ptk_ctx *c) {
+    if (!(equal_ranks(c->s) && approx_available(c->s.N, c->s.ranks[0])))
+        return fail(c, PTK_E_UNSUPPORTED, "no Approx kernels for this shape");
+    if (c->ap_R) return PTK_OK;
+    c->ap_slices = approx_slices(c->s, c->nnz, c->num_cu);
+    HIPCHK(c, dalloc(&c->ap_resid, (size_t)c->nnz + 64));
+    HIPCHK(c, dalloc(&c->ap_part, (size_t)approx_part_doubles(c->s, c->ap_slices)));
+    HIPCHK(c, dalloc(&c->ap_R, (size_t)c->core_cells));
+    HIPCHK(c, dalloc(&c->ap_removed, 1));
+    return PTK_OK;
+}
+
+// Alg. 4 on the bound model: residuals over the mode-0 grouping, R(beta) of
+// every cell into ap_R, and with remove the removal of the top cells from the
+// bound core followed by fresh permuted cores. Kernels only (capturable).
+ptk_status approx_step(ptk_ctx *c, double p, bool remove) {
+    const ModeData &m = c->md[0];
+    const int N = c->s.N;
+    EntryArgs ea{};
+    const int32_t *other[kMaxN];
+    for (int t = 0; t < N - 1; ++t) other[t] = m.oidx + (int64_t)t * c->nnz;
+    fill_common(c, 0, ea, other);
+    ea.gp = c->gpe;
+    ea.own_idx = m.rows;
+    ea.own = c->fac[0];
+    ea.val = m.vals;
+    ea.m = c->nnz;
+    ea.partial = c->ap_resid;
+    HIPCHK(c, permute_entries(c, 0));
+    const int64_t nb = std::max<int64_t>(
+        1, std::min<int64_t>(kSseBlocks, (c->nnz + kWave - 1) / kWave));
+    HIPCHK(c, timed(c, "approx_resid", [&] { return launch_residual(ea, c->s, nb, c->st); }));
+    ApproxArgs aa{};
+    for (int k = 0; k < N; ++k) aa.fac[k] = c->fac[k];
+    aa.idx[0] = m.rows;
+    for (int k = 1; k < N; ++k) aa.idx[k] = m.oidx + (int64_t)(k - 1) * c->nnz;
+    aa.resid = c->ap_resid;
+    aa.nnz = c->nnz;
+    aa.nslices = c->ap_slices;
+    aa.slice = std::max<int64_t>(1, (c->nnz + c->ap_slices - 1) / c->ap_slices);
+    aa.part = c->ap_part;
+    HIPCHK(c, timed(c, "approx_partial", [&] { return launch_partial_error(aa, c->s, c->st); }));
+    HIPCHK(c, timed(c, "approx_reduce", [&] {
+        return launch_partial_reduce(c->ap_part, c->ap_slices, c->core, c->core_cells,
+                                     c->ap_R, c->st);
+    }));
+    if (remove) {
+        HIPCHK(c, timed(c, "approx_select", [&] {
+            return launch_approx_select(c->ap_R, c->core, c->core_cells, p,
+                                        c->ap_removed, c->st);
+        }));
+        for (int n = 0; n < N; ++n) HIPCHK(c, permute(c, n, cache_role(c, n)));
+    }
+    return PTK_OK;
+}
+
 // One iteration of Alg. 2 (lines 3-4) as stream-ordered kernels only: the
 // N mode updates, the error and the factor norms, stored to dres through the
 // device counter. Contains no memset, copy or synchronisation, so it can be
@@ -482,6 +548,8 @@ ptk_status iteration_body(ptk_ctx *c, double lambda) {
     hipLaunchKernelGGL(k_store_iter, dim3(1), dim3(64), 0, c->st, scal, c->dres,
                        c->iter_ctr);
     HIPCHK(c, hipGetLastError());
+    // Approx variant: remove cells of G after the error (Alg. 2, Alg. 4)
+    if (c->opt.approx_rate > 0.0) return approx_step(c, c->opt.approx_rate, true);
     return PTK_OK;
 }
 
@@ -642,6 +710,11 @@ ptk_status ptk_set_options(ptk_ctx *c, const ptk_options *o) {
                     "no pair-cache kernel for this shape and precision");
     if (o->pair_cache != c->opt.pair_cache && c->nnz >= 0)
         return fail(c, PTK_E_STATE, "pair_cache must be set before ptk_set_observed");
+    if (!(o->approx_rate >= 0.0 && o->approx_rate < 1.0))
+        return fail(c, PTK_E_INVALID, "approx_rate must be in [0, 1)");
+    if (o->approx_rate > 0.0 &&
+        !(equal_ranks(c->s) && approx_available(c->s.N, c->s.ranks[0])))
+        return fail(c, PTK_E_UNSUPPORTED, "no Approx kernels for this shape");
     c->opt = *o;
     c->epoch++;
     return PTK_OK;
@@ -837,6 +910,10 @@ ptk_status ptk_iterate(ptk_ctx *c, int32_t iters, double lambda, double *sse_hos
     HIPCHK(c, zero_bad(c));
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, c->iter_ctr, 0, (int64_t)1);
     HIPCHK(c, hipGetLastError());
+    if (c->opt.approx_rate > 0.0) {
+        s = ensure_approx(c);
+        if (s != PTK_OK) return s;
+    }
     const bool use_graph = c->opt.use_graph && !c->opt.profile;
     if (use_graph) {
         s = ensure_iteration_graph(c, lambda);
@@ -958,6 +1035,33 @@ ptk_status ptk_delta(ptk_ctx *c, int32_t n, int64_t m, const int32_t *idx, float
     const int64_t blocks = std::min<int64_t>((m + kWave - 1) / kWave, (int64_t)c->num_cu * 16);
     HIPCHK(c, launch_entries(a, c->s, n, kOutDelta, fast, blocks, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
+    return PTK_OK;
+}
+
+ptk_status ptk_partial_error(ptk_ctx *c, double *R_out) {
+    if (!c) return PTK_E_INVALID;
+    if (!R_out) return fail(c, PTK_E_INVALID, "null output");
+    ptk_status s = need_model(c);
+    if (s != PTK_OK) return s;
+    if ((s = ensure_approx(c)) != PTK_OK) return s;
+    if ((s = approx_step(c, 0.0, false)) != PTK_OK) return s;
+    HIPCHK(c, hipMemcpyAsync(R_out, c->ap_R, sizeof(double) * c->core_cells,
+                             hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    return PTK_OK;
+}
+
+ptk_status ptk_truncate(ptk_ctx *c, double p, int32_t *removed_host) {
+    if (!c) return PTK_E_INVALID;
+    if (!(p >= 0.0 && p < 1.0)) return fail(c, PTK_E_INVALID, "p must be in [0, 1)");
+    ptk_status s = need_model(c);
+    if (s != PTK_OK) return s;
+    if ((s = ensure_approx(c)) != PTK_OK) return s;
+    if ((s = approx_step(c, p, true)) != PTK_OK) return s;
+    int32_t k = 0;
+    HIPCHK(c, hipMemcpyAsync(&k, c->ap_removed, sizeof k, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (removed_host) *removed_host = k;
     return PTK_OK;
 }
 

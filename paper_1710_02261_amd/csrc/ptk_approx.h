@@ -1,0 +1,42 @@
+// Approx variant of the ALS sweep (Alg. 4, Sec. 3.3): launchers.
+#pragma once
+
+#include "ptk_internal.h"
+
+namespace ptk {
+
+// Arguments of the partial-error kernel: the entries in mode-0 grouped order.
+struct ApproxArgs {
+    const float *fac[kMaxN];          // factor matrices, mode order
+    const int32_t *idx[kMaxN];        // index of every mode per entry
+    const double *resid;              // xhat - x per entry
+    int64_t nnz;
+    int64_t slice;                    // entries per slice
+    int32_t nslices;
+    double *part;                     // [nslices][2][cells]: sums S1, S2
+};
+
+// Is the Approx variant compiled for this (N, J) with equal ranks?
+bool approx_available(int N, int J);
+
+// resid[e] = xhat_e - x_e over the entries of the mode-0 grouping (a.m of
+// them); a.partial receives the residuals (FP64), a.gp is the FP64 core
+// permuted for mode 0.
+hipError_t launch_residual(const EntryArgs &a, const Shape &s, int64_t nblocks,
+                           hipStream_t st);
+
+// Slices and part size (doubles) for nnz entries.
+int32_t approx_slices(const Shape &s, int64_t nnz, int num_cu);
+int64_t approx_part_doubles(const Shape &s, int32_t nslices);
+
+// S1, S2 per slice, then R(beta) = 2 G S1 - G^2 S2 for every cell.
+hipError_t launch_partial_error(const ApproxArgs &a, const Shape &s, hipStream_t st);
+hipError_t launch_partial_reduce(const double *part, int32_t nslices, const float *G,
+                                 int64_t cells, double *R, hipStream_t st);
+
+// Alg. 4's removal: zero the floor(p * nz) non-zero cells of G with the
+// largest R (ties: lower cell index first); *removed receives the count.
+hipError_t launch_approx_select(const double *R, float *G, int64_t cells, double p,
+                                int32_t *removed, hipStream_t st);
+
+}  // namespace ptk

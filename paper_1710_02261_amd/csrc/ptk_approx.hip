@@ -1,0 +1,303 @@
+// Approx variant of the ALS sweep (Alg. 4, Sec. 3.3): the partial
+// reconstruction error of every core cell (eq. "recon_partial") and the
+// removal of the cells with the largest values.
+//
+// With r = xhat - x and w(alpha, beta) = prod_n a^(n)_{i_n beta_n}, the
+// definition sum_alpha (x - xhat)^2 - (x - xhat + t)^2, t = G_beta w, becomes
+//     R(beta) = 2 G_beta S1(beta) - G_beta^2 S2(beta),
+//     S1 = sum_alpha r w,   S2 = sum_alpha w^2,
+// two sums over the entries of Kronecker products of factor rows.
+//
+// Partial-error kernel: a wavefront owns J*64 cells. Lane l takes one value
+// p of the last two modes (beta_{N-2}, beta_{N-1}); the wavefront fixes the
+// leading modes 0..N-4 (its lead group) and covers every value k of mode N-3.
+// It walks a slice of the entries: the indices, the residual and the rows of
+// modes 0..N-3 are the same for all lanes (wavefront-uniform scalar loads),
+// only the two values of the last modes are per lane. Sums are FP64; the
+// slices are reduced in a fixed order.
+#include "ptk_approx.h"
+#include "ptk_device.h"
+
+namespace ptk {
+
+#define PTK_APPROX_SHAPES(X) PTK_FAST_SHAPES_LIST(X)
+
+// the same shapes as the fast row-system kernels
+#define PTK_FAST_SHAPES_LIST(X) \
+    X(3, 3) X(3, 4) X(3, 5) X(3, 8) X(3, 10) X(3, 16) \
+    X(4, 3) X(4, 5) X(4, 8) X(4, 10) \
+    X(5, 3) X(5, 5) X(5, 8)
+
+bool approx_available(int N, int J) {
+#define PTK_X(n_, j_) if (N == n_ && J == j_) return true;
+    PTK_APPROX_SHAPES(PTK_X)
+#undef PTK_X
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// residuals xhat - x (FP64) over the mode-0 grouping
+// ---------------------------------------------------------------------------
+template <int N, int J, int U>
+__global__ __launch_bounds__(kWave) void k_residual(EntryArgs a) {
+    constexpr int NO = N - 1;
+    constexpr int NOUT = NO - U;
+    __shared__ float s_aout[(NOUT > 0 ? NOUT : 1) * J * kWave];
+    const int lane = threadIdx.x;
+    for (int64_t base = (int64_t)blockIdx.x * kWave; base < a.m;
+         base += (int64_t)gridDim.x * kWave) {
+        const int64_t pos = base + lane;
+        const bool valid = pos < a.m;
+        double ain[U][J];
+        load_rows_fast<NO, J, U, double>(a, pos, valid, s_aout, lane, ain);
+        __syncthreads();
+        double d[J];
+        delta_fast<NO, J, U, double>(a.gp, s_aout, lane, ain, d);
+        __syncthreads();
+        if (valid) {
+            const float *own = a.own + (int64_t)a.own_idx[pos] * J;
+            double xh = 0.0;
+#pragma unroll
+            for (int j = 0; j < J; ++j) xh = __builtin_fma((double)own[j], d[j], xh);
+            a.partial[pos] = xh - (double)a.val[pos];
+        }
+    }
+}
+
+hipError_t launch_residual(const EntryArgs &a, const Shape &s, int64_t nblocks,
+                           hipStream_t st) {
+    if (a.m <= 0 || nblocks <= 0) return hipSuccess;
+    const int J = s.ranks[0];
+#define PTK_X(n_, j_)                                                               \
+    if (s.N == n_ && J == j_) {                                                     \
+        hipLaunchKernelGGL((k_residual<n_, j_, fast_depth(n_, j_)>), dim3((unsigned)nblocks), \
+                           dim3(kWave), 0, st, a);                                  \
+        return hipGetLastError();                                                   \
+    }
+    PTK_APPROX_SHAPES(PTK_X)
+#undef PTK_X
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// S1, S2 per slice of entries
+// ---------------------------------------------------------------------------
+template <int N, int J>
+__global__ __launch_bounds__(kWave) void k_partial_error(ApproxArgs a) {
+    constexpr int P = J * J;
+    constexpr int NPG = (P + kWave - 1) / kWave;
+    constexpr int NLG = ipow(J, N - 3);
+    constexpr int CELLS = ipow(J, N);
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x;
+    const int pg = b % NPG;
+    const int lg = (b / NPG) % NLG;
+    const int sl = b / (NPG * NLG);
+    const int p = pg * kWave + lane;
+    const bool act = p < P;
+    const int m1 = act ? p / J : 0, m2 = act ? p % J : 0;
+    int pre[N > 3 ? N - 3 : 1];
+    {
+        int t = lg;
+#pragma unroll
+        for (int k = N - 4; k >= 0; --k) {
+            pre[k] = t % J;
+            t /= J;
+        }
+    }
+    double s1[J], s2[J];
+#pragma unroll
+    for (int k = 0; k < J; ++k) s1[k] = s2[k] = 0.0;
+    const int64_t e0 = (int64_t)sl * a.slice;
+    const int64_t e1 = min(e0 + a.slice, a.nnz);
+    const float *fa = a.fac[N - 2], *fb = a.fac[N - 1];
+    const int32_t *ia = a.idx[N - 2], *ib = a.idx[N - 1];
+    cptr<double> res = (cptr<double>)a.resid;
+#pragma unroll 2
+    for (int64_t e = e0; e < e1; ++e) {
+        // wavefront-uniform: indices, residual, rows of modes 0..N-3
+        double lead = 1.0;
+#pragma unroll
+        for (int k = 0; k < N - 3; ++k) {
+            const int32_t i = ((cptr<int32_t>)a.idx[k])[e];
+            lead *= (double)((cptr<float>)a.fac[k])[(int64_t)i * J + pre[k]];
+        }
+        const int32_t il = ((cptr<int32_t>)a.idx[N - 3])[e];
+        cptr<float> row = (cptr<float>)a.fac[N - 3] + (int64_t)il * J;
+        const double r = res[e];
+        // per lane: the values of the last two modes
+        const double v = (double)fa[(int64_t)ia[e] * J + m1] * (double)fb[(int64_t)ib[e] * J + m2];
+        const double vv = v * v;
+#pragma unroll
+        for (int k = 0; k < J; ++k) {
+            const double q = lead * (double)row[k];
+            s1[k] = __builtin_fma(r * q, v, s1[k]);
+            s2[k] = __builtin_fma(q * q, vv, s2[k]);
+        }
+    }
+    if (act) {
+        double *o1 = a.part + (int64_t)sl * 2 * CELLS;
+        double *o2 = o1 + CELLS;
+#pragma unroll
+        for (int k = 0; k < J; ++k) {
+            const int64_t cell = ((int64_t)lg * J + k) * P + p;
+            o1[cell] = s1[k];
+            o2[cell] = s2[k];
+        }
+    }
+}
+
+int32_t approx_slices(const Shape &s, int64_t nnz, int num_cu) {
+    const int J = s.ranks[0];
+    int64_t waves_per_slice = (int64_t)((J * J + kWave - 1) / kWave);
+    for (int k = 3; k < s.N; ++k) waves_per_slice *= J;
+    // about 8 wavefronts per CU in all, slices of at least 256 entries
+    int64_t sl = ((int64_t)8 * num_cu + waves_per_slice - 1) / waves_per_slice;
+    sl = std::min<int64_t>(sl, (nnz + 255) / 256);
+    return (int32_t)std::max<int64_t>(1, sl);
+}
+
+int64_t approx_part_doubles(const Shape &s, int32_t nslices) {
+    int64_t cells = 1;
+    for (int k = 0; k < s.N; ++k) cells *= s.ranks[k];
+    return (int64_t)nslices * 2 * cells;
+}
+
+hipError_t launch_partial_error(const ApproxArgs &a, const Shape &s, hipStream_t st) {
+    const int J = s.ranks[0];
+#define PTK_X(n_, j_)                                                            \
+    if (s.N == n_ && J == j_) {                                                  \
+        const int64_t blocks = (int64_t)((j_ * j_ + kWave - 1) / kWave) *        \
+                               ipow(j_, n_ - 3) * a.nslices;                     \
+        hipLaunchKernelGGL((k_partial_error<n_, j_>), dim3((unsigned)blocks),     \
+                           dim3(kWave), 0, st, a);                               \
+        return hipGetLastError();                                                \
+    }
+    PTK_APPROX_SHAPES(PTK_X)
+#undef PTK_X
+    return hipErrorInvalidValue;
+}
+
+// R(beta) = 2 G S1 - G^2 S2, slices summed in order; 0 (positive) for cells
+// that are not entries of the core.
+__global__ void k_partial_reduce(const double *__restrict__ part, int32_t nslices,
+                                 const float *__restrict__ G, int64_t cells,
+                                 double *__restrict__ R) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    double s1 = 0.0, s2 = 0.0;
+    for (int32_t sl = 0; sl < nslices; ++sl) {
+        s1 += part[((int64_t)sl * 2) * cells + c];
+        s2 += part[((int64_t)sl * 2 + 1) * cells + c];
+    }
+    const double g = (double)G[c];
+    const double r = g == 0.0 ? 0.0 : 2.0 * g * s1 - g * g * s2;
+    R[c] = r + 0.0;                    // -0 -> +0
+}
+
+hipError_t launch_partial_reduce(const double *part, int32_t nslices, const float *G,
+                                 int64_t cells, double *R, hipStream_t st) {
+    hipLaunchKernelGGL(k_partial_reduce, dim3((unsigned)((cells + 255) / 256)), dim3(256),
+                       0, st, part, nslices, G, cells, R);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// removal: one workgroup, radix select of the k-th largest R
+// ---------------------------------------------------------------------------
+// Order-preserving key of a double (larger value -> larger key).
+__device__ __forceinline__ unsigned long long order_key(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+
+constexpr int kSelThreads = 1024;
+
+__global__ __launch_bounds__(kSelThreads) void k_approx_select(
+    const double *__restrict__ R, float *__restrict__ G, int64_t cells, double p,
+    int32_t *__restrict__ removed) {
+    __shared__ int hist[256];
+    __shared__ int s_wcnt[kSelThreads / kWave], s_woff[kSelThreads / kWave];
+    __shared__ unsigned long long s_nz;
+    __shared__ int s_digit;
+    __shared__ long long s_rem;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_nz = 0;
+    __syncthreads();
+    unsigned long long mine = 0;
+    for (int64_t c = tid; c < cells; c += kSelThreads) mine += G[c] != 0.0f;
+    atomicAdd(&s_nz, mine);
+    __syncthreads();
+    const long long k = (long long)floor(p * (double)s_nz);
+    if (k <= 0) {
+        if (tid == 0) *removed = 0;
+        return;
+    }
+    // MSB-first radix select over 8 digits: prefix = key of the k-th largest
+    unsigned long long prefix = 0, mask = 0;
+    long long remaining = k;
+    for (int pos = 7; pos >= 0; --pos) {
+        for (int d = tid; d < 256; d += kSelThreads) hist[d] = 0;
+        __syncthreads();
+        for (int64_t c = tid; c < cells; c += kSelThreads) {
+            if (G[c] == 0.0f) continue;
+            const unsigned long long key = order_key(R[c]);
+            if ((key & mask) == prefix) atomicAdd(&hist[(key >> (8 * pos)) & 255], 1);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            long long cum = 0;
+            int d = 255;
+            for (; d > 0; --d) {
+                if (cum + hist[d] >= remaining) break;
+                cum += hist[d];
+            }
+            s_digit = d;
+            s_rem = remaining - cum;
+        }
+        __syncthreads();
+        prefix |= (unsigned long long)s_digit << (8 * pos);
+        mask |= 0xFFull << (8 * pos);
+        remaining = s_rem;
+        __syncthreads();
+    }
+    // keys above the threshold go; of the keys equal to it, the first
+    // `remaining` in cell order
+    const int wid = tid / kWave, lid = tid % kWave;
+    long long running = 0;
+    for (int64_t base = 0; base < cells; base += kSelThreads) {
+        const int64_t c = base + tid;
+        bool gt = false, eq = false;
+        if (c < cells && G[c] != 0.0f) {
+            const unsigned long long key = order_key(R[c]);
+            gt = key > prefix;
+            eq = key == prefix;
+        }
+        const unsigned long long bal = __ballot(eq);
+        const int below = __popcll(bal & ((1ull << lid) - 1ull));
+        if (lid == 0) s_wcnt[wid] = __popcll(bal);
+        __syncthreads();
+        if (tid == 0) {
+            int acc = 0;
+            for (int w = 0; w < kSelThreads / kWave; ++w) {
+                s_woff[w] = acc;
+                acc += s_wcnt[w];
+            }
+        }
+        __syncthreads();
+        const long long rank = running + s_woff[wid] + below;
+        if (gt || (eq && rank < remaining)) G[c] = 0.0f;
+        running += s_woff[kSelThreads / kWave - 1] + s_wcnt[kSelThreads / kWave - 1];
+        __syncthreads();
+    }
+    if (tid == 0) *removed = (int32_t)k;
+}
+
+hipError_t launch_approx_select(const double *R, float *G, int64_t cells, double p,
+                                int32_t *removed, hipStream_t st) {
+    hipLaunchKernelGGL(k_approx_select, dim3(1), dim3(kSelThreads), 0, st, R, G, cells,
+                       p, removed);
+    return hipGetLastError();
+}
+
+}  // namespace ptk

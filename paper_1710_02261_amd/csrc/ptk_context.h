@@ -51,7 +51,7 @@ struct ptk_ctx {
     hipStream_t st = nullptr;
     int device = 0;
     int num_cu = 256;
-    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1, 0};
+    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1, 0, 0.0};
     int64_t nnz = -1;
     ModeData md[ptk::kMaxN];
     float *core = nullptr;
@@ -64,6 +64,10 @@ struct ptk_ctx {
     double *bbuf = nullptr;
     double *part = nullptr;
     double *pcache = nullptr;    // pair cache [nnz + 1][J][J]
+    // Approx variant: residuals [nnz], slice sums, R per cell, removed count
+    double *ap_resid = nullptr, *ap_part = nullptr, *ap_R = nullptr;
+    int32_t *ap_removed = nullptr;
+    int32_t ap_slices = 0;
     int64_t part_cap = 0;
     double *red = nullptr;       // [kRedBlocks * (N + 1)] partials + scalars
     double *xsq = nullptr;       // sum of x^2 over Omega (device, 1 double)
