@@ -276,6 +276,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=40.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variant", action="store_true")
+    ap.add_argument("--approx-rate", type=float, default=0.0,
+                    help="Approx variant: core cells removed per iteration (0 = off)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a 256 MiB copy kernel (HBM counter scale)")
     ap.add_argument("--pair-cache", action="store_true",
@@ -330,17 +332,18 @@ def main():
 
     use_graph = 0 if args.no_graph else 1
 
-    def run(prec, cache=0):
+    def run(prec, cache=0, approx=0.0):
         fac = [f.clone() for f in fac0]
+        core_run = core.clone()           # the Approx removal edits the core
         ctx = ptk.Context(p.dims, p.ranks)
         ctx.set_options(precision=PREC_NAMES[prec], fuse_error=1, profile=0,
-                        use_graph=use_graph, pair_cache=cache)
+                        use_graph=use_graph, pair_cache=cache, approx_rate=approx)
         torch.cuda.synchronize()
         ts = time.perf_counter()
         ctx.set_observed(idx, val)
         torch.cuda.synchronize()
         setup = time.perf_counter() - ts
-        ctx.bind_model(core, fac)
+        ctx.bind_model(core_run, fac)
         work, tune_s = None, 0.0
         if not args.no_autotune:
             ts = time.perf_counter()
@@ -354,11 +357,12 @@ def main():
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t1
         not_pd = ctx.not_pd_count()
+        core_left = int(torch.count_nonzero(core_run))
         # the model's error by a direct FP64 pass over all entries (untimed)
         _, rmse_direct, _ = ctx.recon_error(p.lam)
         # second pass with per-kernel HIP events on the library's stream
         ctx.set_options(precision=PREC_NAMES[prec], fuse_error=1, profile=1,
-                        use_graph=use_graph, pair_cache=cache)
+                        use_graph=use_graph, pair_cache=cache, approx_rate=approx)
         ctx.reset_timers()
         ctx.iterate(args.steps, p.lam, strict=False)
         times = ctx.kernel_times()
@@ -370,6 +374,7 @@ def main():
                 "not_pd": not_pd, "gram_ms": ms / max(calls, 1),
                 "value": p.nnz * args.steps / elapsed,
                 "rmse": float(rmse_direct), "work": work, "tune_s": tune_s,
+                "core_left": core_left,
                 "rmse_fused": float(np.sqrt(max(sse[-1], 0.0) / p.nnz))}
 
     main_prec = args.precision
@@ -378,7 +383,7 @@ def main():
                 and J in cache_shapes.get(N, ()))
     if args.pair_cache and not cache_ok:
         raise SystemExit("bench.py: no pair-cache kernel for this workload and precision")
-    r = run(main_prec, 1 if args.pair_cache else 0)
+    r = run(main_prec, 1 if args.pair_cache else 0, args.approx_rate)
     log("%s: %.2f ms/step, %.3e nnz*iters/s" % (main_prec, 1e3 * r["elapsed"] / args.steps,
                                                   r["value"]))
     log("kernels: " + ", ".join("%s %.3f ms x%d" % (k, v[1] / max(v[0], 1), v[0])
@@ -430,6 +435,8 @@ def main():
         "autotune": {"work_per_mode": r["work"], "seconds": r["tune_s"]},
         "graph": bool(use_graph),
         "pair_cache": bool(args.pair_cache),
+        "approx_rate": args.approx_rate,
+        "core_cells_left": r["core_left"],
         "rmse_after": r["rmse"],
         "rmse_after_fused": r["rmse_fused"],
         "not_pd_rows_timed": int(r["not_pd"]),
@@ -437,6 +444,15 @@ def main():
     }
     if not args.no_variant:
         variants = {}
+        if args.approx_rate > 0:
+            v = run(main_prec, 1 if args.pair_cache else 0, 0.0)
+            name = main_prec + " (no removal)"
+            variants[name] = {"value": v["value"],
+                              "ms_per_step": 1e3 * v["elapsed"] / args.steps,
+                              "rmse_after": v["rmse"],
+                              "rmse_rel_to_main": v["rmse"] / r["rmse"] - 1.0}
+            log("%s: %.2f ms/step, rmse %.6g (main %.6g)" % (
+                name, variants[name]["ms_per_step"], v["rmse"], r["rmse"]))
         if cache_ok:
             other = 0 if args.pair_cache else 1
             v = run(main_prec, other)

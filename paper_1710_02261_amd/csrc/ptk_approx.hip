@@ -11,10 +11,11 @@
 // Partial-error kernel: a wavefront owns J*64 cells. Lane l takes one value
 // p of the last two modes (beta_{N-2}, beta_{N-1}); the wavefront fixes the
 // leading modes 0..N-4 (its lead group) and covers every value k of mode N-3.
-// It walks a slice of the entries: the indices, the residual and the rows of
-// modes 0..N-3 are the same for all lanes (wavefront-uniform scalar loads),
-// only the two values of the last modes are per lane. Sums are FP64; the
-// slices are reduced in a fixed order.
+// It walks a slice of the entries, 32 at a time: lanes 0..31 stage each
+// entry's residual and leading-mode factor elements in LDS (the same for all
+// cells of the wavefront, read back as broadcasts), then every lane gathers
+// its two last-mode elements for all 32 entries at once and accumulates.
+// Sums are FP64; the slices are reduced in a fixed order.
 #include "ptk_approx.h"
 #include "ptk_device.h"
 
@@ -82,12 +83,19 @@ hipError_t launch_residual(const EntryArgs &a, const Shape &s, int64_t nblocks,
 // ---------------------------------------------------------------------------
 // S1, S2 per slice of entries
 // ---------------------------------------------------------------------------
+constexpr int kApproxChunk = 32;      // entries staged per step
+
 template <int N, int J>
 __global__ __launch_bounds__(kWave) void k_partial_error(ApproxArgs a) {
     constexpr int P = J * J;
     constexpr int NPG = (P + kWave - 1) / kWave;
     constexpr int NLG = ipow(J, N - 3);
     constexpr int CELLS = ipow(J, N);
+    constexpr int CH = kApproxChunk;
+    // per staged entry u and value k of mode N-3: r q and q^2, q = the
+    // product of the entry's factor elements at the leading cell indices
+    __shared__ double s_u[CH][J], s_w[CH][J];
+    __shared__ int32_t s_ia[CH], s_ib[CH];
     const int lane = threadIdx.x;
     const int b = blockIdx.x;
     const int pg = b % NPG;
@@ -111,29 +119,51 @@ __global__ __launch_bounds__(kWave) void k_partial_error(ApproxArgs a) {
     const int64_t e0 = (int64_t)sl * a.slice;
     const int64_t e1 = min(e0 + a.slice, a.nnz);
     const float *fa = a.fac[N - 2], *fb = a.fac[N - 1];
-    const int32_t *ia = a.idx[N - 2], *ib = a.idx[N - 1];
-    cptr<double> res = (cptr<double>)a.resid;
-#pragma unroll 2
-    for (int64_t e = e0; e < e1; ++e) {
-        // wavefront-uniform: indices, residual, rows of modes 0..N-3
-        double lead = 1.0;
+    for (int64_t base = e0; base < e1; base += CH) {
+        const int nb = (int)min((int64_t)CH, e1 - base);
+        // stage: lane t < CH takes entry base + t (zeros past the end)
+        if (lane < CH) {
+            const bool ok = lane < nb;
+            const int64_t e = base + lane;
+            double lead = 0.0, r = 0.0;
+            const float *row = a.fac[N - 3];
+            if (ok) {
+                lead = 1.0;
 #pragma unroll
-        for (int k = 0; k < N - 3; ++k) {
-            const int32_t i = ((cptr<int32_t>)a.idx[k])[e];
-            lead *= (double)((cptr<float>)a.fac[k])[(int64_t)i * J + pre[k]];
-        }
-        const int32_t il = ((cptr<int32_t>)a.idx[N - 3])[e];
-        cptr<float> row = (cptr<float>)a.fac[N - 3] + (int64_t)il * J;
-        const double r = res[e];
-        // per lane: the values of the last two modes
-        const double v = (double)fa[(int64_t)ia[e] * J + m1] * (double)fb[(int64_t)ib[e] * J + m2];
-        const double vv = v * v;
+                for (int k = 0; k < N - 3; ++k)
+                    lead *= (double)a.fac[k][(int64_t)a.idx[k][e] * J + pre[k]];
+                row += (int64_t)a.idx[N - 3][e] * J;
+                r = a.resid[e];
+            }
 #pragma unroll
-        for (int k = 0; k < J; ++k) {
-            const double q = lead * (double)row[k];
-            s1[k] = __builtin_fma(r * q, v, s1[k]);
-            s2[k] = __builtin_fma(q * q, vv, s2[k]);
+            for (int k = 0; k < J; ++k) {
+                const double q = ok ? lead * (double)row[k] : 0.0;
+                s_u[lane][k] = r * q;
+                s_w[lane][k] = q * q;
+            }
+            s_ia[lane] = ok ? a.idx[N - 2][e] : 0;
+            s_ib[lane] = ok ? a.idx[N - 1][e] : 0;
         }
+        __syncthreads();
+        // this lane's factor elements of the last two modes for every
+        // staged entry: independent gathers, all in flight together
+        float va[CH], vb[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            va[u] = fa[(int64_t)s_ia[u] * J + m1];
+            vb[u] = fb[(int64_t)s_ib[u] * J + m2];
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const double v = (double)va[u] * (double)vb[u];
+            const double vv = v * v;
+#pragma unroll
+            for (int k = 0; k < J; ++k) {
+                s1[k] = __builtin_fma(s_u[u][k], v, s1[k]);
+                s2[k] = __builtin_fma(s_w[u][k], vv, s2[k]);
+            }
+        }
+        __syncthreads();
     }
     if (act) {
         double *o1 = a.part + (int64_t)sl * 2 * CELLS;
@@ -151,8 +181,8 @@ int32_t approx_slices(const Shape &s, int64_t nnz, int num_cu) {
     const int J = s.ranks[0];
     int64_t waves_per_slice = (int64_t)((J * J + kWave - 1) / kWave);
     for (int k = 3; k < s.N; ++k) waves_per_slice *= J;
-    // about 8 wavefronts per CU in all, slices of at least 256 entries
-    int64_t sl = ((int64_t)8 * num_cu + waves_per_slice - 1) / waves_per_slice;
+    // about 16 wavefronts per CU in all, slices of at least 256 entries
+    int64_t sl = ((int64_t)16 * num_cu + waves_per_slice - 1) / waves_per_slice;
     sl = std::min<int64_t>(sl, (nnz + 255) / 256);
     return (int32_t)std::max<int64_t>(1, sl);
 }
