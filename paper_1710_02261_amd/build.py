@@ -26,11 +26,15 @@ SOURCES = ["ptk_api.hip", "ptk_kernels.hip", "ptk_cache.hip", "ptk_approx.hip",
 CFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-I", INCLUDE]
+# Matrix-core results written to VGPRs (the VALU folds them right away; the
+# accumulation-register form needs a move per result register).
+MFMA_FLAGS = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    extra = MFMA_FLAGS if src == "ptk_mfma.hip" else []
+    cmd = [HIPCC, *CFLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr[-8000:]))

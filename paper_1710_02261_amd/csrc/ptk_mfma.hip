@@ -31,6 +31,17 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kMfmaWaves = 4;   // wavefronts per workgroup (share the core in LDS)
 constexpr int kBlk = 32;        // entries per block (one Gram MFMA)
 
+// LDS written by some lanes of a wavefront and read by other lanes of the
+// same wavefront: keeps the compiler from moving LDS accesses across this
+// point and waits for the wavefront's outstanding LDS operations. No other
+// wavefront takes part, so the wavefronts of a workgroup run independently.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xc07f);         // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------------------
 // core fragments: frag[t][lane][u] = gp[t][4*(lane/16)+u][lane%16] (bf16, 0 pad)
 // ---------------------------------------------------------------------------
@@ -104,8 +115,8 @@ __global__ __launch_bounds__(kWave * kMfmaWaves) void k_gram_mfma(MfmaArgs a) {
     const int64_t wave = (int64_t)blockIdx.x * kMfmaWaves + wid;
     const int64_t b0 = wave * a.blk_per_wave;
     const int64_t b1 = min(b0 + a.blk_per_wave, a.nblk);
-    // every wavefront of the workgroup runs the same number of steps, so the
-    // workgroup barriers below are reached by all of them
+    // after the fragments are in LDS the wavefronts only share read-only
+    // data: each step synchronises its own wavefront only
     const int64_t cs = (b0 < b1) ? (int64_t)a.blk_start[b0] : 0;
     const int64_t ce = (b0 < b1) ? (int64_t)a.blk_start[b1 - 1] + a.blk_cnt[b1 - 1] : 0;
     const int g = lane / 16;                  // lane group
@@ -181,7 +192,7 @@ __global__ __launch_bounds__(kWave * kMfmaWaves) void k_gram_mfma(MfmaArgs a) {
                 afl[mb][u] = (__bf16)(v - (float)af[mb][u]);
             }
         }
-        __syncthreads();
+        wave_lds_sync();
         if (active) {
         // D = A x B for one tile, with the split products when SPLIT = 3
         auto tile_product = [&](int mb, int t) -> floatx4 {
@@ -258,7 +269,7 @@ __global__ __launch_bounds__(kWave * kMfmaWaves) void k_gram_mfma(MfmaArgs a) {
             Bacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gl, gv, Bacc, 0, 0, 0);
         }
         }
-        __syncthreads();
+        wave_lds_sync();
     }
     if (cur >= 0) flush(cur);
 }

@@ -109,10 +109,101 @@ __global__ void k_solve(const double *__restrict__ bbuf,
     for (int p = 0; p < J; ++p) arow[p] = (float)y[p * bs];
 }
 
+// The same solve with a group of G lanes per row (G = 4, 8 or 16 >= J,
+// 64/G rows per wavefront): lane l keeps row l of B + lambda I in registers.
+// Cholesky column by column (the diagonal and the new column are broadcast
+// within the group), then L y = c with each y_r broadcast, then L^T a = y
+// with a group reduction per step. FP64; a failed diagonal leaves the row
+// unchanged and is counted, as in k_solve.
+template <int J>
+__global__ __launch_bounds__(256) void k_solve_grp(const double *__restrict__ bbuf,
+                                                   const int64_t *__restrict__ rowptr,
+                                                   int64_t I, double lambda,
+                                                   float *__restrict__ A,
+                                                   int32_t *__restrict__ bad) {
+    constexpr int G = J <= 4 ? 4 : (J <= 8 ? 8 : 16);
+    constexpr int T = J * (J + 1) / 2;
+    constexpr int E = T + J;
+    const int l = threadIdx.x % G;
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
+    const bool have = i < I;
+    const bool empty = have && rowptr[i] == rowptr[i + 1];
+    const bool live = have && !empty;          // uniform within the group
+    double b[J];
+    double c = 0.0;
+#pragma unroll
+    for (int k = 0; k < J; ++k) b[k] = 0.0;
+    if (live && l < J) {
+        const double *sys = bbuf + i * E;
+#pragma unroll
+        for (int k = 0; k < J; ++k)
+            b[k] = sys[l <= k ? tri_pos(l, k, J) : tri_pos(k, l, J)];
+        c = sys[T + l];
+#pragma unroll
+        for (int k = 0; k < J; ++k)
+            if (k == l) b[k] += lambda;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < J; ++k) {
+        const double d = __shfl(b[k], k, G);   // updated B_kk
+        ok = ok && d > 0.0;
+        const double lkk = sqrt(d > 0.0 ? d : 1.0);
+        const double mine = (l == k) ? lkk : b[k] / lkk;   // L_lk (l >= k)
+        b[k] = mine;
+#pragma unroll
+        for (int j = k + 1; j < J; ++j) {
+            const double ljk = __shfl(mine, j, G);
+            if (l > k) b[j] = __builtin_fma(-mine, ljk, b[j]);
+        }
+    }
+    // L y = c
+    double y = c;
+#pragma unroll
+    for (int r = 0; r < J; ++r) {
+        const double yr = __shfl(y, r, G) / __shfl(b[r], r, G);
+        if (l == r) y = yr;
+        if (l > r) y = __builtin_fma(-b[r], yr, y);
+    }
+    // L^T a = y, a_r = (y_r - sum_{k > r} L_kr a_k) / L_rr
+    double a = 0.0;
+#pragma unroll
+    for (int r = J - 1; r >= 0; --r) {
+        double t = (l > r && l < J) ? b[r] * a : 0.0;
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) t += __shfl_xor(t, off, G);
+        const double ar = (__shfl(y, r, G) - t) / __shfl(b[r], r, G);
+        if (l == r) a = ar;
+    }
+    if (!have) return;
+    float *arow = A + i * J;
+    if (empty) {
+        if (l < J) arow[l] = 0.0f;             // no entry: B = 0, c = 0 -> a = 0
+        return;
+    }
+    if (!ok) {
+        if (l == 0) atomicAdd(bad, 1);         // row left unchanged
+        return;
+    }
+    if (l < J) arow[l] = (float)a;
+}
+
 hipError_t launch_solve(const double *bbuf, const int64_t *rowptr, int64_t I,
                         int J, double lambda, float *A, int32_t *bad,
                         hipStream_t st) {
     if (I <= 0) return hipSuccess;
+#define PTK_SOLVE_GRP(j_)                                                           \
+    if (J == j_) {                                                                  \
+        constexpr int G = j_ <= 4 ? 4 : (j_ <= 8 ? 8 : 16);                         \
+        const int64_t rows_per_block = 256 / G;                                     \
+        hipLaunchKernelGGL(k_solve_grp<j_>,                                         \
+                           dim3((unsigned)((I + rows_per_block - 1) / rows_per_block)), \
+                           dim3(256), 0, st, bbuf, rowptr, I, lambda, A, bad);      \
+        return hipGetLastError();                                                   \
+    }
+    PTK_SOLVE_GRP(3) PTK_SOLVE_GRP(4) PTK_SOLVE_GRP(5) PTK_SOLVE_GRP(8)
+    PTK_SOLVE_GRP(10) PTK_SOLVE_GRP(16)
+#undef PTK_SOLVE_GRP
     const int E = sys_entries(J);
     int bs = 64;
     while (bs > 8 && (size_t)E * bs * 8 > 64 * 1024) bs /= 2;
