@@ -379,8 +379,10 @@ def main():
 
     main_prec = args.precision
     cache_shapes = {3: (3, 4, 5, 8, 10, 16), 4: (3, 5, 8, 10), 5: (3, 5, 8)}
+    cache_bytes = (p.nnz + 1) * ((J * J + 1) // 2 * 2) * 8
+    cache_fits = cache_bytes <= 0.4 * torch.cuda.mem_get_info()[1]
     cache_ok = (len(set(p.ranks)) == 1 and not main_prec.startswith("bf16")
-                and J in cache_shapes.get(N, ()))
+                and J in cache_shapes.get(N, ()) and cache_fits)
     if args.pair_cache and not cache_ok:
         raise SystemExit("bench.py: no pair-cache kernel for this workload and precision")
     r = run(main_prec, 1 if args.pair_cache else 0, args.approx_rate)
