@@ -477,26 +477,34 @@ ptk_status ensure_approx(ptk_ctx *c) {
 // every cell into ap_R, and with remove the removal of the top cells from the
 // bound core followed by fresh permuted cores. Kernels only (capturable).
 ptk_status approx_step(ptk_ctx *c, double p, bool remove) {
-    const ModeData &m = c->md[0];
     const int N = c->s.N;
+    // group the entries by the mode with the fewest rows (fewest folds)
+    int g = 0;
+    for (int n = 1; n < N; ++n)
+        if (c->s.dims[n] < c->s.dims[g]) g = n;
+    const ModeData &m = c->md[g];
     EntryArgs ea{};
     const int32_t *other[kMaxN];
     for (int t = 0; t < N - 1; ++t) other[t] = m.oidx + (int64_t)t * c->nnz;
-    fill_common(c, 0, ea, other);
+    fill_common(c, g, ea, other);
     ea.gp = c->gpe;
     ea.own_idx = m.rows;
-    ea.own = c->fac[0];
+    ea.own = c->fac[g];
     ea.val = m.vals;
     ea.m = c->nnz;
     ea.partial = c->ap_resid;
-    HIPCHK(c, permute_entries(c, 0));
+    HIPCHK(c, permute_entries(c, g));
     const int64_t nb = std::max<int64_t>(
         1, std::min<int64_t>(kSseBlocks, (c->nnz + kWave - 1) / kWave));
     HIPCHK(c, timed(c, "approx_resid", [&] { return launch_residual(ea, c->s, nb, c->st); }));
     ApproxArgs aa{};
-    for (int k = 0; k < N; ++k) aa.fac[k] = c->fac[k];
-    aa.idx[0] = m.rows;
-    for (int k = 1; k < N; ++k) aa.idx[k] = m.oidx + (int64_t)(k - 1) * c->nnz;
+    for (int t = 0; t < N - 1; ++t) {
+        aa.fac[t] = c->fac[t < g ? t : t + 1];
+        aa.idx[t] = other[t];
+    }
+    aa.fac_g = c->fac[g];
+    aa.rows = m.rows;
+    aa.g = g;
     aa.resid = c->ap_resid;
     aa.nnz = c->nnz;
     aa.nslices = c->ap_slices;

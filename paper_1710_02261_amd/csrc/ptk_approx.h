@@ -5,11 +5,15 @@
 
 namespace ptk {
 
-// Arguments of the partial-error kernel: the entries in mode-0 grouped order.
+// Arguments of the partial-error kernel: the entries grouped by the rows of
+// one mode g (the grouping of the row-system kernels for mode g).
 struct ApproxArgs {
-    const float *fac[kMaxN];          // factor matrices, mode order
-    const int32_t *idx[kMaxN];        // index of every mode per entry
+    const float *fac[kMaxN];          // factors of the modes other than g, in
+    const int32_t *idx[kMaxN];        //   increasing mode order, and their indices
+    const float *fac_g;               // factor of mode g
+    const int32_t *rows;              // mode-g index per entry
     const double *resid;              // xhat - x per entry
+    int32_t g;
     int64_t nnz;
     int64_t slice;                    // entries per slice
     int32_t nslices;
@@ -19,9 +23,9 @@ struct ApproxArgs {
 // Is the Approx variant compiled for this (N, J) with equal ranks?
 bool approx_available(int N, int J);
 
-// resid[e] = xhat_e - x_e over the entries of the mode-0 grouping (a.m of
-// them); a.partial receives the residuals (FP64), a.gp is the FP64 core
-// permuted for mode 0.
+// resid[e] = xhat_e - x_e over the entries of one mode's grouping (a.m of
+// them; a.own / a.own_idx that mode's factor and indices); a.partial
+// receives the residuals (FP64), a.gp is the FP64 core permuted for it.
 hipError_t launch_residual(const EntryArgs &a, const Shape &s, int64_t nblocks,
                            hipStream_t st);
 

@@ -8,13 +8,24 @@
 //     S1 = sum_alpha r w,   S2 = sum_alpha w^2,
 // two sums over the entries of Kronecker products of factor rows.
 //
-// Partial-error kernel: a wavefront owns J*64 cells. Lane l takes one value
-// p of the last two modes (beta_{N-2}, beta_{N-1}); the wavefront fixes the
-// leading modes 0..N-4 (its lead group) and covers every value k of mode N-3.
-// It walks a slice of the entries, 32 at a time: lanes 0..31 stage each
-// entry's residual and leading-mode factor elements in LDS (the same for all
-// cells of the wavefront, read back as broadcasts), then every lane gathers
-// its two last-mode elements for all 32 entries at once and accumulates.
+// The sums are linear in the entries, and the entries are grouped by the
+// rows of one mode g: with T_i(beta') the sum over the entries of row i of
+// r (resp. 1) times the product of the other modes' factor elements at
+// beta' (and its square for S2),
+//     S1(beta) = sum_i a^(g)_{i beta_g} T1_i(beta'),
+//     S2(beta) = sum_i (a^(g)_{i beta_g})^2 T2_i(beta'),
+// so each entry costs J^(N-1) products instead of J^N, and a row is folded
+// in with J multiply-adds when it ends (rows split between slices need no
+// merge: each piece is folded in on its own).
+//
+// Partial-error kernel: a wavefront owns 64 cells beta' of T: lane l takes a
+// value p of the last two other modes, the wavefront fixes the others (the
+// third-last through one index k, the ones before through its lead group),
+// and it accumulates the J values of beta_g for each of them. It walks a
+// slice of the entries, 32 at a time: lanes 0..31 stage each entry's
+// residual-weighted leading product in LDS (the same for the whole
+// wavefront, read back as one broadcast per entry), then every lane gathers
+// its two last-mode elements for the 32 entries at once and accumulates.
 // Sums are FP64; the slices are reduced in a fixed order.
 #include "ptk_approx.h"
 #include "ptk_device.h"
@@ -28,6 +39,12 @@ namespace ptk {
     X(3, 3) X(3, 4) X(3, 5) X(3, 8) X(3, 10) X(3, 16) \
     X(4, 3) X(4, 5) X(4, 8) X(4, 10) \
     X(5, 3) X(5, 5) X(5, 8)
+
+__host__ __device__ inline int64_t ipow_rt(int64_t b, int e) {
+    int64_t r = 1;
+    for (int k = 0; k < e; ++k) r *= b;
+    return r;
+}
 
 bool approx_available(int N, int J) {
 #define PTK_X(n_, j_) if (N == n_ && J == j_) return true;
@@ -87,66 +104,75 @@ constexpr int kApproxChunk = 32;      // entries staged per step
 
 template <int N, int J>
 __global__ __launch_bounds__(kWave) void k_partial_error(ApproxArgs a) {
+    constexpr int NP = N - 1;             // modes of T (all but g)
     constexpr int P = J * J;
     constexpr int NPG = (P + kWave - 1) / kWave;
-    constexpr int NLG = ipow(J, N - 3);
+    constexpr int KS = NP >= 3 ? J : 1;   // third-last other mode, one value per wave
+    constexpr int NLG = NP >= 4 ? ipow(J, NP - 3) : 1;
     constexpr int CELLS = ipow(J, N);
     constexpr int CH = kApproxChunk;
-    // per staged entry u and value k of mode N-3: r q and q^2, q = the
-    // product of the entry's factor elements at the leading cell indices
-    __shared__ double s_u[CH][J], s_w[CH][J];
-    __shared__ int32_t s_ia[CH], s_ib[CH];
+    typedef double double2v __attribute__((ext_vector_type(2)));
+    __shared__ double2v s_uw[CH];         // (r q, q^2) per staged entry
+    __shared__ int32_t s_ia[CH], s_ib[CH], s_row[CH];
     const int lane = threadIdx.x;
-    const int b = blockIdx.x;
+    int b = blockIdx.x;
     const int pg = b % NPG;
-    const int lg = (b / NPG) % NLG;
-    const int sl = b / (NPG * NLG);
+    b /= NPG;
+    const int kk = b % KS;
+    b /= KS;
+    const int lg = b % NLG;
+    const int sl = b / NLG;
     const int p = pg * kWave + lane;
     const bool act = p < P;
     const int m1 = act ? p / J : 0, m2 = act ? p % J : 0;
-    int pre[N > 3 ? N - 3 : 1];
+    int pre[NP > 3 ? NP - 3 : 1];
     {
         int t = lg;
 #pragma unroll
-        for (int k = N - 4; k >= 0; --k) {
+        for (int k = NP - 4; k >= 0; --k) {
             pre[k] = t % J;
             t /= J;
         }
     }
-    double s1[J], s2[J];
+    double S1[J], S2[J];
 #pragma unroll
-    for (int k = 0; k < J; ++k) s1[k] = s2[k] = 0.0;
+    for (int k = 0; k < J; ++k) S1[k] = S2[k] = 0.0;
+    double t1 = 0.0, t2 = 0.0;            // T1, T2 of the current row, this lane's cell
+    int cur = -1;
+    auto fold = [&](int row) {            // S += a^(g)_row (x) T_row
+        cptr<float> ag = (cptr<float>)a.fac_g + (int64_t)row * J;
+#pragma unroll
+        for (int k = 0; k < J; ++k) {
+            const double x = (double)ag[k];
+            S1[k] = __builtin_fma(x, t1, S1[k]);
+            S2[k] = __builtin_fma(x * x, t2, S2[k]);
+        }
+    };
     const int64_t e0 = (int64_t)sl * a.slice;
     const int64_t e1 = min(e0 + a.slice, a.nnz);
-    const float *fa = a.fac[N - 2], *fb = a.fac[N - 1];
+    const float *fa = a.fac[NP - 2], *fb = a.fac[NP - 1];
     for (int64_t base = e0; base < e1; base += CH) {
         const int nb = (int)min((int64_t)CH, e1 - base);
-        // stage: lane t < CH takes entry base + t (zeros past the end)
+        // stage: lane t < CH takes entry base + t
         if (lane < CH) {
             const bool ok = lane < nb;
             const int64_t e = base + lane;
-            double lead = 0.0, r = 0.0;
-            const float *row = a.fac[N - 3];
+            double q = 0.0, r = 0.0;
             if (ok) {
-                lead = 1.0;
+                q = 1.0;
 #pragma unroll
-                for (int k = 0; k < N - 3; ++k)
-                    lead *= (double)a.fac[k][(int64_t)a.idx[k][e] * J + pre[k]];
-                row += (int64_t)a.idx[N - 3][e] * J;
+                for (int k = 0; k < NP - 3; ++k)
+                    q *= (double)a.fac[k][(int64_t)a.idx[k][e] * J + pre[k]];
+                if (NP >= 3) q *= (double)a.fac[NP - 3][(int64_t)a.idx[NP - 3][e] * J + kk];
                 r = a.resid[e];
             }
-#pragma unroll
-            for (int k = 0; k < J; ++k) {
-                const double q = ok ? lead * (double)row[k] : 0.0;
-                s_u[lane][k] = r * q;
-                s_w[lane][k] = q * q;
-            }
-            s_ia[lane] = ok ? a.idx[N - 2][e] : 0;
-            s_ib[lane] = ok ? a.idx[N - 1][e] : 0;
+            s_uw[lane] = double2v{r * q, q * q};
+            s_ia[lane] = ok ? a.idx[NP - 2][e] : 0;
+            s_ib[lane] = ok ? a.idx[NP - 1][e] : 0;
+            s_row[lane] = ok ? a.rows[e] : -1;
         }
         __syncthreads();
-        // this lane's factor elements of the last two modes for every
-        // staged entry: independent gathers, all in flight together
+        // this lane's elements of the last two modes for the staged entries
         float va[CH], vb[CH];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
@@ -155,32 +181,53 @@ __global__ __launch_bounds__(kWave) void k_partial_error(ApproxArgs a) {
         }
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-            const double v = (double)va[u] * (double)vb[u];
-            const double vv = v * v;
-#pragma unroll
-            for (int k = 0; k < J; ++k) {
-                s1[k] = __builtin_fma(s_u[u][k], v, s1[k]);
-                s2[k] = __builtin_fma(s_w[u][k], vv, s2[k]);
+            if (u < nb) {                 // uniform
+                const int row = s_row[u];
+                if (row != cur) {         // uniform
+                    if (cur >= 0) fold(cur);
+                    cur = row;
+                    t1 = t2 = 0.0;
+                }
+                const double2v uw = s_uw[u];
+                const double v = (double)va[u] * (double)vb[u];
+                t1 = __builtin_fma(uw.x, v, t1);
+                t2 = __builtin_fma(uw.y, v * v, t2);
             }
         }
         __syncthreads();
     }
+    if (cur >= 0) fold(cur);
     if (act) {
+        // C-order cell of (beta_g = k, the other modes' digits)
+        int64_t rest = 0;
+        int t = 0;
+#pragma unroll
+        for (int mode = 0; mode < N; ++mode) {
+            if (mode == a.g) continue;
+            const int d = (t < NP - 3) ? pre[t] : (t == NP - 3) ? kk : (t == NP - 2) ? m1 : m2;
+            rest = rest * J + d;
+            ++t;
+        }
+        // insert beta_g at position g: cell = hi * J^(N-g) + beta_g * J^(N-1-g) + lo
+        const int64_t sg = ipow_rt(J, N - 1 - a.g);
+        const int64_t hi = rest / sg, lo = rest % sg;
         double *o1 = a.part + (int64_t)sl * 2 * CELLS;
         double *o2 = o1 + CELLS;
 #pragma unroll
         for (int k = 0; k < J; ++k) {
-            const int64_t cell = ((int64_t)lg * J + k) * P + p;
-            o1[cell] = s1[k];
-            o2[cell] = s2[k];
+            const int64_t cell = (hi * J + k) * sg + lo;
+            o1[cell] = S1[k];
+            o2[cell] = S2[k];
         }
     }
 }
 
 int32_t approx_slices(const Shape &s, int64_t nnz, int num_cu) {
     const int J = s.ranks[0];
+    const int NP = s.N - 1;
     int64_t waves_per_slice = (int64_t)((J * J + kWave - 1) / kWave);
-    for (int k = 3; k < s.N; ++k) waves_per_slice *= J;
+    if (NP >= 3) waves_per_slice *= J;
+    for (int k = 4; k <= NP; ++k) waves_per_slice *= J;
     // about 16 wavefronts per CU in all, slices of at least 256 entries
     int64_t sl = ((int64_t)16 * num_cu + waves_per_slice - 1) / waves_per_slice;
     sl = std::min<int64_t>(sl, (nnz + 255) / 256);
@@ -198,7 +245,8 @@ hipError_t launch_partial_error(const ApproxArgs &a, const Shape &s, hipStream_t
 #define PTK_X(n_, j_)                                                            \
     if (s.N == n_ && J == j_) {                                                  \
         const int64_t blocks = (int64_t)((j_ * j_ + kWave - 1) / kWave) *        \
-                               ipow(j_, n_ - 3) * a.nslices;                     \
+                               (n_ - 1 >= 3 ? j_ : 1) *                          \
+                               (n_ - 1 >= 4 ? ipow(j_, n_ - 4) : 1) * a.nslices; \
         hipLaunchKernelGGL((k_partial_error<n_, j_>), dim3((unsigned)blocks),     \
                            dim3(kWave), 0, st, a);                               \
         return hipGetLastError();                                                \
