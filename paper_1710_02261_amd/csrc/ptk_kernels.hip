@@ -320,7 +320,7 @@ __global__ __launch_bounds__(kWave) void k_entries_generic(EntryArgs a, int kind
 // Unrolled depth U per (N, J): the unrolled body has J^(U+1) multiply-adds.
 
 #define PTK_FAST_SHAPES(X) \
-    X(3, 3) X(3, 4) X(3, 5) X(3, 8) X(3, 10) X(3, 16) \
+    X(3, 3) X(3, 4) X(3, 5) X(3, 7) X(3, 8) X(3, 9) X(3, 10) X(3, 11) X(3, 16) \
     X(4, 3) X(4, 5) X(4, 8) X(4, 10) \
     X(5, 3) X(5, 5) X(5, 8)
 

@@ -129,11 +129,17 @@ __global__ __launch_bounds__(256) void k_solve_grp(const double *__restrict__ bb
     const bool have = i < I;
     const bool empty = have && rowptr[i] == rowptr[i + 1];
     const bool live = have && !empty;          // uniform within the group
+    if (!live) {
+        // nothing to solve; the group leaves together, so no shuffle below
+        // reads its lanes
+        if (empty && l < J) A[i * J + l] = 0.0f;   // no entry: B = 0, c = 0 -> a = 0
+        return;
+    }
     double b[J];
     double c = 0.0;
 #pragma unroll
     for (int k = 0; k < J; ++k) b[k] = 0.0;
-    if (live && l < J) {
+    if (l < J) {
         const double *sys = bbuf + i * E;
 #pragma unroll
         for (int k = 0; k < J; ++k)
@@ -175,12 +181,7 @@ __global__ __launch_bounds__(256) void k_solve_grp(const double *__restrict__ bb
         const double ar = (__shfl(y, r, G) - t) / __shfl(b[r], r, G);
         if (l == r) a = ar;
     }
-    if (!have) return;
     float *arow = A + i * J;
-    if (empty) {
-        if (l < J) arow[l] = 0.0f;             // no entry: B = 0, c = 0 -> a = 0
-        return;
-    }
     if (!ok) {
         if (l == 0) atomicAdd(bad, 1);         // row left unchanged
         return;

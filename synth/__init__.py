@@ -41,6 +41,7 @@ import numpy as np
 __all__ = [
     "Problem", "uniform_distinct", "zipf_distinct", "weighted_distinct",
     "planted_model", "planted_values", "init_model", "make", "CONFIGS",
+    "make_random", "SWEEPS",
 ]
 
 
@@ -356,6 +357,29 @@ def make_c5(seed=4, n_foldin=100_000, pred_every=20, dims=(100_000, 50_000, 1_00
                              for d in dims])
             reqs.append(("p", None, pidx, None))
     return (G.astype(np.float32), [a.astype(np.float32) for a in A], reqs)
+
+
+def make_random(dims, J, nnz, seed=0, lam=0.01):
+    """The paper's synthetic scalability tensors (Sec. 4.2): equal ranks J,
+    nnz distinct cells at uniform random positions, values U[0, 1); initial
+    model U[0, 1) as in Alg. 2."""
+    rng = np.random.default_rng(seed)
+    idx = uniform_distinct(rng, dims, nnz)
+    val = rng.random(nnz, dtype=np.float64).astype(np.float32)
+    ranks = (J,) * len(dims)
+    G0, A0 = init_model(rng, dims, ranks)
+    return Problem("random", tuple(dims), ranks, idx, val, G0, A0, lam, 1,
+                   {"values": "U[0,1)"})
+
+
+# the four sweeps of Sec. 4.2 (order, dimensionality, observed entries, rank)
+SWEEPS = {
+    "order": [((100,) * N, 3, 1_000) for N in range(3, 11)],
+    "dimensionality": [((I,) * 3, 10, 10 * I) for I in (10**2, 10**3, 10**4, 10**5,
+                                                      10**6, 10**7)],
+    "nnz": [((10**7,) * 3, 10, m) for m in (10**3, 10**4, 10**5, 10**6, 10**7)],
+    "rank": [((10**6,) * 3, J, 10**7) for J in (3, 5, 7, 9, 11)],
+}
 
 
 CONFIGS = {"c1": make_c1, "c2": make_c2, "c3": make_c3, "c4": make_c4}
