@@ -267,45 +267,50 @@ FAST_SHAPES = {3: (3, 4, 5, 7, 8, 9, 10, 11, 16), 4: (3, 5, 8, 10), 5: (3, 5, 8)
 
 def sweeps(args):
     """The paper's four synthetic scalability sweeps (Sec. 4.2: order,
-    dimensionality, observed entries, rank) on one GPU: FP64 arithmetic,
-    graph replay, autotuned ranges; seconds per Alg. 2 iteration."""
+    dimensionality, observed entries, rank) and its Cache-variant comparison
+    over orders 6-10 (Sec. 4.3, plain and pair cache) on one GPU: FP64
+    arithmetic, graph replay, autotuned ranges; seconds per Alg. 2 iteration."""
     import paper_1710_02261_amd as ptk
     import synth
     import torch
-    kinds = args.sweep or ["order", "dimensionality", "nnz", "rank"]
+    kinds = args.sweep or ["order", "dimensionality", "nnz", "rank", "cache"]
     table = []
-    for kind in kinds:
-        for dims, J, nnz in synth.SWEEPS[kind]:
-            t0 = time.perf_counter()
-            p = synth.make_random(dims, J, nnz, seed=11)
-            gen = time.perf_counter() - t0
-            dev = torch.device("cuda:0")
-            idx = torch.from_numpy(p.idx).to(dev)
-            val = torch.from_numpy(p.val).to(dev)
-            core = torch.from_numpy(p.core).to(dev)
-            fac = [torch.from_numpy(a).to(dev) for a in p.factors]
-            ctx = ptk.Context(p.dims, p.ranks)
-            ctx.set_options(precision=0, fuse_error=1, profile=0, use_graph=1)
-            ctx.set_observed(idx, val)
-            ctx.bind_model(core, fac)
-            if nnz >= 100_000:
-                ctx.autotune(None)
-            steps = int(max(3, min(50, 2e8 // max(nnz, 1))))
-            ctx.iterate(1, p.lam, strict=False)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            ctx.iterate(steps, p.lam, strict=False)
-            torch.cuda.synchronize()
-            sec = (time.perf_counter() - t1) / steps
-            ctx.close()
-            row = {"sweep": kind, "N": len(dims), "I": dims[0], "J": J, "nnz": nnz,
-                   "ms_per_iteration": 1e3 * sec, "nnz_iters_per_s": nnz / sec,
-                   "kernel": "fast" if J in FAST_SHAPES.get(len(dims), ()) else "generic"}
-            table.append(row)
-            log("%-14s N=%2d I=%-9d J=%2d nnz=%-10d %9.3f ms/iteration  %.3e nnz*iters/s"
-                "  (generated in %.1f s)" % (kind, len(dims), dims[0], J, nnz, 1e3 * sec,
-                                             nnz / sec, gen))
-            del idx, val, core, fac, p
+    runs = [(kind, dims, J, nnz, cache) for kind in kinds
+            for dims, J, nnz in synth.SWEEPS[kind]
+            for cache in ((0, 1) if kind == "cache" else (0,))]
+    for kind, dims, J, nnz, cache in runs:
+        t0 = time.perf_counter()
+        p = synth.make_random(dims, J, nnz, seed=11)
+        gen = time.perf_counter() - t0
+        dev = torch.device("cuda:0")
+        idx = torch.from_numpy(p.idx).to(dev)
+        val = torch.from_numpy(p.val).to(dev)
+        core = torch.from_numpy(p.core).to(dev)
+        fac = [torch.from_numpy(a).to(dev) for a in p.factors]
+        ctx = ptk.Context(p.dims, p.ranks)
+        ctx.set_options(precision=0, fuse_error=1, profile=0, use_graph=1,
+                        pair_cache=cache)
+        ctx.set_observed(idx, val)
+        ctx.bind_model(core, fac)
+        if nnz >= 100_000:
+            ctx.autotune(None)
+        steps = int(max(3, min(50, 2e8 // max(nnz, 1))))
+        ctx.iterate(1, p.lam, strict=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.iterate(steps, p.lam, strict=False)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t1) / steps
+        ctx.close()
+        row = {"sweep": kind, "N": len(dims), "I": dims[0], "J": J, "nnz": nnz,
+               "ms_per_iteration": 1e3 * sec, "nnz_iters_per_s": nnz / sec,
+               "kernel": "fast" if J in FAST_SHAPES.get(len(dims), ()) else "generic",
+               "pair_cache": cache}
+        table.append(row)
+        log("%-14s N=%2d I=%-9d J=%2d nnz=%-10d cache=%d %9.3f ms/iteration  "
+            "%.3e nnz*iters/s  (generated in %.1f s)"
+            % (kind, len(dims), dims[0], J, nnz, cache, 1e3 * sec, nnz / sec, gen))
+        del idx, val, core, fac, p
     print(json.dumps({
         "metric": "seconds per Alg. 2 iteration on the synthetic scalability tensors",
         "value": None, "unit": "ms/iteration", "n_gpus": 1, "higher_is_better": False,
@@ -324,8 +329,8 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["c5", "sweeps"],
                     default="c2")
     ap.add_argument("--sweep", nargs="*", choices=["order", "dimensionality", "nnz",
-                                                   "rank"],
-                    help="sweeps: which ones (default all four)")
+                                                   "rank", "cache"],
+                    help="sweeps: which ones (default all five)")
     ap.add_argument("--requests", type=int, default=100_000, help="c5: fold-ins")
     ap.add_argument("--slots", type=int, default=2)
     ap.add_argument("--max-batch", type=int, default=1024)

@@ -75,10 +75,10 @@ typedef struct ptk_options {
                                forms its deltas from that table and the new
                                mode-2k row instead of from G. Same result up
                                to rounding. Needs equal ranks, PTK_PREC_FP64_ACC
-                               or PTK_PREC_FP32, (N, J) in {3} x {3,4,5,8,10,16},
-                               {4} x {3,5,8,10} or {5} x {3,5,8} (else
-                               PTK_E_UNSUPPORTED), and (nnz + 1) * R * 8 bytes
-                               of device memory, R = J*J rounded up to even
+                               or PTK_PREC_FP32, 3 <= N <= 10 and J in
+                               {3,4,5,8,10,16} (else PTK_E_UNSUPPORTED),
+                               and (nnz + 1) * R * 8 bytes of device
+                               memory, R = J*J rounded up to even
                                (PTK_E_NOMEM from ptk_set_observed). Chosen
                                before ptk_set_observed. ptk_update_mode,
                                ptk_row_systems and fold-in never use it.      */

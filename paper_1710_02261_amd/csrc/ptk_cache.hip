@@ -114,6 +114,122 @@ __global__ __launch_bounds__(kWave) void k_gram_cache_write(GramArgs a) {
     if (cur >= 0) flush_row<EPL>(a, sl, cur, chunk, cs, ce);
 }
 
+// Writer for any order (equal ranks J <= JMAX): the generic odometer walk
+// over the other modes' cells with the partner p as the slowest digit. The
+// J^(N-2) cells of one partner index m_p, summed without the partner's
+// weight, are T[m_p][:]; delta adds a^(p)[m_p] T[m_p][:].
+template <int JMAX, typename T>
+__device__ __forceinline__ void delta_generic_store(const GramArgs &a, const float *arow,
+                                                    int lane, double (&out)[JMAX],
+                                                    double *tdst) {
+    constexpr int KO = kMaxN - 1;
+    cptr<T> gp = (cptr<T>)a.gp;
+    const int jn = a.jn;
+    const int no = a.nother;
+    int jk[KO], off[KO];
+    int64_t Q = 1;                                    // cells per partner index
+#pragma unroll
+    for (int k = 0; k < KO; ++k) {
+        jk[k] = (k < no) ? a.jk[k] : 1;
+        off[k] = (k < no) ? a.aoff[k] : 0;
+        if (k >= 1) Q *= jk[k];
+    }
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j) out[j] = 0.0;
+    for (int mp = 0; mp < jk[0]; ++mp) {
+        double acc[JMAX];
+#pragma unroll
+        for (int j = 0; j < JMAX; ++j) acc[j] = 0.0;
+        int dig[KO];
+#pragma unroll
+        for (int k = 0; k < KO; ++k) dig[k] = 0;
+        cptr<T> g = gp + (int64_t)mp * Q * jn;
+        for (int64_t o = 0; o < Q; ++o, g += jn) {
+            double w = 1.0;
+#pragma unroll
+            for (int k = 1; k < KO; ++k)
+                if (k < no) w *= (double)arow[(off[k] + dig[k]) * kWave + lane];
+#pragma unroll
+            for (int j = 0; j < JMAX; ++j)
+                if (j < jn) acc[j] = __builtin_fma((double)g[j], w, acc[j]);
+            // odometer over the non-partner modes, last one fastest
+            bool carry = true;
+#pragma unroll
+            for (int k = KO - 1; k >= 1; --k) {
+                if (carry && k < no) {
+                    if (++dig[k] == jk[k])
+                        dig[k] = 0;
+                    else
+                        carry = false;
+                }
+            }
+        }
+        const double wp = (double)arow[(off[0] + mp) * kWave + lane];
+#pragma unroll
+        for (int j = 0; j < JMAX; ++j) {
+            if (j < jn) {
+                tdst[mp * jn + j] = acc[j];
+                out[j] = __builtin_fma(wp, acc[j], out[j]);
+            }
+        }
+    }
+}
+
+template <int JMAX, typename T>
+__global__ __launch_bounds__(kWave) void k_gram_cache_write_generic(GramArgs a) {
+    constexpr int EPL = (sys_entries(JMAX) + kWave - 1) / kWave;
+    extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
+    __shared__ int s_row[kWave];
+    const int lane = threadIdx.x;
+    const int J = a.jn;
+    const int RS = (J * J + 1) / 2 * 2;
+    // LDS: [other-mode rows: sum jk x 64 floats][dl: (J+1) x kDlStride doubles]
+    int sumj = 0;
+    for (int k = 0; k < a.nother; ++k) sumj += a.jk[k];
+    float *s_arow = (float *)s_dyn;
+    double *s_dl = (double *)(s_dyn + ((sumj * kWave * 4 + 15) / 16) * 16);
+    const int64_t chunk = blockIdx.x;
+    const int64_t cs = chunk * a.chunk;
+    const int64_t ce = min(cs + a.chunk, a.nnz);
+    SysLane<EPL> sl;
+    sl.init(lane, J);
+    int cur = -1;
+    for (int64_t base = cs; base < ce; base += kWave) {
+        const int64_t pos = base + lane;
+        const bool valid = pos < ce;
+        const int nb = (int)min((int64_t)kWave, ce - base);
+        const int row = valid ? a.rows[pos] : 0;
+        const float x = valid ? a.val[pos] : 0.0f;
+        for (int k = 0; k < a.nother; ++k) {
+            const int32_t i = valid ? a.oidx[k][pos] : 0;
+            const int jk = a.jk[k];
+            const float *r = a.fac[k] + (int64_t)i * jk;
+            for (int j = 0; j < jk; ++j) s_arow[(a.aoff[k] + j) * kWave + lane] = r[j];
+        }
+        __syncthreads();
+        double d[JMAX];
+        // lanes past the range write the spare record at index nnz
+        delta_generic_store<JMAX, T>(a, s_arow, lane, d,
+                                     a.cache + (valid ? pos : a.nnz) * RS);
+#pragma unroll
+        for (int j = 0; j < JMAX; ++j)
+            if (j < J) s_dl[j * kDlStride + lane] = d[j];
+        s_dl[J * kDlStride + lane] = (double)x;
+        s_row[lane] = row;
+        __syncthreads();
+        sweep_tile<EPL>(a, sl, s_dl, s_row, nb, cur, chunk, cs, ce);
+        __syncthreads();
+    }
+    if (cur >= 0) flush_row<EPL>(a, sl, cur, chunk, cs, ce);
+}
+
+static size_t cache_generic_lds_bytes(const GramArgs &a) {
+    int sumj = 0;
+    for (int k = 0; k < a.nother; ++k) sumj += a.jk[k];
+    const size_t arow = ((size_t)sumj * kWave * 4 + 15) / 16 * 16;
+    return arow + (size_t)(a.jn + 1) * kDlStride * 8;
+}
+
 // Reader: delta^(p)[m] = sum_j a^(n)_{i_n}[j] T[m][j] with T written by the
 // partner's update (same sweep, so the other modes have not changed since).
 // Records sit at random writer positions: the wavefront loads them whole,
@@ -222,11 +338,32 @@ __global__ __launch_bounds__(kWave) void k_gram_cache_read(GramArgs a) {
 
 int cache_record_doubles(int J) { return cache_record(J); }
 
+static bool cache_reader_rank(int J) {
+    return J == 3 || J == 4 || J == 5 || J == 8 || J == 10 || J == 16;
+}
+
+// Any order from 3 up with a reader for rank J; the writer is the unrolled
+// kernel for the listed shapes, else the generic one.
 bool cache_available(int N, int J) {
-#define PTK_X(n_, j_) if (N == n_ && J == j_) return true;
-    PTK_CACHE_SHAPES(PTK_X)
-#undef PTK_X
-    return false;
+    return N >= 3 && N <= kMaxN && cache_reader_rank(J);
+}
+
+template <typename T>
+static int generic_writer_blocks(int J, size_t lds) {
+    if (J <= 4) return blocks_per_cu(k_gram_cache_write_generic<4, T>, lds);
+    if (J <= 8) return blocks_per_cu(k_gram_cache_write_generic<8, T>, lds);
+    return blocks_per_cu(k_gram_cache_write_generic<16, T>, lds);
+}
+
+template <typename T>
+static void launch_generic_writer(const GramArgs &a, dim3 grid, size_t lds, hipStream_t st) {
+    dim3 block(kWave);
+    if (a.jn <= 4)
+        hipLaunchKernelGGL((k_gram_cache_write_generic<4, T>), grid, block, lds, st, a);
+    else if (a.jn <= 8)
+        hipLaunchKernelGGL((k_gram_cache_write_generic<8, T>), grid, block, lds, st, a);
+    else
+        hipLaunchKernelGGL((k_gram_cache_write_generic<16, T>), grid, block, lds, st, a);
 }
 
 int gram_cache_blocks_per_cu(const Shape &s, int n, Arith ar, int cm) {
@@ -247,7 +384,13 @@ int gram_cache_blocks_per_cu(const Shape &s, int n, Arith ar, int cm) {
                                : blocks_per_cu(k_gram_cache_write<n_, j_, float>, 0);
     PTK_CACHE_SHAPES(PTK_X)
 #undef PTK_X
-    return 1;
+    GramArgs a{};
+    a.nother = s.N - 1;
+    a.jn = J;
+    for (int k = 0; k < s.N - 1; ++k) a.jk[k] = J;
+    const size_t lds = cache_generic_lds_bytes(a);
+    return ar == kArithF64 ? generic_writer_blocks<double>(J, lds)
+                           : generic_writer_blocks<float>(J, lds);
 }
 
 hipError_t launch_gram_cache(const GramArgs &a, const Shape &s, int n, Arith ar,
@@ -279,7 +422,13 @@ hipError_t launch_gram_cache(const GramArgs &a, const Shape &s, int n, Arith ar,
     }
     PTK_CACHE_SHAPES(PTK_X)
 #undef PTK_X
-    return hipErrorInvalidValue;
+    if (J > 16 || a.nother != s.N - 1) return hipErrorInvalidValue;
+    const size_t lds = cache_generic_lds_bytes(a);
+    if (ar == kArithF64)
+        launch_generic_writer<double>(a, grid, lds, st);
+    else
+        launch_generic_writer<float>(a, grid, lds, st);
+    return hipGetLastError();
 }
 
 }  // namespace ptk

@@ -379,6 +379,8 @@ SWEEPS = {
                                                       10**6, 10**7)],
     "nnz": [((10**7,) * 3, 10, m) for m in (10**3, 10**4, 10**5, 10**6, 10**7)],
     "rank": [((10**6,) * 3, J, 10**7) for J in (3, 5, 7, 9, 11)],
+    # the Cache-variant comparison of Sec. 4.3 (orders 6-10)
+    "cache": [((100,) * N, 3, 1_000) for N in range(6, 11)],
 }
 
 

@@ -8,7 +8,8 @@ of the sweep within the same 1e-5 relative. With FP32 delta arithmetic
 (PTK_PREC_FP32) the bound is the one stated for that arithmetic without the
 cache, 1e-3 per row (ill-conditioned rows amplify FP32 rounding). Cases:
 
-* every shape with a cache kernel, in FP64 and FP32 delta arithmetic;
+* every shape with an unrolled writer, and the generic writer at orders 3-10,
+  in FP64 and FP32 delta arithmetic;
 * rows crossing work ranges (tiny work ranges, skewed rows);
 * factor entries planted at exactly 0 (the paper's cache divides by the old
   factor value and needs a fallback there; this form never divides);
@@ -36,7 +37,12 @@ SHAPES = [((40, 35, 30), 3), ((40, 35, 30), 4), ((40, 35, 30), 5),
           ((50, 45, 40), 8), ((50, 45, 40), 10), ((60, 50, 40), 16),
           ((14, 13, 12, 11), 3), ((14, 13, 12, 11), 5), ((14, 13, 12, 11), 8),
           ((14, 13, 12, 11), 10),
-          ((9, 8, 7, 6, 5), 3), ((9, 8, 7, 6, 5), 5), ((9, 8, 7, 6, 5), 8)]
+          ((9, 8, 7, 6, 5), 3), ((9, 8, 7, 6, 5), 5), ((9, 8, 7, 6, 5), 8),
+          # generic writer: orders 6-10 and shapes without an unrolled writer
+          ((8, 7, 6, 6, 5, 5), 3), ((7,) * 7, 3), ((6,) * 8, 3), ((5,) * 9, 3),
+          ((5,) * 10, 3), ((8, 7, 6, 6, 5, 5), 4), ((14, 13, 12, 11), 4),
+          ((9, 8, 7, 6, 5), 4), ((9, 8, 7, 6, 5), 10), ((30, 25, 20), 16),
+          ((16, 15, 14, 13), 16)]
 
 
 def ids():
@@ -74,7 +80,8 @@ def check_sweep(p, fac, sse, lam, tol=1e-5):
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("dims,J", SHAPES, ids=ids())
 def test_cache_sweep_matches_oracle(dims, J, prec):
-    p = synth.make_small(dims, (J,) * len(dims), 6000, seed=41, skew=1.1)
+    nnz = 6000 if len(dims) <= 8 else 2000          # the oracle's J^N cost
+    p = synth.make_small(dims, (J,) * len(dims), nnz, seed=41, skew=1.1)
     ctx, idx, val, core, fac = context(p, precision=prec, fuse_error=0, pair_cache=1)
     sse, _ = ctx.iterate(1, p.lam, strict=False)
     errs = check_sweep(p, fac, sse[0], p.lam, tol=1e-5 if prec == 0 else 1e-3)
@@ -83,7 +90,8 @@ def test_cache_sweep_matches_oracle(dims, J, prec):
 
 
 @pytest.mark.parametrize("dims,J", [((30, 200, 150), 10), ((8, 300, 9, 200), 5),
-                                    ((100, 6, 7, 120, 5), 3), ((40, 200, 30), 16)])
+                                    ((100, 6, 7, 120, 5), 3), ((40, 200, 30), 16),
+                                    ((60, 5, 6, 80, 5, 4, 5), 3)])
 def test_cache_rows_across_work_ranges(dims, J):
     # 64-entry ranges: long rows of every mode cross ranges and are merged
     p = synth.make_small(dims, (J,) * len(dims), 20000, seed=42, skew=1.3)
@@ -209,9 +217,13 @@ def test_cache_refusals():
     with pytest.raises(ptk.PtkError, match="PTK_E_UNSUPPORTED"):
         ctx.set_options(pair_cache=1)                      # unequal ranks
     ctx.close()
-    ctx = ptk.Context((10,) * 6, (3,) * 6)
+    ctx = ptk.Context((10,) * 3, (7,) * 3)
     with pytest.raises(ptk.PtkError, match="PTK_E_UNSUPPORTED"):
-        ctx.set_options(pair_cache=1)                      # no kernel for order 6
+        ctx.set_options(pair_cache=1)                      # no reader for rank 7
+    ctx.close()
+    ctx = ptk.Context((10,) * 2, (3,) * 2)
+    with pytest.raises(ptk.PtkError, match="PTK_E_UNSUPPORTED"):
+        ctx.set_options(pair_cache=1)                      # order 2: nothing to cache
     ctx.close()
     ctx = ptk.Context((30, 30, 30), (8, 8, 8))
     with pytest.raises(ptk.PtkError, match="PTK_E_UNSUPPORTED"):
