@@ -94,6 +94,19 @@ typedef struct ptk_options {
                                removal. Equal ranks and (N, J) in {3} x
                                {3,4,5,8,10,16}, {4} x {3,5,8,10} or {5} x
                                {3,5,8} (else PTK_E_UNSUPPORTED).             */
+    int32_t delta_slices;   /* generic-kernel modes only (shapes without an
+                               unrolled kernel): the delta sum of every entry
+                               (Eq. 8) cut into this many slices of the core's
+                               cells, one wavefront per 64 entries and slice,
+                               partial sums added in slice order by a second
+                               kernel. For observed sets too small to fill
+                               the GPU otherwise (high orders, few entries).
+                               0 = auto (sliced when nnz <= 64 * 16 * CUs),
+                               1 = never, S > 1 = S slices (at most 65535;
+                               a pair-cache writer rounds S up to a multiple
+                               of its partner's rank, and no slice gets fewer
+                               than one cell). Extra device memory: S * J_n *
+                               nnz doubles. Chosen before ptk_set_observed.  */
 } ptk_options;
 
 /*

@@ -18,6 +18,7 @@
 #include "ptk_approx.h"
 #include "ptk_context.h"
 #include "ptk_internal.h"
+#include "ptk_slice.h"
 
 using namespace ptk;
 
@@ -108,6 +109,8 @@ void free_modes(ptk_ctx *c) {
     dfree(c->part);
     dfree(c->pcache);
     c->pcache = nullptr;
+    dfree(c->dpart);
+    c->dpart = nullptr;
     dfree(c->ap_resid);
     dfree(c->ap_part);
     dfree(c->ap_R);
@@ -201,6 +204,8 @@ GramArgs gram_args(const ptk_ctx *c, int n) {
     return a;
 }
 
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
 // Pair-cache arguments. Writer n: other-mode slots reordered so that the
 // partner n+1 (slot n of the ascending list) leads, as in its permuted core.
 // Reader n: the partner n-1 is slot n-1 of the ascending list.
@@ -258,6 +263,23 @@ ptk_status systems(ptk_ctx *c, int n, int role = 0) {
         }));
         HIPCHK(c, timed(c, "merge", [&] {
             return launch_merge(c->part, m.split, m.nsplit, a.E, c->bbuf, c->st);
+        }));
+        return PTK_OK;
+    }
+    if (m.slices > 1 && role != 2) {
+        SliceArgs sa{};
+        sa.g = role == 1 ? cache_args(c, n, role) : gram_args(c, n);
+        sa.dpart = c->dpart;
+        sa.nnzp = round_up(c->nnz, kWave);
+        sa.S = m.slices;
+        sa.sub = role == 1 ? m.slice_sub : m.slices;
+        sa.writer = role == 1;
+        HIPCHK(c, timed(c, "delta_slices", [&] { return launch_delta_slices(sa, c->st); }));
+        HIPCHK(c, timed(c, role == 1 ? "gram_cache_write" : "gram", [&] {
+            return launch_gram_slices(sa, m.nchunks, c->st);
+        }));
+        HIPCHK(c, timed(c, "merge", [&] {
+            return launch_merge(c->part, m.split, m.nsplit, sa.g.E, c->bbuf, c->st);
         }));
         return PTK_OK;
     }
@@ -384,8 +406,6 @@ ptk_status check_bad(ptk_ctx *c, const char *what) {
     return PTK_OK;
 }
 
-int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
-
 // Default work per wavefront: one round of resident wavefronts covers the mode.
 int64_t default_work(const ptk_ctx *c, int n) {
     const ModeData &m = c->md[n];
@@ -395,8 +415,10 @@ int64_t default_work(const ptk_ctx *c, int n) {
         return std::max<int64_t>(1, (m.nblk + waves - 1) / std::max<int64_t>(waves, 1));
     }
     const int role = cache_role(c, n);
-    const int bpc = role ? gram_cache_blocks_per_cu(c->s, n, arith_of(c, n), role)
-                         : gram_blocks_per_cu(c->s, n, arith_of(c, n), m.fast);
+    const int bpc = (m.slices > 1 && role != 2)
+                        ? gram_slices_blocks_per_cu(c->s.ranks[n])
+                    : role ? gram_cache_blocks_per_cu(c->s, n, arith_of(c, n), role)
+                           : gram_blocks_per_cu(c->s, n, arith_of(c, n), m.fast);
     const int64_t waves = (int64_t)c->num_cu * std::max(1, bpc);
     int64_t chunk = round_up((c->nnz + waves - 1) / std::max<int64_t>(waves, 1), kWave);
     return std::max<int64_t>(chunk, kWave);
@@ -718,6 +740,10 @@ ptk_status ptk_set_options(ptk_ctx *c, const ptk_options *o) {
                     "no pair-cache kernel for this shape and precision");
     if (o->pair_cache != c->opt.pair_cache && c->nnz >= 0)
         return fail(c, PTK_E_STATE, "pair_cache must be set before ptk_set_observed");
+    if (o->delta_slices < 0 || o->delta_slices > 65535)
+        return fail(c, PTK_E_INVALID, "delta_slices must be in [0, 65535]");
+    if (o->delta_slices != c->opt.delta_slices && c->nnz >= 0)
+        return fail(c, PTK_E_STATE, "delta_slices must be set before ptk_set_observed");
     if (!(o->approx_rate >= 0.0 && o->approx_rate < 1.0))
         return fail(c, PTK_E_INVALID, "approx_rate must be in [0, 1)");
     if (o->approx_rate > 0.0 &&
@@ -797,6 +823,16 @@ ptk_status ptk_set_observed(ptk_ctx *c, int64_t nnz, const int32_t *idx,
                         "CSR build of mode %d: %s", n, hipGetErrorString(e));
         }
         m.fast = eq && fast_available(N, s.ranks[n], kArithF64);
+        const bool bf = c->opt.precision == PTK_PREC_BF16 ||
+                        c->opt.precision == PTK_PREC_BF16X3;
+        m.slices = m.slice_sub = 1;
+        if (!m.fast && !bf && role != 2 && nnz > 0 && c->opt.delta_slices != 1) {
+            const int partner = role == 1 ? n + 1 : -1;
+            m.slices = c->opt.delta_slices > 1
+                           ? slice_fixed(s, n, partner, c->opt.delta_slices)
+                           : slice_count(s, n, partner, nnz, c->num_cu);
+            m.slice_sub = role == 1 ? m.slices / s.ranks[n + 1] : m.slices;
+        }
     }
     hipError_t e = hipStreamSynchronize(c->st);
     dfree(work);
@@ -805,6 +841,16 @@ ptk_status ptk_set_observed(ptk_ctx *c, int64_t nnz, const int32_t *idx,
     if (e != hipSuccess) {
         free_modes(c);
         HIPCHK(c, e);
+    }
+    int64_t dpart_need = 0;
+    for (int n = 0; n < N; ++n)
+        if (c->md[n].slices > 1)
+            dpart_need = std::max(dpart_need, slice_part_doubles(s.ranks[n], nnz,
+                                                                 c->md[n].slices));
+    if (dpart_need > 0 && dalloc(&c->dpart, (size_t)dpart_need) != hipSuccess) {
+        free_modes(c);
+        return fail(c, PTK_E_NOMEM, "slice partials: %.2f GB of device memory",
+                    dpart_need * 8e-9);
     }
     if (c->opt.pair_cache) {
         const int64_t rec = cache_record_doubles(s.ranks[0]);

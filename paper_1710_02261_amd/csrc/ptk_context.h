@@ -24,6 +24,9 @@ struct ModeData {
     int32_t *split = nullptr;    // [nsplit][3]
     int32_t nsplit = 0;
     bool fast = false;
+    // generic path on a small observed set: the delta sum cut into slices
+    // of the core cells (1: unsliced), sub slices per partner index
+    int32_t slices = 1, slice_sub = 1;
     // BF16 matrix-core form: blocks of <= 32 entries of one row
     bool bf16 = false;
     int split_bf16 = 1;          // 1: bf16 operands; 3: hi/lo split products
@@ -51,7 +54,7 @@ struct ptk_ctx {
     hipStream_t st = nullptr;
     int device = 0;
     int num_cu = 256;
-    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1, 0, 0.0};
+    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1, 0, 0.0, 0};
     int64_t nnz = -1;
     ModeData md[ptk::kMaxN];
     float *core = nullptr;
@@ -64,6 +67,7 @@ struct ptk_ctx {
     double *bbuf = nullptr;
     double *part = nullptr;
     double *pcache = nullptr;    // pair cache [nnz + 1][J][J]
+    double *dpart = nullptr;     // slice partials of the sliced delta path
     // Approx variant: residuals [nnz], slice sums, R per cell, removed count
     double *ap_resid = nullptr, *ap_part = nullptr, *ap_R = nullptr;
     int32_t *ap_removed = nullptr;

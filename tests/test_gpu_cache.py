@@ -9,7 +9,9 @@ of the sweep within the same 1e-5 relative. With FP32 delta arithmetic
 cache, 1e-3 per row (ill-conditioned rows amplify FP32 rounding). Cases:
 
 * every shape with an unrolled writer, and the generic writer at orders 3-10,
-  in FP64 and FP32 delta arithmetic;
+  in FP64 and FP32 delta arithmetic; the generic writer with its delta sum
+  sliced over the core cells (automatic, forced, one slice per cell) and
+  unsliced;
 * rows crossing work ranges (tiny work ranges, skewed rows);
 * factor entries planted at exactly 0 (the paper's cache divides by the old
   factor value and needs a fallback there; this form never divides);
@@ -86,6 +88,20 @@ def test_cache_sweep_matches_oracle(dims, J, prec):
     sse, _ = ctx.iterate(1, p.lam, strict=False)
     errs = check_sweep(p, fac, sse[0], p.lam, tol=1e-5 if prec == 0 else 1e-3)
     log("pair cache", dims, J, "prec", prec, "max row rel err per mode", errs)
+    ctx.close()
+
+
+@pytest.mark.parametrize("slices", [1, 5, 65535], ids=["unsliced", "s5", "capped"])
+@pytest.mark.parametrize("dims,J", [((8, 7, 6, 6, 5, 5), 3), ((14, 13, 12, 11), 4),
+                                    ((6,) * 8, 3)], ids=["6d-J3", "4d-J4", "8d-J3"])
+def test_cache_generic_writer_slicing(dims, J, slices):
+    # the generic writer with its delta sum unsliced (one wavefront per 64
+    # entries), with a forced slice count (rounded up to a multiple of J)
+    # and with one slice per cell
+    p = synth.make_small(dims, (J,) * len(dims), 4000, seed=52, skew=1.1)
+    ctx, idx, val, core, fac = context(p, fuse_error=0, pair_cache=1, delta_slices=slices)
+    sse, _ = ctx.iterate(1, p.lam, strict=False)
+    check_sweep(p, fac, sse[0], p.lam)
     ctx.close()
 
 
