@@ -34,6 +34,11 @@ KERNEL_SRC = [os.path.join(ROOT, "paper_1710_02261_amd", "csrc", f)
               for f in ("ptk_kernels.hip", "ptk_device.h", "ptk_internal.h")]
 
 
+def command_line():
+    """The command that produced a record (kept with the record)."""
+    return " ".join(["python", "bench.py"] + sys.argv[1:])
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -257,6 +262,7 @@ def serving(args):
                               "predict_p99_ms": pct(plat[~pk], 99)},
     }
     ctx.close()
+    out["command"] = command_line()
     print(json.dumps(out), flush=True)
 
 
@@ -318,7 +324,7 @@ def sweeps(args):
         "config": {"workload": "random tensors of Sec. 4.2: values U[0,1) at uniform "
                                "distinct cells, equal ranks, U[0,1) initial model, seed 11",
                    "sweeps": kinds},
-        "table": table}))
+        "table": table, "command": command_line()}), flush=True)
 
 
 def main():
@@ -555,6 +561,7 @@ def main():
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
         log("cpu baseline in %.1f s" % (time.perf_counter() - t0))
+    out["command"] = command_line()
     print(json.dumps(out), flush=True)
 
 

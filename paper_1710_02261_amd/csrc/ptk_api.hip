@@ -273,6 +273,7 @@ ptk_status systems(ptk_ctx *c, int n, int role = 0) {
         sa.nnzp = round_up(c->nnz, kWave);
         sa.S = m.slices;
         sa.sub = role == 1 ? m.slice_sub : m.slices;
+        sa.W = m.slice_w;
         sa.writer = role == 1;
         HIPCHK(c, timed(c, "delta_slices", [&] { return launch_delta_slices(sa, c->st); }));
         HIPCHK(c, timed(c, role == 1 ? "gram_cache_write" : "gram", [&] {
@@ -825,13 +826,13 @@ ptk_status ptk_set_observed(ptk_ctx *c, int64_t nnz, const int32_t *idx,
         m.fast = eq && fast_available(N, s.ranks[n], kArithF64);
         const bool bf = c->opt.precision == PTK_PREC_BF16 ||
                         c->opt.precision == PTK_PREC_BF16X3;
-        m.slices = m.slice_sub = 1;
-        if (!m.fast && !bf && role != 2 && nnz > 0 && c->opt.delta_slices != 1) {
-            const int partner = role == 1 ? n + 1 : -1;
-            m.slices = c->opt.delta_slices > 1
-                           ? slice_fixed(s, n, partner, c->opt.delta_slices)
-                           : slice_count(s, n, partner, nnz, c->num_cu);
-            m.slice_sub = role == 1 ? m.slices / s.ranks[n + 1] : m.slices;
+        m.slices = m.slice_sub = m.slice_w = 1;
+        if (!m.fast && !bf && role != 2) {
+            const SlicePlan sp = slice_plan(s, n, role == 1 ? n + 1 : -1, nnz, c->num_cu,
+                                            c->opt.delta_slices);
+            m.slices = sp.S;
+            m.slice_sub = sp.sub;
+            m.slice_w = sp.W;
         }
     }
     hipError_t e = hipStreamSynchronize(c->st);
@@ -845,8 +846,10 @@ ptk_status ptk_set_observed(ptk_ctx *c, int64_t nnz, const int32_t *idx,
     int64_t dpart_need = 0;
     for (int n = 0; n < N; ++n)
         if (c->md[n].slices > 1)
-            dpart_need = std::max(dpart_need, slice_part_doubles(s.ranks[n], nnz,
-                                                                 c->md[n].slices));
+            dpart_need = std::max(
+                dpart_need, slice_part_doubles(s.ranks[n], nnz,
+                                               SlicePlan{c->md[n].slices, c->md[n].slice_sub,
+                                                         c->md[n].slice_w}));
     if (dpart_need > 0 && dalloc(&c->dpart, (size_t)dpart_need) != hipSuccess) {
         free_modes(c);
         return fail(c, PTK_E_NOMEM, "slice partials: %.2f GB of device memory",

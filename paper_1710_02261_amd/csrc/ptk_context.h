@@ -25,8 +25,9 @@ struct ModeData {
     int32_t nsplit = 0;
     bool fast = false;
     // generic path on a small observed set: the delta sum cut into slices
-    // of the core cells (1: unsliced), sub slices per partner index
-    int32_t slices = 1, slice_sub = 1;
+    // of the core cells (1: unsliced), sub slices per partner index, W
+    // slices per workgroup
+    int32_t slices = 1, slice_sub = 1, slice_w = 1;
     // BF16 matrix-core form: blocks of <= 32 entries of one row
     bool bf16 = false;
     int split_bf16 = 1;          // 1: bf16 operands; 3: hi/lo split products
