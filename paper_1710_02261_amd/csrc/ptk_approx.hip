@@ -22,11 +22,13 @@
 // value p of the last two other modes, the wavefront fixes the others (the
 // third-last through one index k, the ones before through its lead group),
 // and it accumulates the J values of beta_g for each of them. It walks a
-// slice of the entries, 32 at a time: lanes 0..31 stage each entry's
+// slice of the entries, 64 at a time: each lane stages one entry's
 // residual-weighted leading product in LDS (the same for the whole
-// wavefront, read back as one broadcast per entry), then every lane gathers
-// its two last-mode elements for the 32 entries at once and accumulates.
-// Sums are FP64; the slices are reduced in a fixed order.
+// wavefront, read back as one broadcast per entry), the wavefront then
+// copies the 64 entries' rows of the last two other modes into LDS with
+// contiguous loads, and every lane reads its two elements per entry from
+// there and accumulates. Sums are FP64; the slices are reduced in a fixed
+// order.
 #include "ptk_approx.h"
 #include "ptk_device.h"
 
@@ -100,7 +102,7 @@ hipError_t launch_residual(const EntryArgs &a, const Shape &s, int64_t nblocks,
 // ---------------------------------------------------------------------------
 // S1, S2 per slice of entries
 // ---------------------------------------------------------------------------
-constexpr int kApproxChunk = 32;      // entries staged per step
+constexpr int kApproxChunk = kWave;   // entries staged per step
 
 template <int N, int J>
 __global__ __launch_bounds__(kWave) void k_partial_error(ApproxArgs a) {
@@ -114,6 +116,7 @@ __global__ __launch_bounds__(kWave) void k_partial_error(ApproxArgs a) {
     typedef double double2v __attribute__((ext_vector_type(2)));
     __shared__ double2v s_uw[CH];         // (r q, q^2) per staged entry
     __shared__ int32_t s_ia[CH], s_ib[CH], s_row[CH];
+    __shared__ float s_va[CH * J], s_vb[CH * J];   // rows of the last two modes
     const int lane = threadIdx.x;
     int b = blockIdx.x;
     const int pg = b % NPG;
@@ -153,8 +156,8 @@ __global__ __launch_bounds__(kWave) void k_partial_error(ApproxArgs a) {
     const float *fa = a.fac[NP - 2], *fb = a.fac[NP - 1];
     for (int64_t base = e0; base < e1; base += CH) {
         const int nb = (int)min((int64_t)CH, e1 - base);
-        // stage: lane t < CH takes entry base + t
-        if (lane < CH) {
+        // stage: lane t takes entry base + t
+        {
             const bool ok = lane < nb;
             const int64_t e = base + lane;
             double q = 0.0, r = 0.0;
@@ -172,14 +175,14 @@ __global__ __launch_bounds__(kWave) void k_partial_error(ApproxArgs a) {
             s_row[lane] = ok ? a.rows[e] : -1;
         }
         __syncthreads();
-        // this lane's elements of the last two modes for the staged entries
-        float va[CH], vb[CH];
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            va[u] = fa[(int64_t)s_ia[u] * J + m1];
-            vb[u] = fb[(int64_t)s_ib[u] * J + m2];
+        // the staged entries' rows of the last two other modes
+        for (int t = lane; t < CH * J; t += kWave) {
+            const int u = t / J, j = t % J;
+            s_va[t] = fa[(int64_t)s_ia[u] * J + j];
+            s_vb[t] = fb[(int64_t)s_ib[u] * J + j];
         }
-#pragma unroll
+        __syncthreads();
+#pragma unroll 8
         for (int u = 0; u < CH; ++u) {
             if (u < nb) {                 // uniform
                 const int row = s_row[u];
@@ -189,7 +192,7 @@ __global__ __launch_bounds__(kWave) void k_partial_error(ApproxArgs a) {
                     t1 = t2 = 0.0;
                 }
                 const double2v uw = s_uw[u];
-                const double v = (double)va[u] * (double)vb[u];
+                const double v = (double)s_va[u * J + m1] * (double)s_vb[u * J + m2];
                 t1 = __builtin_fma(uw.x, v, t1);
                 t2 = __builtin_fma(uw.y, v * v, t2);
             }
