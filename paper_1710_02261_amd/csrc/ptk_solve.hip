@@ -112,8 +112,8 @@ __global__ void k_solve(const double *__restrict__ bbuf,
 // The same solve with a group of G lanes per row (G = 4, 8 or 16 >= J,
 // 64/G rows per wavefront): lane l keeps row l of B + lambda I in registers.
 // Cholesky column by column (the diagonal and the new column are broadcast
-// within the group), then L y = c with each y_r broadcast, then L^T a = y
-// with a group reduction per step. FP64; a failed diagonal leaves the row
+// within the group, 1 / L_kk kept in every lane), then L y = c with each y_r
+// broadcast, then L^T a = y with a group reduction per step. FP64; a failed diagonal leaves the row
 // unchanged and is counted, as in k_solve.
 template <int J>
 __global__ __launch_bounds__(256) void k_solve_grp(const double *__restrict__ bbuf,
@@ -150,12 +150,14 @@ __global__ __launch_bounds__(256) void k_solve_grp(const double *__restrict__ bb
             if (k == l) b[k] += lambda;
     }
     bool ok = true;
+    double rinv[J];                            // 1 / L_kk, the same in every lane
 #pragma unroll
     for (int k = 0; k < J; ++k) {
         const double d = __shfl(b[k], k, G);   // updated B_kk
         ok = ok && d > 0.0;
         const double lkk = sqrt(d > 0.0 ? d : 1.0);
-        const double mine = (l == k) ? lkk : b[k] / lkk;   // L_lk (l >= k)
+        rinv[k] = 1.0 / lkk;
+        const double mine = (l == k) ? lkk : b[k] * rinv[k];   // L_lk (l >= k)
         b[k] = mine;
 #pragma unroll
         for (int j = k + 1; j < J; ++j) {
@@ -167,7 +169,7 @@ __global__ __launch_bounds__(256) void k_solve_grp(const double *__restrict__ bb
     double y = c;
 #pragma unroll
     for (int r = 0; r < J; ++r) {
-        const double yr = __shfl(y, r, G) / __shfl(b[r], r, G);
+        const double yr = __shfl(y, r, G) * rinv[r];
         if (l == r) y = yr;
         if (l > r) y = __builtin_fma(-b[r], yr, y);
     }
@@ -178,7 +180,7 @@ __global__ __launch_bounds__(256) void k_solve_grp(const double *__restrict__ bb
         double t = (l > r && l < J) ? b[r] * a : 0.0;
 #pragma unroll
         for (int off = G / 2; off > 0; off >>= 1) t += __shfl_xor(t, off, G);
-        const double ar = (__shfl(y, r, G) - t) / __shfl(b[r], r, G);
+        const double ar = (__shfl(y, r, G) - t) * rinv[r];
         if (l == r) a = ar;
     }
     float *arow = A + i * J;
@@ -189,10 +191,88 @@ __global__ __launch_bounds__(256) void k_solve_grp(const double *__restrict__ bb
     if (l < J) arow[l] = (float)a;
 }
 
+// One row per lane for J <= 11: the packed system (J(J+1)/2 + J doubles)
+// lives in the lane's registers, with every index known at compile time, so
+// the factorisation and both substitutions are plain FMA chains with no
+// exchange between lanes; 64 rows per wavefront run side by side. The upper
+// triangle is overwritten by L^T (Cholesky, right-looking); same results,
+// failure rule and empty-row rule as k_solve_grp.
+template <int J>
+__global__ __launch_bounds__(kWave) void k_solve_row(const double *__restrict__ bbuf,
+                                                     const int64_t *__restrict__ rowptr,
+                                                     int64_t I, double lambda,
+                                                     float *__restrict__ A,
+                                                     int32_t *__restrict__ bad) {
+    constexpr int T = J * (J + 1) / 2;
+    constexpr int E = T + J;
+    const int64_t i = (int64_t)blockIdx.x * kWave + threadIdx.x;
+    if (i >= I) return;
+    float *arow = A + i * J;
+    if (rowptr[i] == rowptr[i + 1]) {          // no entry: B = 0, c = 0 -> a = 0
+#pragma unroll
+        for (int k = 0; k < J; ++k) arow[k] = 0.0f;
+        return;
+    }
+    const double *sys = bbuf + i * E;
+    double m[T], y[J];
+#pragma unroll
+    for (int t = 0; t < T; ++t) m[t] = sys[t];
+#pragma unroll
+    for (int k = 0; k < J; ++k) y[k] = sys[T + k];
+#pragma unroll
+    for (int k = 0; k < J; ++k) m[tri_pos(k, k, J)] += lambda;
+    bool ok = true;
+    double rinv[J];
+#pragma unroll
+    for (int k = 0; k < J; ++k) {
+        const double d = m[tri_pos(k, k, J)];
+        ok = ok && d > 0.0;
+        const double lkk = sqrt(d > 0.0 ? d : 1.0);
+        rinv[k] = 1.0 / lkk;
+#pragma unroll
+        for (int j = k + 1; j < J; ++j) m[tri_pos(k, j, J)] *= rinv[k];   // L_jk
+#pragma unroll
+        for (int j = k + 1; j < J; ++j) {
+#pragma unroll
+            for (int q = j; q < J; ++q)
+                m[tri_pos(j, q, J)] =
+                    __builtin_fma(-m[tri_pos(k, j, J)], m[tri_pos(k, q, J)], m[tri_pos(j, q, J)]);
+        }
+    }
+    // L y = c, then L^T a = y (L_rk at (k, r) of the upper triangle)
+#pragma unroll
+    for (int r = 0; r < J; ++r) {
+#pragma unroll
+        for (int k = 0; k < r; ++k) y[r] = __builtin_fma(-m[tri_pos(k, r, J)], y[k], y[r]);
+        y[r] *= rinv[r];
+    }
+#pragma unroll
+    for (int r = J - 1; r >= 0; --r) {
+#pragma unroll
+        for (int k = r + 1; k < J; ++k) y[r] = __builtin_fma(-m[tri_pos(r, k, J)], y[k], y[r]);
+        y[r] *= rinv[r];
+    }
+    if (!ok) {
+        atomicAdd(bad, 1);                     // row left unchanged
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < J; ++k) arow[k] = (float)y[k];
+}
+
 hipError_t launch_solve(const double *bbuf, const int64_t *rowptr, int64_t I,
                         int J, double lambda, float *A, int32_t *bad,
                         hipStream_t st) {
     if (I <= 0) return hipSuccess;
+#define PTK_SOLVE_ROW(j_)                                                           \
+    if (J == j_) {                                                                  \
+        hipLaunchKernelGGL(k_solve_row<j_>, dim3((unsigned)((I + kWave - 1) / kWave)), \
+                           dim3(kWave), 0, st, bbuf, rowptr, I, lambda, A, bad);    \
+        return hipGetLastError();                                                   \
+    }
+    PTK_SOLVE_ROW(3) PTK_SOLVE_ROW(4) PTK_SOLVE_ROW(5) PTK_SOLVE_ROW(7) PTK_SOLVE_ROW(8)
+    PTK_SOLVE_ROW(9) PTK_SOLVE_ROW(10) PTK_SOLVE_ROW(11)
+#undef PTK_SOLVE_ROW
 #define PTK_SOLVE_GRP(j_)                                                           \
     if (J == j_) {                                                                  \
         constexpr int G = j_ <= 4 ? 4 : (j_ <= 8 ? 8 : 16);                         \
@@ -202,8 +282,7 @@ hipError_t launch_solve(const double *bbuf, const int64_t *rowptr, int64_t I,
                            dim3(256), 0, st, bbuf, rowptr, I, lambda, A, bad);      \
         return hipGetLastError();                                                   \
     }
-    PTK_SOLVE_GRP(3) PTK_SOLVE_GRP(4) PTK_SOLVE_GRP(5) PTK_SOLVE_GRP(8)
-    PTK_SOLVE_GRP(10) PTK_SOLVE_GRP(16)
+    PTK_SOLVE_GRP(16)
 #undef PTK_SOLVE_GRP
     const int E = sys_entries(J);
     int bs = 64;
@@ -251,9 +330,52 @@ __global__ __launch_bounds__(256) void k_row_sse(const double *__restrict__ bbuf
         partial[blockIdx.x] = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
 }
 
+// The same sum with a group of lanes per row (the grouping of k_solve_grp):
+// lane l takes row l of B_i and c_i, and adds a_l (B_i a)_l - 2 a_l c_l.
+template <int J>
+__global__ __launch_bounds__(256) void k_row_sse_grp(const double *__restrict__ bbuf,
+                                                     const int64_t *__restrict__ rowptr,
+                                                     const float *__restrict__ A,
+                                                     int64_t I,
+                                                     double *__restrict__ partial) {
+    constexpr int G = J <= 4 ? 4 : (J <= 8 ? 8 : 16);
+    constexpr int T = J * (J + 1) / 2;
+    constexpr int E = T + J;
+    __shared__ double s_part[256 / kWave];
+    const int l = threadIdx.x % G;
+    const int64_t stride = (int64_t)gridDim.x * (256 / G);
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G; i < I; i += stride) {
+        if (l >= J || rowptr[i] == rowptr[i + 1]) continue;
+        const double *sys = bbuf + i * E;
+        const float *a = A + i * J;
+        double r = 0.0;
+#pragma unroll
+        for (int k = 0; k < J; ++k)
+            r = __builtin_fma(sys[l <= k ? tri_pos(l, k, J) : tri_pos(k, l, J)],
+                              (double)a[k], r);
+        acc += (double)a[l] * (r - 2.0 * sys[T + l]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, kWave);
+    if ((threadIdx.x % kWave) == 0) s_part[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
+}
+
 hipError_t launch_row_sse(const double *bbuf, const int64_t *rowptr, const float *A,
                           int64_t I, int J, double *partial, int nblocks,
                           hipStream_t st) {
+#define PTK_SSE_GRP(j_)                                                                  \
+    if (J == j_) {                                                                       \
+        hipLaunchKernelGGL(k_row_sse_grp<j_>, dim3(nblocks), dim3(256), 0, st, bbuf, rowptr, \
+                           A, I, partial);                                               \
+        return hipGetLastError();                                                        \
+    }
+    PTK_SSE_GRP(3) PTK_SSE_GRP(4) PTK_SSE_GRP(5) PTK_SSE_GRP(7) PTK_SSE_GRP(8)
+    PTK_SSE_GRP(9) PTK_SSE_GRP(10) PTK_SSE_GRP(11) PTK_SSE_GRP(16)
+#undef PTK_SSE_GRP
     hipLaunchKernelGGL(k_row_sse, dim3(nblocks), dim3(256), 0, st, bbuf, rowptr, A, I, J,
                        partial);
     return hipGetLastError();
