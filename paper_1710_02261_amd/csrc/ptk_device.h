@@ -52,7 +52,15 @@ __device__ __forceinline__ void delta_fast(const void *gp_raw, const float *aout
     constexpr int NOUT = NO - U;
     constexpr int OUTER = ipow(J, NOUT);
     constexpr int BLOCK = ipow(J, U) * J;
-    cptr<T> gp = (cptr<T>)gp_raw;
+    const void *gq = gp_raw;
+    // With every other mode unrolled (NOUT = 0), or a core small enough for
+    // the outer loop to be unrolled, the core loads do not depend on the
+    // entry: without this opaque copy of the pointer the compiler hoists all
+    // J^N scalar loads out of the caller's loop over tiles and spills them.
+    // The core is then read again per tile from the scalar cache, like the
+    // blocks of the larger shapes.
+    if constexpr (NOUT == 0 || OUTER * BLOCK <= 256) asm volatile("" : "+s"(gq));
+    cptr<T> gp = (cptr<T>)gq;
 #pragma unroll
     for (int j = 0; j < J; ++j) out[j] = 0.0;
     for (int o = 0; o < OUTER; ++o) {
