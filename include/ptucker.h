@@ -123,7 +123,9 @@ ptk_status ptk_create(ptk_ctx **out, int32_t N, const int64_t *dims_host,
 /* Release the context and all device memory it owns. NULL is accepted. */
 ptk_status ptk_destroy(ptk_ctx *ctx);
 
-/* Message of the last failed call on ctx (owned by ctx; never NULL). */
+/* Message of the last failed call on ctx (owned by ctx; never NULL). With
+ * ctx = NULL: the message of the last failed context-free call (ptk_coo_*)
+ * on the calling thread, or of a call that was given a NULL context. */
 const char *ptk_last_error(const ptk_ctx *ctx);
 
 /* Set options (see ptk_options). PTK_E_INVALID for unknown values,
@@ -259,6 +261,79 @@ ptk_status ptk_row_systems(ptk_ctx *ctx, int32_t n, double *B_out,
  */
 ptk_status ptk_partial_error(ptk_ctx *ctx, double *R_out);
 ptk_status ptk_truncate(ptk_ctx *ctx, double p, int32_t *removed_host);
+
+/* ------------------------------------------------------------------------
+ * Steps either side of the fit (Sec. 4.1, Sec. 4.5, Sec. 5).
+ * --------------------------------------------------------------------- */
+
+/*
+ * COO text input: one observed entry per line, N indices starting at 1 (the
+ * paper's convention, Sec. 2) and then the value, separated by blanks or
+ * tabs; lines holding only blanks are skipped. Host code, no GPU, parsed by
+ * up to 16 threads. ptk_coo_scan gives the entry count and, per mode, the
+ * largest index (so dims_out[n] = max index; dims_out [N] host). ptk_coo_read
+ * fills idx_host [N][nnz] int32 (0-based) and val_host [nnz] float32 (host
+ * memory, caller-owned) in file order; nnz must be the scanned count.
+ * Errors (text from ptk_last_error(NULL)): PTK_E_INVALID for an unreadable
+ * file, N outside [1, 10], a line without exactly N integers >= 1 and a
+ * finite value (the message gives the line number), an index above 2^31 - 1,
+ * or an nnz that differs from the file's count.
+ */
+ptk_status ptk_coo_scan(const char *path, int32_t N, int64_t *nnz_out, int64_t *dims_out);
+ptk_status ptk_coo_read(const char *path, int32_t N, int64_t nnz, int32_t *idx_host,
+                        float *val_host);
+
+/*
+ * Min-max normalisation of the values to [0, 1] (Sec. 4.1): val [nnz] float32
+ * device, in place, v <- (v - min) / (max - min) computed in FP64 (all 0 when
+ * max = min). minmax_host [2] (may be NULL) receives min and max. Values must
+ * be finite. Synchronises the stream.
+ */
+ptk_status ptk_normalize_values(ptk_ctx *ctx, int64_t nnz, float *val, double *minmax_host);
+
+/*
+ * Seeded train/test split of an entry list (Sec. 4.1 holds out 10 %). Entry e
+ * is held out when u_e < test_fraction, where u_e is the top 53 bits, over
+ * 2^53, of output e + 1 of the SplitMix64 generator (Steele, Lea and Flood,
+ * 2014) seeded with `seed`: a pure function of (seed, e), so any subset can
+ * be recomputed. ptk_split_count gives the held-out count. ptk_split_entries
+ * writes both sides in their original order: idx_train [N][nnz - ntest],
+ * val_train [nnz - ntest], idx_test [N][ntest], val_test [ntest] (device,
+ * caller-owned) from idx [N][nnz], val [nnz] (device). ntest must be the
+ * count ptk_split_count returns (else PTK_E_INVALID). test_fraction in
+ * [0, 1]. Both synchronise the stream.
+ */
+ptk_status ptk_split_count(ptk_ctx *ctx, int64_t nnz, double test_fraction, uint64_t seed,
+                           int64_t *ntest_host);
+ptk_status ptk_split_entries(ptk_ctx *ctx, int32_t N, int64_t nnz, const int32_t *idx,
+                             const float *val, double test_fraction, uint64_t seed,
+                             int64_t ntest, int32_t *idx_train, float *val_train,
+                             int32_t *idx_test, float *val_test);
+
+/*
+ * Error of the bound model over any entry list (the test RMSE of Sec. 4.5):
+ * idx [N][m] int32, val [m] float32 (device), indices within the model's
+ * dims (not range-checked here). *sse_host = sum (x - xhat)^2 (eq.
+ * "reconfull" over the list), *rmse_host = sqrt(sse / m) (0 for m = 0).
+ * Synchronises the stream.
+ */
+ptk_status ptk_entry_error(ptk_ctx *ctx, int64_t m, const int32_t *idx, const float *val,
+                           double *sse_host, double *rmse_host);
+
+/*
+ * K-means over the rows of the bound factor A^(n) (concept discovery, Sec. 5):
+ * Lloyd's iterations from the given centroids. centroids [K][J_n] float64
+ * device, in/out: initial centroids on entry (the caller draws them), final
+ * ones on return. Each of `iters` rounds assigns every row to its nearest
+ * centroid (squared Euclidean distance in FP64, the lowest index among equal
+ * distances) and moves each centroid to the mean of its rows (a centroid
+ * without rows stays); a last assignment follows. assign [I_n] int32 device
+ * receives it. result_host [2] (may be NULL): the inertia (sum of squared
+ * distances of the last assignment) and the number of rows whose cluster
+ * changed in it. K * (J_n + 1) * 8 <= 32768. Deterministic; synchronises.
+ */
+ptk_status ptk_kmeans(ptk_ctx *ctx, int32_t n, int32_t K, int32_t iters, double *centroids,
+                      int32_t *assign, double *result_host);
 
 /*
  * Per-kernel timing collected while options.profile = 1: for each kernel

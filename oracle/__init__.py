@@ -24,6 +24,8 @@ Functions and the passages they follow:
 * ``qr`` / ``core_update`` / ``orthogonalize`` -- Alg. 2's final QR and core
   update (Sec. 3.1, n-mode product of Sec. 2.1).
 * ``fold_in``        -- the row update for a new row with the model fixed.
+* ``data_steps``     -- (numpy) the steps either side of the fit: SplitMix64
+  train/test split, min-max normalisation, k-means over factor rows.
 """
 from __future__ import annotations
 

@@ -73,6 +73,14 @@ def load_library():
         "ptk_autotune": [_vp, C.c_char_p, C.POINTER(_i64)],
         "ptk_partial_error": [_vp, _vp],
         "ptk_truncate": [_vp, _dbl, C.POINTER(_i32)],
+        "ptk_coo_scan": [C.c_char_p, _i32, C.POINTER(_i64), C.POINTER(_i64)],
+        "ptk_coo_read": [C.c_char_p, _i32, _i64, _vp, _vp],
+        "ptk_normalize_values": [_vp, _i64, _vp, C.POINTER(_dbl)],
+        "ptk_split_count": [_vp, _i64, _dbl, C.c_uint64, C.POINTER(_i64)],
+        "ptk_split_entries": [_vp, _i32, _i64, _vp, _vp, _dbl, C.c_uint64, _i64, _vp, _vp,
+                              _vp, _vp],
+        "ptk_entry_error": [_vp, _i64, _vp, _vp, C.POINTER(_dbl), C.POINTER(_dbl)],
+        "ptk_kmeans": [_vp, _i32, _i32, _i32, _vp, _vp, C.POINTER(_dbl)],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -87,6 +95,33 @@ def load_library():
 def _torch():
     import torch
     return torch
+
+
+def _global_check(lib, st):
+    if st != PTK_OK:
+        msg = lib.ptk_last_error(None)
+        raise PtkError(st, msg.decode() if msg else "")
+
+
+def coo_scan(path, N):
+    """ptk_coo_scan: (entry count, dims) of a COO text file (1-based indices)."""
+    lib = load_library()
+    nnz = _i64(0)
+    dims = (_i64 * int(N))()
+    _global_check(lib, lib.ptk_coo_scan(os.fsencode(path), int(N), C.byref(nnz), dims))
+    return int(nnz.value), tuple(int(d) for d in dims)
+
+
+def coo_read(path, N, nnz=None):
+    """ptk_coo_read: host arrays idx [N][nnz] int32 (0-based), val [nnz] float32."""
+    lib = load_library()
+    if nnz is None:
+        nnz, _ = coo_scan(path, N)
+    idx = np.empty((int(N), int(nnz)), dtype=np.int32)
+    val = np.empty(int(nnz), dtype=np.float32)
+    _global_check(lib, lib.ptk_coo_read(os.fsencode(path), int(N), int(nnz),
+                                        idx.ctypes.data_as(_vp), val.ctypes.data_as(_vp)))
+    return idx, val
 
 
 def _dev_ptr(t, dtype, name):
@@ -271,6 +306,66 @@ class Context:
         k = _i32(0)
         self._check(self._lib.ptk_truncate(self._h, float(p), C.byref(k)))
         return int(k.value)
+
+    # -- steps either side of the fit ----------------------------------------
+    def normalize_values(self, val):
+        """ptk_normalize_values in place; returns (min, max)."""
+        torch = _torch()
+        mm = (_dbl * 2)()
+        n = int(val.numel())
+        ptr = _dev_ptr(val, torch.float32, "val") if n else _vp(0)
+        self._check(self._lib.ptk_normalize_values(self._h, n, ptr, mm))
+        return float(mm[0]), float(mm[1])
+
+    def split(self, idx, val, test_fraction=0.1, seed=0):
+        """ptk_split_count + ptk_split_entries: (idx_train, val_train, idx_test,
+        val_test) device tensors, each side in the original order."""
+        torch = _torch()
+        N, nnz = int(idx.shape[0]), int(idx.shape[1])
+        nt = _i64(0)
+        self._check(self._lib.ptk_split_count(self._h, nnz, float(test_fraction),
+                                              C.c_uint64(int(seed)), C.byref(nt)))
+        ntest = int(nt.value)
+        dev = idx.device
+        it = torch.empty((N, nnz - ntest), dtype=torch.int32, device=dev)
+        vt = torch.empty(nnz - ntest, dtype=torch.float32, device=dev)
+        ie = torch.empty((N, ntest), dtype=torch.int32, device=dev)
+        ve = torch.empty(ntest, dtype=torch.float32, device=dev)
+
+        def ptr(t, dt, name):
+            return _dev_ptr(t, dt, name) if t.numel() else _vp(0)
+        if nnz:
+            self._check(self._lib.ptk_split_entries(
+                self._h, N, nnz, ptr(idx, torch.int32, "idx"), ptr(val, torch.float32, "val"),
+                float(test_fraction), C.c_uint64(int(seed)), ntest,
+                ptr(it, torch.int32, "idx_train"), ptr(vt, torch.float32, "val_train"),
+                ptr(ie, torch.int32, "idx_test"), ptr(ve, torch.float32, "val_test")))
+        return it, vt, ie, ve
+
+    def entry_error(self, idx, val):
+        """ptk_entry_error: (sse, rmse) of the bound model over an entry list."""
+        torch = _torch()
+        m = int(idx.shape[1])
+        sse, rmse = _dbl(0.0), _dbl(0.0)
+        ip = _dev_ptr(idx, torch.int32, "idx") if m else _vp(0)
+        vp = _dev_ptr(val, torch.float32, "val") if m else _vp(0)
+        self._check(self._lib.ptk_entry_error(self._h, m, ip, vp, C.byref(sse), C.byref(rmse)))
+        return float(sse.value), float(rmse.value)
+
+    def kmeans(self, n, centroids, iters):
+        """ptk_kmeans over the rows of the bound factor n from the given initial
+        centroids (float64 [K][J_n] device, updated in place); returns
+        (assignment int32 [I_n] device, inertia, rows changed in the last pass)."""
+        torch = _torch()
+        K = int(centroids.shape[0])
+        if tuple(centroids.shape) != (K, self.ranks[n]):
+            raise ValueError("centroids must be [K][J_n]")
+        assign = torch.empty(self.dims[n], dtype=torch.int32, device=centroids.device)
+        res = (_dbl * 2)()
+        self._check(self._lib.ptk_kmeans(self._h, int(n), K, int(iters),
+                                         _dev_ptr(centroids, torch.float64, "centroids"),
+                                         _dev_ptr(assign, torch.int32, "assign"), res))
+        return assign, float(res[0]), int(res[1])
 
     def kernel_times(self):
         cnt = _i32(64)

@@ -712,7 +712,7 @@ ptk_status ptk_destroy(ptk_ctx *c) {
 }
 
 const char *ptk_last_error(const ptk_ctx *c) {
-    if (!c) return "null context";
+    if (!c) return global_error();
     return c->err.c_str();
 }
 
@@ -1067,6 +1067,46 @@ ptk_status ptk_predict(ptk_ctx *c, int64_t m, const int32_t *idx, float *out) {
     HIPCHK(c, timed(c, "predict", [&] {
         return launch_entries(a, c->s, 0, kOutPredict, fast, blocks, c->st);
     }));
+    return PTK_OK;
+}
+
+ptk_status ptk_entry_error(ptk_ctx *c, int64_t m, const int32_t *idx, const float *val,
+                           double *sse_host, double *rmse_host) {
+    if (!c) return PTK_E_INVALID;
+    if (m < 0) return fail(c, PTK_E_INVALID, "m < 0");
+    if (!c->core) return fail(c, PTK_E_STATE, "no model bound (ptk_bind_model)");
+    if (m > 0 && (!idx || !val)) return fail(c, PTK_E_INVALID, "null buffer");
+    ptk_status s = ensure_host(c, 1);
+    if (s != PTK_OK) return s;
+    double sse = 0.0;
+    if (m > 0) {
+        HIPCHK(c, permute_entries(c, 0));
+        EntryArgs a{};
+        const int32_t *other[kMaxN];
+        for (int k = 1; k < c->s.N; ++k) other[k - 1] = idx + (int64_t)k * m;
+        fill_common(c, 0, a, other);
+        a.gp = c->gpe;
+        a.own_idx = idx;
+        a.own = c->fac[0];
+        a.val = val;
+        a.m = m;
+        a.partial = c->red;
+        const bool fast =
+            equal_ranks(c->s) && fast_available(c->s.N, c->s.ranks[0], kArithF64);
+        const int64_t nb =
+            std::max<int64_t>(1, std::min<int64_t>(kSseBlocks, (m + kWave - 1) / kWave));
+        HIPCHK(c, timed(c, "entry_error", [&] {
+            hipError_t e = launch_entries(a, c->s, 0, kOutSSE, fast, nb, c->st);
+            if (e != hipSuccess) return e;
+            return launch_reduce(c->red, (int)nb, c->scal, c->st);
+        }));
+        HIPCHK(c, hipMemcpyAsync(c->host, c->scal, sizeof(double), hipMemcpyDeviceToHost,
+                                 c->st));
+        HIPCHK(c, hipStreamSynchronize(c->st));
+        sse = c->host[0];
+    }
+    if (sse_host) *sse_host = sse;
+    if (rmse_host) *rmse_host = m > 0 ? std::sqrt(sse / (double)m) : 0.0;
     return PTK_OK;
 }
 

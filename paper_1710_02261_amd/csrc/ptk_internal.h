@@ -179,6 +179,9 @@ hipError_t launch_invert_perm(const int32_t *perm, int64_t nnz, int32_t *inv,
 hipError_t launch_compose_perm(const int32_t *inv, const int32_t *perm, int64_t nnz,
                                int32_t *out, hipStream_t st);
 
+// message of the last failed context-free call on this thread (ptk_data.hip)
+const char *global_error();
+
 // finalisation (ptk_finalize.hip)
 size_t qr_workspace_bytes(int64_t I, int J);
 hipError_t launch_cholqr2(float *A, int64_t I, int J, void *work, double *R,
