@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gram_c2_traffic.json")
 KERNEL_SRC = [os.path.join(ROOT, "paper_1710_02261_amd", "csrc", f)
-              for f in ("ptk_kernels.hip", "ptk_device.h", "ptk_internal.h")]
+              for f in ("ptk_kernels.hip", "ptk_gram2.hip", "ptk_device.h", "ptk_internal.h")]
 
 
 def command_line():
@@ -478,7 +478,10 @@ def main():
     achieved = flops / avg_s / 1e12
     peak = PREC_PEAK[main_prec] / 1e12
     traffic = traffic_record(p.nnz) if args.workload == "c2" and main_prec == "f64" else None
-    kname = {"f64": "k_gram_fast<%d,%d,U,double>" % (N, J),
+    # two entries per lane on the shapes where that wins (ptk_gram2.hip)
+    dual = {(4, 10): 1, (5, 8): 2}
+    kname = {"f64": ("k_gram_fast2<%d,%d,%d,double>" % (N, J, dual[(N, J)])
+                     if (N, J) in dual else "k_gram_fast<%d,%d,U,double>" % (N, J)),
              "f32": "k_gram_fast<%d,%d,U,float>" % (N, J),
              "bf16": "k_gram_mfma<%d,%d,1>" % (N, J),
              "bf16x3": "k_gram_mfma<%d,%d,3>" % (N, J)}[main_prec]

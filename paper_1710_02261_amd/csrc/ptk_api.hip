@@ -296,6 +296,8 @@ ptk_status systems(ptk_ctx *c, int n, int role = 0) {
     }
     GramArgs a = gram_args(c, n);
     HIPCHK(c, timed(c, "gram", [&] {
+        if (m.fast && gram2_available(c->s.N, c->s.ranks[n], arith_of(c, n)))
+            return launch_gram2(a, c->s.N, c->s.ranks[n], arith_of(c, n), m.nchunks, c->st);
         return launch_gram(a, c->s, n, arith_of(c, n), m.nchunks, m.fast, c->st);
     }));
     HIPCHK(c, timed(c, "merge", [&] {
@@ -419,7 +421,9 @@ int64_t default_work(const ptk_ctx *c, int n) {
     const int bpc = (m.slices > 1 && role != 2)
                         ? gram_slices_blocks_per_cu(c->s.ranks[n])
                     : role ? gram_cache_blocks_per_cu(c->s, n, arith_of(c, n), role)
-                           : gram_blocks_per_cu(c->s, n, arith_of(c, n), m.fast);
+                    : (m.fast && gram2_available(c->s.N, c->s.ranks[n], arith_of(c, n)))
+                        ? gram2_blocks_per_cu(c->s.N, c->s.ranks[n], arith_of(c, n))
+                        : gram_blocks_per_cu(c->s, n, arith_of(c, n), m.fast);
     const int64_t waves = (int64_t)c->num_cu * std::max(1, bpc);
     int64_t chunk = round_up((c->nnz + waves - 1) / std::max<int64_t>(waves, 1), kWave);
     return std::max<int64_t>(chunk, kWave);

@@ -136,6 +136,11 @@ hipError_t launch_gram_cache(const GramArgs &a, const Shape &s, int n, Arith ar,
                              int64_t nchunks, int cache_mode, hipStream_t st);
 int gram_cache_blocks_per_cu(const Shape &s, int n, Arith ar, int cache_mode);
 int gram_blocks_per_cu(const Shape &s, int n, Arith ar, bool fast);
+// two entries per lane (ptk_gram2.hip), equal ranks
+bool gram2_available(int N, int J, Arith ar);
+int gram2_blocks_per_cu(int N, int J, Arith ar);
+hipError_t launch_gram2(const GramArgs &a, int N, int J, Arith ar, int64_t nchunks,
+                        hipStream_t st);
 hipError_t launch_merge(const double *part, const int32_t *split, int32_t nsplit,
                         int E, double *bbuf, hipStream_t st);
 hipError_t launch_solve(const double *bbuf, const int64_t *rowptr, int64_t I,
