@@ -114,6 +114,141 @@ __global__ __launch_bounds__(kWave) void k_gram_cache_write(GramArgs a) {
     if (cur >= 0) flush_row<EPL>(a, sl, cur, chunk, cs, ce);
 }
 
+// Writer with EL entries per lane (as k_gram_multi for the plain path): each
+// core value from the scalar cache feeds EL multiply-adds. U is the number
+// of unrolled (VGPR) levels after the partner; the records of a lane's EL
+// entries are stored as in k_gram_cache_write.
+template <int J, int U, int L, typename T, int EL>
+__device__ __forceinline__ void inner_accum_el(cptr<T> g, const T (&w)[EL],
+                                               const T (&a)[EL][U][J], T (&c)[EL][J]) {
+    if constexpr (L == U) {
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const T gj = g[j];
+#pragma unroll
+            for (int e = 0; e < EL; ++e) c[e][j] = fma_t<T>(gj, w[e], c[e][j]);
+        }
+    } else {
+        constexpr int st = ipow(J, U - L);
+#pragma unroll
+        for (int m = 0; m < J; ++m) {
+            T wm[EL];
+#pragma unroll
+            for (int e = 0; e < EL; ++e) wm[e] = w[e] * a[e][L][m];
+            inner_accum_el<J, U, L + 1, T, EL>(g + m * st, wm, a, c);
+        }
+    }
+}
+
+template <int N, int J, int U, typename T, int EL>
+__global__ __launch_bounds__(kWave) void k_gram_cache_write_el(GramArgs a) {
+    constexpr int NO = N - 1;
+    constexpr int NOUT = NO - U;                 // partner + NMID mid levels
+    constexpr int NMID = NO - 1 - U;
+    constexpr int MID = ipow(J, NMID);
+    constexpr int BLOCK = ipow(J, U) * J;
+    constexpr int RS = cache_record(J);
+    constexpr int E = sys_entries(J);
+    constexpr int EPL = (E + kWave - 1) / kWave;
+    constexpr int W = EL * kWave;                // LDS row stride
+    constexpr int AOUT = NOUT * J * W;           // floats
+    constexpr int DL = (J + 1) * kDlStride;      // doubles
+    constexpr int LDS_BYTES = (AOUT * 4 > DL * 8) ? AOUT * 4 : DL * 8;
+    static_assert(NOUT >= 1, "the partner is the leading LDS level");
+    __shared__ __attribute__((aligned(16))) unsigned char s_raw[LDS_BYTES];
+    __shared__ int s_row[kWave];
+    __shared__ float s_ones[J];
+    float *s_aout = (float *)s_raw;
+    double *s_dl = (double *)s_raw;
+    const int lane = threadIdx.x;
+    const int64_t chunk = blockIdx.x;
+    const int64_t cs = chunk * a.chunk;
+    const int64_t ce = min(cs + a.chunk, a.nnz);
+    if (lane < J) s_ones[lane] = 1.0f;
+    SysLane<EPL> sl;
+    sl.init(lane, J);
+    int cur = -1;
+    cptr<T> gp = (cptr<T>)a.gp;
+    for (int64_t base = cs; base < ce; base += W) {
+        T av[EL][U][J];
+#pragma unroll
+        for (int k = 0; k < NO; ++k) {
+#pragma unroll
+            for (int e = 0; e < EL; ++e) {
+                const int64_t p = base + e * kWave + lane;
+                const float *r = a.fac[k] + (int64_t)(p < ce ? a.oidx[k][p] : 0) * J;
+                if (k < NOUT) {
+#pragma unroll
+                    for (int j = 0; j < J; ++j) s_aout[(k * J + j) * W + e * kWave + lane] = r[j];
+                } else {
+#pragma unroll
+                    for (int j = 0; j < J; ++j) av[e][k - NOUT][j] = (T)r[j];
+                }
+            }
+        }
+        __syncthreads();
+        double d[EL][J];
+#pragma unroll
+        for (int e = 0; e < EL; ++e)
+#pragma unroll
+            for (int j = 0; j < J; ++j) d[e][j] = 0.0;
+#pragma unroll 1
+        for (int o = 0; o < J; ++o) {
+            T acc[EL][J];
+#pragma unroll
+            for (int e = 0; e < EL; ++e)
+#pragma unroll
+                for (int j = 0; j < J; ++j) acc[e][j] = (T)0;
+#pragma unroll 1
+            for (int mo = 0; mo < MID; ++mo) {
+                T w[EL];
+                // unit weight from LDS (keeps the inner weight products in the loop)
+#pragma unroll
+                for (int e = 0; e < EL; ++e) w[e] = (T)s_ones[o];
+                int t = mo;
+#pragma unroll
+                for (int k = NMID; k >= 1; --k) {
+                    const int dg = t % J;
+                    t /= J;
+#pragma unroll
+                    for (int e = 0; e < EL; ++e)
+                        w[e] *= (T)s_aout[(k * J + dg) * W + e * kWave + lane];
+                }
+                inner_accum_el<J, U, 0, T, EL>(gp + ((int64_t)o * MID + mo) * BLOCK, w, av, acc);
+            }
+#pragma unroll
+            for (int e = 0; e < EL; ++e) {
+                const int64_t p = base + e * kWave + lane;
+                double *tdst = a.cache + (p < ce ? p : a.nnz) * RS;   // spare record
+                const double wp = (double)s_aout[o * W + e * kWave + lane];
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    tdst[o * J + j] = (double)acc[e][j];
+                    d[e][j] = __builtin_fma(wp, (double)acc[e][j], d[e][j]);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < EL; ++e) {
+            const int64_t p = base + e * kWave + lane;
+            const int nb = (int)max((int64_t)0, min((int64_t)kWave, ce - base - e * kWave));
+            if (nb == 0) break;                    // uniform
+#pragma unroll
+            for (int j = 0; j < J; ++j) s_dl[j * kDlStride + lane] = d[e][j];
+            s_dl[J * kDlStride + lane] = p < ce ? (double)a.val[p] : 0.0;
+            s_row[lane] = p < ce ? a.rows[p] : 0;
+            __syncthreads();
+            sweep_tile<EPL>(a, sl, s_dl, s_row, nb, cur, chunk, cs, ce);
+            __syncthreads();
+        }
+    }
+    if (cur >= 0) flush_row<EPL>(a, sl, cur, chunk, cs, ce);
+}
+
+// shapes with a multi-entry writer: (N, J, type, U, entries per lane)
+#define PTK_CACHE_EL_SHAPES(X) X(4, 10, double, 1, 2)
+
 // Writer for any order (equal ranks J <= JMAX): the generic odometer walk
 // over the other modes' cells with the partner p as the slowest digit. The
 // J^(N-2) cells of one partner index m_p, summed without the partner's
@@ -378,6 +513,11 @@ int gram_cache_blocks_per_cu(const Shape &s, int n, Arith ar, int cm) {
             default: return blocks_per_cu(k_gram_cache_read<16>, 0);
         }
     }
+#define PTK_Y(n_, j_, t_, u_, e_)                                                  \
+    if (s.N == n_ && J == j_ && (sizeof(t_) == 8) == (ar == kArithF64))            \
+        return blocks_per_cu(k_gram_cache_write_el<n_, j_, u_, t_, e_>, 0);
+    PTK_CACHE_EL_SHAPES(PTK_Y)
+#undef PTK_Y
 #define PTK_X(n_, j_)                                                             \
     if (s.N == n_ && J == j_)                                                     \
         return ar == kArithF64 ? blocks_per_cu(k_gram_cache_write<n_, j_, double>, 0) \
@@ -410,6 +550,14 @@ hipError_t launch_gram_cache(const GramArgs &a, const Shape &s, int n, Arith ar,
         }
         return hipGetLastError();
     }
+#define PTK_Y(n_, j_, t_, u_, e_)                                                     \
+    if (s.N == n_ && J == j_ && (sizeof(t_) == 8) == (ar == kArithF64)) {             \
+        hipLaunchKernelGGL((k_gram_cache_write_el<n_, j_, u_, t_, e_>), grid, block, 0, \
+                           st, a);                                                    \
+        return hipGetLastError();                                                     \
+    }
+    PTK_CACHE_EL_SHAPES(PTK_Y)
+#undef PTK_Y
 #define PTK_X(n_, j_)                                                                \
     if (s.N == n_ && J == j_) {                                                      \
         if (ar == kArithF64)                                                         \
