@@ -104,24 +104,31 @@ hipError_t launch_residual(const EntryArgs &a, const Shape &s, int64_t nblocks,
 // ---------------------------------------------------------------------------
 constexpr int kApproxChunk = kWave;   // entries staged per step
 
+// Third-last-mode values per wavefront of the partial-error kernel: each
+// lane then updates KG cells per staged entry from one pair of loads.
+constexpr int kk_per_wave(int N, int J) { return (N - 1 >= 3 && J % 2 == 0) ? 2 : 1; }
+
 template <int N, int J>
 __global__ __launch_bounds__(kWave) void k_partial_error(ApproxArgs a) {
     constexpr int NP = N - 1;             // modes of T (all but g)
     constexpr int P = J * J;
     constexpr int NPG = (P + kWave - 1) / kWave;
-    constexpr int KS = NP >= 3 ? J : 1;   // third-last other mode, one value per wave
+    // values of the third-last other mode per wavefront (KG of them) and the
+    // number of such groups
+    constexpr int KG = kk_per_wave(N, J);
+    constexpr int KS = NP >= 3 ? J / KG : 1;
     constexpr int NLG = NP >= 4 ? ipow(J, NP - 3) : 1;
     constexpr int CELLS = ipow(J, N);
     constexpr int CH = kApproxChunk;
     typedef double double2v __attribute__((ext_vector_type(2)));
-    __shared__ double2v s_uw[CH];         // (r q, q^2) per staged entry
+    __shared__ double2v s_uw[CH][KG];     // (r q, q^2) per staged entry and kk
     __shared__ int32_t s_ia[CH], s_ib[CH], s_row[CH];
     __shared__ float s_va[CH * J], s_vb[CH * J];   // rows of the last two modes
     const int lane = threadIdx.x;
     int b = blockIdx.x;
     const int pg = b % NPG;
     b /= NPG;
-    const int kk = b % KS;
+    const int kk0 = (b % KS) * KG;        // first third-last value of this wave
     b /= KS;
     const int lg = b % NLG;
     const int sl = b / NLG;
@@ -137,18 +144,25 @@ __global__ __launch_bounds__(kWave) void k_partial_error(ApproxArgs a) {
             t /= J;
         }
     }
-    double S1[J], S2[J];
+    double S1[KG][J], S2[KG][J];
 #pragma unroll
-    for (int k = 0; k < J; ++k) S1[k] = S2[k] = 0.0;
-    double t1 = 0.0, t2 = 0.0;            // T1, T2 of the current row, this lane's cell
+    for (int i = 0; i < KG; ++i)
+#pragma unroll
+        for (int k = 0; k < J; ++k) S1[i][k] = S2[i][k] = 0.0;
+    double t1[KG], t2[KG];                // T1, T2 of the current row, this lane's cells
+#pragma unroll
+    for (int i = 0; i < KG; ++i) t1[i] = t2[i] = 0.0;
     int cur = -1;
     auto fold = [&](int row) {            // S += a^(g)_row (x) T_row
         cptr<float> ag = (cptr<float>)a.fac_g + (int64_t)row * J;
 #pragma unroll
         for (int k = 0; k < J; ++k) {
             const double x = (double)ag[k];
-            S1[k] = __builtin_fma(x, t1, S1[k]);
-            S2[k] = __builtin_fma(x * x, t2, S2[k]);
+#pragma unroll
+            for (int i = 0; i < KG; ++i) {
+                S1[i][k] = __builtin_fma(x, t1[i], S1[i][k]);
+                S2[i][k] = __builtin_fma(x * x, t2[i], S2[i][k]);
+            }
         }
     };
     const int64_t e0 = (int64_t)sl * a.slice;
@@ -160,16 +174,21 @@ __global__ __launch_bounds__(kWave) void k_partial_error(ApproxArgs a) {
         {
             const bool ok = lane < nb;
             const int64_t e = base + lane;
-            double q = 0.0, r = 0.0;
+            double q0 = 0.0, r = 0.0;
             if (ok) {
-                q = 1.0;
+                q0 = 1.0;
 #pragma unroll
                 for (int k = 0; k < NP - 3; ++k)
-                    q *= (double)a.fac[k][(int64_t)a.idx[k][e] * J + pre[k]];
-                if (NP >= 3) q *= (double)a.fac[NP - 3][(int64_t)a.idx[NP - 3][e] * J + kk];
+                    q0 *= (double)a.fac[k][(int64_t)a.idx[k][e] * J + pre[k]];
                 r = a.resid[e];
             }
-            s_uw[lane] = double2v{r * q, q * q};
+#pragma unroll
+            for (int i = 0; i < KG; ++i) {
+                double q = q0;
+                if (NP >= 3 && ok)
+                    q *= (double)a.fac[NP - 3][(int64_t)a.idx[NP - 3][e] * J + kk0 + i];
+                s_uw[lane][i] = double2v{r * q, q * q};
+            }
             s_ia[lane] = ok ? a.idx[NP - 2][e] : 0;
             s_ib[lane] = ok ? a.idx[NP - 1][e] : 0;
             s_row[lane] = ok ? a.rows[e] : -1;
@@ -189,38 +208,49 @@ __global__ __launch_bounds__(kWave) void k_partial_error(ApproxArgs a) {
                 if (row != cur) {         // uniform
                     if (cur >= 0) fold(cur);
                     cur = row;
-                    t1 = t2 = 0.0;
+#pragma unroll
+                    for (int i = 0; i < KG; ++i) t1[i] = t2[i] = 0.0;
                 }
-                const double2v uw = s_uw[u];
                 const double v = (double)s_va[u * J + m1] * (double)s_vb[u * J + m2];
-                t1 = __builtin_fma(uw.x, v, t1);
-                t2 = __builtin_fma(uw.y, v * v, t2);
+                const double v2 = v * v;
+#pragma unroll
+                for (int i = 0; i < KG; ++i) {
+                    const double2v uw = s_uw[u][i];
+                    t1[i] = __builtin_fma(uw.x, v, t1[i]);
+                    t2[i] = __builtin_fma(uw.y, v2, t2[i]);
+                }
             }
         }
         __syncthreads();
     }
     if (cur >= 0) fold(cur);
     if (act) {
-        // C-order cell of (beta_g = k, the other modes' digits)
-        int64_t rest = 0;
-        int t = 0;
 #pragma unroll
-        for (int mode = 0; mode < N; ++mode) {
-            if (mode == a.g) continue;
-            const int d = (t < NP - 3) ? pre[t] : (t == NP - 3) ? kk : (t == NP - 2) ? m1 : m2;
-            rest = rest * J + d;
-            ++t;
-        }
-        // insert beta_g at position g: cell = hi * J^(N-g) + beta_g * J^(N-1-g) + lo
-        const int64_t sg = ipow_rt(J, N - 1 - a.g);
-        const int64_t hi = rest / sg, lo = rest % sg;
-        double *o1 = a.part + (int64_t)sl * 2 * CELLS;
-        double *o2 = o1 + CELLS;
+        for (int i = 0; i < KG; ++i) {
+            // C-order cell of (beta_g = k, the other modes' digits)
+            int64_t rest = 0;
+            int t = 0;
 #pragma unroll
-        for (int k = 0; k < J; ++k) {
-            const int64_t cell = (hi * J + k) * sg + lo;
-            o1[cell] = S1[k];
-            o2[cell] = S2[k];
+            for (int mode = 0; mode < N; ++mode) {
+                if (mode == a.g) continue;
+                const int d = (t < NP - 3)    ? pre[t]
+                              : (t == NP - 3) ? kk0 + i
+                              : (t == NP - 2) ? m1
+                                              : m2;
+                rest = rest * J + d;
+                ++t;
+            }
+            // insert beta_g at position g: cell = hi * J^(N-g) + beta_g * J^(N-1-g) + lo
+            const int64_t sg = ipow_rt(J, N - 1 - a.g);
+            const int64_t hi = rest / sg, lo = rest % sg;
+            double *o1 = a.part + (int64_t)sl * 2 * CELLS;
+            double *o2 = o1 + CELLS;
+#pragma unroll
+            for (int k = 0; k < J; ++k) {
+                const int64_t cell = (hi * J + k) * sg + lo;
+                o1[cell] = S1[i][k];
+                o2[cell] = S2[i][k];
+            }
         }
     }
 }
@@ -229,7 +259,7 @@ int32_t approx_slices(const Shape &s, int64_t nnz, int num_cu) {
     const int J = s.ranks[0];
     const int NP = s.N - 1;
     int64_t waves_per_slice = (int64_t)((J * J + kWave - 1) / kWave);
-    if (NP >= 3) waves_per_slice *= J;
+    if (NP >= 3) waves_per_slice *= J / kk_per_wave(s.N, J);
     for (int k = 4; k <= NP; ++k) waves_per_slice *= J;
     // about 16 wavefronts per CU in all, slices of at least 256 entries
     int64_t sl = ((int64_t)16 * num_cu + waves_per_slice - 1) / waves_per_slice;
@@ -248,7 +278,7 @@ hipError_t launch_partial_error(const ApproxArgs &a, const Shape &s, hipStream_t
 #define PTK_X(n_, j_)                                                            \
     if (s.N == n_ && J == j_) {                                                  \
         const int64_t blocks = (int64_t)((j_ * j_ + kWave - 1) / kWave) *        \
-                               (n_ - 1 >= 3 ? j_ : 1) *                          \
+                               (n_ - 1 >= 3 ? j_ / kk_per_wave(n_, j_) : 1) *   \
                                (n_ - 1 >= 4 ? ipow(j_, n_ - 4) : 1) * a.nslices; \
         hipLaunchKernelGGL((k_partial_error<n_, j_>), dim3((unsigned)blocks),     \
                            dim3(kWave), 0, st, a);                               \
