@@ -107,6 +107,12 @@ typedef struct ptk_options {
                                of its partner's rank, and no slice gets fewer
                                than one cell). Extra device memory: S * J_n *
                                nnz doubles. Chosen before ptk_set_observed.  */
+    double tol;             /* early stop of ptk_iterate (Alg. 2's "until the
+                               error converges"): after iteration t >= 2 it
+                               stops when |e_t - e_{t-1}| <= tol * e_{t-1},
+                               e = sqrt(SSE); 0 = run all iterations. With
+                               tol > 0 every iteration waits for its error
+                               (one small copy and synchronisation each).   */
 } ptk_options;
 
 /*
@@ -179,6 +185,10 @@ ptk_status ptk_update_mode(ptk_ctx *ctx, int32_t n, double lambda);
  */
 ptk_status ptk_iterate(ptk_ctx *ctx, int32_t iters, double lambda,
                        double *sse_host, double *loss_host);
+
+/* Iterations the last ptk_iterate ran (fewer than asked when options.tol
+ * stopped it early; the sse/loss entries past them are NaN). */
+ptk_status ptk_iterations_done(const ptk_ctx *ctx, int32_t *n_host);
 
 /*
  * Number of row systems that were not positive definite in floating point

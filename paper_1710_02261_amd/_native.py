@@ -28,7 +28,7 @@ _dbl = C.c_double
 class _Options(C.Structure):
     _fields_ = [("precision", _i32), ("chunk_nnz", _i32), ("fuse_error", _i32),
                 ("profile", _i32), ("use_graph", _i32), ("pair_cache", _i32),
-                ("approx_rate", _dbl), ("delta_slices", _i32)]
+                ("approx_rate", _dbl), ("delta_slices", _i32), ("tol", _dbl)]
 
 
 class PtkError(RuntimeError):
@@ -81,6 +81,7 @@ def load_library():
                               _vp, _vp],
         "ptk_entry_error": [_vp, _i64, _vp, _vp, C.POINTER(_dbl), C.POINTER(_dbl)],
         "ptk_kmeans": [_vp, _i32, _i32, _i32, _vp, _vp, C.POINTER(_dbl)],
+        "ptk_iterations_done": [_vp, C.POINTER(_i32)],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -184,9 +185,9 @@ class Context:
     # -- C ABI calls ---------------------------------------------------------
     def set_options(self, precision=PREC_FP64_ACC, chunk_nnz=0, fuse_error=1,
                     profile=0, use_graph=1, pair_cache=0, approx_rate=0.0,
-                    delta_slices=0):
+                    delta_slices=0, tol=0.0):
         o = _Options(precision, chunk_nnz, fuse_error, profile, use_graph, pair_cache,
-                     float(approx_rate), delta_slices)
+                     float(approx_rate), delta_slices, float(tol))
         self._check(self._lib.ptk_set_options(self._h, C.byref(o)))
 
     def set_observed(self, idx, val):
@@ -306,6 +307,12 @@ class Context:
         k = _i32(0)
         self._check(self._lib.ptk_truncate(self._h, float(p), C.byref(k)))
         return int(k.value)
+
+    def iterations_done(self):
+        """Iterations the last iterate() ran (fewer when options.tol stopped it)."""
+        n = _i32(0)
+        self._check(self._lib.ptk_iterations_done(self._h, C.byref(n)))
+        return int(n.value)
 
     # -- steps either side of the fit ----------------------------------------
     def normalize_values(self, val):

@@ -745,6 +745,8 @@ ptk_status ptk_set_options(ptk_ctx *c, const ptk_options *o) {
                     "no pair-cache kernel for this shape and precision");
     if (o->pair_cache != c->opt.pair_cache && c->nnz >= 0)
         return fail(c, PTK_E_STATE, "pair_cache must be set before ptk_set_observed");
+    if (!(o->tol >= 0.0) || !std::isfinite(o->tol))
+        return fail(c, PTK_E_INVALID, "tol must be finite and >= 0");
     if (o->delta_slices < 0 || o->delta_slices > 65535)
         return fail(c, PTK_E_INVALID, "delta_slices must be in [0, 65535]");
     if (o->delta_slices != c->opt.delta_slices && c->nnz >= 0)
@@ -955,6 +957,7 @@ ptk_status ptk_iterate(ptk_ctx *c, int32_t iters, double lambda, double *sse_hos
         return fail(c, PTK_E_INVALID, "lambda must be > 0");
     ptk_status s = need_model(c);
     if (s != PTK_OK) return s;
+    c->last_iters = 0;
     if (iters == 0) return PTK_OK;
     s = ensure_host(c, 2 * (size_t)iters);
     if (s != PTK_OK) return s;
@@ -979,21 +982,44 @@ ptk_status ptk_iterate(ptk_ctx *c, int32_t iters, double lambda, double *sse_hos
     if (use_graph) {
         s = ensure_iteration_graph(c, lambda);
         if (s != PTK_OK) return s;
-        for (int t = 0; t < iters; ++t) HIPCHK(c, hipGraphLaunch(c->gexec, c->st));
-    } else {
-        for (int t = 0; t < iters; ++t) {
+    }
+    const double tol = c->opt.tol;
+    int done = 0;
+    while (done < iters) {
+        if (use_graph) {
+            HIPCHK(c, hipGraphLaunch(c->gexec, c->st));
+        } else {
             s = iteration_body(c, lambda);
             if (s != PTK_OK) return s;
         }
+        ++done;
+        if (tol > 0.0 && done >= 2) {
+            // the errors of the last two iterations (Alg. 2's stopping test)
+            HIPCHK(c, hipMemcpyAsync(c->host, c->dres + 2 * (done - 2), 4 * sizeof(double),
+                                     hipMemcpyDeviceToHost, c->st));
+            HIPCHK(c, hipStreamSynchronize(c->st));
+            const double e0 = std::sqrt(std::max(c->host[0], 0.0));
+            const double e1 = std::sqrt(std::max(c->host[2], 0.0));
+            if (std::fabs(e1 - e0) <= tol * e0) break;
+        }
     }
-    HIPCHK(c, hipMemcpyAsync(c->host, c->dres, 2 * sizeof(double) * iters,
+    c->last_iters = done;
+    HIPCHK(c, hipMemcpyAsync(c->host, c->dres, 2 * sizeof(double) * done,
                              hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
     for (int t = 0; t < iters; ++t) {
-        if (sse_host) sse_host[t] = c->host[2 * t];
-        if (loss_host) loss_host[t] = c->host[2 * t] + lambda * c->host[2 * t + 1];
+        const bool ran = t < done;
+        if (sse_host) sse_host[t] = ran ? c->host[2 * t] : std::nan("");
+        if (loss_host)
+            loss_host[t] = ran ? c->host[2 * t] + lambda * c->host[2 * t + 1] : std::nan("");
     }
     return check_bad(c, "ptk_iterate");
+}
+
+ptk_status ptk_iterations_done(const ptk_ctx *c, int32_t *n_host) {
+    if (!c || !n_host) return PTK_E_INVALID;
+    *n_host = c->last_iters;
+    return PTK_OK;
 }
 
 ptk_status ptk_recon_error(ptk_ctx *c, double lambda, double *sse_host,

@@ -55,7 +55,7 @@ struct ptk_ctx {
     hipStream_t st = nullptr;
     int device = 0;
     int num_cu = 256;
-    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1, 0, 0.0, 0};
+    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1, 0, 0.0, 0, 0.0};
     int64_t nnz = -1;
     ModeData md[ptk::kMaxN];
     float *core = nullptr;
@@ -88,6 +88,7 @@ struct ptk_ctx {
     int g_fuse = -1;
     int32_t *bad = nullptr;
     int64_t last_not_pd = 0;
+    int32_t last_iters = 0;      // iterations the last ptk_iterate ran
     double *host = nullptr;      // pinned results
     size_t host_cap = 0;
     void *qr_work = nullptr;

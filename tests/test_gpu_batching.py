@@ -100,3 +100,33 @@ def test_autotune_then_update_matches_oracle(prec, dims, ranks, tmp_path):
     assert c2.autotune(cache) == work
     c.close()
     c2.close()
+
+
+@pytest.mark.parametrize("graph", [1, 0])
+def test_iterate_early_stop_by_tolerance(graph):
+    """options.tol stops ptk_iterate after the first iteration t >= 2 whose
+    error sqrt(SSE) moved by at most tol times the previous one; the
+    iterations it ran equal those of a run without it, bitwise, and the
+    entries past them are NaN."""
+    import paper_1710_02261_amd as ptk
+    p = synth.make_small((40, 35, 30), (5, 5, 5), 6000, seed=71)
+    ref, _, _, _, _ = context(p)
+    ref.set_options(use_graph=graph)
+    want, want_loss = ref.iterate(12, p.lam, strict=False)
+    e = np.sqrt(want)
+    for tol in (1.0, 1e-3, 1e-6):
+        ctx, _, _, _, _ = context(p)
+        ctx.set_options(use_graph=graph, tol=tol)
+        got, loss = ctx.iterate(12, p.lam, strict=False)
+        done = ctx.iterations_done()
+        stop = next((t + 1 for t in range(1, 12) if abs(e[t] - e[t - 1]) <= tol * e[t - 1]), 12)
+        assert done == stop, (tol, done, stop)
+        assert np.array_equal(got[:done], want[:done])
+        assert np.array_equal(loss[:done], want_loss[:done])
+        assert np.all(np.isnan(got[done:])) and np.all(np.isnan(loss[done:]))
+        ctx.close()
+    ref.close()
+    c = ptk.Context(p.dims, p.ranks)
+    with pytest.raises(ptk.PtkError, match="tol"):
+        c.set_options(tol=-1.0)
+    c.close()
