@@ -12,10 +12,12 @@ namespace ptk {
 // Merge the partial systems of rows that cross work-range boundaries:
 // split[3*s + {0,1,2}] = (row, first range, last range). The first range
 // holds the row's head in its tail slot, every later range its head slot.
-// A block of 256 threads serves one row: 64 entries of the packed system at a
-// time, the ranges dealt round-robin to 4 groups whose sums are combined in a
-// fixed order (deterministic for any range count).
-constexpr int kMergeGroups = 4;
+// A block of 1024 threads serves one row: 64 entries of the packed system at
+// a time, the ranges dealt round-robin to 16 groups whose sums are combined in
+// a fixed order (deterministic for any range count). The loop is unrolled by
+// 16 so that a long row (thousands of ranges) keeps 16 loads in flight per
+// lane.
+constexpr int kMergeGroups = 16;
 
 __global__ __launch_bounds__(kWave * kMergeGroups) void k_merge(
     const double *__restrict__ part, const int32_t *__restrict__ split, int E,
@@ -32,15 +34,18 @@ __global__ __launch_bounds__(kWave * kMergeGroups) void k_merge(
         double acc = 0.0;
         if (e < E) {
             if (grp == 0) acc = part[((int64_t)c0 * 2 + 1) * E + e];
-#pragma unroll 4
+#pragma unroll 16
             for (int c = c0 + 1 + grp; c <= c1; c += kMergeGroups)
                 acc += part[((int64_t)c * 2 + 0) * E + e];
         }
         s_acc[grp][lane] = acc;
         __syncthreads();
-        if (grp == 0 && e < E)
-            bbuf[(int64_t)row * E + e] =
-                (s_acc[0][lane] + s_acc[1][lane]) + (s_acc[2][lane] + s_acc[3][lane]);
+        if (grp == 0 && e < E) {
+            double t = s_acc[0][lane];
+#pragma unroll
+            for (int q = 1; q < kMergeGroups; ++q) t += s_acc[q][lane];
+            bbuf[(int64_t)row * E + e] = t;
+        }
         __syncthreads();
     }
 }
