@@ -31,6 +31,8 @@ GENERIC = [
     ((9, 8, 7, 6), (2, 3, 4, 5), 1500),
     ((5, 5, 4, 4, 3, 3), (2, 2, 2, 2, 2, 3), 1200),
     ((30, 20, 25), (20, 3, 4), 1700),
+    ((40, 30, 20), (32, 3, 2), 1500),                 # the largest rank
+    ((4,) * 10, (2,) * 10, 1500),                      # the highest order
 ]
 
 
@@ -94,8 +96,9 @@ def test_row_systems_match_oracle(dims, ranks, nnz):
     ctx.close()
 
 
-def _check_update(p, chunk_nnz=0, precision=0, tol=1e-5):
-    ctx, idx, val, core, fac = context(p, chunk_nnz=chunk_nnz, precision=precision)
+def _check_update(p, chunk_nnz=0, precision=0, tol=1e-5, delta_slices=0):
+    ctx, idx, val, core, fac = context(p, chunk_nnz=chunk_nnz, precision=precision,
+                                       delta_slices=delta_slices)
     G, A, v = oracle_inputs(p)
     worst = 0.0
     for n in range(p.N):
@@ -119,6 +122,13 @@ def _check_update(p, chunk_nnz=0, precision=0, tol=1e-5):
 def test_update_mode_matches_oracle(dims, ranks, nnz):
     p = problem(dims, ranks, nnz, seed=3)
     log("update", dims, ranks, nnz, "worst", _check_update(p))
+
+
+@pytest.mark.parametrize("dims,ranks,nnz", GENERIC[-2:], ids=ids(GENERIC[-2:]))
+def test_update_largest_rank_and_order_unsliced(dims, ranks, nnz):
+    # the generic kernel with one wavefront per 64 entries (no slicing)
+    p = problem(dims, ranks, nnz, seed=6)
+    log("update unsliced", dims, ranks, "worst", _check_update(p, delta_slices=1))
 
 
 @pytest.mark.parametrize("chunk", [64, 192, 1024])
