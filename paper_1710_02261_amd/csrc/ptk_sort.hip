@@ -212,13 +212,22 @@ __global__ void k_gather(GatherArgs g) {
     }
 }
 
+// rowptr[r] = number of sorted keys below r, for r = 0..I: one thread per
+// row, a binary search over the keys (balanced however the rows are spread;
+// a huge mode with few entries is as fast as a dense one).
 __global__ void k_rowptr(const int32_t *__restrict__ keys, int64_t nnz, int64_t I,
                          int64_t *__restrict__ rowptr) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > nnz) return;
-    const int64_t kp = (p < nnz) ? keys[p] : I;
-    const int64_t kprev = (p == 0) ? -1 : keys[p - 1];
-    for (int64_t r = kprev + 1; r <= kp; ++r) rowptr[r] = p;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > I) return;
+    int64_t lo = 0, hi = nnz;                 // first position with key >= r
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if ((int64_t)keys[mid] < r)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    rowptr[r] = lo;
 }
 
 static int64_t n_tiles(int64_t nnz) { return (nnz + kRsTile - 1) / kRsTile; }
@@ -239,8 +248,8 @@ hipError_t build_mode_csr(const int32_t *idx, const float *val, int64_t nnz,
                           hipStream_t st, int32_t *perm_out) {
     const int64_t I = s.dims[n];
     if (nnz == 0) {
-        hipLaunchKernelGGL(k_rowptr, dim3(1), dim3(64), 0, st, rows, (int64_t)0, I,
-                           rowptr);
+        hipLaunchKernelGGL(k_rowptr, dim3((unsigned)((I + 1 + 255) / 256)), dim3(256), 0, st,
+                           rows, (int64_t)0, I, rowptr);
         return hipGetLastError();
     }
     const int64_t nt = n_tiles(nnz);
@@ -296,8 +305,8 @@ hipError_t build_mode_csr(const int32_t *idx, const float *val, int64_t nnz,
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_gather, dim3((unsigned)blocks), dim3(256), 0, st, g);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rowptr, dim3((unsigned)((nnz + 1 + 255) / 256)), dim3(256),
-                       0, st, rows, nnz, I, rowptr);
+    hipLaunchKernelGGL(k_rowptr, dim3((unsigned)((I + 1 + 255) / 256)), dim3(256), 0, st,
+                       rows, nnz, I, rowptr);
     return hipGetLastError();
 }
 

@@ -320,3 +320,46 @@ def test_error_statuses():
         ctx.update_mode(3, 0.01)
     ctx.update_mode(0, 0.01)          # still usable after the errors
     ctx.close()
+
+
+def test_huge_sparse_mode_64bit_offsets():
+    """A mode of 2.5e8 rows holding 1000 entries near its top: row-system
+    offsets (row * E, E = 9) pass 2^31, the row pointers and the solve cover
+    every row. Updated rows against the oracle (1e-5), all other rows exactly
+    0 (no entries: B = 0, c = 0)."""
+    import torch
+    rng = np.random.default_rng(81)
+    I0 = 250_000_000
+    dims, ranks = (I0, 30, 20), (3, 3, 3)
+    m = 1000
+    rows = np.sort(rng.choice(np.arange(I0 - 5_000_000, I0), 600, replace=False))
+    idx = np.stack([rows[rng.integers(0, 600, m)], rng.integers(0, 30, m),
+                    rng.integers(0, 20, m)]).astype(np.int32)
+    val = rng.standard_normal(m).astype(np.float32)
+    core = rng.random(ranks).astype(np.float32)
+    facs = [rng.random((d, r)).astype(np.float32) if d < 1000 else None
+            for d, r in zip(dims, ranks)]
+    import paper_1710_02261_amd as ptk
+    dev = torch.device("cuda:0")
+    A0 = torch.rand((I0, 3), dtype=torch.float32, device=dev)   # overwritten rows
+    fac = [A0] + [torch.from_numpy(a).to(dev) for a in facs[1:]]
+    ctx = ptk.Context(dims, ranks)
+    ctx.set_observed(torch.from_numpy(idx).to(dev), torch.from_numpy(val).to(dev))
+    ctx.bind_model(torch.from_numpy(core).to(dev), fac)
+    ctx.update_mode(0, 0.01)
+    torch.cuda.synchronize()
+    used = np.unique(idx[0])
+    got = A0[torch.from_numpy(used.astype(np.int64)).to(dev)].cpu().numpy().astype(np.float64)
+    # the oracle on the same problem with mode 0 relabelled to its used rows
+    remap = np.searchsorted(used, idx[0]).astype(np.int32)
+    small = np.stack([remap, idx[1], idx[2]]).astype(np.int32)
+    A = [np.zeros((len(used), 3))] + [a.astype(np.float64) for a in facs[1:]]
+    want = oracle.update_rows(core.astype(np.float64), A, small, val.astype(np.float64), 0,
+                              0.01)
+    err = row_rel_err(got, want)
+    log("huge mode: %d rows used, worst rel err %.3g" % (len(used), err.max()))
+    assert err.max() <= 1e-5
+    mask = torch.ones(I0, dtype=torch.bool, device=dev)
+    mask[torch.from_numpy(used.astype(np.int64)).to(dev)] = False
+    assert bool(torch.all(A0[mask] == 0))
+    ctx.close()
