@@ -113,6 +113,20 @@ typedef struct ptk_options {
                                e = sqrt(SSE); 0 = run all iterations. With
                                tol > 0 every iteration waits for its error
                                (one small copy and synchronisation each).   */
+    int32_t approx_form;    /* how the Approx variant forms its sums S1, S2
+                               (ptk_iterate with approx_rate > 0,
+                               ptk_partial_error, ptk_truncate); same values
+                               up to rounding order. 0 = auto: row sums where
+                               available and their buffers take at most a
+                               quarter of the free device memory, else
+                               per-cell groups. 1 = per-cell groups: no memory
+                               beyond the sums. 2 = row sums, orders 4 and 5
+                               only (else PTK_E_UNSUPPORTED): every entry's
+                               2J weights r a and a^2 of one mode, nnz * 2J
+                               doubles, and one J^(N-1)-cell pair of sums per
+                               row of the grouping mode (the one with the
+                               fewest rows) and per slice of entries,
+                               (rows + slices) * 2 * J^(N-1) doubles.         */
 } ptk_options;
 
 /*

@@ -28,7 +28,8 @@ _dbl = C.c_double
 class _Options(C.Structure):
     _fields_ = [("precision", _i32), ("chunk_nnz", _i32), ("fuse_error", _i32),
                 ("profile", _i32), ("use_graph", _i32), ("pair_cache", _i32),
-                ("approx_rate", _dbl), ("delta_slices", _i32), ("tol", _dbl)]
+                ("approx_rate", _dbl), ("delta_slices", _i32), ("tol", _dbl),
+                ("approx_form", _i32)]
 
 
 class PtkError(RuntimeError):
@@ -185,9 +186,9 @@ class Context:
     # -- C ABI calls ---------------------------------------------------------
     def set_options(self, precision=PREC_FP64_ACC, chunk_nnz=0, fuse_error=1,
                     profile=0, use_graph=1, pair_cache=0, approx_rate=0.0,
-                    delta_slices=0, tol=0.0):
+                    delta_slices=0, tol=0.0, approx_form=0):
         o = _Options(precision, chunk_nnz, fuse_error, profile, use_graph, pair_cache,
-                     float(approx_rate), delta_slices, float(tol))
+                     float(approx_rate), delta_slices, float(tol), approx_form)
         self._check(self._lib.ptk_set_options(self._h, C.byref(o)))
 
     def set_observed(self, idx, val):

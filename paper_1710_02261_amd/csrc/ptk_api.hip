@@ -91,6 +91,21 @@ void collect_timers(ptk_ctx *c) {
     c->pending.clear();
 }
 
+void free_approx(ptk_ctx *c) {
+    dfree(c->ap_resid);
+    dfree(c->ap_part);
+    dfree(c->ap_R);
+    dfree(c->ap_removed);
+    dfree(c->ap_uw);
+    dfree(c->ap_tbuf);
+    c->ap_resid = c->ap_part = c->ap_R = c->ap_uw = c->ap_tbuf = nullptr;
+    c->ap_removed = nullptr;
+    c->ap_slices = 0;
+    c->ap_form = 0;
+    c->ap_rs_slices = 0;
+    c->ap_nfold = 0;
+}
+
 void free_modes(ptk_ctx *c) {
     for (int n = 0; n < kMaxN; ++n) {
         ModeData &m = c->md[n];
@@ -111,13 +126,7 @@ void free_modes(ptk_ctx *c) {
     c->pcache = nullptr;
     dfree(c->dpart);
     c->dpart = nullptr;
-    dfree(c->ap_resid);
-    dfree(c->ap_part);
-    dfree(c->ap_R);
-    dfree(c->ap_removed);
-    c->ap_resid = c->ap_part = c->ap_R = nullptr;
-    c->ap_removed = nullptr;
-    c->ap_slices = 0;
+    free_approx(c);
     c->bbuf = c->part = nullptr;
     c->part_cap = 0;
     c->nnz = -1;
@@ -488,15 +497,51 @@ ptk_status configure_ranges(ptk_ctx *c, int n, int64_t work) {
 
 // Buffers of the Approx variant, sized for the observed set (not inside a
 // graph capture).
+// The mode whose rows group the entries of the partial errors: the one with
+// the fewest rows (fewest folds).
+int approx_mode(const ptk_ctx *c) {
+    int g = 0;
+    for (int n = 1; n < c->s.N; ++n)
+        if (c->s.dims[n] < c->s.dims[g]) g = n;
+    return g;
+}
+
 ptk_status ensure_approx(ptk_ctx *c) {
-    if (!(equal_ranks(c->s) && approx_available(c->s.N, c->s.ranks[0])))
+    const int N = c->s.N, J = c->s.ranks[0];
+    if (!(equal_ranks(c->s) && approx_available(N, J)))
         return fail(c, PTK_E_UNSUPPORTED, "no Approx kernels for this shape");
-    if (c->ap_R) return PTK_OK;
+    // form: row sums where compiled and their buffers take at most a quarter
+    // of the free device memory (or when asked for), else per-cell groups
+    int form = 1;
+    int64_t rs_slices = 0, tdoubles = 0, udoubles = 0;
+    if (c->opt.approx_form != 1 && row_sums_available(N, J)) {
+        rs_slices = row_sums_slices(c->s, c->nnz, c->num_cu);
+        tdoubles = row_sums_tbuf_doubles(c->s, approx_mode(c), rs_slices);
+        udoubles = std::max<int64_t>(c->nnz, 1) * 2 * J;
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+        const double need = 8.0 * (double)(tdoubles + udoubles);
+        if (c->opt.approx_form == 2 || need <= 0.25 * (double)free_b) form = 2;
+    } else if (c->opt.approx_form == 2) {
+        return fail(c, PTK_E_UNSUPPORTED, "no row-sum form of the partial errors for this shape");
+    }
+    if (c->ap_R && c->ap_form == form) return PTK_OK;
+    if (c->ap_R) free_approx(c);
     c->ap_slices = approx_slices(c->s, c->nnz, c->num_cu);
+    int64_t ranges = c->ap_slices;
+    if (form == 2) {
+        c->ap_rs_slices = rs_slices;
+        c->ap_nfold = (int32_t)std::min<int64_t>(256, c->s.dims[approx_mode(c)] + rs_slices);
+        ranges = std::max<int64_t>(ranges, c->ap_nfold);
+        HIPCHK(c, dalloc(&c->ap_uw, (size_t)udoubles));
+        HIPCHK(c, dalloc(&c->ap_tbuf, (size_t)tdoubles));
+    }
     HIPCHK(c, dalloc(&c->ap_resid, (size_t)c->nnz + 64));
-    HIPCHK(c, dalloc(&c->ap_part, (size_t)approx_part_doubles(c->s, c->ap_slices)));
+    HIPCHK(c, dalloc(&c->ap_part, (size_t)approx_part_doubles(c->s, (int32_t)ranges)));
     HIPCHK(c, dalloc(&c->ap_R, (size_t)c->core_cells));
     HIPCHK(c, dalloc(&c->ap_removed, 1));
+    c->ap_form = form;
+    c->epoch++;
     return PTK_OK;
 }
 
@@ -505,10 +550,7 @@ ptk_status ensure_approx(ptk_ctx *c) {
 // bound core followed by fresh permuted cores. Kernels only (capturable).
 ptk_status approx_step(ptk_ctx *c, double p, bool remove) {
     const int N = c->s.N;
-    // group the entries by the mode with the fewest rows (fewest folds)
-    int g = 0;
-    for (int n = 1; n < N; ++n)
-        if (c->s.dims[n] < c->s.dims[g]) g = n;
+    const int g = approx_mode(c);
     const ModeData &m = c->md[g];
     EntryArgs ea{};
     const int32_t *other[kMaxN];
@@ -524,24 +566,53 @@ ptk_status approx_step(ptk_ctx *c, double p, bool remove) {
     const int64_t nb = std::max<int64_t>(
         1, std::min<int64_t>(kSseBlocks, (c->nnz + kWave - 1) / kWave));
     HIPCHK(c, timed(c, "approx_resid", [&] { return launch_residual(ea, c->s, nb, c->st); }));
-    ApproxArgs aa{};
-    for (int t = 0; t < N - 1; ++t) {
-        aa.fac[t] = c->fac[t < g ? t : t + 1];
-        aa.idx[t] = other[t];
+    if (c->ap_form == 2) {
+        RowSumArgs ra{};
+        for (int t = 0; t < N - 1; ++t) {
+            ra.fac[t] = c->fac[t < g ? t : t + 1];
+            ra.idx[t] = other[t];
+        }
+        ra.fac_g = c->fac[g];
+        ra.rows = m.rows;
+        ra.rowptr = m.rowptr;
+        ra.resid = c->ap_resid;
+        ra.uw = c->ap_uw;
+        ra.tbuf = c->ap_tbuf;
+        ra.g = g;
+        ra.nrows = c->s.dims[g];
+        ra.nnz = c->nnz;
+        ra.nslices = c->ap_rs_slices;
+        ra.slice = std::max<int64_t>(1, (c->nnz + ra.nslices - 1) / ra.nslices);
+        ra.nslots = ra.nrows + ra.nslices;
+        ra.nfold = c->ap_nfold;
+        ra.fold_per = (ra.nslots + ra.nfold - 1) / ra.nfold;
+        ra.part = c->ap_part;
+        HIPCHK(c, timed(c, "approx_partial", [&] { return launch_row_sums(ra, c->s, c->st); }));
+        HIPCHK(c, timed(c, "approx_reduce", [&] {
+            return launch_partial_reduce(c->ap_part, ra.nfold, c->core, c->core_cells,
+                                         c->ap_R, c->st);
+        }));
+    } else {
+        ApproxArgs aa{};
+        for (int t = 0; t < N - 1; ++t) {
+            aa.fac[t] = c->fac[t < g ? t : t + 1];
+            aa.idx[t] = other[t];
+        }
+        aa.fac_g = c->fac[g];
+        aa.rows = m.rows;
+        aa.g = g;
+        aa.resid = c->ap_resid;
+        aa.nnz = c->nnz;
+        aa.nslices = c->ap_slices;
+        aa.slice = std::max<int64_t>(1, (c->nnz + c->ap_slices - 1) / c->ap_slices);
+        aa.part = c->ap_part;
+        HIPCHK(c, timed(c, "approx_partial",
+                        [&] { return launch_partial_error(aa, c->s, c->st); }));
+        HIPCHK(c, timed(c, "approx_reduce", [&] {
+            return launch_partial_reduce(c->ap_part, c->ap_slices, c->core, c->core_cells,
+                                         c->ap_R, c->st);
+        }));
     }
-    aa.fac_g = c->fac[g];
-    aa.rows = m.rows;
-    aa.g = g;
-    aa.resid = c->ap_resid;
-    aa.nnz = c->nnz;
-    aa.nslices = c->ap_slices;
-    aa.slice = std::max<int64_t>(1, (c->nnz + c->ap_slices - 1) / c->ap_slices);
-    aa.part = c->ap_part;
-    HIPCHK(c, timed(c, "approx_partial", [&] { return launch_partial_error(aa, c->s, c->st); }));
-    HIPCHK(c, timed(c, "approx_reduce", [&] {
-        return launch_partial_reduce(c->ap_part, c->ap_slices, c->core, c->core_cells,
-                                     c->ap_R, c->st);
-    }));
     if (remove) {
         HIPCHK(c, timed(c, "approx_select", [&] {
             return launch_approx_select(c->ap_R, c->core, c->core_cells, p,
@@ -753,6 +824,8 @@ ptk_status ptk_set_options(ptk_ctx *c, const ptk_options *o) {
         return fail(c, PTK_E_STATE, "delta_slices must be set before ptk_set_observed");
     if (!(o->approx_rate >= 0.0 && o->approx_rate < 1.0))
         return fail(c, PTK_E_INVALID, "approx_rate must be in [0, 1)");
+    if (o->approx_form < 0 || o->approx_form > 2)
+        return fail(c, PTK_E_INVALID, "approx_form must be 0, 1 or 2");
     if (o->approx_rate > 0.0 &&
         !(equal_ranks(c->s) && approx_available(c->s.N, c->s.ranks[0])))
         return fail(c, PTK_E_UNSUPPORTED, "no Approx kernels for this shape");

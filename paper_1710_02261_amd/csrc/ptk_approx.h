@@ -20,6 +20,27 @@ struct ApproxArgs {
     double *part;                     // [nslices][2][cells]: sums S1, S2
 };
 
+// Arguments of the row-sum form (orders 4 and 5).
+struct RowSumArgs {
+    const float *fac[kMaxN];          // as ApproxArgs: modes other than g
+    const int32_t *idx[kMaxN];
+    const float *fac_g;
+    const int32_t *rows;              // mode-g index per entry (grouped order)
+    const int64_t *rowptr;            // CSR row pointers of mode g
+    const double *resid;              // xhat - x per entry
+    double *uw;                       // [nnz][2][J] per-entry weights (scratch)
+    double *tbuf;                     // [nslots][2][J^(N-1)] row-piece sums
+    int32_t g;
+    int64_t nrows;                    // rows of mode g
+    int64_t nnz;
+    int64_t slice;                    // entries per slice
+    int64_t nslices;
+    int64_t nslots;                   // nrows + nslices
+    int64_t fold_per;                 // slots per fold range
+    int32_t nfold;                    // fold ranges
+    double *part;                     // [nfold][2][cells]: sums S1, S2
+};
+
 // Is the Approx variant compiled for this (N, J) with equal ranks?
 bool approx_available(int N, int J);
 
@@ -37,6 +58,13 @@ int64_t approx_part_doubles(const Shape &s, int32_t nslices);
 hipError_t launch_partial_error(const ApproxArgs &a, const Shape &s, hipStream_t st);
 hipError_t launch_partial_reduce(const double *part, int32_t nslices, const float *G,
                                  int64_t cells, double *R, hipStream_t st);
+
+// Row-sum form: available for orders 4 and 5; slices; slot buffer size
+// (doubles); S1, S2 per fold range into a.part.
+bool row_sums_available(int N, int J);
+int64_t row_sums_slices(const Shape &s, int64_t nnz, int num_cu);
+int64_t row_sums_tbuf_doubles(const Shape &s, int g, int64_t nslices);
+hipError_t launch_row_sums(const RowSumArgs &a, const Shape &s, hipStream_t st);
 
 // Alg. 4's removal: zero the floor(p * nz) non-zero cells of G with the
 // largest R (ties: lower cell index first); *removed receives the count.

@@ -289,6 +289,251 @@ hipError_t launch_partial_error(const ApproxArgs &a, const Shape &s, hipStream_t
     return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------------------
+// Row-sum form (orders 4 and 5): the same sums S1, S2 in three kernels.
+//
+// The cells beta' of T factor into (lead modes, third-last mode k, last two
+// modes p). Every lane owns one p and all J values of k, so that per entry
+// the 2J values r a[k] and a[k]^2 of the third-last mode's row are the same
+// for the whole wavefront: they are read once per entry through the scalar
+// cache (precomputed per entry by k_approx_uw) and each feeds one FMA per
+// lane, as the core values do in the row-system kernels. The lane holds T1,
+// T2 of its J cells for the current row; at the end of a row piece it
+// stores them to that piece's slot, and k_row_fold then forms
+// S(beta) = sum over slots a^(g)_{row, beta_g} T_slot(beta') per range of
+// slots. Slots: slot i for the piece of row i that holds its first entry,
+// slot rows + s for the first piece of slice s when its row began in an
+// earlier slice.
+// ---------------------------------------------------------------------------
+template <int J>
+__global__ void k_approx_uw(const double *__restrict__ resid, const float *__restrict__ fac3,
+                            const int32_t *__restrict__ idx3, int64_t nnz,
+                            double *__restrict__ uw) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (entry, k)
+    if (t >= nnz * J) return;
+    const int64_t e = t / J;
+    const int k = (int)(t % J);
+    const double a = (double)fac3[(int64_t)idx3[e] * J + k];
+    uw[e * 2 * J + k] = resid[e] * a;
+    uw[e * 2 * J + J + k] = a * a;
+}
+
+template <int N, int J>
+__global__ __launch_bounds__(kWave) void k_row_sums(RowSumArgs a) {
+    constexpr int NP = N - 1;             // other modes, NP >= 3
+    constexpr int P = J * J;
+    constexpr int NPG = (P + kWave - 1) / kWave;
+    constexpr int NLG = ipow(J, NP - 3);
+    constexpr int NT = ipow(J, NP);
+    __shared__ float s_va[kWave * J], s_vb[kWave * J];
+    __shared__ double s_q[kWave];
+    __shared__ int32_t s_ia[kWave], s_ib[kWave], s_row[kWave];
+    const int lane = threadIdx.x;
+    int b = blockIdx.x;
+    const int pg = b % NPG;
+    b /= NPG;
+    const int lg = b % NLG;
+    const int sl = b / NLG;
+    const int64_t e0 = (int64_t)sl * a.slice;
+    const int64_t e1 = min(e0 + a.slice, a.nnz);
+    if (e0 >= e1) return;                 // uniform
+    const int p = pg * kWave + lane;
+    const bool act = p < P;
+    const int m1 = act ? p / J : 0, m2 = act ? p % J : 0;
+    int pre[NP > 3 ? NP - 3 : 1];
+    {
+        int t = lg;
+#pragma unroll
+        for (int k = NP - 4; k >= 0; --k) {
+            pre[k] = t % J;
+            t /= J;
+        }
+    }
+    double T1[J], T2[J];
+#pragma unroll
+    for (int k = 0; k < J; ++k) T1[k] = T2[k] = 0.0;
+    int cur = -1;
+    int64_t slot = 0;
+    const float *fa = a.fac[NP - 2], *fb = a.fac[NP - 1];
+    // the weights of a tile are 8J lines of 128 bytes; the tile after the one
+    // being staged is touched with vector loads so that its scalar loads hit
+    // L2 instead of waiting on HBM (the values are folded into pf, which is
+    // consumed by a store that never happens, nnz being >= 0)
+    constexpr int kLines = 8 * J;
+    const unsigned char *uw_bytes = (const unsigned char *)a.uw;
+    const int64_t uw_end = a.nnz * 2 * J * 8;
+    uint32_t pf = 0;
+    for (int64_t base = e0; base < e1; base += kWave) {
+        const int nb = (int)min((int64_t)kWave, e1 - base);
+        for (int t = lane; t < kLines; t += kWave) {
+            const int64_t off = (base + kWave) * 2 * J * 8 + (int64_t)t * 128;
+            if (base + kWave < e1 && off < uw_end) pf += *(const uint32_t *)(uw_bytes + off);
+        }
+        {
+            const bool ok = lane < nb;
+            const int64_t e = base + lane;
+            double q = 1.0;
+            if (ok) {
+#pragma unroll
+                for (int k = 0; k < NP - 3; ++k)
+                    q *= (double)a.fac[k][(int64_t)a.idx[k][e] * J + pre[k]];
+            }
+            s_q[lane] = q;
+            s_ia[lane] = ok ? a.idx[NP - 2][e] : 0;
+            s_ib[lane] = ok ? a.idx[NP - 1][e] : 0;
+            s_row[lane] = ok ? a.rows[e] : -1;
+        }
+        __syncthreads();
+        for (int t = lane; t < kWave * J; t += kWave) {
+            const int u = t / J, j = t % J;
+            s_va[t] = fa[(int64_t)s_ia[u] * J + j];
+            s_vb[t] = fb[(int64_t)s_ib[u] * J + j];
+        }
+        __syncthreads();
+        for (int u = 0; u < nb; ++u) {
+            const int row = __builtin_amdgcn_readfirstlane(s_row[u]);
+            if (row != cur) {
+                if (cur >= 0 && act) {
+                    double *o = a.tbuf + slot * 2 * NT + (int64_t)lg * J * P + p;
+#pragma unroll
+                    for (int k = 0; k < J; ++k) {
+                        o[k * P] = T1[k];
+                        o[NT + k * P] = T2[k];
+                    }
+                }
+                cur = row;
+                const int64_t e = base + u;
+                slot = (e == e0 && e0 > 0 && a.rows[e0 - 1] == row) ? a.nrows + sl : row;
+#pragma unroll
+                for (int k = 0; k < J; ++k) T1[k] = T2[k] = 0.0;
+            }
+            double v = (double)s_va[u * J + m1] * (double)s_vb[u * J + m2];
+            if constexpr (NP > 3) v *= s_q[u];
+            const double v2 = v * v;
+            cptr<double> w = (cptr<double>)(a.uw + (base + u) * 2 * J);
+#pragma unroll
+            for (int k = 0; k < J; ++k) {
+                T1[k] = __builtin_fma(w[k], v, T1[k]);
+                T2[k] = __builtin_fma(w[J + k], v2, T2[k]);
+            }
+        }
+        __syncthreads();
+    }
+    if (cur >= 0 && act) {
+        double *o = a.tbuf + slot * 2 * NT + (int64_t)lg * J * P + p;
+#pragma unroll
+        for (int k = 0; k < J; ++k) {
+            o[k * P] = T1[k];
+            o[NT + k * P] = T2[k];
+        }
+    }
+    if (a.nnz < 0) a.tbuf[lane] = (double)pf;
+}
+
+// part[r][0..1][cell] = S1, S2 over the slots of range r (fixed order).
+template <int N, int J>
+__global__ __launch_bounds__(256) void k_row_fold(RowSumArgs a) {
+    constexpr int NT = ipow(J, N - 1);
+    constexpr int CELLS = NT * J;
+    const int rest = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    const int64_t s0 = (int64_t)r * a.fold_per;
+    const int64_t s1 = min(s0 + a.fold_per, a.nslots);
+    double S1[J], S2[J];
+#pragma unroll
+    for (int k = 0; k < J; ++k) S1[k] = S2[k] = 0.0;
+    if (rest < NT) {
+        // slots never written (empty rows, slices that start a row) are read
+        // but replaced by zero; no branch, so several slots' loads overlap
+#pragma unroll 4
+        for (int64_t q = s0; q < s1; ++q) {
+            int64_t row = 0;
+            bool valid;
+            if (q < a.nrows) {
+                row = q;
+                valid = a.rowptr[row + 1] > a.rowptr[row];
+            } else {
+                const int64_t e = (q - a.nrows) * a.slice;
+                valid = e > 0 && e < a.nnz && a.rows[e - 1] == a.rows[e];
+                row = valid ? a.rows[e] : 0;
+            }
+            const double t1v = a.tbuf[q * 2 * NT + rest];
+            const double t2v = a.tbuf[q * 2 * NT + NT + rest];
+            const double t1 = valid ? t1v : 0.0, t2 = valid ? t2v : 0.0;
+            cptr<float> ag = (cptr<float>)(a.fac_g + row * J);
+#pragma unroll
+            for (int k = 0; k < J; ++k) {
+                const double x = (double)ag[k];
+                S1[k] = __builtin_fma(x, t1, S1[k]);
+                S2[k] = __builtin_fma(x * x, t2, S2[k]);
+            }
+        }
+        // C-order cell of (beta_g = k, beta' = rest): beta_g inserted at mode g
+        const int64_t sg = ipow_rt(J, N - 1 - a.g);
+        const int64_t hi = rest / sg, lo = rest % sg;
+        double *o1 = a.part + (int64_t)r * 2 * CELLS;
+        double *o2 = o1 + CELLS;
+#pragma unroll
+        for (int k = 0; k < J; ++k) {
+            const int64_t cell = (hi * J + k) * sg + lo;
+            o1[cell] = S1[k];
+            o2[cell] = S2[k];
+        }
+    }
+}
+
+// the Approx shapes of orders 4 and 5
+#define PTK_ROWSUM_SHAPES(X) X(4, 3) X(4, 5) X(4, 8) X(4, 10) X(5, 3) X(5, 5) X(5, 8)
+
+bool row_sums_available(int N, int J) {
+#define PTK_X(n_, j_) if (N == n_ && J == j_) return true;
+    PTK_ROWSUM_SHAPES(PTK_X)
+#undef PTK_X
+    return false;
+}
+
+int64_t row_sums_slices(const Shape &s, int64_t nnz, int num_cu) {
+    const int J = s.ranks[0];
+    int64_t waves_per_slice = (int64_t)((J * J + kWave - 1) / kWave);
+    for (int k = 4; k <= s.N - 1; ++k) waves_per_slice *= J;
+    // about 16 wavefronts per CU in all, slices of at least 256 entries
+    int64_t sl = ((int64_t)16 * num_cu + waves_per_slice - 1) / waves_per_slice;
+    sl = std::min<int64_t>(sl, (nnz + 255) / 256);
+    return std::max<int64_t>(1, sl);
+}
+
+int64_t row_sums_tbuf_doubles(const Shape &s, int g, int64_t nslices) {
+    return (s.dims[g] + nslices) * 2 * ipow_rt(s.ranks[0], s.N - 1);
+}
+
+hipError_t launch_row_sums(const RowSumArgs &a, const Shape &s, hipStream_t st) {
+    const int J = s.ranks[0];
+#define PTK_X(n_, j_)                                                                   \
+    if (s.N == n_ && J == j_) {                                                         \
+        if (a.nnz > 0) {                                                                \
+            const int64_t t = a.nnz * j_;                                               \
+            hipLaunchKernelGGL((k_approx_uw<j_>), dim3((unsigned)((t + 255) / 256)),    \
+                               dim3(256), 0, st, a.resid, a.fac[n_ - 4], a.idx[n_ - 4], \
+                               a.nnz, a.uw);                                            \
+            hipError_t e = hipGetLastError();                                           \
+            if (e != hipSuccess) return e;                                              \
+            const int64_t blocks = (int64_t)((j_ * j_ + kWave - 1) / kWave) *           \
+                                   ipow(j_, n_ - 4) * a.nslices;                         \
+            hipLaunchKernelGGL((k_row_sums<n_, j_>), dim3((unsigned)blocks), dim3(kWave), \
+                               0, st, a);                                               \
+            if ((e = hipGetLastError()) != hipSuccess) return e;                        \
+        }                                                                               \
+        const int nt = ipow(j_, n_ - 1);                                                \
+        hipLaunchKernelGGL((k_row_fold<n_, j_>),                                        \
+                           dim3((unsigned)((nt + 255) / 256), (unsigned)a.nfold),       \
+                           dim3(256), 0, st, a);                                        \
+        return hipGetLastError();                                                       \
+    }
+    PTK_ROWSUM_SHAPES(PTK_X)
+#undef PTK_X
+    return hipErrorInvalidValue;
+}
+
 // R(beta) = 2 G S1 - G^2 S2, slices summed in order; 0 (positive) for cells
 // that are not entries of the core.
 __global__ void k_partial_reduce(const double *__restrict__ part, int32_t nslices,

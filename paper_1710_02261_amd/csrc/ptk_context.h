@@ -55,7 +55,7 @@ struct ptk_ctx {
     hipStream_t st = nullptr;
     int device = 0;
     int num_cu = 256;
-    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1, 0, 0.0, 0, 0.0};
+    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1, 0, 0.0, 0, 0.0, 0};
     int64_t nnz = -1;
     ModeData md[ptk::kMaxN];
     float *core = nullptr;
@@ -73,6 +73,11 @@ struct ptk_ctx {
     double *ap_resid = nullptr, *ap_part = nullptr, *ap_R = nullptr;
     int32_t *ap_removed = nullptr;
     int32_t ap_slices = 0;
+    // row-sum form of the partial errors: per-entry weights, row-piece sums
+    double *ap_uw = nullptr, *ap_tbuf = nullptr;
+    int32_t ap_form = 0;         // 0 none yet, 1 per-cell-group sums, 2 row sums
+    int64_t ap_rs_slices = 0;
+    int32_t ap_nfold = 0;
     int64_t part_cap = 0;
     double *red = nullptr;       // [kRedBlocks * (N + 1)] partials + scalars
     double *xsq = nullptr;       // sum of x^2 over Omega (device, 1 double)

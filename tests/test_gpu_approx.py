@@ -68,10 +68,17 @@ def check_removal(G_before, G_gpu, R, sse, p):
     assert np.all(rem_gpu[clear_in]) and not np.any(rem_gpu[clear_out])
 
 
-@pytest.mark.parametrize("dims,J", SHAPES, ids=ids())
-def test_partial_error_matches_oracle(dims, J):
+FORMS = [(d, j, 0) for d, j in SHAPES] + [(d, j, 1) for d, j in SHAPES if len(d) >= 4]
+
+
+@pytest.mark.parametrize("dims,J,form", FORMS,
+                         ids=["%dd-J%d-form%d" % (len(d), j, f) for d, j, f in FORMS])
+def test_partial_error_matches_oracle(dims, J, form):
+    """form 0 (auto) takes the row sums at orders 4 and 5, form 1 the
+    per-cell groups."""
     p = problem(dims, J, seed=51)
     ctx, idx, val, core, fac = context(p)
+    ctx.set_options(approx_form=form)
     R = ctx.partial_error().cpu().numpy()
     G, A = model64(p)
     v = p.val.astype(np.float64)
@@ -174,6 +181,34 @@ def test_rate_removing_nothing_is_plain_path():
     cp.close()
 
 
+@pytest.mark.parametrize("dims,J", [((40, 30, 20, 6), 5), ((9, 8, 7, 7, 6), 3),
+                                    ((60, 50, 40, 8), 10), ((10, 9, 8, 7, 5), 8)])
+def test_row_sum_form_equals_cell_groups(dims, J):
+    """The two forms of S1, S2 give R equal up to rounding order, on entries
+    whose grouping mode (the last, fewest rows) has empty rows and one row
+    holding most entries, so that row pieces cross many slices."""
+    rng = np.random.default_rng(57)
+    p = problem(dims, J, seed=57, nnz=6000)
+    last = len(dims) - 1
+    used = np.array([0, 2, dims[last] - 1])
+    p.idx[last] = used[np.minimum(rng.geometric(0.25, p.idx.shape[1]) - 1, 2)]
+    G, A = model64(p)
+    v = p.val.astype(np.float64)
+    Rs = []
+    for form in (2, 1):
+        ctx, idx, val, core, fac = context(p)
+        ctx.set_options(approx_form=form)
+        Rs.append(ctx.partial_error().cpu().numpy())
+        ctx.close()
+    want = oracle.partial_error(G, A, p.idx, v)
+    sse = oracle.sse(G, A, p.idx, v)
+    scale = sse + np.abs(want).max()
+    log("row sums vs cell groups", dims, J, "diff %.3g, vs oracle %.3g, scale %.3g"
+        % (np.abs(Rs[0] - Rs[1]).max(), np.abs(Rs[0] - want).max(), scale))
+    assert np.abs(Rs[0] - Rs[1]).max() <= 1e-12 * scale
+    assert np.abs(Rs[0] - want).max() <= 1e-9 * scale
+
+
 def test_approx_refusals():
     import paper_1710_02261_amd as ptk
     p = problem((20, 20, 20), 4, seed=56, nnz=500)
@@ -183,6 +218,11 @@ def test_approx_refusals():
             ctx.set_options(approx_rate=bad)
     with pytest.raises(ptk.PtkError, match="PTK_E_INVALID"):
         ctx.truncate(1.5)
+    with pytest.raises(ptk.PtkError, match="PTK_E_INVALID"):
+        ctx.set_options(approx_form=3)
+    ctx.set_options(approx_form=2)          # order 3: no row-sum form
+    with pytest.raises(ptk.PtkError, match="PTK_E_UNSUPPORTED"):
+        ctx.partial_error()
     ctx.close()
     ctx = ptk.Context((20, 20, 20), (3, 2, 4))
     with pytest.raises(ptk.PtkError, match="PTK_E_UNSUPPORTED"):
