@@ -480,7 +480,7 @@ def main():
     traffic = traffic_record(p.nnz) if args.workload == "c2" and main_prec == "f64" else None
     # two entries per lane on the shapes where that wins (ptk_gram2.hip)
     dual = {(4, 10): 1, (5, 8): 2}
-    kname = {"f64": ("k_gram_fast2<%d,%d,%d,double>" % (N, J, dual[(N, J)])
+    kname = {"f64": ("k_gram_fast2<%d,%d,%d,double,false>" % (N, J, dual[(N, J)])
                      if (N, J) in dual else "k_gram_fast<%d,%d,U,double>" % (N, J)),
              "f32": "k_gram_fast<%d,%d,U,float>" % (N, J),
              "bf16": "k_gram_mfma<%d,%d,1>" % (N, J),

@@ -98,7 +98,8 @@ void free_approx(ptk_ctx *c) {
     dfree(c->ap_removed);
     dfree(c->ap_uw);
     dfree(c->ap_tbuf);
-    c->ap_resid = c->ap_part = c->ap_R = c->ap_uw = c->ap_tbuf = nullptr;
+    dfree(c->ap_delta);
+    c->ap_resid = c->ap_part = c->ap_R = c->ap_uw = c->ap_tbuf = c->ap_delta = nullptr;
     c->ap_removed = nullptr;
     c->ap_slices = 0;
     c->ap_form = 0;
@@ -304,8 +305,13 @@ ptk_status systems(ptk_ctx *c, int n, int role = 0) {
         return PTK_OK;
     }
     GramArgs a = gram_args(c, n);
+    const bool two = m.fast && gram2_available(c->s.N, c->s.ranks[n], arith_of(c, n));
+    if (two && c->ap_store && c->ap_delta) {
+        a.dstore = c->ap_delta;
+        c->ap_stored = true;
+    }
     HIPCHK(c, timed(c, "gram", [&] {
-        if (m.fast && gram2_available(c->s.N, c->s.ranks[n], arith_of(c, n)))
+        if (two)
             return launch_gram2(a, c->s.N, c->s.ranks[n], arith_of(c, n), m.nchunks, c->st);
         return launch_gram(a, c->s, n, arith_of(c, n), m.nchunks, m.fast, c->st);
     }));
@@ -498,10 +504,11 @@ ptk_status configure_ranges(ptk_ctx *c, int n, int64_t work) {
 // Buffers of the Approx variant, sized for the observed set (not inside a
 // graph capture).
 // The mode whose rows group the entries of the partial errors: the one with
-// the fewest rows (fewest folds).
+// the fewest rows (fewest folds); among equals the last one, whose row-system
+// kernel runs last in an iteration and can keep its deltas.
 int approx_mode(const ptk_ctx *c) {
-    int g = 0;
-    for (int n = 1; n < c->s.N; ++n)
+    int g = c->s.N - 1;
+    for (int n = c->s.N - 2; n >= 0; --n)
         if (c->s.dims[n] < c->s.dims[g]) g = n;
     return g;
 }
@@ -536,6 +543,13 @@ ptk_status ensure_approx(ptk_ctx *c) {
         HIPCHK(c, dalloc(&c->ap_uw, (size_t)udoubles));
         HIPCHK(c, dalloc(&c->ap_tbuf, (size_t)tdoubles));
     }
+    if (approx_mode(c) == N - 1 && gram2_available(N, J, kArithF64)) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+        const double need = 8.0 * (double)J * (double)std::max<int64_t>(c->nnz, 1);
+        if (need <= 0.25 * (double)free_b)
+            HIPCHK(c, dalloc(&c->ap_delta, (size_t)J * std::max<int64_t>(c->nnz, 1)));
+    }
     HIPCHK(c, dalloc(&c->ap_resid, (size_t)c->nnz + 64));
     HIPCHK(c, dalloc(&c->ap_part, (size_t)approx_part_doubles(c->s, (int32_t)ranges)));
     HIPCHK(c, dalloc(&c->ap_R, (size_t)c->core_cells));
@@ -548,7 +562,7 @@ ptk_status ensure_approx(ptk_ctx *c) {
 // Alg. 4 on the bound model: residuals over the mode-0 grouping, R(beta) of
 // every cell into ap_R, and with remove the removal of the top cells from the
 // bound core followed by fresh permuted cores. Kernels only (capturable).
-ptk_status approx_step(ptk_ctx *c, double p, bool remove) {
+ptk_status approx_step(ptk_ctx *c, double p, bool remove, bool deltas_kept = false) {
     const int N = c->s.N;
     const int g = approx_mode(c);
     const ModeData &m = c->md[g];
@@ -565,7 +579,14 @@ ptk_status approx_step(ptk_ctx *c, double p, bool remove) {
     HIPCHK(c, permute_entries(c, g));
     const int64_t nb = std::max<int64_t>(
         1, std::min<int64_t>(kSseBlocks, (c->nnz + kWave - 1) / kWave));
-    HIPCHK(c, timed(c, "approx_resid", [&] { return launch_residual(ea, c->s, nb, c->st); }));
+    const bool kept = deltas_kept && g == N - 1;
+    HIPCHK(c, timed(c, kept ? "approx_resid_kept" : "approx_resid", [&] {
+        // g is the last mode and its kernel kept the deltas of this iteration
+        if (kept)
+            return launch_resid_from_delta(c->ap_delta, c->fac[g], m.rows, m.vals, c->nnz,
+                                           c->s.ranks[g], c->ap_resid, c->st);
+        return launch_residual(ea, c->s, nb, c->st);
+    }));
     if (c->ap_form == 2) {
         RowSumArgs ra{};
         for (int t = 0; t < N - 1; ++t) {
@@ -631,8 +652,13 @@ ptk_status iteration_body(ptk_ctx *c, double lambda) {
     const int N = c->s.N;
     double *partial = c->red;
     double *scal = c->scal;
+    // Approx variant: the last mode's kernel may keep its deltas for the
+    // residuals (when the partial errors group by that mode)
+    c->ap_stored = false;
     for (int n = 0; n < N; ++n) {
+        c->ap_store = c->opt.approx_rate > 0.0 && n == N - 1;
         ptk_status s = update_mode_impl(c, n, lambda, cache_role(c, n));
+        c->ap_store = false;
         if (s != PTK_OK) return s;
     }
     HIPCHK(c, timed(c, "error", [&]() -> hipError_t {
@@ -655,7 +681,8 @@ ptk_status iteration_body(ptk_ctx *c, double lambda) {
                        c->iter_ctr);
     HIPCHK(c, hipGetLastError());
     // Approx variant: remove cells of G after the error (Alg. 2, Alg. 4)
-    if (c->opt.approx_rate > 0.0) return approx_step(c, c->opt.approx_rate, true);
+    if (c->opt.approx_rate > 0.0)
+        return approx_step(c, c->opt.approx_rate, true, c->ap_stored);
     return PTK_OK;
 }
 

@@ -50,6 +50,12 @@ bool approx_available(int N, int J);
 hipError_t launch_residual(const EntryArgs &a, const Shape &s, int64_t nblocks,
                            hipStream_t st);
 
+// The residuals of the same grouping from stored deltas ([J][nnz]) and the
+// updated factor of that mode: resid = delta . a_new - x.
+hipError_t launch_resid_from_delta(const double *delta, const float *fac, const int32_t *rows,
+                                   const float *val, int64_t nnz, int J, double *resid,
+                                   hipStream_t st);
+
 // Slices and part size (doubles) for nnz entries.
 int32_t approx_slices(const Shape &s, int64_t nnz, int num_cu);
 int64_t approx_part_doubles(const Shape &s, int32_t nslices);

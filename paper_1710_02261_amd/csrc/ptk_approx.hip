@@ -99,6 +99,41 @@ hipError_t launch_residual(const EntryArgs &a, const Shape &s, int64_t nblocks,
     return hipErrorInvalidValue;
 }
 
+// The same residuals from deltas the last mode's row-system kernel stored
+// ([J][nnz], its grouped order): xhat = delta . a_new, J multiply-adds.
+template <int J>
+__global__ void k_resid_from_delta(const double *__restrict__ delta,
+                                   const float *__restrict__ fac,
+                                   const int32_t *__restrict__ rows,
+                                   const float *__restrict__ val, int64_t nnz,
+                                   double *__restrict__ resid) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nnz) return;
+    const float *own = fac + (int64_t)rows[p] * J;
+    double xh = 0.0;
+#pragma unroll
+    for (int j = 0; j < J; ++j) xh = __builtin_fma((double)own[j], delta[(int64_t)j * nnz + p], xh);
+    resid[p] = xh - (double)val[p];
+}
+
+hipError_t launch_resid_from_delta(const double *delta, const float *fac, const int32_t *rows,
+                                   const float *val, int64_t nnz, int J, double *resid,
+                                   hipStream_t st) {
+    if (nnz <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((nnz + 255) / 256)), block(256);
+    switch (J) {
+#define PTK_X(j_)                                                                          \
+    case j_:                                                                               \
+        hipLaunchKernelGGL(k_resid_from_delta<j_>, grid, block, 0, st, delta, fac, rows, val, \
+                           nnz, resid);                                                    \
+        return hipGetLastError();
+        PTK_X(3) PTK_X(4) PTK_X(5) PTK_X(8) PTK_X(10) PTK_X(16)
+#undef PTK_X
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // S1, S2 per slice of entries
 // ---------------------------------------------------------------------------

@@ -78,6 +78,10 @@ struct ptk_ctx {
     int32_t ap_form = 0;         // 0 none yet, 1 per-cell-group sums, 2 row sums
     int64_t ap_rs_slices = 0;
     int32_t ap_nfold = 0;
+    // deltas of the last mode kept by its row-system kernel ([J][nnz]) for the
+    // residuals; ap_store asks systems() to keep them, ap_stored says it did
+    double *ap_delta = nullptr;
+    bool ap_store = false, ap_stored = false;
     int64_t part_cap = 0;
     double *red = nullptr;       // [kRedBlocks * (N + 1)] partials + scalars
     double *xsq = nullptr;       // sum of x^2 over Omega (device, 1 double)

@@ -68,7 +68,8 @@ __device__ __forceinline__ void delta_fast2(const void *gp_raw, const float *aou
     }
 }
 
-template <int N, int J, int U, typename T>
+// KEEP: also store every entry's delta to a.dstore ([J][nnz], grouped order).
+template <int N, int J, int U, typename T, bool KEEP>
 __global__ __launch_bounds__(kWave) void k_gram_fast2(GramArgs a) {
     constexpr int NO = N - 1;
     constexpr int NOUT = NO - U;
@@ -116,6 +117,13 @@ __global__ __launch_bounds__(kWave) void k_gram_fast2(GramArgs a) {
         __syncthreads();
         double d0[J], d1[J];
         delta_fast2<NO, J, U, T>(a.gp, s_aout, lane, a0, a1, d0, d1);
+        if constexpr (KEEP) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                if (v0) a.dstore[(int64_t)j * a.nnz + p0] = d0[j];
+                if (v1) a.dstore[(int64_t)j * a.nnz + p1] = d1[j];
+            }
+        }
         __syncthreads();
         // first half: entries base .. base + 63
 #pragma unroll
@@ -151,7 +159,7 @@ bool gram2_available(int N, int J, Arith ar) {
 int gram2_blocks_per_cu(int N, int J, Arith ar) {
 #define PTK_X(n_, j_, t_, u_)                                                             \
     if (N == n_ && J == j_ && (sizeof(t_) == 8) == (ar == kArithF64))                   \
-        return blocks_per_cu(k_gram_fast2<n_, j_, u_, t_>, 0);
+        return blocks_per_cu(k_gram_fast2<n_, j_, u_, t_, false>, 0);
     PTK_FAST2_SHAPES(PTK_X)
 #undef PTK_X
     return 1;
@@ -162,8 +170,12 @@ hipError_t launch_gram2(const GramArgs &a, int N, int J, Arith ar, int64_t nchun
     if (nchunks <= 0) return hipSuccess;
 #define PTK_X(n_, j_, t_, u_)                                                             \
     if (N == n_ && J == j_ && (sizeof(t_) == 8) == (ar == kArithF64)) {                 \
-        hipLaunchKernelGGL((k_gram_fast2<n_, j_, u_, t_>),                               \
-                           dim3((unsigned)nchunks), dim3(kWave), 0, st, a);               \
+        if (a.dstore)                                                                     \
+            hipLaunchKernelGGL((k_gram_fast2<n_, j_, u_, t_, true>),                     \
+                               dim3((unsigned)nchunks), dim3(kWave), 0, st, a);           \
+        else                                                                              \
+            hipLaunchKernelGGL((k_gram_fast2<n_, j_, u_, t_, false>),                    \
+                               dim3((unsigned)nchunks), dim3(kWave), 0, st, a);           \
         return hipGetLastError();                                                         \
     }
     PTK_FAST2_SHAPES(PTK_X)

@@ -68,6 +68,9 @@ struct GramArgs {
     double *cache;
     const int32_t *cmap;
     int32_t cslot;
+    // optional (two-entry kernel): the delta of every entry, [jn][nnz] FP64 in
+    // the grouped order, kept for the residuals of the Approx variant
+    double *dstore;
 };
 
 // Arguments of the per-entry kernels (predict, error, delta inspection).

@@ -110,12 +110,16 @@ def test_truncate_matches_oracle_ranking(dims, J, rate):
 
 
 @pytest.mark.parametrize("dims,J", [((30, 25, 20), 5), ((12, 11, 10, 9), 8),
-                                    ((8, 7, 6, 5, 4), 3)])
+                                    ((8, 7, 6, 5, 4), 3), ((12, 11, 10, 9), 10),
+                                    ((8, 7, 6, 5, 4), 8)])
 def test_approx_iterations_match_oracle(dims, J):
+    """At (4, 10) and (5, 8) the last mode has the fewest rows and its
+    two-entry row-system kernel keeps the deltas the residuals are formed
+    from; the other shapes recompute them."""
     import torch
     p = problem(dims, J, seed=53, nnz=4000)
-    ctx, idx, val, core, fac = context(p)
-    ctx.set_options(fuse_error=0, approx_rate=0.2)
+    ctx, idx, val, core, fac = context(p, profile=1)
+    ctx.set_options(fuse_error=0, approx_rate=0.2, profile=1, use_graph=0)
     v = p.val.astype(np.float64)
     n_left = core.numel()
     for t in range(3):
@@ -137,6 +141,8 @@ def test_approx_iterations_match_oracle(dims, J):
         n_left -= int(np.floor(0.2 * n_left))
         assert np.count_nonzero(G_gpu) == n_left
         log("approx iteration", t, "sse", sse[0], "core cells left", n_left)
+        kept = "approx_resid_kept" in ctx.kernel_times()
+        assert kept == ((len(dims), J) in ((4, 10), (5, 8)))
         # continue both from the oracle's state
         Go, _ = oracle.truncate(G, R, 0.2)
         core.copy_(torch.from_numpy(Go.astype(np.float32)))
