@@ -353,6 +353,8 @@ __global__ void k_approx_uw(const double *__restrict__ resid, const float *__res
     uw[e * 2 * J + J + k] = a * a;
 }
 
+constexpr int kXcds = 8;                 // XCDs of the MI355X
+
 template <int N, int J>
 __global__ __launch_bounds__(kWave) void k_row_sums(RowSumArgs a) {
     constexpr int NP = N - 1;             // other modes, NP >= 3
@@ -364,11 +366,15 @@ __global__ __launch_bounds__(kWave) void k_row_sums(RowSumArgs a) {
     __shared__ double s_q[kWave];
     __shared__ int32_t s_ia[kWave], s_ib[kWave], s_row[kWave];
     const int lane = threadIdx.x;
-    int b = blockIdx.x;
+    // workgroups go to the 8 XCDs in turn (block b on XCD b % 8): the
+    // wavefronts of one slice take blocks 8 apart, so that they share one
+    // XCD's L2 for the slice's weights and factor rows (nslices % 8 == 0)
+    const int x = blockIdx.x % kXcds;
+    int b = blockIdx.x / kXcds;
     const int pg = b % NPG;
     b /= NPG;
     const int lg = b % NLG;
-    const int sl = b / NLG;
+    const int sl = (b / NLG) * kXcds + x;
     const int64_t e0 = (int64_t)sl * a.slice;
     const int64_t e1 = min(e0 + a.slice, a.nnz);
     if (e0 >= e1) return;                 // uniform
@@ -534,7 +540,8 @@ int64_t row_sums_slices(const Shape &s, int64_t nnz, int num_cu) {
     // about 16 wavefronts per CU in all, slices of at least 256 entries
     int64_t sl = ((int64_t)16 * num_cu + waves_per_slice - 1) / waves_per_slice;
     sl = std::min<int64_t>(sl, (nnz + 255) / 256);
-    return std::max<int64_t>(1, sl);
+    sl = std::max<int64_t>(1, sl);
+    return (sl + kXcds - 1) / kXcds * kXcds;     // whole rounds of the XCDs
 }
 
 int64_t row_sums_tbuf_doubles(const Shape &s, int g, int64_t nslices) {
