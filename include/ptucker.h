@@ -239,7 +239,10 @@ ptk_status ptk_recon_error(ptk_ctx *ctx, double lambda, double *sse_host,
 /*
  * Final step of Alg. 2 (Sec. 3.1): for n = 0..N-1, A^(n) = Q R (thin QR,
  * diag(R) > 0), A^(n) <- Q, G <- G x_n R. Writes the bound factors and core.
- * PTK_E_NOT_PD if some A^(n) does not have full column rank.
+ * The QR is shifted CholeskyQR3 in FP64 (three Gram + Cholesky passes, the
+ * first with a small diagonal shift), defined for factors with condition
+ * numbers up to about 1e15. PTK_E_NOT_PD if some A^(n) does not have full
+ * column rank in floating point.
  */
 ptk_status ptk_orthogonalize(ptk_ctx *ctx);
 

@@ -1167,7 +1167,7 @@ ptk_status ptk_orthogonalize(ptk_ctx *c) {
     HIPCHK(c, zero_bad(c));
     for (int n = 0; n < s.N; ++n)
         HIPCHK(c, timed(c, "qr", [&] {
-            return launch_cholqr2(c->fac[n], s.dims[n], s.ranks[n], qrw,
+            return launch_thin_qr(c->fac[n], s.dims[n], s.ranks[n], qrw,
                                   Rs + (size_t)n * kMaxJ * kMaxJ, c->bad, c->st);
         }));
     HIPCHK(c, timed(c, "core_update", [&] {

@@ -1,11 +1,17 @@
 // Final step of Alg. 2 (Sec. 3.1): A^(n) = Q^(n) R^(n), A^(n) <- Q^(n),
 // G <- G x_n R^(n), in FP64.
 //
-// The thin QR of the tall-skinny I x J factor is taken by CholeskyQR2
-// (Fukaya et al., 2014): W = A^T A, W = R^T R (Cholesky), Q = A R^{-1},
-// repeated once on Q, R = R_2 R_1. Cholesky factors have a positive diagonal,
-// so this is the unique thin QR with diag(R) > 0 when A has full column rank.
-// The Gram sums are deterministic two-level reductions.
+// The thin QR of the tall-skinny I x J factor is taken by shifted
+// CholeskyQR3 (Fukaya, Kannan, Nakatsukasa, Yamamoto and Yanagisawa, 2020):
+// a first pass factors W + s I = R_0^T R_0, W = A^T A, with the shift
+// s = 11 (I J + J (J + 1)) u ||A||_F^2 (u = 2^-53, ||A||_F^2 = trace W), and
+// Q_0 = A R_0^{-1} is then well enough conditioned for CholeskyQR2 (Fukaya
+// et al., 2014): W = Q^T Q = R^T R, Q = Q R^{-1}, twice; R = R_2 R_1 R_0.
+// The shift keeps the first Cholesky factorisation defined up to
+// cond(A) of about 1/u instead of 1/sqrt(u); the two unshifted passes make
+// Q orthonormal to working precision. Cholesky factors have a positive
+// diagonal, so this is the unique thin QR with diag(R) > 0 when A has full
+// column rank. The Gram sums are deterministic two-level reductions.
 #include "ptk_internal.h"
 
 namespace ptk {
@@ -62,8 +68,9 @@ __global__ __launch_bounds__(kQrThreads) void k_colgram(const T *__restrict__ X,
 
 // Sum the block partials in order, factor W = R^T R; R (J x J, row-major,
 // upper) goes to R_out. If Rprev is given, R_out = R * Rprev and Rcur keeps R.
+// With shift_frac > 0, shift_frac * trace(W) is added to the diagonal first.
 __global__ __launch_bounds__(64) void k_chol_small(const double *__restrict__ part,
-                                                   int nparts, int J,
+                                                   int nparts, int J, double shift_frac,
                                                    double *__restrict__ Rcur,
                                                    const double *__restrict__ Rprev,
                                                    double *__restrict__ Rout,
@@ -83,6 +90,11 @@ __global__ __launch_bounds__(64) void k_chol_small(const double *__restrict__ pa
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        if (shift_frac > 0.0) {
+            double tr = 0.0;
+            for (int i = 0; i < J; ++i) tr += W[i * J + i];
+            for (int i = 0; i < J; ++i) W[i * J + i] += shift_frac * tr;
+        }
         // W = R^T R, R upper: R[i][j] for j >= i
         bool ok = true;
         for (int i = 0; i < J * J; ++i) R[i] = 0.0;
@@ -145,34 +157,45 @@ __global__ void k_right_solve(const T *__restrict__ X, int64_t I, int J,
 
 size_t qr_workspace_bytes(int64_t I, int J) {
     const int Tn = J * (J + 1) / 2;
-    return (size_t)I * J * 8 + (size_t)kQrBlocks * Tn * 8 + 3 * kMaxJ * kMaxJ * 8 +
+    return (size_t)2 * I * J * 8 + (size_t)kQrBlocks * Tn * 8 + 4 * kMaxJ * kMaxJ * 8 +
            1024;
 }
 
-hipError_t launch_cholqr2(float *A, int64_t I, int J, void *work, double *R,
+hipError_t launch_thin_qr(float *A, int64_t I, int J, void *work, double *R,
                           int32_t *bad, hipStream_t st) {
     const int Tn = J * (J + 1) / 2;
-    double *Q = (double *)work;
-    double *part = Q + I * J;
-    double *R1 = part + (size_t)kQrBlocks * Tn;
-    double *R2 = R1 + kMaxJ * kMaxJ;
+    double *Q0 = (double *)work;
+    double *Q1 = Q0 + I * J;
+    double *part = Q1 + I * J;
+    double *R0 = part + (size_t)kQrBlocks * Tn;
+    double *R1 = R0 + kMaxJ * kMaxJ;
+    double *R10 = R1 + kMaxJ * kMaxJ;
+    double *R2 = R10 + kMaxJ * kMaxJ;
     int64_t nb64 = (I + kQrRows - 1) / kQrRows;
     int blocks = (int)(nb64 < kQrBlocks ? nb64 : kQrBlocks);
     if (blocks < 1) blocks = 1;
     const unsigned rs_blocks = (unsigned)((I + 255) / 256);
-    // pass 1: W = A^T A, R1, Q = A R1^{-1}
+    const double shift = 11.0 * ((double)I * J + (double)J * (J + 1)) * 0x1p-53;
+    // shifted pass: W = A^T A, W + s I = R0^T R0, Q0 = A R0^{-1}
     hipLaunchKernelGGL(k_colgram<float>, dim3(blocks), dim3(kQrThreads), 0, st, A, I,
                        J, part);
-    hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(64), 0, st, part, blocks, J, R1,
+    hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(64), 0, st, part, blocks, J, shift, R0,
                        (const double *)nullptr, (double *)nullptr, bad);
     hipLaunchKernelGGL(k_right_solve<float>, dim3(rs_blocks), dim3(256), 0, st, A, I,
-                       J, R1, Q, (float *)nullptr);
-    // pass 2: W = Q^T Q, R2, Q = Q R2^{-1} (written to A), R = R2 R1
-    hipLaunchKernelGGL(k_colgram<double>, dim3(blocks), dim3(kQrThreads), 0, st, Q,
+                       J, R0, Q0, (float *)nullptr);
+    // CholeskyQR2 on Q0: R1 (R10 = R1 R0), Q1 = Q0 R1^{-1}; R2 (R = R2 R10),
+    // Q = Q1 R2^{-1} written to A
+    hipLaunchKernelGGL(k_colgram<double>, dim3(blocks), dim3(kQrThreads), 0, st, Q0,
                        I, J, part);
-    hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(64), 0, st, part, blocks, J, R2,
-                       R1, R, bad);
-    hipLaunchKernelGGL(k_right_solve<double>, dim3(rs_blocks), dim3(256), 0, st, Q,
+    hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(64), 0, st, part, blocks, J, 0.0, R1,
+                       R0, R10, bad);
+    hipLaunchKernelGGL(k_right_solve<double>, dim3(rs_blocks), dim3(256), 0, st, Q0,
+                       I, J, R1, Q1, (float *)nullptr);
+    hipLaunchKernelGGL(k_colgram<double>, dim3(blocks), dim3(kQrThreads), 0, st, Q1,
+                       I, J, part);
+    hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(64), 0, st, part, blocks, J, 0.0, R2,
+                       R10, R, bad);
+    hipLaunchKernelGGL(k_right_solve<double>, dim3(rs_blocks), dim3(256), 0, st, Q1,
                        I, J, R2, (double *)nullptr, A);
     return hipGetLastError();
 }

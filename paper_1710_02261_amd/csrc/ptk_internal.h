@@ -192,7 +192,9 @@ const char *global_error();
 
 // finalisation (ptk_finalize.hip)
 size_t qr_workspace_bytes(int64_t I, int J);
-hipError_t launch_cholqr2(float *A, int64_t I, int J, void *work, double *R,
+// thin QR by shifted CholeskyQR3: A (I x J, float) <- Q, R (J x J, row-major,
+// device) <- R; *bad counts factorisations that failed (rank-deficient A)
+hipError_t launch_thin_qr(float *A, int64_t I, int J, void *work, double *R,
                           int32_t *bad, hipStream_t st);
 hipError_t launch_core_mode_product(const float *G, float *Gout, const Shape &s,
                                     int n, const double *R, hipStream_t st);

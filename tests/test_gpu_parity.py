@@ -230,6 +230,36 @@ def test_orthogonalize_matches_oracle(dims, ranks):
     ctx.close()
 
 
+def test_orthogonalize_ill_conditioned_factor():
+    """Two columns of A^(0) equal up to one float32 ulp in a row of size 1e-3:
+    cond(A) about 6e11, so cond(A^T A) is far beyond 1/u and the Cholesky
+    factorisation of plain CholeskyQR2 breaks down (numpy's does on this
+    matrix). The shifted first pass keeps it: Q orthonormal, the model's
+    predictions unchanged, and Q against the oracle's Householder Q within
+    1e-4 (the two FP64 methods differ by 2e-6 here: cond(A) * u * (I J))."""
+    p = problem((1000, 40, 30), (3, 3, 3), 3000, seed=12)
+    a = (np.random.default_rng(12).random(1000) + 0.5).astype(np.float32)
+    a[0] = np.float32(1e-3)
+    p.factors[0][:, 0] = a
+    p.factors[0][:, 1] = a
+    p.factors[0][0, 1] = np.nextafter(a[0], np.float32(2.0))
+    A0 = p.factors[0].astype(np.float64)
+    s = np.linalg.svd(A0, compute_uv=False)
+    log("ill-conditioned factor: cond %.3g" % (s[0] / s[-1]))
+    assert s[0] / s[-1] > 1e11
+    ctx, idx, val, core, fac = context(p)
+    before = f64(ctx.predict(idx))
+    ctx.orthogonalize()
+    G, A, _ = oracle_inputs(p)
+    Go, Ao, Rs = oracle.orthogonalize(G, A)
+    Q = f64(fac[0])
+    np.testing.assert_allclose(Q.T @ Q, np.eye(3), atol=2e-6)
+    np.testing.assert_allclose(Q, Ao[0], atol=1e-4)
+    after = f64(ctx.predict(idx))
+    np.testing.assert_allclose(after, before, rtol=1e-5, atol=1e-5 * np.abs(before).max())
+    ctx.close()
+
+
 @pytest.mark.parametrize("k", [0, 1, 7, 300, 70000])
 def test_fold_in_matches_oracle(k):
     import torch
