@@ -230,3 +230,55 @@ def test_fullsize_rating_tensor_sampled_rows(c3, prec, bound, rmse_tol):
         log("precision", prec, "RMSE relative to FP64 %.4g" % rel)
         assert abs(rel) <= rmse_tol
     ctx.close()
+
+
+def test_fullsize_approx_paths_agree(c2):
+    """The Approx variant (Alg. 4, p = 0.2) at full size, in the graph as the
+    benchmark runs it, against the GPU path that the oracle pins at small
+    sizes (per-cell-group sums, residuals by a full contraction per entry):
+
+    * R(beta) of the row-sum form equals the per-cell groups' to 1e-12 of
+      SSE + max |R|;
+    * one iteration (mode updates; residuals from the deltas the last mode's
+      kernel kept; row sums; removal) removes floor(p * nz) cells, and they
+      are the top cells of R recomputed from the same state by the pinned
+      path, up to R within 1e-10 (SSE + max |R|) of the cut."""
+    p, ctx, idx, core, fac, work = c2
+    saved_core = core.clone()
+    saved_fac = [f.clone() for f in fac]
+    R = {}
+    for form in (2, 1):
+        ctx.set_options(precision=0, fuse_error=1, use_graph=1, approx_form=form)
+        R[form] = ctx.partial_error().cpu().numpy()
+    sse = ctx.recon_error(p.lam)[0]
+    scale = sse + np.abs(R[1]).max()
+    log("full size: row sums vs cell groups max diff %.3g, scale %.3g"
+        % (np.abs(R[2] - R[1]).max(), scale))
+    assert np.abs(R[2] - R[1]).max() <= 1e-12 * scale
+    # one iteration with the removal inside the graph
+    ctx.set_options(precision=0, fuse_error=1, use_graph=1, approx_rate=0.2)
+    G0 = core.cpu().numpy().copy()
+    ctx.iterate(1, p.lam, strict=False)
+    G1 = core.cpu().numpy()
+    # R from the same state (factors after the updates, core before removal)
+    core.copy_(torch_from(G0, core))
+    ctx.set_options(precision=0, fuse_error=1, use_graph=1, approx_form=1)
+    Rref = ctx.partial_error().cpu().numpy()
+    nz = G0 != 0
+    k = int(np.floor(0.2 * np.count_nonzero(nz)))
+    removed = nz & (G1 == 0)
+    assert np.count_nonzero(removed) == k
+    tol = 1e-10 * (sse + np.abs(Rref).max())
+    cut = np.sort(Rref[nz])[::-1][k - 1]
+    log("full size: %d cells removed, cut %.6g, tol %.3g" % (k, cut, tol))
+    assert np.all(removed[nz & (Rref > cut + tol)])
+    assert not np.any(removed[nz & (Rref < cut - tol)])
+    core.copy_(saved_core)
+    for f, s in zip(fac, saved_fac):
+        f.copy_(s)
+    ctx.set_options(precision=0, fuse_error=1, use_graph=1)
+
+
+def torch_from(a, like):
+    import torch
+    return torch.from_numpy(a).to(like.device)
