@@ -349,6 +349,9 @@ def main():
     ap.add_argument("--no-variant", action="store_true")
     ap.add_argument("--approx-rate", type=float, default=0.0,
                     help="Approx variant: core cells removed per iteration (0 = off)")
+    ap.add_argument("--fp64-ceiling", action="store_true",
+                    help="print the sustained FP64 rates of the GPU (FMA loop, "
+                         "matrix cores, both) as one JSON line and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a 256 MiB copy kernel (HBM counter scale)")
     ap.add_argument("--pair-cache", action="store_true",
@@ -374,6 +377,11 @@ def main():
         from paper_1710_02261_amd import build as hipbuild
         hipbuild.build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.fp64_ceiling:
+        rates = ptk.fp64_rates(2000)
+        print(json.dumps({"fp64_rates_tflops": rates, "published_peak_tflops": 78.6,
+                          "command": command_line()}), flush=True)
+        return
     if args.workload == "sweeps":
         sweeps(args)
         return
@@ -492,6 +500,9 @@ def main():
     roofline = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak, "traffic": traffic, "kernel": kname,
                 "avg_launch_ms": r["gram_ms"], "flops_per_launch": flops}
+    if main_prec == "f64":
+        # context: what a plain loop of independent FP64 FMAs sustains here
+        roofline["fma_loop_tflops"] = ptk.fp64_rates(2000)["fma_f64"]
 
     out = {
         "metric": "nnz*ALS-iters/s for row-wise factor update (1 GPU); fold-in p50/p99 ms",

@@ -449,6 +449,22 @@ const char *ptk_server_last_error(const ptk_server *srv);
 /* Finish every submitted request, stop the thread, free everything. */
 ptk_status ptk_server_destroy(ptk_server *srv);
 
+/* ------------------------------------------------------------------------
+ * Measurement.
+ * --------------------------------------------------------------------- */
+
+/*
+ * Sustained FP64 rates of the current device, the ceiling for the roofline
+ * of the row-system kernels (one FP64 multiply-add per core cell and entry,
+ * Alg. 3). Runs three kernels with no memory traffic, each over 2048 x 256
+ * lanes for `iters` iterations (1..1e6), timed with HIP events on the null
+ * stream after one warm-up launch. tflops_host[3] (host) receives TFLOP/s of:
+ * [0] independent v_fma_f64 chains; [1] v_mfma_f64_16x16x4f64; [2] both
+ * interleaved in every wavefront. Allocates and frees 4 MB of device memory.
+ * Errors: PTK_E_INVALID, PTK_E_HIP.
+ */
+ptk_status ptk_fp64_rates(int32_t iters, double *tflops_host);
+
 #ifdef __cplusplus
 }
 #endif

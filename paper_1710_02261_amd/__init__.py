@@ -9,8 +9,9 @@ library has not been built.
 """
 from ._native import (  # noqa: F401
     Context, PtkError, Server, PREC_FP64_ACC, PREC_FP32, PREC_BF16, PREC_BF16X3, library_path,
-    load_library, coo_scan, coo_read,
+    load_library, coo_scan, coo_read, fp64_rates,
 )
 
 __all__ = ["Context", "PtkError", "Server", "PREC_FP64_ACC", "PREC_FP32", "PREC_BF16", "PREC_BF16X3",
-           "library_path", "load_library", "coo_scan", "coo_read"]
+           "library_path", "load_library", "coo_scan", "coo_read",
+           "fp64_rates"]

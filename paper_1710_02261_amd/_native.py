@@ -76,6 +76,7 @@ def load_library():
         "ptk_truncate": [_vp, _dbl, C.POINTER(_i32)],
         "ptk_coo_scan": [C.c_char_p, _i32, C.POINTER(_i64), C.POINTER(_i64)],
         "ptk_coo_read": [C.c_char_p, _i32, _i64, _vp, _vp],
+        "ptk_fp64_rates": [_i32, _vp],
         "ptk_normalize_values": [_vp, _i64, _vp, C.POINTER(_dbl)],
         "ptk_split_count": [_vp, _i64, _dbl, C.c_uint64, C.POINTER(_i64)],
         "ptk_split_entries": [_vp, _i32, _i64, _vp, _vp, _dbl, C.c_uint64, _i64, _vp, _vp,
@@ -103,6 +104,15 @@ def _global_check(lib, st):
     if st != PTK_OK:
         msg = lib.ptk_last_error(None)
         raise PtkError(st, msg.decode() if msg else "")
+
+
+def fp64_rates(iters=2000):
+    """ptk_fp64_rates: sustained TFLOP/s of independent FP64 FMA chains, of
+    the FP64 matrix cores, and of both at once, on the current device."""
+    lib = load_library()
+    out = (_dbl * 3)()
+    _global_check(lib, lib.ptk_fp64_rates(int(iters), out))
+    return {"fma_f64": out[0], "mfma_f64": out[1], "both": out[2]}
 
 
 def coo_scan(path, N):

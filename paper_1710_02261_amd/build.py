@@ -21,7 +21,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["ptk_api.hip", "ptk_kernels.hip", "ptk_cache.hip", "ptk_approx.hip",
            "ptk_gram2.hip", "ptk_slice.hip", "ptk_solve.hip", "ptk_data.hip",
-           "ptk_sort.hip", "ptk_finalize.hip", "ptk_mfma.hip", "ptk_server.hip"]
+           "ptk_sort.hip", "ptk_finalize.hip", "ptk_mfma.hip", "ptk_server.hip",
+           "ptk_ceiling.hip"]
 
 CFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
