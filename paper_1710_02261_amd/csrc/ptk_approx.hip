@@ -393,7 +393,7 @@ __global__ __launch_bounds__(kWave) void k_row_sums(RowSumArgs a) {
     double T1[J], T2[J];
 #pragma unroll
     for (int k = 0; k < J; ++k) T1[k] = T2[k] = 0.0;
-    int cur = -1;
+    int cur = -1, myrow = -1;
     int64_t slot = 0;
     const float *fa = a.fac[NP - 2], *fb = a.fac[NP - 1];
     // the weights of a tile are 8J lines of 128 bytes; the tile after the one
@@ -422,7 +422,8 @@ __global__ __launch_bounds__(kWave) void k_row_sums(RowSumArgs a) {
             s_q[lane] = q;
             s_ia[lane] = ok ? a.idx[NP - 2][e] : 0;
             s_ib[lane] = ok ? a.idx[NP - 1][e] : 0;
-            s_row[lane] = ok ? a.rows[e] : -1;
+            myrow = ok ? a.rows[e] : -1;
+            s_row[lane] = myrow;
         }
         __syncthreads();
         for (int t = lane; t < kWave * J; t += kWave) {
@@ -430,10 +431,21 @@ __global__ __launch_bounds__(kWave) void k_row_sums(RowSumArgs a) {
             s_va[t] = fa[(int64_t)s_ia[u] * J + j];
             s_vb[t] = fb[(int64_t)s_ib[u] * J + j];
         }
+        // the tile's row changes as one scalar mask (bit u: entry u starts
+        // a row piece), so the entry loop tests a bit instead of waiting on
+        // an LDS read per entry
+        const int prevrow = lane == 0 ? cur : s_row[lane > 0 ? lane - 1 : 0];
+        const uint64_t change = __ballot(lane < nb && myrow != prevrow);
         __syncthreads();
         for (int u = 0; u < nb; ++u) {
-            const int row = __builtin_amdgcn_readfirstlane(s_row[u]);
-            if (row != cur) {
+            // the entry's weights first: all their scalar loads in flight
+            // before the LDS reads, so that one wait covers both
+            cptr<double> w = (cptr<double>)(a.uw + (base + u) * 2 * J);
+            double wv[2 * J];
+#pragma unroll
+            for (int k = 0; k < 2 * J; ++k) wv[k] = w[k];
+            if ((change >> u) & 1) {
+                const int row = __builtin_amdgcn_readlane(myrow, u);
                 if (cur >= 0 && act) {
                     double *o = a.tbuf + slot * 2 * NT + (int64_t)lg * J * P + p;
 #pragma unroll
@@ -451,11 +463,10 @@ __global__ __launch_bounds__(kWave) void k_row_sums(RowSumArgs a) {
             double v = (double)s_va[u * J + m1] * (double)s_vb[u * J + m2];
             if constexpr (NP > 3) v *= s_q[u];
             const double v2 = v * v;
-            cptr<double> w = (cptr<double>)(a.uw + (base + u) * 2 * J);
 #pragma unroll
             for (int k = 0; k < J; ++k) {
-                T1[k] = __builtin_fma(w[k], v, T1[k]);
-                T2[k] = __builtin_fma(w[J + k], v2, T2[k]);
+                T1[k] = __builtin_fma(wv[k], v, T1[k]);
+                T2[k] = __builtin_fma(wv[J + k], v2, T2[k]);
             }
         }
         __syncthreads();
