@@ -117,9 +117,10 @@ typedef struct ptk_options {
                                (ptk_iterate with approx_rate > 0,
                                ptk_partial_error, ptk_truncate); same values
                                up to rounding order. 0 = auto: row sums where
-                               available and their buffers take at most a
-                               quarter of the free device memory, else
-                               per-cell groups. 1 = per-cell groups: no memory
+                               available, when the grouping mode's rows plus
+                               the slices number at most nnz / 20 and the
+                               buffers take at most a quarter of the free
+                               device memory, else per-cell groups. 1 = per-cell groups: no memory
                                beyond the sums. 2 = row sums, orders 4 and 5
                                only (else PTK_E_UNSUPPORTED): every entry's
                                2J weights r a and a^2 of one mode, nnz * 2J

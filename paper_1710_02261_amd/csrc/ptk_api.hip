@@ -517,18 +517,24 @@ ptk_status ensure_approx(ptk_ctx *c) {
     const int N = c->s.N, J = c->s.ranks[0];
     if (!(equal_ranks(c->s) && approx_available(N, J)))
         return fail(c, PTK_E_UNSUPPORTED, "no Approx kernels for this shape");
-    // form: row sums where compiled and their buffers take at most a quarter
-    // of the free device memory (or when asked for), else per-cell groups
+    // form: row sums where compiled, when the row pieces average at least
+    // 20 entries and the buffers take at most a quarter of the free device
+    // memory (or when asked for), else per-cell groups. Each slot costs
+    // 2 J^(N-1) doubles written and read again, which the row sums' faster
+    // per-entry loop (14 against 4.5 TFLOP/s) repays from about 20 entries on.
     int form = 1;
     int64_t rs_slices = 0, tdoubles = 0, udoubles = 0;
     if (c->opt.approx_form != 1 && row_sums_available(N, J)) {
         rs_slices = row_sums_slices(c->s, c->nnz, c->num_cu);
+        const int64_t slots = c->s.dims[approx_mode(c)] + rs_slices;
         tdoubles = row_sums_tbuf_doubles(c->s, approx_mode(c), rs_slices);
         udoubles = std::max<int64_t>(c->nnz, 1) * 2 * J;
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
         const double need = 8.0 * (double)(tdoubles + udoubles);
-        if (c->opt.approx_form == 2 || need <= 0.25 * (double)free_b) form = 2;
+        if (c->opt.approx_form == 2 ||
+            (need <= 0.25 * (double)free_b && 20.0 * (double)slots <= (double)c->nnz))
+            form = 2;
     } else if (c->opt.approx_form == 2) {
         return fail(c, PTK_E_UNSUPPORTED, "no row-sum form of the partial errors for this shape");
     }
