@@ -565,9 +565,12 @@ ptk_status ensure_approx(ptk_ctx *c) {
     return PTK_OK;
 }
 
-// Alg. 4 on the bound model: residuals over the mode-0 grouping, R(beta) of
-// every cell into ap_R, and with remove the removal of the top cells from the
-// bound core followed by fresh permuted cores. Kernels only (capturable).
+// Alg. 4 on the bound model: residuals over the grouping of mode g
+// (approx_mode), from the deltas the last mode's kernel kept in this
+// iteration when deltas_kept and g is that mode, else by a full contraction;
+// R(beta) of every cell into ap_R; with remove, the removal of the top cells
+// from the bound core followed by fresh permuted cores. Kernels only
+// (capturable).
 ptk_status approx_step(ptk_ctx *c, double p, bool remove, bool deltas_kept = false) {
     const int N = c->s.N;
     const int g = approx_mode(c);

@@ -18,7 +18,10 @@
 // in with J multiply-adds when it ends (rows split between slices need no
 // merge: each piece is folded in on its own).
 //
-// Partial-error kernel: a wavefront owns 64 cells beta' of T: lane l takes a
+// Two forms compute the same S1, S2 (up to rounding order): the per-cell
+// groups below (any order) and the row sums further down (orders 4 and 5).
+//
+// Per-cell groups: a wavefront owns 64 cells beta' of T: lane l takes a
 // value p of the last two other modes, the wavefront fixes the others (the
 // third-last through one index k, the ones before through its lead group),
 // and it accumulates the J values of beta_g for each of them. It walks a
@@ -56,7 +59,7 @@ bool approx_available(int N, int J) {
 }
 
 // ---------------------------------------------------------------------------
-// residuals xhat - x (FP64) over the mode-0 grouping
+// residuals xhat - x (FP64) over one mode's grouping
 // ---------------------------------------------------------------------------
 template <int N, int J, int U>
 __global__ __launch_bounds__(kWave) void k_residual(EntryArgs a) {
