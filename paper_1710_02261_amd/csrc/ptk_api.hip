@@ -589,8 +589,15 @@ ptk_status approx_step(ptk_ctx *c, double p, bool remove, bool deltas_kept = fal
     const int64_t nb = std::max<int64_t>(
         1, std::min<int64_t>(kSseBlocks, (c->nnz + kWave - 1) / kWave));
     const bool kept = deltas_kept && g == N - 1;
+    // with the row sums, the kept-delta pass also writes their weights
+    const bool fused = kept && c->ap_form == 2;
     HIPCHK(c, timed(c, kept ? "approx_resid_kept" : "approx_resid", [&] {
         // g is the last mode and its kernel kept the deltas of this iteration
+        if (fused)
+            return launch_resid_uw_from_delta(c->ap_delta, c->fac[g], m.rows, m.vals,
+                                              c->fac[N - 4 < g ? N - 4 : N - 3],
+                                              other[N - 4], c->nnz, c->s.ranks[g],
+                                              c->ap_resid, c->ap_uw, c->st);
         if (kept)
             return launch_resid_from_delta(c->ap_delta, c->fac[g], m.rows, m.vals, c->nnz,
                                            c->s.ranks[g], c->ap_resid, c->st);
@@ -607,6 +614,7 @@ ptk_status approx_step(ptk_ctx *c, double p, bool remove, bool deltas_kept = fal
         ra.rowptr = m.rowptr;
         ra.resid = c->ap_resid;
         ra.uw = c->ap_uw;
+        ra.uw_ready = fused ? 1 : 0;
         ra.tbuf = c->ap_tbuf;
         ra.g = g;
         ra.nrows = c->s.dims[g];

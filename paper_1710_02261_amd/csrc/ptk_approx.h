@@ -29,6 +29,7 @@ struct RowSumArgs {
     const int64_t *rowptr;            // CSR row pointers of mode g
     const double *resid;              // xhat - x per entry
     double *uw;                       // [nnz][2][J] per-entry weights (scratch)
+    int32_t uw_ready;                 // 1: uw already written (with the residuals)
     double *tbuf;                     // [nslots][2][J^(N-1)] row-piece sums
     int32_t g;
     int64_t nrows;                    // rows of mode g
@@ -55,6 +56,14 @@ hipError_t launch_residual(const EntryArgs &a, const Shape &s, int64_t nblocks,
 hipError_t launch_resid_from_delta(const double *delta, const float *fac, const int32_t *rows,
                                    const float *val, int64_t nnz, int J, double *resid,
                                    hipStream_t st);
+
+// The same residuals into resid and, in the same pass, the row-sum form's
+// weights into uw ([nnz][2][J]) from the rows of the third-last other mode
+// (fac3, idx3); J in {3, 5, 8, 10}.
+hipError_t launch_resid_uw_from_delta(const double *delta, const float *fac,
+                                      const int32_t *rows, const float *val,
+                                      const float *fac3, const int32_t *idx3, int64_t nnz,
+                                      int J, double *resid, double *uw, hipStream_t st);
 
 // Slices and part size (doubles) for nnz entries.
 int32_t approx_slices(const Shape &s, int64_t nnz, int num_cu);

@@ -119,6 +119,69 @@ __global__ void k_resid_from_delta(const double *__restrict__ delta,
     resid[p] = xh - (double)val[p];
 }
 
+// Residuals from kept deltas and, in the same pass, the row-sum form's
+// per-entry weights uw[e] = (r a[k], a[k]^2), a the entry's row of the
+// third-last other mode. A wavefront forms the residuals of 64 entries
+// (lane = entry) and stages them with the entries' rows in LDS, then writes
+// their 2J weights each as one contiguous run of 64 x 2J doubles (lane =
+// consecutive output).
+template <int J>
+__global__ __launch_bounds__(kWave) void k_resid_uw_from_delta(
+    const double *__restrict__ delta, const float *__restrict__ fac,
+    const int32_t *__restrict__ rows, const float *__restrict__ val,
+    const float *__restrict__ fac3, const int32_t *__restrict__ idx3, int64_t nnz,
+    double *__restrict__ resid, double *__restrict__ uw) {
+    __shared__ double s_r[kWave];
+    __shared__ float s_a[kWave * J];
+    const int lane = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kWave;
+    const int64_t p = base + lane;
+    double r = 0.0;
+    if (p < nnz) {
+        const float *own = fac + (int64_t)rows[p] * J;
+        const float *a3 = fac3 + (int64_t)idx3[p] * J;
+        double xh = 0.0;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            xh = __builtin_fma((double)own[j], delta[(int64_t)j * nnz + p], xh);
+            s_a[lane * J + j] = a3[j];
+        }
+        r = xh - (double)val[p];
+        resid[p] = r;
+    }
+    s_r[lane] = r;
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 2 * J; ++t) {
+        const int o = t * kWave + lane;            // output within the run
+        const int e = o / (2 * J), kk = o % (2 * J);
+        if (base + e < nnz) {
+            const int k = kk < J ? kk : kk - J;
+            const double a = (double)s_a[e * J + k];
+            uw[base * 2 * J + o] = kk < J ? s_r[e] * a : a * a;
+        }
+    }
+}
+
+hipError_t launch_resid_uw_from_delta(const double *delta, const float *fac,
+                                      const int32_t *rows, const float *val,
+                                      const float *fac3, const int32_t *idx3, int64_t nnz,
+                                      int J, double *resid, double *uw, hipStream_t st) {
+    if (nnz <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((nnz + kWave - 1) / kWave)), block(kWave);
+    switch (J) {
+#define PTK_X(j_)                                                                          \
+    case j_:                                                                               \
+        hipLaunchKernelGGL(k_resid_uw_from_delta<j_>, grid, block, 0, st, delta, fac, rows,  \
+                           val, fac3, idx3, nnz, resid, uw);                               \
+        return hipGetLastError();
+        PTK_X(3) PTK_X(5) PTK_X(8) PTK_X(10)
+#undef PTK_X
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_resid_from_delta(const double *delta, const float *fac, const int32_t *rows,
                                    const float *val, int64_t nnz, int J, double *resid,
                                    hipStream_t st) {
@@ -567,12 +630,14 @@ hipError_t launch_row_sums(const RowSumArgs &a, const Shape &s, hipStream_t st) 
 #define PTK_X(n_, j_)                                                                   \
     if (s.N == n_ && J == j_) {                                                         \
         if (a.nnz > 0) {                                                                \
-            const int64_t t = a.nnz * j_;                                               \
-            hipLaunchKernelGGL((k_approx_uw<j_>), dim3((unsigned)((t + 255) / 256)),    \
-                               dim3(256), 0, st, a.resid, a.fac[n_ - 4], a.idx[n_ - 4], \
-                               a.nnz, a.uw);                                            \
-            hipError_t e = hipGetLastError();                                           \
-            if (e != hipSuccess) return e;                                              \
+            hipError_t e = hipSuccess;                                                  \
+            if (!a.uw_ready) {                                                          \
+                const int64_t t = a.nnz * j_;                                           \
+                hipLaunchKernelGGL((k_approx_uw<j_>), dim3((unsigned)((t + 255) / 256)), \
+                                   dim3(256), 0, st, a.resid, a.fac[n_ - 4],            \
+                                   a.idx[n_ - 4], a.nnz, a.uw);                         \
+                if ((e = hipGetLastError()) != hipSuccess) return e;                    \
+            }                                                                           \
             const int64_t blocks = (int64_t)((j_ * j_ + kWave - 1) / kWave) *           \
                                    ipow(j_, n_ - 4) * a.nslices;                         \
             hipLaunchKernelGGL((k_row_sums<n_, j_>), dim3((unsigned)blocks), dim3(kWave), \
