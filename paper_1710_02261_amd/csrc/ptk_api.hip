@@ -521,7 +521,7 @@ ptk_status ensure_approx(ptk_ctx *c) {
     // 20 entries and the buffers take at most a quarter of the free device
     // memory (or when asked for), else per-cell groups. Each slot costs
     // 2 J^(N-1) doubles written and read again, which the row sums' faster
-    // per-entry loop (14 against 4.5 TFLOP/s) repays from about 20 entries on.
+    // per-entry loop (19 against 4.5 TFLOP/s) repays from about 20 entries on.
     int form = 1;
     int64_t rs_slices = 0, tdoubles = 0, udoubles = 0;
     if (c->opt.approx_form != 1 && row_sums_available(N, J)) {

@@ -421,11 +421,18 @@ __global__ void k_approx_uw(const double *__restrict__ resid, const float *__res
 
 constexpr int kXcds = 8;                 // XCDs of the MI355X
 
+// Pairs p of the last two other modes per lane of the row-sum kernel (two
+// when J*J exceeds a wavefront: every weight read then feeds two FMAs per
+// lane), and the wavefronts that cover the J*J pairs.
+constexpr int rs_ppl(int J) { return J * J > kWave ? 2 : 1; }
+constexpr int rs_groups(int J) { return (J * J + kWave * rs_ppl(J) - 1) / (kWave * rs_ppl(J)); }
+
 template <int N, int J>
 __global__ __launch_bounds__(kWave) void k_row_sums(RowSumArgs a) {
     constexpr int NP = N - 1;             // other modes, NP >= 3
     constexpr int P = J * J;
-    constexpr int NPG = (P + kWave - 1) / kWave;
+    constexpr int PPL = rs_ppl(J);
+    constexpr int NPG = rs_groups(J);
     constexpr int NLG = ipow(J, NP - 3);
     constexpr int NT = ipow(J, NP);
     __shared__ float s_va[kWave * J], s_vb[kWave * J];
@@ -444,9 +451,15 @@ __global__ __launch_bounds__(kWave) void k_row_sums(RowSumArgs a) {
     const int64_t e0 = (int64_t)sl * a.slice;
     const int64_t e1 = min(e0 + a.slice, a.nnz);
     if (e0 >= e1) return;                 // uniform
-    const int p = pg * kWave + lane;
-    const bool act = p < P;
-    const int m1 = act ? p / J : 0, m2 = act ? p % J : 0;
+    int p[PPL], m1[PPL], m2[PPL];
+    bool act[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+        p[i] = (pg * PPL + i) * kWave + lane;
+        act[i] = p[i] < P;
+        m1[i] = act[i] ? p[i] / J : 0;
+        m2[i] = act[i] ? p[i] % J : 0;
+    }
     int pre[NP > 3 ? NP - 3 : 1];
     {
         int t = lg;
@@ -456,9 +469,24 @@ __global__ __launch_bounds__(kWave) void k_row_sums(RowSumArgs a) {
             t /= J;
         }
     }
-    double T1[J], T2[J];
+    double T1[PPL][J], T2[PPL][J];
 #pragma unroll
-    for (int k = 0; k < J; ++k) T1[k] = T2[k] = 0.0;
+    for (int i = 0; i < PPL; ++i)
+#pragma unroll
+        for (int k = 0; k < J; ++k) T1[i][k] = T2[i][k] = 0.0;
+    // the lane's sums of the current row piece to its slot
+    auto store = [&](int64_t sl_) {
+#pragma unroll
+        for (int i = 0; i < PPL; ++i) {
+            if (!act[i]) continue;
+            double *o = a.tbuf + sl_ * 2 * NT + (int64_t)lg * J * P + p[i];
+#pragma unroll
+            for (int k = 0; k < J; ++k) {
+                o[k * P] = T1[i][k];
+                o[NT + k * P] = T2[i][k];
+            }
+        }
+    };
     int cur = -1, myrow = -1;
     int64_t slot = 0;
     const float *fa = a.fac[NP - 2], *fb = a.fac[NP - 1];
@@ -512,39 +540,33 @@ __global__ __launch_bounds__(kWave) void k_row_sums(RowSumArgs a) {
             for (int k = 0; k < 2 * J; ++k) wv[k] = w[k];
             if ((change >> u) & 1) {
                 const int row = __builtin_amdgcn_readlane(myrow, u);
-                if (cur >= 0 && act) {
-                    double *o = a.tbuf + slot * 2 * NT + (int64_t)lg * J * P + p;
-#pragma unroll
-                    for (int k = 0; k < J; ++k) {
-                        o[k * P] = T1[k];
-                        o[NT + k * P] = T2[k];
-                    }
-                }
+                if (cur >= 0) store(slot);
                 cur = row;
                 const int64_t e = base + u;
                 slot = (e == e0 && e0 > 0 && a.rows[e0 - 1] == row) ? a.nrows + sl : row;
 #pragma unroll
-                for (int k = 0; k < J; ++k) T1[k] = T2[k] = 0.0;
-            }
-            double v = (double)s_va[u * J + m1] * (double)s_vb[u * J + m2];
-            if constexpr (NP > 3) v *= s_q[u];
-            const double v2 = v * v;
+                for (int i = 0; i < PPL; ++i)
 #pragma unroll
-            for (int k = 0; k < J; ++k) {
-                T1[k] = __builtin_fma(wv[k], v, T1[k]);
-                T2[k] = __builtin_fma(wv[J + k], v2, T2[k]);
+                    for (int k = 0; k < J; ++k) T1[i][k] = T2[i][k] = 0.0;
             }
+            double v[PPL], v2[PPL];
+#pragma unroll
+            for (int i = 0; i < PPL; ++i) {
+                v[i] = (double)s_va[u * J + m1[i]] * (double)s_vb[u * J + m2[i]];
+                if constexpr (NP > 3) v[i] *= s_q[u];
+                v2[i] = v[i] * v[i];
+            }
+#pragma unroll
+            for (int k = 0; k < J; ++k)
+#pragma unroll
+                for (int i = 0; i < PPL; ++i) {
+                    T1[i][k] = __builtin_fma(wv[k], v[i], T1[i][k]);
+                    T2[i][k] = __builtin_fma(wv[J + k], v2[i], T2[i][k]);
+                }
         }
         __syncthreads();
     }
-    if (cur >= 0 && act) {
-        double *o = a.tbuf + slot * 2 * NT + (int64_t)lg * J * P + p;
-#pragma unroll
-        for (int k = 0; k < J; ++k) {
-            o[k * P] = T1[k];
-            o[NT + k * P] = T2[k];
-        }
-    }
+    if (cur >= 0) store(slot);
     if (a.nnz < 0) a.tbuf[lane] = (double)pf;
 }
 
@@ -612,7 +634,7 @@ bool row_sums_available(int N, int J) {
 
 int64_t row_sums_slices(const Shape &s, int64_t nnz, int num_cu) {
     const int J = s.ranks[0];
-    int64_t waves_per_slice = (int64_t)((J * J + kWave - 1) / kWave);
+    int64_t waves_per_slice = rs_groups(J);
     for (int k = 4; k <= s.N - 1; ++k) waves_per_slice *= J;
     // about 16 wavefronts per CU in all, slices of at least 256 entries
     int64_t sl = ((int64_t)16 * num_cu + waves_per_slice - 1) / waves_per_slice;
@@ -638,8 +660,7 @@ hipError_t launch_row_sums(const RowSumArgs &a, const Shape &s, hipStream_t st) 
                                    a.idx[n_ - 4], a.nnz, a.uw);                         \
                 if ((e = hipGetLastError()) != hipSuccess) return e;                    \
             }                                                                           \
-            const int64_t blocks = (int64_t)((j_ * j_ + kWave - 1) / kWave) *           \
-                                   ipow(j_, n_ - 4) * a.nslices;                         \
+            const int64_t blocks = (int64_t)rs_groups(j_) * ipow(j_, n_ - 4) * a.nslices; \
             hipLaunchKernelGGL((k_row_sums<n_, j_>), dim3((unsigned)blocks), dim3(kWave), \
                                0, st, a);                                               \
             if ((e = hipGetLastError()) != hipSuccess) return e;                        \
