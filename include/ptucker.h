@@ -93,7 +93,15 @@ typedef struct ptk_options {
                                reported for the iteration are those before the
                                removal. Equal ranks and (N, J) in {3} x
                                {3,4,5,8,10,16}, {4} x {3,5,8,10} or {5} x
-                               {3,5,8} (else PTK_E_UNSUPPORTED).             */
+                               {3,5,8} (else PTK_E_UNSUPPORTED). Device
+                               memory, allocated on first use: nnz + 64
+                               doubles of residuals, the sums (per range,
+                               2 * prod J_n doubles each) and R; J * nnz
+                               doubles for the deltas the last mode's kernel
+                               keeps when that mode has the fewest rows and
+                               (N, J) is (4, 10) or (5, 8) in FP64 (only if
+                               they fit in a quarter of the free memory);
+                               plus the row-sum buffers of approx_form.      */
     int32_t delta_slices;   /* generic-kernel modes only (shapes without an
                                unrolled kernel): the delta sum of every entry
                                (Eq. 8) cut into this many slices of the core's
