@@ -12,8 +12,11 @@ Functions and the passages they follow:
 * ``predict``        -- eq. "recon2" (Sec. 2.2).
 * ``sse`` / ``loss`` -- eq. "reconfull" squared / eq. "TF_PARTIAL".
 * ``row_system``     -- eqs. "rowB", "rowC" for one row.
-* ``solve``          -- eq. "rowupdate" as a Cholesky solve.
-* ``update_rows`` / ``update_mode`` -- Alg. 3 for one mode.
+* ``solve``          -- eq. "rowupdate" as a Cholesky solve of a formed system.
+* ``ls_solve``       -- eq. "rowupdate" as the regularised least-squares
+  problem it is the normal equations of (Givens QR of the stacked matrix).
+* ``update_rows`` / ``update_mode`` -- Alg. 3 for one mode, each row by the
+  least-squares form (defined for every row and lambda > 0).
 * ``fit``            -- Alg. 2 iterations (factor sweeps + error).
 * ``partial_error`` / ``truncate`` / ``fit_approx`` -- the Approx variant
   (Alg. 4, eq. "recon_partial"): per-cell partial reconstruction error,
@@ -26,10 +29,17 @@ Functions and the passages they follow:
 * ``fold_in``        -- the row update for a new row with the model fixed.
 * ``data_steps``     -- (numpy) the steps either side of the fit: SplitMix64
   train/test split, min-max normalisation, k-means over factor rows.
+
+The C file is built with ``-O3`` for the host it runs on (``-march=native``)
+and OpenMP: the rows of a mode are dealt to threads dynamically (Sec. 3.4),
+each row computed by one thread in a fixed order, so results do not depend
+on the thread count (``set_threads``). The library file name carries a tag of
+the host CPU, so a copy built on another machine is never loaded.
 """
 from __future__ import annotations
 
 import ctypes as C
+import hashlib
 import os
 import subprocess
 
@@ -37,7 +47,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ptk_oracle.c")
-_LIB = os.path.join(_HERE, "libptk_oracle.so")
+_FLAGS = ["-O3", "-march=native", "-fopenmp", "-std=c99", "-shared", "-fPIC"]
 _lib = None
 
 _dp = C.POINTER(C.c_double)
@@ -46,15 +56,45 @@ _lp = C.POINTER(C.c_int64)
 _dpp = C.POINTER(_dp)
 
 
+def host_cpu():
+    """Model name and logical CPU count of this host (from /proc/cpuinfo)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def _lib_path():
+    h = hashlib.sha1()
+    with open(_SRC, "rb") as f:
+        h.update(f.read())
+    h.update(" ".join(_FLAGS).encode())
+    h.update(host_cpu()[0].encode())
+    try:     # the instruction-set flags, so -march=native matches this host
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("flags"):
+                    h.update(line.encode())
+                    break
+    except OSError:
+        pass
+    return os.path.join(_HERE, "libptk_oracle_%s.so" % h.hexdigest()[:12])
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with the host C compiler (plain -O2)."""
-    if force or not os.path.exists(_LIB) or \
-            os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC",
-                               _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+    """Compile the oracle with the host C compiler for this host's CPU."""
+    lib = _lib_path()
+    if force or not os.path.exists(lib):
+        tmp = lib + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *_FLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, lib)
+    return lib
 
 
 def _load(path=None):
@@ -64,8 +104,8 @@ def _load(path=None):
     if path is None:
         path = os.environ.get("PTK_ORACLE_LIB")   # mutation tests only
     if path is None:
-        build()
-    lib = C.CDLL(path or _LIB)
+        path = build()
+    lib = C.CDLL(path)
     sig = {
         "ora_delta": (None, [C.c_int, _ip, _dp, _dpp, C.c_int, _dp]),
         "ora_predict_one": (C.c_double, [C.c_int, _ip, _dp, _dpp]),
@@ -74,6 +114,8 @@ def _load(path=None):
         "ora_loss": (C.c_double, [C.c_int, _lp, _ip, _dp, _dpp, C.c_int64, _ip,
                                   _dp, C.c_double]),
         "ora_solve": (C.c_int, [C.c_int, _dp, _dp, C.c_double, _dp]),
+        "ora_ls_solve": (C.c_int, [C.c_int, C.c_int64, _dp, _dp, C.c_double, _dp]),
+        "ora_set_threads": (C.c_int, [C.c_int]),
         "ora_row_system": (C.c_int, [C.c_int, _ip, _dp, _dpp, C.c_int64, _ip,
                                      _dp, C.c_int, C.c_int32, _dp, _dp]),
         "ora_update_rows": (C.c_int64, [C.c_int, _lp, _ip, _dp, _dpp, C.c_int64,
@@ -236,11 +278,33 @@ def solve(B, c, lam):
     return a
 
 
+def ls_solve(Delta, x, lam):
+    """Solution of min ||x - Delta a||^2 + lam ||a||^2, i.e. of
+    (Delta^T Delta + lam I) a = Delta^T x (eq. "rowupdate" with the entries'
+    deltas as the rows of Delta), by the oracle's Givens QR."""
+    lib = _load()
+    Delta, Dp = _d(np.atleast_2d(Delta))
+    x, xp = _d(x)
+    a = np.zeros(Delta.shape[1])
+    rc = lib.ora_ls_solve(Delta.shape[1], Delta.shape[0], Dp, xp, float(lam),
+                          a.ctypes.data_as(_dp))
+    if rc:
+        raise RuntimeError("ora_ls_solve failed: %d" % rc)
+    return a
+
+
+def set_threads(t=0):
+    """Threads of the row updates and residuals (0: leave as is). Returns the
+    count in effect (1 when the oracle was built without OpenMP)."""
+    return int(_load().ora_set_threads(int(t)))
+
+
 def update_rows(G, A, idx, val, n, lam, rows=None, return_bad=False):
     """New values of the requested rows of A^(n) (all rows when None).
 
-    A row whose system is not positive definite in FP64 keeps its previous
-    value; with return_bad=True the number of such rows is returned too."""
+    Every row is solved by the least-squares form of eq. "rowupdate"; with
+    return_bad=True the number of rows whose result is not finite (zero for
+    finite inputs and lam > 0) is returned too."""
     lib = _load()
     G, Gp = _d(G)
     I, J = _shape(G, A)

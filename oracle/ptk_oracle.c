@@ -13,13 +13,24 @@
  * Conventions: indices are 0-based (the paper counts from 1); the core G is
  * stored in C order (last mode fastest); factor A^(n) is row-major I_n x J_n;
  * the observed set is structure-of-arrays idx[n*nnz + e] with values val[e].
+ *
+ * Threads: the rows of one mode are independent (Sec. 3.2), so the row
+ * updates may run on several OpenMP threads, rows dealt dynamically as in
+ * the paper's Sec. 3.4; each row is computed by one thread in the same order
+ * whatever the thread count, so results do not depend on it. Per-entry
+ * residuals are formed in parallel and summed in entry order.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORA_MAX_ORDER 16
+/* rows with at least this many entries form their deltas on all threads */
+#define ORA_HEAVY_ROW 4096
 
 /* Number of cells of the core, prod_n J_n. */
 static int64_t ora_core_cells(int N, const int32_t *J)
@@ -27,6 +38,18 @@ static int64_t ora_core_cells(int N, const int32_t *J)
     int64_t s = 1;
     for (int n = 0; n < N; ++n) s *= J[n];
     return s;
+}
+
+/* Threads for the row updates and residuals (1 without OpenMP). */
+int ora_set_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+    return omp_get_max_threads();
+#else
+    (void)t;
+    return 1;
+#endif
 }
 
 /* Advance a core-cell multi-index in C order (last mode fastest). */
@@ -104,13 +127,18 @@ double ora_sse(int N, const int32_t *J, const double *G,
                const double *const *A, int64_t nnz, const int32_t *idx,
                const double *val)
 {
-    const double *rows[ORA_MAX_ORDER];
-    double sse = 0.0;
+    double *r2 = (double *)malloc(sizeof(double) * (nnz ? nnz : 1));
+    if (!r2) return NAN;
+    #pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < nnz; ++e) {
+        const double *rows[ORA_MAX_ORDER];
         ora_rows_of(N, J, A, idx, nnz, e, rows);
         double r = val[e] - ora_predict_one(N, J, G, rows);
-        sse += r * r;
+        r2[e] = r * r;
     }
+    double sse = 0.0;
+    for (int64_t e = 0; e < nnz; ++e) sse += r2[e];
+    free(r2);
     return sse;
 }
 
@@ -127,9 +155,11 @@ double ora_loss(int N, const int64_t *I, const int32_t *J, const double *G,
 
 /*
  * Solve (B + lambda I) a = c for symmetric B by Cholesky factorisation
- * (Golub & Van Loan, Alg. 4.2.1) and two triangular solves. This is the
- * row update of eq. "rowupdate" written as a linear solve instead of an
- * explicit inverse. Returns 0, or -1 if B + lambda I is not positive definite.
+ * (Golub & Van Loan, Alg. 4.2.1) and two triangular solves: eq. "rowupdate"
+ * written as a linear solve instead of an explicit inverse, for a B that is
+ * already formed. Returns 0, or -1 if B + lambda I is not positive definite
+ * in floating point. The row updates below do not use it: they take the
+ * least-squares form, which needs no formed B and cannot break down.
  */
 int ora_solve(int Jn, const double *B, const double *c, double lambda,
               double *a)
@@ -164,6 +194,109 @@ int ora_solve(int Jn, const double *B, const double *c, double lambda,
     }
     free(L);
     free(y);
+    return rc;
+}
+
+/*
+ * The row update as the regularised least-squares problem it solves.
+ *
+ * eq. "rowupdate" is the normal-equation form of
+ *     min_a  sum_alpha (x_alpha - a^T delta_alpha)^2 + lambda ||a||^2
+ * (the loss of eq. "TF_PARTIAL" restricted to one row, Theorem 1), whose
+ * normal equations are (B + lambda I) a = c with B and c of eqs. "rowB",
+ * "rowC". Forming B squares the conditioning: when ||B|| * eps exceeds lambda
+ * the FP64 sum B + lambda I no longer holds lambda and its Cholesky factor
+ * can fail or be wrong, although the minimiser is unique. The oracle
+ * therefore solves the stacked problem
+ *     || [ sqrt(lambda) I ; Delta ] a - [ 0 ; x ] ||  ->  min
+ * by a QR factorisation built one entry at a time with Givens rotations
+ * (Golub & Van Loan, Sec. 5.1.8 and 6.5, updating R by a row): R starts as
+ * sqrt(lambda) I and z as 0; each entry's row [delta^T | x] is rotated into
+ * [R | z]; finally R a = z by back substitution. In exact arithmetic this is
+ * the solution of eq. "rowupdate". The diagonal of R never falls below
+ * sqrt(lambda), so the solve exists for every lambda > 0 and every row (an
+ * empty row gives a = 0 exactly).
+ */
+static void ora_ls_init(int Jn, double lambda, double *R, double *z)
+{
+    const double s = sqrt(lambda);
+    for (int p = 0; p < Jn; ++p) {
+        for (int q = 0; q < Jn; ++q) R[p * Jn + q] = (p == q) ? s : 0.0;
+        z[p] = 0.0;
+    }
+}
+
+/* Rotate the row [d | x] into [R | z]; d is overwritten. */
+static void ora_ls_add(int Jn, double *R, double *z, double *d, double x)
+{
+    for (int j = 0; j < Jn; ++j) {
+        if (d[j] == 0.0) continue;
+        const double r = hypot(R[j * Jn + j], d[j]);
+        const double cs = R[j * Jn + j] / r;
+        const double sn = d[j] / r;
+        R[j * Jn + j] = r;
+        d[j] = 0.0;
+        for (int q = j + 1; q < Jn; ++q) {
+            const double t = R[j * Jn + q];
+            R[j * Jn + q] = cs * t + sn * d[q];
+            d[q] = cs * d[q] - sn * t;
+        }
+        const double t = z[j];
+        z[j] = cs * t + sn * x;
+        x = cs * x - sn * t;
+    }
+}
+
+/* R a = z (R upper triangular). Returns 0, or -1 if a is not finite. */
+static int ora_ls_finish(int Jn, const double *R, const double *z, double *a)
+{
+    int ok = 1;
+    for (int j = Jn - 1; j >= 0; --j) {
+        double s = z[j];
+        for (int q = j + 1; q < Jn; ++q) s -= R[j * Jn + q] * a[q];
+        a[j] = s / R[j * Jn + j];
+        ok = ok && isfinite(a[j]);
+    }
+    return ok ? 0 : -1;
+}
+
+/* The row update of eq. "rowupdate" for the entries ents[0..cnt) of row i of
+   mode n, by the least-squares form above. R (J_n x J_n), z and d (J_n) are
+   work arrays. Returns 0, or -1 if the result is not finite. */
+static int ora_row_update_list(int N, const int32_t *J, const double *G,
+                               const double *const *A, int64_t nnz,
+                               const int32_t *idx, const double *val, int n,
+                               const int64_t *ents, int64_t cnt, double lambda,
+                               double *R, double *z, double *d, double *a)
+{
+    const int Jn = J[n];
+    const double *rows[ORA_MAX_ORDER];
+    ora_ls_init(Jn, lambda, R, z);
+    for (int64_t t = 0; t < cnt; ++t) {
+        const int64_t e = ents[t];
+        ora_rows_of(N, J, A, idx, nnz, e, rows);
+        ora_delta(N, J, G, rows, n, d);
+        ora_ls_add(Jn, R, z, d, val[e]);
+    }
+    return ora_ls_finish(Jn, R, z, a);
+}
+
+/* The same from the matrices of eq. "rowupdate" written as a stacked
+   problem: solve for the rows of a given Delta (cnt x J_n, row-major) and x. */
+int ora_ls_solve(int Jn, int64_t cnt, const double *Delta, const double *x,
+                 double lambda, double *a)
+{
+    double *R = (double *)malloc(sizeof(double) * Jn * Jn);
+    double *z = (double *)malloc(sizeof(double) * Jn);
+    double *d = (double *)malloc(sizeof(double) * Jn);
+    if (!R || !z || !d) { free(R); free(z); free(d); return -2; }
+    ora_ls_init(Jn, lambda, R, z);
+    for (int64_t t = 0; t < cnt; ++t) {
+        memcpy(d, Delta + t * Jn, sizeof(double) * Jn);
+        ora_ls_add(Jn, R, z, d, x[t]);
+    }
+    int rc = ora_ls_finish(Jn, R, z, a);
+    free(R); free(z); free(d);
     return rc;
 }
 
@@ -214,14 +347,14 @@ int ora_row_system(int N, const int32_t *J, const double *G,
 
 /*
  * One pass of Alg. 3 for mode n (the rows of A^(n) are independent, Sec. 3.2):
- * every requested row i gets a_i = c_i (B_i + lambda I)^{-1}; a row with no
- * observed entry gets B = 0, c = 0 and hence a_i = 0.
+ * every requested row i gets a_i = c_i (B_i + lambda I)^{-1}, evaluated by
+ * the least-squares form above; a row with no observed entry gets a_i = 0.
  *
  * rows_req: nreq row ids, or NULL for all I_n rows in order. Results go to
  * out (nreq x J_n, or I_n x J_n when rows_req is NULL); A is not modified.
- * Returns the number of rows whose system was not positive definite in
- * floating point (their output is their previous value), or a negative code
- * on allocation failure.
+ * Returns the number of rows whose result is not finite (none for finite
+ * inputs and lambda > 0), or a negative code on allocation failure. Rows are
+ * dealt to the threads dynamically.
  */
 int64_t ora_update_rows(int N, const int64_t *I, const int32_t *J,
                         const double *G, const double *const *A, int64_t nnz,
@@ -236,10 +369,8 @@ int64_t ora_update_rows(int N, const int64_t *I, const int32_t *J,
     int64_t *start = (int64_t *)calloc((size_t)In + 1, sizeof(int64_t));
     int64_t *ents = (int64_t *)malloc(sizeof(int64_t) * (nnz ? nnz : 1));
     int64_t *fill = (int64_t *)calloc((size_t)In + 1, sizeof(int64_t));
-    double *B = (double *)malloc(sizeof(double) * Jn * Jn);
-    double *c = (double *)malloc(sizeof(double) * Jn);
-    if (!start || !ents || !fill || !B || !c) {
-        free(start); free(ents); free(fill); free(B); free(c);
+    if (!start || !ents || !fill) {
+        free(start); free(ents); free(fill);
         return -2;
     }
     for (int64_t e = 0; e < nnz; ++e) start[idx[(int64_t)n * nnz + e] + 1]++;
@@ -248,25 +379,63 @@ int64_t ora_update_rows(int N, const int64_t *I, const int32_t *J,
         int32_t i = idx[(int64_t)n * nnz + e];
         ents[start[i] + fill[i]++] = e;
     }
+    free(fill);
     int64_t bad = 0;
-    int64_t count = rows_req ? nreq : In;
-    for (int64_t r = 0; r < count; ++r) {
-        int64_t i = rows_req ? rows_req[r] : r;
-        double *a = out + r * Jn;
-        for (int j = 0; j < Jn; ++j) a[j] = 0.0;
-        ora_row_system_list(N, J, G, A, nnz, idx, val, n, ents + start[i],
-                            start[i + 1] - start[i], B, c);
-        if (ora_solve(Jn, B, c, lambda, a) != 0) {
-            /* B + lambda I is positive definite in exact arithmetic, but not
-               always in floating point: when ||B|| * eps exceeds lambda for a
-               rank-deficient B (fewer entries than J_n) the factorisation
-               breaks down. Such a row keeps its previous value. */
-            for (int j = 0; j < Jn; ++j) a[j] = A[n][i * Jn + j];
-            ++bad;
+    int nomem = 0;
+    const int64_t count = rows_req ? nreq : In;
+    /* rows with many entries one at a time, their deltas formed by all
+       threads and rotated in by one, in entry order (the same arithmetic as
+       the per-row loop below) */
+    {
+        double *R = (double *)malloc(sizeof(double) * Jn * Jn);
+        double *z = (double *)malloc(sizeof(double) * Jn);
+        double *dl = NULL;
+        int64_t dl_cap = 0;
+        if (!R || !z) nomem = 1;
+        for (int64_t r = 0; r < count && !nomem; ++r) {
+            const int64_t i = rows_req ? rows_req[r] : r;
+            const int64_t cnt = start[i + 1] - start[i];
+            if (cnt < ORA_HEAVY_ROW) continue;
+            if (cnt > dl_cap) {
+                free(dl);
+                dl = (double *)malloc(sizeof(double) * Jn * cnt);
+                dl_cap = dl ? cnt : 0;
+                if (!dl) { nomem = 1; break; }
+            }
+            const int64_t *re = ents + start[i];
+            #pragma omp parallel for schedule(static)
+            for (int64_t t = 0; t < cnt; ++t) {
+                const double *rows[ORA_MAX_ORDER];
+                ora_rows_of(N, J, A, idx, nnz, re[t], rows);
+                ora_delta(N, J, G, rows, n, dl + t * Jn);
+            }
+            ora_ls_init(Jn, lambda, R, z);
+            for (int64_t t = 0; t < cnt; ++t)
+                ora_ls_add(Jn, R, z, dl + t * Jn, val[re[t]]);
+            if (ora_ls_finish(Jn, R, z, out + r * Jn) != 0) ++bad;
         }
+        free(R); free(z); free(dl);
     }
-    free(start); free(ents); free(fill); free(B); free(c);
-    return bad;
+    #pragma omp parallel reduction(+:bad) reduction(|:nomem)
+    {
+        double *R = (double *)malloc(sizeof(double) * Jn * Jn);
+        double *z = (double *)malloc(sizeof(double) * Jn);
+        double *d = (double *)malloc(sizeof(double) * Jn);
+        if (!R || !z || !d) nomem = 1;
+        #pragma omp for schedule(dynamic, 1)
+        for (int64_t r = 0; r < count; ++r) {
+            if (!R || !z || !d) continue;
+            const int64_t i = rows_req ? rows_req[r] : r;
+            if (start[i + 1] - start[i] >= ORA_HEAVY_ROW) continue;
+            if (ora_row_update_list(N, J, G, A, nnz, idx, val, n, ents + start[i],
+                                    start[i + 1] - start[i], lambda, R, z, d,
+                                    out + r * Jn) != 0)
+                ++bad;
+        }
+        free(R); free(z); free(d);
+    }
+    free(start); free(ents);
+    return nomem ? -2 : bad;
 }
 
 /* Alg. 3 for mode n, writing the new rows into A[n]. */
@@ -430,12 +599,13 @@ int ora_fold_in(int N, const int32_t *J, const double *G,
 {
     const int Jn = J[n];
     if (Jn > 256) return -3;
-    double *B = (double *)malloc(sizeof(double) * Jn * Jn);
-    double *c = (double *)malloc(sizeof(double) * Jn);
+    double *R = (double *)malloc(sizeof(double) * Jn * Jn);
+    double *z = (double *)malloc(sizeof(double) * Jn);
+    double *d = (double *)malloc(sizeof(double) * Jn);
     int64_t *ents = (int64_t *)malloc(sizeof(int64_t) * (k ? k : 1));
     int32_t *ix = (int32_t *)malloc(sizeof(int32_t) * N * (k ? k : 1));
-    if (!B || !c || !ents || !ix) {
-        free(B); free(c); free(ents); free(ix);
+    if (!R || !z || !d || !ents || !ix) {
+        free(R); free(z); free(d); free(ents); free(ix);
         return -2;
     }
     for (int64_t e = 0; e < k; ++e) ents[e] = e;
@@ -443,11 +613,9 @@ int ora_fold_in(int N, const int32_t *J, const double *G,
        delta never reads */
     memcpy(ix, idx, sizeof(int32_t) * N * k);
     for (int64_t e = 0; e < k; ++e) ix[(int64_t)n * k + e] = 0;
-    ora_row_system_list(N, J, G, A, k, ix, val, n, ents, k, B, c);
-    for (int j = 0; j < Jn; ++j) out[j] = 0.0;
-    int rc = ora_solve(Jn, B, c, lambda, out);
-    free(ix);
-    free(B); free(c); free(ents);
+    int rc = ora_row_update_list(N, J, G, A, k, ix, val, n, ents, k, lambda, R, z,
+                                 d, out);
+    free(R); free(z); free(d); free(ents); free(ix);
     return rc;
 }
 
@@ -474,8 +642,9 @@ static double ora_cell_product(int N, const int32_t *J, const double *G,
 }
 
 /* One mode of the Cache variant: new rows of A^(n) from Pres, then the
-   rescale of Pres. Returns the number of rows whose system was not positive
-   definite (they keep their previous value), or a negative code. */
+   rescale of Pres. Each row is solved by the least-squares form of the row
+   update, its entries rotated in in entry order. Returns the number of rows
+   whose result is not finite, or a negative code. */
 static int64_t ora_update_mode_cached(int N, const int64_t *I, const int32_t *J,
                                       const double *G, double *const *A,
                                       int64_t nnz, const int32_t *idx,
@@ -486,15 +655,16 @@ static int64_t ora_update_mode_cached(int N, const int64_t *I, const int32_t *J,
     const int64_t In = I[n];
     const int64_t S = ora_core_cells(N, J);
     double *anew = (double *)malloc(sizeof(double) * In * Jn);
-    double *B = (double *)calloc((size_t)In * Jn * Jn, sizeof(double));
-    double *c = (double *)calloc((size_t)In * Jn, sizeof(double));
+    double *R = (double *)malloc(sizeof(double) * In * Jn * Jn);
+    double *z = (double *)malloc(sizeof(double) * In * Jn);
     double delta[256];
-    if (!anew || !B || !c || Jn > 256) {
-        free(anew); free(B); free(c);
+    if (!anew || !R || !z || Jn > 256) {
+        free(anew); free(R); free(z);
         return Jn > 256 ? -3 : -2;
     }
+    for (int64_t i = 0; i < In; ++i) ora_ls_init(Jn, lambda, R + i * Jn * Jn, z + i * Jn);
     const double *rows[ORA_MAX_ORDER];
-    /* B_i and c_i of every row from the deltas of its entries */
+    /* every entry's delta from Pres, rotated into its row's problem */
     for (int64_t e = 0; e < nnz; ++e) {
         ora_rows_of(N, J, (const double *const *)A, idx, nnz, e, rows);
         const int64_t i = idx[(int64_t)n * nnz + e];
@@ -506,19 +676,11 @@ static int64_t ora_update_mode_cached(int N, const int64_t *I, const int32_t *J,
                                         : ora_cell_product(N, J, G, rows, beta, s, n);
             ora_next_cell(N, J, beta);
         }
-        for (int p = 0; p < Jn; ++p) {
-            for (int q = 0; q < Jn; ++q) B[(i * Jn + p) * Jn + q] += delta[p] * delta[q];
-            c[i * Jn + p] += val[e] * delta[p];
-        }
+        ora_ls_add(Jn, R + i * Jn * Jn, z + i * Jn, delta, val[e]);
     }
     int64_t bad = 0;
-    for (int64_t i = 0; i < In; ++i) {
-        double *a = anew + i * Jn;
-        if (ora_solve(Jn, B + i * Jn * Jn, c + i * Jn, lambda, a) != 0) {
-            for (int j = 0; j < Jn; ++j) a[j] = A[n][i * Jn + j];
-            ++bad;
-        }
-    }
+    for (int64_t i = 0; i < In; ++i)
+        if (ora_ls_finish(Jn, R + i * Jn * Jn, z + i * Jn, anew + i * Jn) != 0) ++bad;
     /* rescale Pres: old -> new value of the n-th factor element */
     for (int64_t e = 0; e < nnz; ++e) {
         const int64_t i = idx[(int64_t)n * nnz + e];
@@ -534,7 +696,7 @@ static int64_t ora_update_mode_cached(int N, const int64_t *I, const int32_t *J,
         }
     }
     memcpy(A[n], anew, sizeof(double) * In * Jn);
-    free(anew); free(B); free(c);
+    free(anew); free(R); free(z);
     return bad;
 }
 

@@ -27,6 +27,17 @@ MUTANTS = {
     "core_update_transposed": ("* U[j * J[n] + k];", "* U[k * J[n] + j];"),
     "qr_no_sign_fix": ("if (R[i * Jn + i] < 0.0) {", "if (R[i * Jn + i] < -1e300) {"),
     "back_substitution_index": ("s -= L[k * Jn + i] * a[k];", "s -= L[i * Jn + k] * a[k];"),
+    "ls_half_regulariser": ("const double s = sqrt(lambda);",
+                            "const double s = sqrt(0.5 * lambda);"),
+    "ls_rotation_sign": ("d[q] = cs * d[q] - sn * t;", "d[q] = cs * d[q] + sn * t;"),
+    "ls_rhs_not_rotated": ("z[j] = cs * t + sn * x;", "z[j] = t + sn * x;"),
+    "ls_back_substitution_index": ("s -= R[j * Jn + q] * a[q];",
+                                   "s -= R[q * Jn + j] * a[q];"),
+    "ls_last_entry_dropped": ("for (int64_t t = 0; t < cnt; ++t) {\n        const int64_t e = ents[t];",
+                              "for (int64_t t = 0; t + 1 < cnt; ++t) {\n        const int64_t e = ents[t];"),
+    "heavy_row_skips_first_entry": (
+        "for (int64_t t = 0; t < cnt; ++t)\n                ora_ls_add(Jn, R, z, dl + t * Jn, val[re[t]]);",
+        "for (int64_t t = 1; t < cnt; ++t)\n                ora_ls_add(Jn, R, z, dl + t * Jn, val[re[t]]);"),
     "cache_no_zero_fallback": ("delta[beta[n]] += an != 0.0 ? Pres[e * S + s] / an",
                                "delta[beta[n]] += 1 ? Pres[e * S + s] / an"),
     "cache_no_rescale": ("Pres[e * S + s] / ao * rows[n][beta[n]]",

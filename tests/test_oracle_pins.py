@@ -204,6 +204,32 @@ def test_order2_identity_core_is_matrix_completion_als():
             np.testing.assert_allclose(got[i], want, rtol=1e-11, atol=1e-13)
 
 
+def test_rows_of_many_entries_match_matrix_completion_als():
+    """P7 with rows of 6000 entries, which the oracle forms on all threads
+    (the deltas in parallel, rotated in in entry order): numpy's solve of the
+    normal equations, and the same bits for any thread count."""
+    rng = np.random.default_rng(35)
+    dims, J = (3, 6000), 4
+    G = np.eye(J)
+    A = [rng.standard_normal((d, J)) for d in dims]
+    idx = np.array(list(itertools.product(range(dims[0]), range(dims[1]))),
+                   dtype=np.int32).T.copy()
+    val = rng.standard_normal(idx.shape[1])
+    lam = 0.5
+    got = oracle.update_rows(G, A, idx, val, 0, lam)
+    for i in range(dims[0]):
+        Bm = A[1][idx[1, idx[0] == i]]
+        want = np.linalg.solve(Bm.T @ Bm + lam * np.eye(J), Bm.T @ val[idx[0] == i])
+        np.testing.assert_allclose(got[i], want, rtol=1e-10, atol=1e-13)
+    prev = oracle.set_threads(0)
+    try:
+        oracle.set_threads(1)
+        one = oracle.update_rows(G, A, idx, val, 0, lam)
+    finally:
+        oracle.set_threads(prev)
+    np.testing.assert_array_equal(one, got)
+
+
 # --------------------------------------------------------------------------
 # P8: fully observed, tiny lambda -> ordinary least squares per row
 # --------------------------------------------------------------------------
@@ -361,21 +387,114 @@ def test_solve_rejects_non_positive_definite():
         oracle.solve(-np.eye(3), np.ones(3), 0.01)
 
 
-def test_numerically_singular_row_keeps_previous_value():
-    """B + lambda I is PD in exact arithmetic; with a one-entry row and huge
-    factors, ||B|| * eps far exceeds lambda and FP64 Cholesky breaks down.
-    The row then keeps its previous value (the library does the same)."""
+def test_huge_norm_single_entry_row_is_sherman_morrison():
+    """P4 where forming B + lambda I fails in FP64: factors x 1e7 make
+    ||B|| * eps exceed lambda by many orders, yet the minimiser of the row's
+    problem is still x delta / (lambda + delta^T delta) (Sherman-Morrison),
+    of order 1e-14 here."""
     rng = np.random.default_rng(23)
     dims, ranks = (4, 5, 6), (3, 3, 3)
     G, A = rand_model(dims, ranks, rng)
     A = [a * 1e7 for a in A]
     idx = np.array([[1], [2], [3]], dtype=np.int32)
     val = np.array([1.0])
-    out, bad = oracle.update_rows(G, A, idx, val, 0, 1e-2, return_bad=True)
-    if bad:
-        np.testing.assert_array_equal(out[1], A[0][1])
-    # rows without entries are still exactly zero
-    assert np.all(out[[0, 2, 3]] == 0.0)
+    lam = 1e-2
+    for n in range(3):
+        d = D.deltas(G, A, idx, n)[0]
+        assert d @ d * np.finfo(float).eps > 1e6 * lam
+        want = val[0] * d / (lam + d @ d)
+        out, bad = oracle.update_rows(G, A, idx, val, n, lam, return_bad=True)
+        assert bad == 0
+        np.testing.assert_allclose(out[idx[n, 0]], want, rtol=1e-12, atol=0)
+        # the rows without entries are exactly zero
+        others = np.setdiff1d(np.arange(dims[n]), idx[n])
+        assert np.all(out[others] == 0.0)
+
+
+@pytest.mark.parametrize("k", [2, 3, 5])
+def test_rank_deficient_huge_norm_rows_match_dual_form(k):
+    """Rows with k < J_n entries and factors x 1e6: B has rank k and norm far
+    above lambda / eps. The minimiser is a = Delta^T (Delta Delta^T +
+    lambda I)^{-1} x (push-through identity; Delta is k x J_n, so the k x k
+    system keeps lambda's effect relative to its own, well conditioned
+    scale)."""
+    rng = np.random.default_rng(300 + k)
+    dims, ranks = (3, 9, 8), (6, 2, 3)
+    G, A = rand_model(dims, ranks, rng)
+    A = [a * 1e6 for a in A]
+    # row 1 of mode 0 gets k entries at distinct (i_2, i_3)
+    cells = rng.choice(dims[1] * dims[2], size=k, replace=False)
+    idx = np.stack([np.full(k, 1), cells // dims[2], cells % dims[2]]).astype(np.int32)
+    val = rng.standard_normal(k)
+    lam = 1e-2
+    Dl = D.deltas(G, A, idx, 0)                      # k x 6
+    assert np.linalg.norm(Dl.T @ Dl) * np.finfo(float).eps > 1e6 * lam
+    want = Dl.T @ np.linalg.solve(Dl @ Dl.T + lam * np.eye(k), val)
+    out, bad = oracle.update_rows(G, A, idx, val, 0, lam, return_bad=True)
+    assert bad == 0
+    np.testing.assert_allclose(out[1], want, rtol=1e-9, atol=1e-9 * np.abs(want).max())
+    # and the solution has no component outside the row space of Delta
+    P = Dl.T @ np.linalg.pinv(Dl.T)
+    np.testing.assert_allclose(P @ out[1], out[1], rtol=1e-9, atol=1e-9 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("k,J", [(0, 3), (1, 4), (7, 4), (40, 6)])
+def test_ls_solve_matches_normal_equations(k, J):
+    """On well-conditioned data the least-squares form equals numpy's solve
+    of (Delta^T Delta + lambda I) a = Delta^T x; no entry gives a = 0."""
+    rng = np.random.default_rng(31 + k)
+    Dl = rng.standard_normal((k, J))
+    x = rng.standard_normal(k)
+    lam = 0.3
+    got = oracle.ls_solve(Dl.reshape(k, J), x, lam) if k else \
+        oracle.ls_solve(np.zeros((0, J)), np.zeros(0), lam)
+    want = np.linalg.solve(Dl.T @ Dl + lam * np.eye(J), Dl.T @ x)
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-14)
+
+
+def test_cholesky_solve_matches_numpy():
+    rng = np.random.default_rng(32)
+    M = rng.standard_normal((9, 5))
+    B = M.T @ M
+    c = rng.standard_normal(5)
+    for lam in (0.01, 2.0):
+        want = np.linalg.solve(B + lam * np.eye(5), c)
+        np.testing.assert_allclose(oracle.solve(B, c, lam), want, rtol=1e-12)
+
+
+def test_row_system_matches_dense_gram():
+    """eqs. "rowB", "rowC": B_i = sum delta delta^T, c_i = sum x delta over
+    the row's entries, from the dense partial tensor's deltas."""
+    rng = np.random.default_rng(33)
+    dims, ranks = (5, 6, 4, 3), (2, 4, 3, 2)
+    G, A = rand_model(dims, ranks, rng)
+    idx, val = rand_obs(dims, 150, rng)
+    for n in range(4):
+        dl = D.deltas(G, A, idx, n)
+        for i in range(dims[n]):
+            sel = idx[n] == i
+            B, c = oracle.row_system(G, A, idx, val, n, i)
+            np.testing.assert_allclose(B, dl[sel].T @ dl[sel], rtol=1e-12, atol=1e-13)
+            np.testing.assert_allclose(c, dl[sel].T @ val[sel], rtol=1e-12, atol=1e-13)
+
+
+def test_results_do_not_depend_on_thread_count():
+    rng = np.random.default_rng(34)
+    dims, ranks = (9, 8, 7), (3, 2, 4)
+    G, A = rand_model(dims, ranks, rng)
+    idx, val = rand_obs(dims, 250, rng)
+    prev = oracle.set_threads(0)
+    try:
+        oracle.set_threads(1)
+        A1, L1, S1 = oracle.fit(G, A, idx, val, 0.05, 2)
+        oracle.set_threads(4)
+        A4, L4, S4 = oracle.fit(G, A, idx, val, 0.05, 2)
+    finally:
+        oracle.set_threads(prev)
+    for a, b in zip(A1, A4):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(S1, S4)
+    np.testing.assert_array_equal(L1, L4)
 
 
 # --------------------------------------------------------------------------
