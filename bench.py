@@ -72,55 +72,97 @@ def traffic_record(launch_nnz):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(p, seconds=20.0):
-    """FP64 oracle on a bounded sample of the workload (single thread)."""
+def _oracle_rate(p, G, A, v, seconds, rng):
+    """Seconds per entry-iteration of the oracle on a bounded sample of the
+    workload: Alg. 3 row updates of random rows per mode (sized from a
+    calibration on a few rows) and the error of random entries."""
     import oracle
-    G = p.core.astype(np.float64)
-    A = [a.astype(np.float64) for a in p.factors]
-    v = p.val.astype(np.float64)
-    rng = np.random.default_rng(123)
     N = p.N
     per = seconds / (N + 1)
-    # calibrate the per-entry cost on a few rows, then size each sample
     t_per_nnz = []
-    total_nnz = 0
+    total_nnz, total_rows = 0, 0
     for n in range(N):
         cnt = np.bincount(p.idx[n], minlength=p.dims[n])
         nz = np.flatnonzero(cnt)
         order = rng.permutation(nz)
-        # calibration rows
         csum = np.cumsum(cnt[order])
-        k0 = int(np.searchsorted(csum, 200)) + 1
+        k0 = int(np.searchsorted(csum, 2000)) + 1
         t0 = time.perf_counter()
         oracle.update_rows(G, A, p.idx, v, n, p.lam, rows=order[:k0])
-        dt = time.perf_counter() - t0
-        rate = max(dt, 1e-3) / max(csum[k0 - 1], 1)
-        target = max(200, int(per / rate))
+        rate = max(time.perf_counter() - t0, 1e-3) / max(csum[k0 - 1], 1)
+        target = max(2000, int(per / rate))
         k = int(np.searchsorted(csum, target)) + 1
-        rows = order[:k]
+        rows = order[k0:k0 + k]
         t0 = time.perf_counter()
         oracle.update_rows(G, A, p.idx, v, n, p.lam, rows=rows)
         dt = time.perf_counter() - t0
         nn = int(cnt[rows].sum())
         t_per_nnz.append(dt / nn)
         total_nnz += nn
-    m = max(200, int(per / max(t_per_nnz[0], 1e-9)))
+        total_rows += len(rows)
+    m = max(2000, int(per / max(t_per_nnz[0], 1e-9)))
     sel = rng.choice(p.nnz, size=min(m, p.nnz), replace=False)
     sub = np.ascontiguousarray(p.idx[:, sel])
     t0 = time.perf_counter()
     oracle.sse(G, A, sub, v[sel])
     t_err = (time.perf_counter() - t0) / len(sel)
-    per_nnz_iter = sum(t_per_nnz) + t_err
+    return sum(t_per_nnz) + t_err, total_rows, total_nnz, len(sel)
+
+
+def host_cores():
+    """(model, logical CPUs this process may use, physical cores of the host
+    from lscpu or None)."""
+    import oracle
+    import subprocess
+    model, _ = oracle.host_cpu()
+    try:
+        logical = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        logical = os.cpu_count() or 1
+    physical = None
+    try:
+        out = subprocess.run(["lscpu", "-p=CORE,SOCKET"], capture_output=True, text=True,
+                             timeout=10).stdout
+        pairs = {tuple(l.split(",")) for l in out.splitlines() if l and not l.startswith("#")}
+        physical = len(pairs) or None
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return model, logical, physical
+
+
+def cpu_baseline(p, seconds=20.0):
+    """FP64 oracle on a bounded sample of the workload: one thread, then all
+    the threads this process may use (OpenMP, rows dealt dynamically as in
+    the paper's Sec. 3.4). The value is the all-thread rate."""
+    import oracle
+    G = p.core.astype(np.float64)
+    A = [a.astype(np.float64) for a in p.factors]
+    v = p.val.astype(np.float64)
+    model, logical, physical = host_cores()
+    threads = min(logical, int(os.environ.get("OMP_NUM_THREADS", logical) or logical))
+    prev = oracle.set_threads(0)
+    try:
+        oracle.set_threads(1)
+        t1, rows1, nnz1, e1 = _oracle_rate(p, G, A, v, seconds / 2, np.random.default_rng(123))
+        used = oracle.set_threads(threads)
+        tm, rowsm, nnzm, em = _oracle_rate(p, G, A, v, seconds / 2, np.random.default_rng(124))
+    finally:
+        oracle.set_threads(prev)
     return {
-        "value": 1.0 / per_nnz_iter,
+        "value": 1.0 / tm,
         "unit": "nnz*iters/s",
-        "cores": 1,
+        "cores": used,
         "kind": "oracle",
-        "sample": "FP64 oracle, one thread: Alg. 3 row updates of %d random rows "
-                  "per mode (%d entries in all) and the error of %d random "
-                  "entries of the same workload; seconds per entry-iteration "
-                  "summed over the 4 modes and the error pass" %
-                  (len(rows), total_nnz, len(sel)),
+        "single_thread_value": 1.0 / t1,
+        "cpu_model": model,
+        "logical_cpus_available": logical,
+        "physical_cores_host": physical,
+        "build": "gcc -O3 -march=native -fopenmp",
+        "sample": "FP64 oracle: Alg. 3 row updates of random rows of every mode "
+                  "(%d rows, %d entries on %d threads; %d rows, %d entries on one "
+                  "thread) and the error of random entries (%d / %d); seconds per "
+                  "entry-iteration summed over the %d modes and the error pass"
+                  % (rowsm, nnzm, used, rows1, nnz1, em, e1, p.N),
     }
 
 
@@ -344,7 +386,7 @@ def main():
     ap.add_argument("--plain-requests", type=int, default=10_000)
     ap.add_argument("--nnz", type=int, default=0, help="override the entry count")
     ap.add_argument("--precision", choices=sorted(PREC_NAMES), default="f64")
-    ap.add_argument("--cpu-seconds", type=float, default=40.0)
+    ap.add_argument("--cpu-seconds", type=float, default=24.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variant", action="store_true")
     ap.add_argument("--approx-rate", type=float, default=0.0,

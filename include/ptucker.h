@@ -38,7 +38,9 @@ typedef enum ptk_status {
     PTK_E_NOT_PD = 4,       /* a J x J system was not positive definite     */
     PTK_E_HIP = 5,          /* a HIP runtime call or kernel launch failed   */
     PTK_E_STATE = 6,        /* call order violated (e.g. no observed set)   */
-    PTK_E_BUSY = 7          /* queue full, or a wait timed out              */
+    PTK_E_BUSY = 7,         /* queue full, or a wait timed out              */
+    PTK_E_DIVERGED = 8      /* ptk_iterate: an error or loss not finite, or
+                               the loss rose between iterations             */
 } ptk_status;
 
 typedef struct ptk_ctx ptk_ctx;
@@ -136,6 +138,20 @@ typedef struct ptk_options {
                                row of the grouping mode (the one with the
                                fewest rows) and per slice of entries,
                                (rows + slices) * 2 * J^(N-1) doubles.         */
+    double cond_limit;      /* accuracy limit of the Cholesky row solve (Sec.
+                               3.2, eq. "rowupdate"): with M = B_i + lambda I
+                               and S = diag(M)^-1/2 M diag(M)^-1/2, a row whose
+                               factorisation breaks down or whose tr(S^-1)
+                               exceeds cond_limit (cond(S) is within a factor
+                               J_n of it) is solved instead as the regularised
+                               least-squares problem whose normal equations
+                               eq. "rowupdate" are: Householder QR of
+                               [sqrt(lambda) I ; Delta] from the row's
+                               entries, deltas recomputed in FP64. That form
+                               needs no formed B_i and never breaks down for
+                               lambda > 0. 0 = the default, 1e9; 1 sends
+                               every non-empty row to the least-squares form.
+                               Negative or not finite: PTK_E_INVALID.        */
 } ptk_options;
 
 /*
@@ -192,8 +208,10 @@ ptk_status ptk_bind_model(ptk_ctx *ctx, float *core, float *const *factors_host)
  * solution of (B_i + lambda I) a_i = c_i (eq. "rowupdate"), where B_i and
  * c_i sum delta delta^T and x delta (eqs. "rowB", "rowC", "delta") over the
  * entries of row i. A row with no entry becomes 0. Requires lambda > 0
- * (PTK_E_INVALID otherwise). PTK_E_NOT_PD if some system could not be
- * factorised (those rows are left unchanged; the count is in the message).
+ * (PTK_E_INVALID otherwise). Rows whose Cholesky solve would be inaccurate
+ * are solved in the least-squares form (see ptk_options.cond_limit), so every
+ * row gets the unique solution; PTK_E_NOT_PD only if a result is not finite
+ * (non-finite or overflowing data; those rows are left unchanged).
  */
 ptk_status ptk_update_mode(ptk_ctx *ctx, int32_t n, double lambda);
 
@@ -201,10 +219,15 @@ ptk_status ptk_update_mode(ptk_ctx *ctx, int32_t n, double lambda);
  * iters iterations of Alg. 2 (lines 3-4): modes 0..N-1 in order, then the
  * reconstruction error. sse_host[t] / loss_host[t] (either may be NULL)
  * receive, after iteration t, sum over Omega of (x - x_hat)^2 (the square of
- * eq. "reconfull") and the loss of eq. "TF_PARTIAL". If some row systems were
- * not positive definite in floating point, all iterations still run, the
- * outputs are filled, those rows keep their previous values and the call
- * returns PTK_E_NOT_PD (count in the message and from ptk_not_pd_count).
+ * eq. "reconfull") and the loss of eq. "TF_PARTIAL". Every row is solved as
+ * in ptk_update_mode. Status, after all iterations ran and the outputs are
+ * filled: PTK_E_NOT_PD if some row result was not finite (count from
+ * ptk_not_pd_count); else PTK_E_DIVERGED if some SSE or loss is not finite,
+ * or a loss exceeds the previous iteration's of the same call by more than
+ * 1e-6 relative (Theorem 2 makes the loss non-increasing in exact
+ * arithmetic; the FP32 and BF16 forms can break this, the FP64 form only by
+ * the rounding of the stored float32 factors; not checked with approx_rate >
+ * 0, whose removal changes the model between iterations); else PTK_OK.
  */
 ptk_status ptk_iterate(ptk_ctx *ctx, int32_t iters, double lambda,
                        double *sse_host, double *loss_host);
@@ -214,13 +237,20 @@ ptk_status ptk_iterate(ptk_ctx *ctx, int32_t iters, double lambda,
 ptk_status ptk_iterations_done(const ptk_ctx *ctx, int32_t *n_host);
 
 /*
- * Number of row systems that were not positive definite in floating point
- * during the last ptk_update_mode / ptk_iterate / ptk_orthogonalize call.
- * B_i + lambda I is positive definite in exact arithmetic; in FP64 the
- * factorisation can break down when ||B_i|| * 2^-52 exceeds lambda for a row
- * with fewer entries than J_n. Synchronises the stream.
+ * Number of rows left unsolved (result not finite, row unchanged) during the
+ * last ptk_update_mode / ptk_iterate call, or of rank-deficient factors of the
+ * last ptk_orthogonalize. Zero for finite data and lambda > 0. Synchronises
+ * the stream.
  */
 ptk_status ptk_not_pd_count(ptk_ctx *ctx, int64_t *count_host);
+
+/*
+ * Rows of the last ptk_update_mode / ptk_iterate call (summed over modes and
+ * iterations) that the least-squares form solved (see
+ * ptk_options.cond_limit), and the most entries any of them had.
+ */
+ptk_status ptk_solve_stats(ptk_ctx *ctx, int64_t *ls_rows_host,
+                           int64_t *ls_max_entries_host);
 
 /*
  * Autotuner of the batching form (the GPU counterpart of the dynamic row

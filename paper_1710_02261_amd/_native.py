@@ -17,7 +17,7 @@ PREC_BF16 = 2
 PREC_BF16X3 = 3
 _STATUS = {0: "PTK_OK", 1: "PTK_E_INVALID", 2: "PTK_E_NOMEM",
            3: "PTK_E_UNSUPPORTED", 4: "PTK_E_NOT_PD", 5: "PTK_E_HIP",
-           6: "PTK_E_STATE"}
+           6: "PTK_E_STATE", 7: "PTK_E_BUSY", 8: "PTK_E_DIVERGED"}
 
 _vp = C.c_void_p
 _i32 = C.c_int32
@@ -29,7 +29,7 @@ class _Options(C.Structure):
     _fields_ = [("precision", _i32), ("chunk_nnz", _i32), ("fuse_error", _i32),
                 ("profile", _i32), ("use_graph", _i32), ("pair_cache", _i32),
                 ("approx_rate", _dbl), ("delta_slices", _i32), ("tol", _dbl),
-                ("approx_form", _i32)]
+                ("approx_form", _i32), ("cond_limit", _dbl)]
 
 
 class PtkError(RuntimeError):
@@ -71,6 +71,7 @@ def load_library():
                              C.POINTER(_i64), C.POINTER(_dbl)],
         "ptk_reset_timers": [_vp],
         "ptk_not_pd_count": [_vp, C.POINTER(_i64)],
+        "ptk_solve_stats": [_vp, C.POINTER(_i64), C.POINTER(_i64)],
         "ptk_autotune": [_vp, C.c_char_p, C.POINTER(_i64)],
         "ptk_partial_error": [_vp, _vp],
         "ptk_truncate": [_vp, _dbl, C.POINTER(_i32)],
@@ -196,9 +197,10 @@ class Context:
     # -- C ABI calls ---------------------------------------------------------
     def set_options(self, precision=PREC_FP64_ACC, chunk_nnz=0, fuse_error=1,
                     profile=0, use_graph=1, pair_cache=0, approx_rate=0.0,
-                    delta_slices=0, tol=0.0, approx_form=0):
+                    delta_slices=0, tol=0.0, approx_form=0, cond_limit=0.0):
         o = _Options(precision, chunk_nnz, fuse_error, profile, use_graph, pair_cache,
-                     float(approx_rate), delta_slices, float(tol), approx_form)
+                     float(approx_rate), delta_slices, float(tol), approx_form,
+                     float(cond_limit))
         self._check(self._lib.ptk_set_options(self._h, C.byref(o)))
 
     def set_observed(self, idx, val):
@@ -232,15 +234,17 @@ class Context:
         self._check(self._lib.ptk_update_mode(self._h, int(n), float(lam)))
 
     def iterate(self, iters, lam, strict=True):
-        """Alg. 2 iterations; with strict=False a PTK_E_NOT_PD status (rows
-        whose system was not positive definite in FP64 keep their values) is
-        not raised and the results are returned."""
+        """Alg. 2 iterations; with strict=False the statuses PTK_E_NOT_PD (rows
+        left unsolved) and PTK_E_DIVERGED (an error or loss not finite, or a
+        rising loss) are not raised and the results are returned;
+        ``last_status`` keeps the status either way."""
         sse = np.zeros(max(iters, 1))
         loss = np.zeros(max(iters, 1))
         st = self._lib.ptk_iterate(
             self._h, int(iters), float(lam),
             sse.ctypes.data_as(C.POINTER(_dbl)), loss.ctypes.data_as(C.POINTER(_dbl)))
-        if not (st == 4 and not strict):
+        self.last_status = st
+        if not (st in (4, 8) and not strict):
             self._check(st)
         return sse[:iters], loss[:iters]
 
@@ -255,6 +259,13 @@ class Context:
         n = _i64()
         self._check(self._lib.ptk_not_pd_count(self._h, C.byref(n)))
         return n.value
+
+    def solve_stats(self):
+        """(rows solved in least-squares form, most entries of such a row) of
+        the last update_mode / iterate call."""
+        a, b = _i64(), _i64()
+        self._check(self._lib.ptk_solve_stats(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def recon_error(self, lam=0.0):
         s, r, l = _dbl(), _dbl(), _dbl()

@@ -321,14 +321,60 @@ ptk_status systems(ptk_ctx *c, int n, int role = 0) {
     return PTK_OK;
 }
 
-ptk_status update_mode_impl(ptk_ctx *c, int n, double lambda, int role = 0) {
+// The FP64 permuted core of mode n in the default order (the other modes
+// ascending, j_n fastest) for the least-squares solve: the row-system core
+// itself when it has that form, else the per-entry kernels' copy.
+hipError_t ls_core(ptk_ctx *c, int n, int role, const void **gp) {
+    if (!c->md[n].bf16 && arith_of(c, n) == kArithF64 && role != 1) {
+        *gp = c->gp[n];
+        return hipSuccess;
+    }
+    *gp = c->gpe;
+    return permute_entries(c, n);
+}
+
+// Cholesky solve of every row of mode n; the rows it flags (breakdown or a
+// large condition estimate) are then solved in least-squares form from their
+// entries. want_rsse: keep those rows' error terms for the fused error.
+ptk_status update_mode_impl(ptk_ctx *c, int n, double lambda, int role = 0,
+                            bool want_rsse = false) {
     ptk_status s = systems(c, n, role);
     if (s != PTK_OK) return s;
     const ModeData &m = c->md[n];
+    SolveFlags f{};
+    f.rflag = c->rflag;
+    f.list = c->lslist;
+    f.cnt = c->ctr + 4 + 2 * n;
+    f.cap = c->max_rows;
+    f.cond_limit = c->opt.cond_limit > 0.0 ? c->opt.cond_limit : kCondLimitDefault;
     HIPCHK(c, timed(c, "solve", [&] {
         return launch_solve(c->bbuf, m.rowptr, c->s.dims[n], c->s.ranks[n], lambda,
-                            c->fac[n], c->bad, c->st);
+                            c->fac[n], f, c->st);
     }));
+    ResolveArgs r{};
+    HIPCHK(c, ls_core(c, n, role, &r.gp));
+    int t = 0, off = 0;
+    for (int k = 0; k < c->s.N; ++k) {
+        if (k == n) continue;
+        r.fac[t] = c->fac[k];
+        r.oidx[t] = m.oidx + (int64_t)t * c->nnz;
+        r.jk[t] = c->s.ranks[k];
+        r.aoff[t] = off;
+        off += c->s.ranks[k];
+        ++t;
+    }
+    r.nother = c->s.N - 1;
+    r.jn = c->s.ranks[n];
+    r.val = m.vals;
+    r.rowptr = m.rowptr;
+    r.list = f.list;
+    r.cnt = f.cnt;
+    r.cap = f.cap;
+    r.lambda = lambda;
+    r.A = c->fac[n];
+    r.rsse = want_rsse ? c->rsse : nullptr;
+    r.stats = c->ctr;
+    HIPCHK(c, timed(c, "solve_ls", [&] { return launch_resolve(r, c->num_cu, c->st); }));
     return PTK_OK;
 }
 
@@ -357,8 +403,16 @@ __global__ void k_add_scalar(double *partial, int n, const double *x) {
     if (threadIdx.x == 0) partial[n] = *x;
 }
 
+// All counters (call start) / the per-mode list counters (iteration start).
 hipError_t zero_bad(ptk_ctx *c) {
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, c->bad, 0, (int64_t)1);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, c->ctr, 0,
+                       (int64_t)kCtrSlots);
+    return hipGetLastError();
+}
+
+hipError_t zero_lists(ptk_ctx *c) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, c->ctr + 4, 0,
+                       (int64_t)2 * c->s.N);
     return hipGetLastError();
 }
 
@@ -414,13 +468,15 @@ hipError_t sse_direct(ptk_ctx *c, double *partial, double *out) {
 }
 
 ptk_status check_bad(ptk_ctx *c, const char *what) {
-    int32_t bad = 0;
-    HIPCHK(c, hipMemcpyAsync(&bad, c->bad, sizeof bad, hipMemcpyDeviceToHost, c->st));
+    int32_t v[3] = {0, 0, 0};
+    HIPCHK(c, hipMemcpyAsync(v, c->ctr, sizeof v, hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
-    c->last_not_pd = bad;
-    if (bad > 0)
-        return fail(c, PTK_E_NOT_PD, "%s: %d system(s) not positive definite", what,
-                    bad);
+    c->last_not_pd = v[0];
+    c->last_ls_rows = v[1];
+    c->last_ls_max = v[2];
+    if (v[0] > 0)
+        return fail(c, PTK_E_NOT_PD, "%s: %d row(s) or factor(s) could not be solved", what,
+                    v[0]);
     return PTK_OK;
 }
 
@@ -672,9 +728,11 @@ ptk_status iteration_body(ptk_ctx *c, double lambda) {
     // Approx variant: the last mode's kernel may keep its deltas for the
     // residuals (when the partial errors group by that mode)
     c->ap_stored = false;
+    HIPCHK(c, zero_lists(c));
     for (int n = 0; n < N; ++n) {
         c->ap_store = c->opt.approx_rate > 0.0 && n == N - 1;
-        ptk_status s = update_mode_impl(c, n, lambda, cache_role(c, n));
+        ptk_status s = update_mode_impl(c, n, lambda, cache_role(c, n),
+                                        n == N - 1 && c->opt.fuse_error);
         c->ap_store = false;
         if (s != PTK_OK) return s;
     }
@@ -683,8 +741,8 @@ ptk_status iteration_body(ptk_ctx *c, double lambda) {
             // from the last mode's row systems, still in bbuf
             const ModeData &m = c->md[N - 1];
             hipError_t e = launch_row_sse(c->bbuf, m.rowptr, c->fac[N - 1],
-                                          c->s.dims[N - 1], c->s.ranks[N - 1], partial,
-                                          kRedBlocks, c->st);
+                                          c->s.dims[N - 1], c->s.ranks[N - 1], c->rflag,
+                                          c->rsse, partial, kRedBlocks, c->st);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, c->st, partial,
                                kRedBlocks, c->xsq);
@@ -785,7 +843,16 @@ ptk_status ptk_create(ptk_ctx **out, int32_t N, const int64_t *dims_host,
     if (e == hipSuccess) e = dalloc(&c->gpe, (size_t)(cells + 64));
     if (e == hipSuccess)
         e = dalloc(&c->red, std::max<size_t>((size_t)kRedBlocks * (N + 1), kSseBlocks + 2) + 64);
-    if (e == hipSuccess) e = dalloc(&c->bad, 1);
+    int64_t max_rows = 1;
+    for (int n = 0; n < N; ++n) max_rows = std::max<int64_t>(max_rows, dims_host[n]);
+    c->max_rows = max_rows;
+    if (e == hipSuccess) e = dalloc(&c->ctr, kCtrSlots);
+    if (e == hipSuccess) e = hipMemset(c->ctr, 0, kCtrSlots * sizeof(int32_t));
+    c->bad = c->ctr;
+    if (e == hipSuccess) e = dalloc(&c->lslist, (size_t)max_rows);
+    if (e == hipSuccess) e = dalloc(&c->rflag, (size_t)max_rows);
+    if (e == hipSuccess) e = dalloc(&c->rsse, (size_t)max_rows);
+    if (e == hipSuccess) e = dalloc(&c->fold_ls, 4);
     if (e == hipSuccess) e = dalloc(&c->xsq, 1);
     if (e == hipSuccess) e = dalloc(&c->scal, 4);
     if (e == hipSuccess) e = dalloc(&c->iter_ctr, 1);
@@ -808,7 +875,11 @@ ptk_status ptk_destroy(ptk_ctx *c) {
     }
     dfree(c->gpe);
     dfree(c->red);
-    dfree(c->bad);
+    dfree(c->ctr);
+    dfree(c->lslist);
+    dfree(c->rflag);
+    dfree(c->rsse);
+    dfree(c->fold_ls);
     dfree(c->xsq);
     dfree(c->scal);
     dfree(c->dres);
@@ -873,6 +944,8 @@ ptk_status ptk_set_options(ptk_ctx *c, const ptk_options *o) {
     if (o->approx_rate > 0.0 &&
         !(equal_ranks(c->s) && approx_available(c->s.N, c->s.ranks[0])))
         return fail(c, PTK_E_UNSUPPORTED, "no Approx kernels for this shape");
+    if (!(o->cond_limit >= 0.0) || !std::isfinite(o->cond_limit))
+        return fail(c, PTK_E_INVALID, "cond_limit must be finite and >= 0");
     c->opt = *o;
     c->epoch++;
     return PTK_OK;
@@ -1124,13 +1197,29 @@ ptk_status ptk_iterate(ptk_ctx *c, int32_t iters, double lambda, double *sse_hos
     HIPCHK(c, hipMemcpyAsync(c->host, c->dres, 2 * sizeof(double) * done,
                              hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
+    int diverged = -1;
+    double prev = 0.0;
     for (int t = 0; t < iters; ++t) {
         const bool ran = t < done;
-        if (sse_host) sse_host[t] = ran ? c->host[2 * t] : std::nan("");
-        if (loss_host)
-            loss_host[t] = ran ? c->host[2 * t] + lambda * c->host[2 * t + 1] : std::nan("");
+        const double sse = ran ? c->host[2 * t] : std::nan("");
+        const double loss = ran ? c->host[2 * t] + lambda * c->host[2 * t + 1] : std::nan("");
+        if (sse_host) sse_host[t] = sse;
+        if (loss_host) loss_host[t] = loss;
+        if (ran && diverged < 0) {
+            const bool rise = t > 0 && c->opt.approx_rate == 0.0 && loss > prev * (1.0 + 1e-6);
+            if (!std::isfinite(sse) || !std::isfinite(loss) || rise) diverged = t;
+        }
+        prev = loss;
     }
-    return check_bad(c, "ptk_iterate");
+    s = check_bad(c, "ptk_iterate");
+    if (s != PTK_OK || diverged < 0) return s;
+    return fail(c, PTK_E_DIVERGED,
+                "ptk_iterate: iteration %d: error %.17g, loss %.17g (previous loss %.17g)",
+                diverged, c->host[2 * diverged],
+                c->host[2 * diverged] + lambda * c->host[2 * diverged + 1],
+                diverged > 0 ? c->host[2 * (diverged - 1)] +
+                                   lambda * c->host[2 * (diverged - 1) + 1]
+                             : std::nan(""));
 }
 
 ptk_status ptk_iterations_done(const ptk_ctx *c, int32_t *n_host) {
@@ -1329,13 +1418,15 @@ ptk_status ptk_row_systems(ptk_ctx *c, int32_t n, double *B_out, double *c_out) 
 namespace {
 
 __global__ void k_fold_setup(int64_t *rowptr, int32_t *split, int64_t k,
-                             int32_t nchunks) {
+                             int32_t nchunks, int32_t *ls) {
     if (threadIdx.x == 0) {
         rowptr[0] = 0;
         rowptr[1] = k;
         split[0] = 0;
         split[1] = 0;
         split[2] = nchunks - 1;
+        ls[1] = 0;          // light / heavy counts of the least-squares list
+        ls[2] = 0;
     }
 }
 
@@ -1366,7 +1457,7 @@ extern "C" ptk_status ptk_fold_in(ptk_ctx *c, int32_t n, int64_t k, const int32_
     while ((k + chunk - 1) / chunk > kFoldMaxChunks) chunk *= 2;
     const int64_t nchunks = (k + chunk - 1) / chunk;
     hipLaunchKernelGGL(k_fold_setup, dim3(1), dim3(64), 0, c->st, c->fold_rowptr,
-                       c->fold_split, k, (int32_t)std::max<int64_t>(nchunks, 1));
+                       c->fold_split, k, (int32_t)std::max<int64_t>(nchunks, 1), c->fold_ls);
     HIPCHK(c, hipGetLastError());
     GramArgs a{};
     const int32_t *other[kMaxN];
@@ -1393,10 +1484,39 @@ extern "C" ptk_status ptk_fold_in(ptk_ctx *c, int32_t n, int64_t k, const int32_
     }));
     if (nchunks > 1)
         HIPCHK(c, launch_merge(c->fold_part, c->fold_split, 1, E, c->fold_bbuf, c->st));
+    SolveFlags f{};
+    f.list = c->fold_ls;                 // one slot: the row is light or heavy
+    f.cnt = c->fold_ls + 1;
+    f.cap = 1;
+    f.cond_limit = c->opt.cond_limit > 0.0 ? c->opt.cond_limit : kCondLimitDefault;
     HIPCHK(c, timed(c, "fold_solve", [&] {
-        return launch_solve(c->fold_bbuf, c->fold_rowptr, 1, J, lambda, row_out,
-                            c->bad, c->st);
+        return launch_solve(c->fold_bbuf, c->fold_rowptr, 1, J, lambda, row_out, f, c->st);
     }));
+    ResolveArgs r{};
+    if (ar == kArithF64) {
+        r.gp = c->gp[n];
+    } else {
+        r.gp = c->gpe;
+        HIPCHK(c, permute_entries(c, n));
+    }
+    for (int q = 0; q < c->s.N - 1; ++q) {
+        r.fac[q] = a.fac[q];
+        r.oidx[q] = a.oidx[q];
+        r.jk[q] = a.jk[q];
+        r.aoff[q] = a.aoff[q];
+    }
+    r.nother = a.nother;
+    r.jn = J;
+    r.val = val;
+    r.rowptr = c->fold_rowptr;
+    r.list = f.list;
+    r.cnt = f.cnt;
+    r.cap = 1;
+    r.lambda = lambda;
+    r.A = row_out;
+    r.rsse = nullptr;
+    r.stats = c->ctr;
+    HIPCHK(c, timed(c, "fold_solve_ls", [&] { return launch_resolve(r, c->num_cu, c->st); }));
     return PTK_OK;
 }
 
@@ -1524,6 +1644,13 @@ extern "C" ptk_status ptk_autotune(ptk_ctx *c, const char *cache_path, int64_t *
 extern "C" ptk_status ptk_not_pd_count(ptk_ctx *c, int64_t *count) {
     if (!c || !count) return PTK_E_INVALID;
     *count = c->last_not_pd;
+    return PTK_OK;
+}
+
+extern "C" ptk_status ptk_solve_stats(ptk_ctx *c, int64_t *ls_rows, int64_t *ls_max) {
+    if (!c || !ls_rows || !ls_max) return PTK_E_INVALID;
+    *ls_rows = c->last_ls_rows;
+    *ls_max = c->last_ls_max;
     return PTK_OK;
 }
 

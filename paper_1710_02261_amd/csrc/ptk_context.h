@@ -13,6 +13,7 @@ namespace ptk {
 
 constexpr int kRedBlocks = 1024;   // blocks of the error / norm reductions
 constexpr int kSseBlocks = 8192;   // single-wave blocks of the direct error pass
+constexpr int kCtrSlots = 4 + 2 * kMaxN;
 
 struct ModeData {
     int64_t *rowptr = nullptr;
@@ -55,7 +56,7 @@ struct ptk_ctx {
     hipStream_t st = nullptr;
     int device = 0;
     int num_cu = 256;
-    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1, 0, 0.0, 0, 0.0, 0};
+    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1, 0, 0.0, 0, 0.0, 0, 0.0};
     int64_t nnz = -1;
     ModeData md[ptk::kMaxN];
     float *core = nullptr;
@@ -95,8 +96,21 @@ struct ptk_ctx {
     uint64_t g_epoch = 0;
     double g_lambda = 0.0;
     int g_fuse = -1;
-    int32_t *bad = nullptr;
-    int64_t last_not_pd = 0;
+    // counters [kCtrSlots] int32: [0] rows left unsolved (or rank-deficient
+    // factors of the final QR), [1] rows solved in least-squares form, [2] the
+    // most entries of such a row, [3] spare, [4 + 2n], [5 + 2n] light and heavy
+    // rows flagged in mode n (zeroed at the start of every iteration)
+    int32_t *ctr = nullptr;
+    int32_t *bad = nullptr;      // ctr + 0
+    // rows handed to the least-squares solve: the list (max I_n), a flag byte
+    // per row and the rows' error terms (last mode of a fused-error iteration)
+    int32_t *lslist = nullptr;
+    uint8_t *rflag = nullptr;
+    double *rsse = nullptr;
+    int64_t max_rows = 0;
+    int64_t last_not_pd = 0, last_ls_rows = 0, last_ls_max = 0;
+    // fold-in: list and counters of its one row
+    int32_t *fold_ls = nullptr;
     int32_t last_iters = 0;      // iterations the last ptk_iterate ran
     double *host = nullptr;      // pinned results
     size_t host_cap = 0;

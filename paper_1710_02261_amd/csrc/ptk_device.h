@@ -106,6 +106,63 @@ __device__ __forceinline__ void load_rows_fast(const Args &a, int64_t pos,
 }
 
 // ---------------------------------------------------------------------------
+// generic delta: any ranks (J_k <= 32), any order; mode-n rank <= JMAX
+// ---------------------------------------------------------------------------
+constexpr int kMaxOther = kMaxN - 1;
+
+template <int JMAX, typename Args>
+__device__ __forceinline__ void load_rows_generic(const Args &a, int64_t pos,
+                                                  bool valid, float *arow,
+                                                  int lane) {
+    for (int k = 0; k < a.nother; ++k) {
+        const int32_t i = valid ? a.oidx[k][pos] : 0;
+        const int jk = a.jk[k];
+        const float *r = a.fac[k] + (int64_t)i * jk;
+        for (int j = 0; j < jk; ++j) arow[(a.aoff[k] + j) * kWave + lane] = r[j];
+    }
+}
+
+template <int JMAX, typename Args>
+__device__ __forceinline__ void delta_generic(const Args &a, const float *arow,
+                                              int lane, double (&out)[JMAX]) {
+    cptr<double> gp = (cptr<double>)a.gp;
+    const int jn = a.jn;
+    const int no = a.nother;
+    int jk[kMaxOther], off[kMaxOther], dig[kMaxOther];
+    int64_t P = 1;
+#pragma unroll
+    for (int k = 0; k < kMaxOther; ++k) {
+        jk[k] = (k < no) ? a.jk[k] : 1;
+        off[k] = (k < no) ? a.aoff[k] : 0;
+        dig[k] = 0;
+        P *= jk[k];
+    }
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j) out[j] = 0.0;
+    for (int64_t o = 0; o < P; ++o) {
+        double w = 1.0;
+#pragma unroll
+        for (int k = 0; k < kMaxOther; ++k)
+            if (k < no) w *= (double)arow[(off[k] + dig[k]) * kWave + lane];
+        cptr<double> g = gp + o * jn;
+#pragma unroll
+        for (int j = 0; j < JMAX; ++j)
+            if (j < jn) out[j] = __builtin_fma(g[j], w, out[j]);
+        // advance the odometer, last other mode fastest
+        bool carry = true;
+#pragma unroll
+        for (int k = kMaxOther - 1; k >= 0; --k) {
+            if (carry && k < no) {
+                if (++dig[k] == jk[k])
+                    dig[k] = 0;
+                else
+                    carry = false;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // row-system sweep over one tile of deltas in LDS
 // ---------------------------------------------------------------------------
 // s_dl layout: [j][65] doubles, row J holds the values x (stride 65 keeps the

@@ -146,12 +146,55 @@ hipError_t launch_gram2(const GramArgs &a, int N, int J, Arith ar, int64_t nchun
                         hipStream_t st);
 hipError_t launch_merge(const double *part, const int32_t *split, int32_t nsplit,
                         int E, double *bbuf, hipStream_t st);
+// Rows the Cholesky solve hands to the least-squares solve (ptk_resolve.hip):
+// those whose factorisation broke down or whose scaled condition estimate
+// tr((D^-1/2 M D^-1/2)^-1), M = B_i + lambda I, D = diag(M), exceeds
+// cond_limit. Light rows (at most kLsLight entries) are appended at the front
+// of list, heavy rows at the back (list[cap - 1 - k]); cnt[0], cnt[1] count
+// them. rflag (optional, one byte per row) marks every flagged row.
+constexpr int64_t kLsLight = 256;
+constexpr double kCondLimitDefault = 1e9;
+struct SolveFlags {
+    uint8_t *rflag;
+    int32_t *list;
+    int32_t *cnt;
+    int64_t cap;
+    double cond_limit;
+};
 hipError_t launch_solve(const double *bbuf, const int64_t *rowptr, int64_t I,
-                        int J, double lambda, float *A, int32_t *bad,
+                        int J, double lambda, float *A, const SolveFlags &f,
                         hipStream_t st);
+
+// Arguments of the least-squares row solve of the flagged rows (the entries
+// of mode n in grouped order, as for the row-system kernels).
+struct ResolveArgs {
+    const void *gp;                   // FP64 permuted core of mode n
+    const float *fac[kMaxN];
+    const int32_t *oidx[kMaxN];
+    int32_t jk[kMaxN];
+    int32_t aoff[kMaxN];
+    int32_t nother;
+    int32_t jn;
+    const float *val;
+    const int64_t *rowptr;
+    const int32_t *list;              // as SolveFlags
+    const int32_t *cnt;
+    int64_t cap;
+    double lambda;
+    float *A;                         // A^(n): the flagged rows are written
+    double *rsse;                     // optional: per flagged row i,
+                                      // sum over its entries of p (p - 2x),
+                                      // p = a_i^T delta (a_i as stored)
+    int32_t *stats;                   // [0] rows left unsolved (result not
+                                      // finite), [1] rows solved here,
+                                      // [2] most entries of such a row
+};
+hipError_t launch_resolve(const ResolveArgs &a, int num_cu, hipStream_t st);
+// rflag / rsse (optional): rows marked in rflag add rsse[i] instead of the
+// identity of their row system.
 hipError_t launch_row_sse(const double *bbuf, const int64_t *rowptr, const float *A,
-                          int64_t I, int J, double *partial, int nblocks,
-                          hipStream_t st);
+                          int64_t I, int J, const uint8_t *rflag, const double *rsse,
+                          double *partial, int nblocks, hipStream_t st);
 hipError_t launch_entries(const EntryArgs &a, const Shape &s, int n, int kind,
                           bool fast, int64_t nblocks, hipStream_t st);
 hipError_t launch_sumsq(const float *x, int64_t n, double *partial, int nblocks,

@@ -66,7 +66,7 @@ struct Slot {
     hipEvent_t ev = nullptr;
     char *dev = nullptr;
     char *host = nullptr;
-    int32_t *bad = nullptr;
+    int32_t *bad = nullptr;     // least-squares solve counters [3]
     bool busy = false;
     std::vector<ReqPtr> reqs;
     std::vector<size_t> out_off;
@@ -117,7 +117,7 @@ size_t request_bytes(const ptk_server *sv, const Request &r) {
     const size_t P = (size_t)((r.count + kSeg - 1) / kSeg * kSeg);
     const size_t chunks = P / kSeg;
     return P * (4 * (N - 1) + 8) + J * 4 + E * 8 + chunks * 2 * E * 8 + chunks * 12 +
-           16 + 8 * kAlign;
+           16 + 12 + 9 * kAlign;
 }
 
 // Bump allocator over a slot's arena (same offsets in staging and device).
@@ -143,6 +143,7 @@ hipError_t launch_batch(ptk_server *sv, Slot &sl) {
         std::vector<size_t> ri;         // indices into sl.reqs
         int64_t P = 0;
         size_t o_oidx = 0, o_val = 0, o_rows = 0, o_rowptr = 0, o_split = 0;
+        size_t o_ls = 0;                // least-squares counters [2] + list [q]
         size_t o_bbuf = 0, o_part = 0, o_out = 0;
         int32_t nsplit = 0;
     };
@@ -173,6 +174,7 @@ hipError_t launch_batch(ptk_server *sv, Slot &sl) {
         g.o_rows = L.take((size_t)g.P * 4);
         g.o_rowptr = L.take((size_t)(q + 2) * 8);
         g.o_split = L.take((size_t)(g.P / kSeg + 1) * 12);
+        g.o_ls = L.take((size_t)(q + 2) * 4);
     }
     const size_t o_pidx = L.take((size_t)N * M * 4);
     const size_t in_end = L.off;
@@ -225,6 +227,9 @@ hipError_t launch_batch(ptk_server *sv, Slot &sl) {
         }
         rowptr[q] = pos;
         rowptr[q + 1] = pos;
+        int32_t *ls = (int32_t *)(H + g.o_ls);
+        ls[0] = 0;                      // no row flagged yet
+        ls[1] = 0;
     }
     {
         int32_t *pidx = (int32_t *)(H + o_pidx);
@@ -276,8 +281,36 @@ hipError_t launch_batch(ptk_server *sv, Slot &sl) {
         if (e == hipSuccess)
             e = launch_merge(a.part, (const int32_t *)(D + g.o_split), g.nsplit, a.E, a.bbuf,
                              sl.st);
+        SolveFlags f{};
+        f.cnt = (int32_t *)(D + g.o_ls);
+        f.list = f.cnt + 2;
+        f.cap = q;
+        f.cond_limit = c->opt.cond_limit > 0.0 ? c->opt.cond_limit : kCondLimitDefault;
         if (e == hipSuccess)
-            e = launch_solve(a.bbuf, a.rowptr, q, J, sv->opt.lambda, out, sl.bad, sl.st);
+            e = launch_solve(a.bbuf, a.rowptr, q, J, sv->opt.lambda, out, f, sl.st);
+        if (e == hipSuccess) {
+            // rows whose Cholesky solve would be inaccurate: least-squares form
+            ResolveArgs r{};
+            r.gp = a.gp;
+            for (int k = 0; k < N - 1; ++k) {
+                r.fac[k] = a.fac[k];
+                r.oidx[k] = a.oidx[k];
+                r.jk[k] = a.jk[k];
+                r.aoff[k] = a.aoff[k];
+            }
+            r.nother = N - 1;
+            r.jn = J;
+            r.val = a.val;
+            r.rowptr = a.rowptr;
+            r.list = f.list;
+            r.cnt = f.cnt;
+            r.cap = q;
+            r.lambda = sv->opt.lambda;
+            r.A = out;
+            r.rsse = nullptr;
+            r.stats = sl.bad;
+            e = launch_resolve(r, c->num_cu, sl.st);
+        }
     }
     if (e == hipSuccess && M > 0) {
         EntryArgs a{};
@@ -500,7 +533,8 @@ ptk_status ptk_server_create(ptk_server **out, ptk_ctx *ctx, const ptk_server_op
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
         if (e == hipSuccess) e = hipMalloc((void **)&sl.dev, sv->slot_cap);
         if (e == hipSuccess) e = hipHostMalloc((void **)&sl.host, sv->slot_cap);
-        if (e == hipSuccess) e = hipMalloc((void **)&sl.bad, 4);
+        if (e == hipSuccess) e = hipMalloc((void **)&sl.bad, 4 * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMemset(sl.bad, 0, 4 * sizeof(int32_t));
     }
     if (e != hipSuccess) {
         ptk_server_destroy(sv.release());

@@ -3,11 +3,27 @@
 // a_i = c_i (B_i + lambda I)^{-1} is computed as the solution of the
 // symmetric positive definite system (B_i + lambda I) a_i^T = c_i^T by a
 // Cholesky factorisation and two triangular solves (Golub & Van Loan,
-// Alg. 4.2.1) instead of the explicit inverse of Alg. 3. One thread owns one
-// row; its packed system lives in LDS, one column per thread.
+// Alg. 4.2.1) instead of the explicit inverse of Alg. 3.
+//
+// Accuracy check. With M = B_i + lambda I and D = diag(M), the forward error
+// of the Cholesky solve grows with the condition of the scaled matrix
+// S = D^-1/2 M D^-1/2. Each kernel computes tr(S^-1) = sum_k M_kk (M^-1)_kk
+// from the factor, (M^-1)_kk = ||L^-1 e_k||^2 (about J^3/6 more multiply-adds
+// per row); cond(S) lies within a factor J of it either way. A row whose
+// factorisation breaks down, or whose tr(S^-1) exceeds the limit, is not
+// written: it is flagged and handed to the least-squares solve of
+// ptk_resolve.hip, which works from the entries and needs no formed B_i.
 #include "ptk_internal.h"
 
 namespace ptk {
+
+// Hand row i over to the least-squares solve (one caller per row).
+__device__ __forceinline__ void flag_row(const SolveFlags &f, int64_t i, int64_t cnt) {
+    if (cnt <= kLsLight)
+        f.list[atomicAdd(&f.cnt[0], 1)] = (int32_t)i;
+    else
+        f.list[f.cap - 1 - atomicAdd(&f.cnt[1], 1)] = (int32_t)i;
+}
 
 // Merge the partial systems of rows that cross work-range boundaries:
 // split[3*s + {0,1,2}] = (row, first range, last range). The first range
@@ -58,18 +74,21 @@ hipError_t launch_merge(const double *part, const int32_t *split, int32_t nsplit
     return hipGetLastError();
 }
 
-// Packed Cholesky in place: L(i, j), j <= i, overwrites B(j, i).
+// Packed Cholesky in place: L(i, j), j <= i, overwrites B(j, i). One thread
+// per row; the packed system and a J-vector of work space live in LDS, one
+// column per thread.
 __global__ void k_solve(const double *__restrict__ bbuf,
                         const int64_t *__restrict__ rowptr, int64_t I, int J,
-                        double lambda, float *__restrict__ A,
-                        int32_t *__restrict__ bad) {
+                        double lambda, float *__restrict__ A, SolveFlags f) {
     extern __shared__ double s_sys[];
     const int bs = blockDim.x;
     const int64_t i = (int64_t)blockIdx.x * bs + threadIdx.x;
     if (i >= I) return;
     float *arow = A + i * J;
-    if (rowptr[i] == rowptr[i + 1]) {      // no entry: B = 0, c = 0 -> a = 0
+    const int64_t cnt = rowptr[i + 1] - rowptr[i];
+    if (cnt == 0) {                        // no entry: B = 0, c = 0 -> a = 0
         for (int p = 0; p < J; ++p) arow[p] = 0.0f;
+        if (f.rflag) f.rflag[i] = 0;
         return;
     }
     const int T = J * (J + 1) / 2;
@@ -96,9 +115,32 @@ __global__ void k_solve(const double *__restrict__ bbuf,
             }
         }
     }
-    if (!ok) {
-        atomicAdd(bad, 1);
-        return;                            // row left unchanged
+    // tr(S^-1) = sum_k M_kk ||L^-1 e_k||^2, M_kk = sum_{q <= k} L_kq^2
+    double tr = 0.0;
+    if (ok) {
+        double *y = m + (size_t)E * bs;    // work space, J entries
+        for (int k = 0; k < J; ++k) {
+            double mkk = 0.0;
+            for (int q = 0; q <= k; ++q) {
+                const double l = m[tri_pos(q, k, J) * bs];
+                mkk += l * l;
+            }
+            y[k * bs] = 1.0 / m[tri_pos(k, k, J) * bs];
+            double ss = y[k * bs] * y[k * bs];
+            for (int r = k + 1; r < J; ++r) {
+                double t = 0.0;
+                for (int q = k; q < r; ++q) t += m[tri_pos(q, r, J) * bs] * y[q * bs];
+                y[r * bs] = -t / m[tri_pos(r, r, J) * bs];
+                ss += y[r * bs] * y[r * bs];
+            }
+            tr += mkk * ss;
+        }
+    }
+    const bool flag = !ok || !(tr <= f.cond_limit);
+    if (f.rflag) f.rflag[i] = flag;
+    if (flag) {
+        flag_row(f, i, cnt);
+        return;
     }
     double *y = m + T * bs;                // rhs c, overwritten by y then a
     for (int r = 0; r < J; ++r) {          // L y = c
@@ -118,26 +160,28 @@ __global__ void k_solve(const double *__restrict__ bbuf,
 // 64/G rows per wavefront): lane l keeps row l of B + lambda I in registers.
 // Cholesky column by column (the diagonal and the new column are broadcast
 // within the group, 1 / L_kk kept in every lane), then L y = c with each y_r
-// broadcast, then L^T a = y with a group reduction per step. FP64; a failed diagonal leaves the row
-// unchanged and is counted, as in k_solve.
+// broadcast, then L^T a = y with a group reduction per step. For the
+// condition estimate lane l forms column l of L^-1 (the rows of L broadcast
+// from their lanes). FP64; same flagging and empty-row rule as k_solve.
 template <int J>
 __global__ __launch_bounds__(256) void k_solve_grp(const double *__restrict__ bbuf,
                                                    const int64_t *__restrict__ rowptr,
                                                    int64_t I, double lambda,
-                                                   float *__restrict__ A,
-                                                   int32_t *__restrict__ bad) {
+                                                   float *__restrict__ A, SolveFlags f) {
     constexpr int G = J <= 4 ? 4 : (J <= 8 ? 8 : 16);
     constexpr int T = J * (J + 1) / 2;
     constexpr int E = T + J;
     const int l = threadIdx.x % G;
     const int64_t i = (int64_t)blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
     const bool have = i < I;
-    const bool empty = have && rowptr[i] == rowptr[i + 1];
+    const int64_t cnt = have ? rowptr[i + 1] - rowptr[i] : 0;
+    const bool empty = have && cnt == 0;
     const bool live = have && !empty;          // uniform within the group
     if (!live) {
         // nothing to solve; the group leaves together, so no shuffle below
         // reads its lanes
         if (empty && l < J) A[i * J + l] = 0.0f;   // no entry: B = 0, c = 0 -> a = 0
+        if (empty && l == 0 && f.rflag) f.rflag[i] = 0;
         return;
     }
     double b[J];
@@ -170,6 +214,26 @@ __global__ __launch_bounds__(256) void k_solve_grp(const double *__restrict__ bb
             if (l > k) b[j] = __builtin_fma(-mine, ljk, b[j]);
         }
     }
+    // tr(S^-1): lane l solves L y = e_l (y_r = 0 for r < l) and adds
+    // M_ll ||y||^2, M_ll = sum_{q <= l} L_lq^2
+    double ss = 0.0, mll = 0.0;
+    {
+        double y[J];
+#pragma unroll
+        for (int r = 0; r < J; ++r) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < r; ++q) t = __builtin_fma(__shfl(b[q], r, G), y[q], t);
+            y[r] = (r < l) ? 0.0 : (r == l ? rinv[r] : -t * rinv[r]);
+            ss = __builtin_fma(y[r], y[r], ss);
+        }
+#pragma unroll
+        for (int q = 0; q < J; ++q)
+            if (q <= l) mll = __builtin_fma(b[q], b[q], mll);
+    }
+    double tr = (l < J) ? mll * ss : 0.0;
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) tr += __shfl_xor(tr, off, G);
     // L y = c
     double y = c;
 #pragma unroll
@@ -188,34 +252,36 @@ __global__ __launch_bounds__(256) void k_solve_grp(const double *__restrict__ bb
         const double ar = (__shfl(y, r, G) - t) * rinv[r];
         if (l == r) a = ar;
     }
-    float *arow = A + i * J;
-    if (!ok) {
-        if (l == 0) atomicAdd(bad, 1);         // row left unchanged
-        return;
+    const bool flag = !ok || !(tr <= f.cond_limit);      // uniform within the group
+    if (l == 0) {
+        if (f.rflag) f.rflag[i] = flag;
+        if (flag) flag_row(f, i, cnt);
     }
-    if (l < J) arow[l] = (float)a;
+    if (!flag && l < J) A[i * J + l] = (float)a;
 }
 
 // One row per lane for J <= 11: the packed system (J(J+1)/2 + J doubles)
 // lives in the lane's registers, with every index known at compile time, so
-// the factorisation and both substitutions are plain FMA chains with no
-// exchange between lanes; 64 rows per wavefront run side by side. The upper
-// triangle is overwritten by L^T (Cholesky, right-looking); same results,
-// failure rule and empty-row rule as k_solve_grp.
+// the factorisation, the condition estimate and both substitutions are plain
+// FMA chains with no exchange between lanes; 64 rows per wavefront run side by
+// side. The upper triangle is overwritten by L^T (Cholesky, right-looking; the
+// diagonal keeps the pivots L_kk^2); same results, flagging and empty-row
+// rule as k_solve.
 template <int J>
 __global__ __launch_bounds__(kWave) void k_solve_row(const double *__restrict__ bbuf,
                                                      const int64_t *__restrict__ rowptr,
                                                      int64_t I, double lambda,
-                                                     float *__restrict__ A,
-                                                     int32_t *__restrict__ bad) {
+                                                     float *__restrict__ A, SolveFlags f) {
     constexpr int T = J * (J + 1) / 2;
     constexpr int E = T + J;
     const int64_t i = (int64_t)blockIdx.x * kWave + threadIdx.x;
     if (i >= I) return;
     float *arow = A + i * J;
-    if (rowptr[i] == rowptr[i + 1]) {          // no entry: B = 0, c = 0 -> a = 0
+    const int64_t cnt = rowptr[i + 1] - rowptr[i];
+    if (cnt == 0) {                            // no entry: B = 0, c = 0 -> a = 0
 #pragma unroll
         for (int k = 0; k < J; ++k) arow[k] = 0.0f;
+        if (f.rflag) f.rflag[i] = 0;
         return;
     }
     const double *sys = bbuf + i * E;
@@ -244,6 +310,33 @@ __global__ __launch_bounds__(kWave) void k_solve_row(const double *__restrict__ 
                     __builtin_fma(-m[tri_pos(k, j, J)], m[tri_pos(k, q, J)], m[tri_pos(j, q, J)]);
         }
     }
+    // tr(S^-1) = sum_k M_kk ||L^-1 e_k||^2 with M_kk = L_kk^2 + sum_{q<k} L_kq^2
+    double tr = 0.0;
+#pragma unroll
+    for (int k = 0; k < J; ++k) {
+        double mkk = m[tri_pos(k, k, J)];
+#pragma unroll
+        for (int q = 0; q < k; ++q)
+            mkk = __builtin_fma(m[tri_pos(q, k, J)], m[tri_pos(q, k, J)], mkk);
+        double z[J];
+        z[k] = rinv[k];
+        double ss = z[k] * z[k];
+#pragma unroll
+        for (int r = k + 1; r < J; ++r) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = k; q < r; ++q) t = __builtin_fma(m[tri_pos(q, r, J)], z[q], t);
+            z[r] = -t * rinv[r];
+            ss = __builtin_fma(z[r], z[r], ss);
+        }
+        tr = __builtin_fma(mkk, ss, tr);
+    }
+    const bool flag = !ok || !(tr <= f.cond_limit);
+    if (f.rflag) f.rflag[i] = flag;
+    if (flag) {
+        flag_row(f, i, cnt);
+        return;
+    }
     // L y = c, then L^T a = y (L_rk at (k, r) of the upper triangle)
 #pragma unroll
     for (int r = 0; r < J; ++r) {
@@ -257,22 +350,18 @@ __global__ __launch_bounds__(kWave) void k_solve_row(const double *__restrict__ 
         for (int k = r + 1; k < J; ++k) y[r] = __builtin_fma(-m[tri_pos(r, k, J)], y[k], y[r]);
         y[r] *= rinv[r];
     }
-    if (!ok) {
-        atomicAdd(bad, 1);                     // row left unchanged
-        return;
-    }
 #pragma unroll
     for (int k = 0; k < J; ++k) arow[k] = (float)y[k];
 }
 
 hipError_t launch_solve(const double *bbuf, const int64_t *rowptr, int64_t I,
-                        int J, double lambda, float *A, int32_t *bad,
+                        int J, double lambda, float *A, const SolveFlags &f,
                         hipStream_t st) {
     if (I <= 0) return hipSuccess;
 #define PTK_SOLVE_ROW(j_)                                                           \
     if (J == j_) {                                                                  \
         hipLaunchKernelGGL(k_solve_row<j_>, dim3((unsigned)((I + kWave - 1) / kWave)), \
-                           dim3(kWave), 0, st, bbuf, rowptr, I, lambda, A, bad);    \
+                           dim3(kWave), 0, st, bbuf, rowptr, I, lambda, A, f);      \
         return hipGetLastError();                                                   \
     }
     PTK_SOLVE_ROW(3) PTK_SOLVE_ROW(4) PTK_SOLVE_ROW(5) PTK_SOLVE_ROW(7) PTK_SOLVE_ROW(8)
@@ -284,17 +373,17 @@ hipError_t launch_solve(const double *bbuf, const int64_t *rowptr, int64_t I,
         const int64_t rows_per_block = 256 / G;                                     \
         hipLaunchKernelGGL(k_solve_grp<j_>,                                         \
                            dim3((unsigned)((I + rows_per_block - 1) / rows_per_block)), \
-                           dim3(256), 0, st, bbuf, rowptr, I, lambda, A, bad);      \
+                           dim3(256), 0, st, bbuf, rowptr, I, lambda, A, f);        \
         return hipGetLastError();                                                   \
     }
     PTK_SOLVE_GRP(16)
 #undef PTK_SOLVE_GRP
-    const int E = sys_entries(J);
+    const int E = sys_entries(J) + J;       // the system and a work vector
     int bs = 64;
     while (bs > 8 && (size_t)E * bs * 8 > 64 * 1024) bs /= 2;
     const size_t lds = (size_t)E * bs * 8;
     hipLaunchKernelGGL(k_solve, dim3((unsigned)((I + bs - 1) / bs)), dim3(bs), lds,
-                       st, bbuf, rowptr, I, J, lambda, A, bad);
+                       st, bbuf, rowptr, I, J, lambda, A, f);
     return hipGetLastError();
 }
 
@@ -302,11 +391,16 @@ hipError_t launch_solve(const double *bbuf, const int64_t *rowptr, int64_t I,
 // row i, sum (x - a_i^T delta)^2 = sum x^2 - 2 a_i^T c_i + a_i^T B_i a_i, so
 // the squared error of eq. "reconfull" after the sweep is
 //     sum_Omega x^2 + sum_i (a_i^T B_i a_i - 2 a_i^T c_i)
-// with a_i the stored (float32) row. Per-block partial sums, FP64.
+// with a_i the stored (float32) row. A row solved by the least-squares path
+// (marked in rflag) adds rsse[i] instead: the same term, summed from its
+// entries' deltas, since its formed B_i is the inaccurate part. Per-block
+// partial sums, FP64.
 __global__ __launch_bounds__(256) void k_row_sse(const double *__restrict__ bbuf,
                                                  const int64_t *__restrict__ rowptr,
                                                  const float *__restrict__ A,
                                                  int64_t I, int J,
+                                                 const uint8_t *__restrict__ rflag,
+                                                 const double *__restrict__ rsse,
                                                  double *__restrict__ partial) {
     __shared__ double s_part[256 / kWave];
     const int T = J * (J + 1) / 2;
@@ -315,6 +409,10 @@ __global__ __launch_bounds__(256) void k_row_sse(const double *__restrict__ bbuf
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I;
          i += (int64_t)gridDim.x * blockDim.x) {
         if (rowptr[i] == rowptr[i + 1]) continue;
+        if (rflag && rflag[i]) {
+            acc += rsse[i];
+            continue;
+        }
         const double *sys = bbuf + i * E;
         const float *a = A + i * J;
         double q = 0.0;
@@ -342,6 +440,8 @@ __global__ __launch_bounds__(256) void k_row_sse_grp(const double *__restrict__ 
                                                      const int64_t *__restrict__ rowptr,
                                                      const float *__restrict__ A,
                                                      int64_t I,
+                                                     const uint8_t *__restrict__ rflag,
+                                                     const double *__restrict__ rsse,
                                                      double *__restrict__ partial) {
     constexpr int G = J <= 4 ? 4 : (J <= 8 ? 8 : 16);
     constexpr int T = J * (J + 1) / 2;
@@ -352,6 +452,10 @@ __global__ __launch_bounds__(256) void k_row_sse_grp(const double *__restrict__ 
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G; i < I; i += stride) {
         if (l >= J || rowptr[i] == rowptr[i + 1]) continue;
+        if (rflag && rflag[i]) {
+            if (l == 0) acc += rsse[i];
+            continue;
+        }
         const double *sys = bbuf + i * E;
         const float *a = A + i * J;
         double r = 0.0;
@@ -370,19 +474,19 @@ __global__ __launch_bounds__(256) void k_row_sse_grp(const double *__restrict__ 
 }
 
 hipError_t launch_row_sse(const double *bbuf, const int64_t *rowptr, const float *A,
-                          int64_t I, int J, double *partial, int nblocks,
-                          hipStream_t st) {
+                          int64_t I, int J, const uint8_t *rflag, const double *rsse,
+                          double *partial, int nblocks, hipStream_t st) {
 #define PTK_SSE_GRP(j_)                                                                  \
     if (J == j_) {                                                                       \
         hipLaunchKernelGGL(k_row_sse_grp<j_>, dim3(nblocks), dim3(256), 0, st, bbuf, rowptr, \
-                           A, I, partial);                                               \
+                           A, I, rflag, rsse, partial);                                  \
         return hipGetLastError();                                                        \
     }
     PTK_SSE_GRP(3) PTK_SSE_GRP(4) PTK_SSE_GRP(5) PTK_SSE_GRP(7) PTK_SSE_GRP(8)
     PTK_SSE_GRP(9) PTK_SSE_GRP(10) PTK_SSE_GRP(11) PTK_SSE_GRP(16)
 #undef PTK_SSE_GRP
     hipLaunchKernelGGL(k_row_sse, dim3(nblocks), dim3(256), 0, st, bbuf, rowptr, A, I, J,
-                       partial);
+                       rflag, rsse, partial);
     return hipGetLastError();
 }
 
