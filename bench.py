@@ -473,14 +473,18 @@ def main():
             ts = time.perf_counter()
             work = ctx.autotune(None)
             tune_s = time.perf_counter() - ts
+        statuses = []
         if args.warmup:
             ctx.iterate(args.warmup, p.lam, strict=False)
+            statuses.append(ctx.last_status)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         sse, loss = ctx.iterate(args.steps, p.lam, strict=False)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t1
+        statuses.append(ctx.last_status)
         not_pd = ctx.not_pd_count()
+        ls_rows, ls_max = ctx.solve_stats()
         core_left = int(torch.count_nonzero(core_run))
         # the model's error by a direct FP64 pass over all entries (untimed)
         _, rmse_direct, _ = ctx.recon_error(p.lam)
@@ -498,7 +502,10 @@ def main():
                 "not_pd": not_pd, "gram_ms": ms / max(calls, 1),
                 "value": p.nnz * args.steps / elapsed,
                 "rmse": float(rmse_direct), "work": work, "tune_s": tune_s,
-                "core_left": core_left,
+                "core_left": core_left, "ls_rows": ls_rows, "ls_max": ls_max,
+                "diverged": 8 in statuses,
+                "status": max(statuses, key=lambda v: v != 0),
+                "loss": [float(x) for x in loss],
                 "rmse_fused": float(np.sqrt(max(sse[-1], 0.0) / p.nnz))}
 
     main_prec = args.precision
@@ -572,6 +579,11 @@ def main():
         "rmse_after": r["rmse"],
         "rmse_after_fused": r["rmse_fused"],
         "not_pd_rows_timed": int(r["not_pd"]),
+        "least_squares_rows_timed": int(r["ls_rows"]),
+        "least_squares_max_entries": int(r["ls_max"]),
+        "iterate_status": int(r["status"]),
+        "loss_non_increasing": bool(all(b <= a * (1 + 1e-9)
+                                        for a, b in zip(r["loss"], r["loss"][1:]))),
         "kernel_ms": {k: v[1] / max(v[0], 1) for k, v in r["times"].items()},
     }
     if not args.no_variant:
@@ -604,6 +616,14 @@ def main():
                                                 and len(set(p.ranks)) == 1):
                 continue
             v = run(prec)
+            if v["diverged"]:
+                # the fit failed: no throughput is reported for it
+                variants[prec] = {"diverged": True, "status": "PTK_E_DIVERGED",
+                                  "rmse_after": v["rmse"],
+                                  "note": "error or loss not finite, or the loss rose: "
+                                          "not a usable form on this workload"}
+                log("%s: diverged (rmse %.6g), no throughput reported" % (prec, v["rmse"]))
+                continue
             variants[prec] = {"value": v["value"], "ms_per_step": 1e3 * v["elapsed"] / args.steps,
                               "gram_ms": v["gram_ms"], "rmse_after": v["rmse"],
                               "rmse_rel_to_main": v["rmse"] / r["rmse"] - 1.0}

@@ -22,6 +22,7 @@
 
 using namespace ptk;
 
+
 namespace {
 
 ptk_status fail(ptk_ctx *c, ptk_status s, const char *fmt, ...) {
@@ -130,6 +131,13 @@ void free_modes(ptk_ctx *c) {
     free_approx(c);
     c->bbuf = c->part = nullptr;
     c->part_cap = 0;
+    dfree(c->ls_hrow);
+    dfree(c->ls_hoff);
+    dfree(c->ls_htask);
+    dfree(c->ls_tri);
+    c->ls_hrow = c->ls_hoff = c->ls_htask = nullptr;
+    c->ls_tri = nullptr;
+    c->ls_hcap = c->ls_tcap = 0;
     c->nnz = -1;
 }
 
@@ -343,15 +351,22 @@ ptk_status update_mode_impl(ptk_ctx *c, int n, double lambda, int role = 0,
     const ModeData &m = c->md[n];
     SolveFlags f{};
     f.rflag = c->rflag;
+    f.cnt = c->ctr + 4 + 4 * n;
     f.list = c->lslist;
-    f.cnt = c->ctr + 4 + 2 * n;
     f.cap = c->max_rows;
+    f.hrow = c->ls_hrow;
+    f.hoff = c->ls_hoff;
+    f.htask = c->ls_htask;
+    f.hcap = c->ls_hcap;
+    f.tcap = c->ls_tcap;
+    f.task_len = kLsTaskLen;
+    f.pack = c->s.ranks[n] < kLsPack;
     f.cond_limit = c->opt.cond_limit > 0.0 ? c->opt.cond_limit : kCondLimitDefault;
     HIPCHK(c, timed(c, "solve", [&] {
         return launch_solve(c->bbuf, m.rowptr, c->s.dims[n], c->s.ranks[n], lambda,
                             c->fac[n], f, c->st);
     }));
-    ResolveArgs r{};
+    LsArgs r{};
     HIPCHK(c, ls_core(c, n, role, &r.gp));
     int t = 0, off = 0;
     for (int k = 0; k < c->s.N; ++k) {
@@ -367,14 +382,16 @@ ptk_status update_mode_impl(ptk_ctx *c, int n, double lambda, int role = 0,
     r.jn = c->s.ranks[n];
     r.val = m.vals;
     r.rowptr = m.rowptr;
-    r.list = f.list;
-    r.cnt = f.cnt;
-    r.cap = f.cap;
+    r.f = f;
+    r.tri = c->ls_tri;
     r.lambda = lambda;
     r.A = c->fac[n];
     r.rsse = want_rsse ? c->rsse : nullptr;
     r.stats = c->ctr;
-    HIPCHK(c, timed(c, "solve_ls", [&] { return launch_resolve(r, c->num_cu, c->st); }));
+    const bool fast = equal_ranks(c->s) && fast_available(c->s.N, c->s.ranks[n], kArithF64);
+    HIPCHK(c, timed(c, "solve_ls", [&] {
+        return launch_ls(r, c->s.N, fast, c->num_cu, c->st);
+    }));
     return PTK_OK;
 }
 
@@ -412,7 +429,7 @@ hipError_t zero_bad(ptk_ctx *c) {
 
 hipError_t zero_lists(ptk_ctx *c) {
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, c->ctr + 4, 0,
-                       (int64_t)2 * c->s.N);
+                       (int64_t)4 * c->s.N);
     return hipGetLastError();
 }
 
@@ -852,7 +869,7 @@ ptk_status ptk_create(ptk_ctx **out, int32_t N, const int64_t *dims_host,
     if (e == hipSuccess) e = dalloc(&c->lslist, (size_t)max_rows);
     if (e == hipSuccess) e = dalloc(&c->rflag, (size_t)max_rows);
     if (e == hipSuccess) e = dalloc(&c->rsse, (size_t)max_rows);
-    if (e == hipSuccess) e = dalloc(&c->fold_ls, 4);
+    if (e == hipSuccess) e = dalloc(&c->fold_ls, 8 + kFoldTasks);
     if (e == hipSuccess) e = dalloc(&c->xsq, 1);
     if (e == hipSuccess) e = dalloc(&c->scal, 4);
     if (e == hipSuccess) e = dalloc(&c->iter_ctr, 1);
@@ -1103,6 +1120,17 @@ ptk_status ptk_set_observed(ptk_ctx *c, int64_t nnz, const int32_t *idx,
         bbuf_elems = std::max(bbuf_elems, s.dims[n] * E);
     }
     HIPCHK(c, dalloc(&c->bbuf, bbuf_elems));
+    // least-squares solve: heavy rows, their tasks and the tasks' triangles
+    {
+        int jmax = 1;
+        for (int n = 0; n < s.N; ++n) jmax = std::max(jmax, (int)s.ranks[n]);
+        c->ls_hcap = std::min<int64_t>({nnz / kLsTaskLen + 1, c->max_rows, kLsMaxTasks});
+        c->ls_tcap = std::min<int64_t>(2 * (nnz / kLsTaskLen) + 1, kLsMaxTasks);
+        HIPCHK(c, dalloc(&c->ls_hrow, (size_t)c->ls_hcap));
+        HIPCHK(c, dalloc(&c->ls_hoff, (size_t)c->ls_hcap));
+        HIPCHK(c, dalloc(&c->ls_htask, (size_t)c->ls_tcap));
+        HIPCHK(c, dalloc(&c->ls_tri, (size_t)c->ls_tcap * jmax * (jmax + 1)));
+    }
     // sum of x^2 for the error identity of the fused pass
     if (nnz > 0) {
         HIPCHK(c, launch_sumsq(c->md[0].vals, nnz, c->red, kRedBlocks, c->st));
@@ -1419,14 +1447,13 @@ namespace {
 
 __global__ void k_fold_setup(int64_t *rowptr, int32_t *split, int64_t k,
                              int32_t nchunks, int32_t *ls) {
+    if (threadIdx.x < 4) ls[threadIdx.x] = 0;   // least-squares list counters
     if (threadIdx.x == 0) {
         rowptr[0] = 0;
         rowptr[1] = k;
         split[0] = 0;
         split[1] = 0;
         split[2] = nchunks - 1;
-        ls[1] = 0;          // light / heavy counts of the least-squares list
-        ls[2] = 0;
     }
 }
 
@@ -1434,9 +1461,24 @@ constexpr int64_t kFoldMaxChunks = 1024;
 
 }  // namespace
 
-extern "C" ptk_status ptk_fold_in(ptk_ctx *c, int32_t n, int64_t k, const int32_t *idx,
-                                  const float *val, double lambda, float *row_out) {
-    if (!c) return PTK_E_INVALID;
+namespace {
+
+// Device buffers of one fold-in: the row system, the partial systems of at
+// most max_chunks work ranges (reused for the least-squares tasks'
+// triangles), the row pointers, the merge list, and the least-squares lists
+// (8 + tasks ints).
+struct FoldBufs {
+    double *bbuf;
+    double *part;
+    int64_t max_chunks;
+    int64_t *rowptr;
+    int32_t *split;
+    int32_t *ls;
+    int64_t tasks;
+};
+
+ptk_status fold_check(ptk_ctx *c, int32_t n, int64_t k, const int32_t *idx, const float *val,
+                      double lambda, float *row_out) {
     if (n < 0 || n >= c->s.N) return fail(c, PTK_E_INVALID, "mode %d out of range", n);
     if (k < 0 || k >= (int64_t(1) << 31)) return fail(c, PTK_E_INVALID, "k out of range");
     if (!(lambda > 0.0) || !std::isfinite(lambda))
@@ -1444,20 +1486,22 @@ extern "C" ptk_status ptk_fold_in(ptk_ctx *c, int32_t n, int64_t k, const int32_
     if (!c->core) return fail(c, PTK_E_STATE, "no model bound (ptk_bind_model)");
     if (!row_out || (k > 0 && (!idx || !val)))
         return fail(c, PTK_E_INVALID, "null buffer");
+    return PTK_OK;
+}
+
+// The fold-in of eq. "rowupdate" on the given buffers: delta + Gram over
+// work ranges, merge, Cholesky solve, least-squares solve if flagged.
+// Kernels only; no allocation.
+ptk_status fold_in_impl(ptk_ctx *c, int32_t n, int64_t k, const int32_t *idx,
+                        const float *val, double lambda, float *row_out, const FoldBufs &b) {
     const int J = c->s.ranks[n];
     const int E = sys_entries(J);
-    if (!c->fold_bbuf) {
-        HIPCHK(c, dalloc(&c->fold_bbuf, (size_t)sys_entries(kMaxJ)));
-        HIPCHK(c, dalloc(&c->fold_part, (size_t)kFoldMaxChunks * 2 * sys_entries(kMaxJ)));
-        HIPCHK(c, dalloc(&c->fold_rowptr, 2));
-        HIPCHK(c, dalloc(&c->fold_split, 3));
-    }
     int64_t chunk = round_up((k + c->num_cu * 4 - 1) / (c->num_cu * 4), kWave);
     chunk = std::max<int64_t>(chunk, 4 * kWave);
-    while ((k + chunk - 1) / chunk > kFoldMaxChunks) chunk *= 2;
+    while ((k + chunk - 1) / chunk > b.max_chunks) chunk *= 2;
     const int64_t nchunks = (k + chunk - 1) / chunk;
-    hipLaunchKernelGGL(k_fold_setup, dim3(1), dim3(64), 0, c->st, c->fold_rowptr,
-                       c->fold_split, k, (int32_t)std::max<int64_t>(nchunks, 1), c->fold_ls);
+    hipLaunchKernelGGL(k_fold_setup, dim3(1), dim3(64), 0, c->st, b.rowptr, b.split, k,
+                       (int32_t)std::max<int64_t>(nchunks, 1), b.ls);
     HIPCHK(c, hipGetLastError());
     GramArgs a{};
     const int32_t *other[kMaxN];
@@ -1469,11 +1513,11 @@ extern "C" ptk_status ptk_fold_in(ptk_ctx *c, int32_t n, int64_t k, const int32_
     a.E = E;
     a.rows = nullptr;
     a.val = val;
-    a.rowptr = c->fold_rowptr;
+    a.rowptr = b.rowptr;
     a.nnz = k;
     a.chunk = chunk;
-    a.bbuf = c->fold_bbuf;
-    a.part = c->fold_part;
+    a.bbuf = b.bbuf;
+    a.part = b.part;
     const bool fast = equal_ranks(c->s) && fast_available(c->s.N, J, kArithF64);
     const Arith ar = (fast && c->opt.precision == PTK_PREC_FP32) ? kArithF32 : kArithF64;
     HIPCHK(c, timed(c, "permute_core", [&] {
@@ -1482,17 +1526,27 @@ extern "C" ptk_status ptk_fold_in(ptk_ctx *c, int32_t n, int64_t k, const int32_
     HIPCHK(c, timed(c, "fold_gram", [&] {
         return launch_gram(a, c->s, n, ar, nchunks, fast, c->st);
     }));
-    if (nchunks > 1)
-        HIPCHK(c, launch_merge(c->fold_part, c->fold_split, 1, E, c->fold_bbuf, c->st));
+    if (nchunks > 1) HIPCHK(c, launch_merge(b.part, b.split, 1, E, b.bbuf, c->st));
+    // the row's least-squares solve, if the Cholesky solve flags it: tasks
+    // long enough that at most b.tasks - 1 are needed, their triangles in
+    // part (free after the merge)
     SolveFlags f{};
-    f.list = c->fold_ls;                 // one slot: the row is light or heavy
-    f.cnt = c->fold_ls + 1;
+    f.cnt = b.ls;
+    f.list = b.ls + 4;
     f.cap = 1;
+    f.hrow = b.ls + 5;
+    f.hoff = b.ls + 6;
+    f.htask = b.ls + 8;
+    f.hcap = 1;
+    f.tcap = b.tasks;
+    f.task_len = (int32_t)std::max<int64_t>(
+        kLsTaskLen, round_up((k + b.tasks - 2) / (b.tasks - 1), kWave));
+    f.pack = J < kLsPack;
     f.cond_limit = c->opt.cond_limit > 0.0 ? c->opt.cond_limit : kCondLimitDefault;
     HIPCHK(c, timed(c, "fold_solve", [&] {
-        return launch_solve(c->fold_bbuf, c->fold_rowptr, 1, J, lambda, row_out, f, c->st);
+        return launch_solve(b.bbuf, b.rowptr, 1, J, lambda, row_out, f, c->st);
     }));
-    ResolveArgs r{};
+    LsArgs r{};
     if (ar == kArithF64) {
         r.gp = c->gp[n];
     } else {
@@ -1508,16 +1562,35 @@ extern "C" ptk_status ptk_fold_in(ptk_ctx *c, int32_t n, int64_t k, const int32_
     r.nother = a.nother;
     r.jn = J;
     r.val = val;
-    r.rowptr = c->fold_rowptr;
-    r.list = f.list;
-    r.cnt = f.cnt;
-    r.cap = 1;
+    r.rowptr = b.rowptr;
+    r.f = f;
+    r.tri = b.part;
     r.lambda = lambda;
     r.A = row_out;
     r.rsse = nullptr;
     r.stats = c->ctr;
-    HIPCHK(c, timed(c, "fold_solve_ls", [&] { return launch_resolve(r, c->num_cu, c->st); }));
+    HIPCHK(c, timed(c, "fold_solve_ls", [&] {
+        return launch_ls(r, c->s.N, fast, c->num_cu, c->st);
+    }));
     return PTK_OK;
+}
+
+}  // namespace
+
+extern "C" ptk_status ptk_fold_in(ptk_ctx *c, int32_t n, int64_t k, const int32_t *idx,
+                                  const float *val, double lambda, float *row_out) {
+    if (!c) return PTK_E_INVALID;
+    ptk_status s = fold_check(c, n, k, idx, val, lambda, row_out);
+    if (s != PTK_OK) return s;
+    if (!c->fold_bbuf) {
+        HIPCHK(c, dalloc(&c->fold_bbuf, (size_t)sys_entries(kMaxJ)));
+        HIPCHK(c, dalloc(&c->fold_part, (size_t)kFoldMaxChunks * 2 * sys_entries(kMaxJ)));
+        HIPCHK(c, dalloc(&c->fold_rowptr, 2));
+        HIPCHK(c, dalloc(&c->fold_split, 3));
+    }
+    const FoldBufs b{c->fold_bbuf, c->fold_part, kFoldMaxChunks, c->fold_rowptr,
+                     c->fold_split, c->fold_ls, kFoldTasks};
+    return fold_in_impl(c, n, k, idx, val, lambda, row_out, b);
 }
 
 extern "C" ptk_status ptk_kernel_times(ptk_ctx *c, int32_t *count, const char **names,

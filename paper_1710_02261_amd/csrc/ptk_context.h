@@ -13,7 +13,8 @@ namespace ptk {
 
 constexpr int kRedBlocks = 1024;   // blocks of the error / norm reductions
 constexpr int kSseBlocks = 8192;   // single-wave blocks of the direct error pass
-constexpr int kCtrSlots = 4 + 2 * kMaxN;
+constexpr int kCtrSlots = 4 + 4 * kMaxN;
+constexpr int kFoldTasks = 1025;   // heavy-task capacity of one fold-in row
 
 struct ModeData {
     int64_t *rowptr = nullptr;
@@ -98,18 +99,25 @@ struct ptk_ctx {
     int g_fuse = -1;
     // counters [kCtrSlots] int32: [0] rows left unsolved (or rank-deficient
     // factors of the final QR), [1] rows solved in least-squares form, [2] the
-    // most entries of such a row, [3] spare, [4 + 2n], [5 + 2n] light and heavy
-    // rows flagged in mode n (zeroed at the start of every iteration)
+    // most entries of such a row, [3] spare, [4 + 4n .. 7 + 4n] the packed,
+    // single and heavy rows and heavy tasks flagged in mode n (zeroed at the
+    // start of every iteration)
     int32_t *ctr = nullptr;
     int32_t *bad = nullptr;      // ctr + 0
     // rows handed to the least-squares solve: the list (max I_n), a flag byte
-    // per row and the rows' error terms (last mode of a fused-error iteration)
+    // per row, the rows' error terms (last mode of a fused-error iteration);
+    // heavy rows, their first tasks, the tasks and their triangles (sized at
+    // ptk_set_observed, see SolveFlags)
     int32_t *lslist = nullptr;
     uint8_t *rflag = nullptr;
     double *rsse = nullptr;
     int64_t max_rows = 0;
+    int32_t *ls_hrow = nullptr, *ls_hoff = nullptr, *ls_htask = nullptr;
+    double *ls_tri = nullptr;
+    int64_t ls_hcap = 0, ls_tcap = 0;
     int64_t last_not_pd = 0, last_ls_rows = 0, last_ls_max = 0;
-    // fold-in: list and counters of its one row
+    // fold-in: counters [4], list [1], heavy row and first task [2], spare,
+    // tasks [kFoldTasks]; its triangles go to fold_part
     int32_t *fold_ls = nullptr;
     int32_t last_iters = 0;      // iterations the last ptk_iterate ran
     double *host = nullptr;      // pinned results

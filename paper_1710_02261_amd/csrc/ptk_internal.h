@@ -149,16 +149,32 @@ hipError_t launch_merge(const double *part, const int32_t *split, int32_t nsplit
 // Rows the Cholesky solve hands to the least-squares solve (ptk_resolve.hip):
 // those whose factorisation broke down or whose scaled condition estimate
 // tr((D^-1/2 M D^-1/2)^-1), M = B_i + lambda I, D = diag(M), exceeds
-// cond_limit. Light rows (at most kLsLight entries) are appended at the front
-// of list, heavy rows at the back (list[cap - 1 - k]); cnt[0], cnt[1] count
-// them. rflag (optional, one byte per row) marks every flagged row.
-constexpr int64_t kLsLight = 256;
+// cond_limit. They are sorted by length into three lists:
+//  * packed: rows of at most kLsPack entries (with pack set), four per
+//    wavefront; list[0, cnt[0]);
+//  * single: other rows of at most task_len entries, one wavefront each;
+//    list[cap - 1 - k], k < cnt[1];
+//  * heavy: longer rows, cut into tasks of task_len entries (any wavefront
+//    takes any task) whose triangles a second kernel merges: hrow[h] / hoff[h]
+//    (first task), h < cnt[2]; htask[t] = h, t < cnt[3].
+// Capacities: cap >= rows. A heavy row whose tasks find no room in hcap /
+// tcap goes to the single list instead (with hcap >= nnz / task_len + 1 and
+// tcap >= 2 nnz / task_len + 1 every heavy row finds room). rflag (optional,
+// one byte per row) marks the flagged rows whose error term the
+// least-squares kernel supplies (packed and single rows).
+constexpr int kLsPack = 16;
+constexpr int32_t kLsTaskLen = 1024;
+constexpr int64_t kLsMaxTasks = 65536;
 constexpr double kCondLimitDefault = 1e9;
 struct SolveFlags {
     uint8_t *rflag;
-    int32_t *list;
     int32_t *cnt;
+    int32_t *list;
     int64_t cap;
+    int32_t *hrow, *hoff, *htask;
+    int64_t hcap, tcap;
+    int32_t task_len;
+    int32_t pack;
     double cond_limit;
 };
 hipError_t launch_solve(const double *bbuf, const int64_t *rowptr, int64_t I,
@@ -167,7 +183,7 @@ hipError_t launch_solve(const double *bbuf, const int64_t *rowptr, int64_t I,
 
 // Arguments of the least-squares row solve of the flagged rows (the entries
 // of mode n in grouped order, as for the row-system kernels).
-struct ResolveArgs {
+struct LsArgs {
     const void *gp;                   // FP64 permuted core of mode n
     const float *fac[kMaxN];
     const int32_t *oidx[kMaxN];
@@ -177,19 +193,20 @@ struct ResolveArgs {
     int32_t jn;
     const float *val;
     const int64_t *rowptr;
-    const int32_t *list;              // as SolveFlags
-    const int32_t *cnt;
-    int64_t cap;
+    SolveFlags f;                     // the lists the solve kernel filled
+    double *tri;                      // [tcap][jn][jn + 1] triangles of heavy tasks
     double lambda;
     float *A;                         // A^(n): the flagged rows are written
-    double *rsse;                     // optional: per flagged row i,
-                                      // sum over its entries of p (p - 2x),
+    double *rsse;                     // optional: for packed and single rows i,
+                                      // sum over the entries of p (p - 2x),
                                       // p = a_i^T delta (a_i as stored)
     int32_t *stats;                   // [0] rows left unsolved (result not
                                       // finite), [1] rows solved here,
                                       // [2] most entries of such a row
 };
-hipError_t launch_resolve(const ResolveArgs &a, int num_cu, hipStream_t st);
+// equal_fast: the (N, J) of an unrolled delta kernel with all ranks J
+hipError_t launch_ls(const LsArgs &a, int N, bool equal_fast, int num_cu,
+                     hipStream_t st);
 // rflag / rsse (optional): rows marked in rflag add rsse[i] instead of the
 // identity of their row system.
 hipError_t launch_row_sse(const double *bbuf, const int64_t *rowptr, const float *A,

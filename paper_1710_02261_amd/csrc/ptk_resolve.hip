@@ -5,275 +5,350 @@
 // squares problem
 //     min_a  sum_alpha (x_alpha - a^T delta_alpha)^2 + lambda ||a||^2,
 // i.e. of the stacked system [sqrt(lambda) I ; Delta] a ~ [0 ; x]. Forming
-// B_i = Delta^T Delta squares the conditioning: once ||B_i|| * 2^-52 is near
+// B_i = Delta^T Delta squares the conditioning: once ||B_i|| * 2^-52 nears
 // lambda the FP64 factorisation of B_i + lambda I is wrong or breaks down,
 // although the minimiser is unique and well defined. The solve kernels flag
-// such rows (breakdown, or a large scaled condition estimate); this kernel
-// solves them from the entries instead: it recomputes every entry's delta in
-// FP64 and builds the QR factorisation of the stacked system with Householder
-// reflections (Golub & Van Loan, Sec. 5.2), 64 entries at a time, then
-// back-substitutes. |R_jj| never falls below sqrt(lambda), so every row is
-// solved.
+// such rows (breakdown, or a large scaled condition estimate); these kernels
+// solve them from the entries instead: every entry's delta is recomputed in
+// FP64 (the unrolled contraction of the row-system kernels where the shape
+// has one) and the QR factorisation of the stacked system is built with
+// Householder reflections (Golub & Van Loan, Sec. 5.2), one chunk of entries
+// at a time, then back-substituted. |R_jj| never falls below sqrt(lambda), so
+// every row is solved.
 //
-// Layout of the triangle: lane q of a wavefront holds column q of [R | z]
+// Layout of a triangle: lane q of a segment holds column q of [R | z]
 // (column jn is z) in registers; lane l holds the delta row and value of one
-// entry of the chunk. Each reflection needs one wavefront sum per column.
+// entry of the chunk; each reflection needs one segment sum per column.
+// Segments are whole wavefronts, or 16-lane quarters for the packed rows.
 //
-// Light rows (at most kLsLight entries) take one wavefront each; heavy rows
-// take all W wavefronts of a workgroup, each reducing every W-th chunk into
-// its own triangle, merged in wavefront order (the rows of a triangle are fed
-// to the next one as entries). Results do not depend on the order in which
-// rows were flagged.
+// Work: k_ls takes, with every wavefront on its own, (1) the tasks of the
+// heavy rows: task_len entries each, reduced to a triangle in memory (the
+// first task of a row starts from sqrt(lambda) I, the others from 0); (2) the
+// single rows: a row per wavefront, solved and its error term summed in a
+// second pass; (3) the packed rows: four per wavefront, 16 lanes each, deltas
+// kept for the error term. k_ls_merge then merges the triangles of every
+// heavy row in task order (W wavefronts each merge every W-th one, then the
+// first merges the others in order) and back-substitutes. A row's result
+// depends only on its own entries, never on where it sits in the lists, so
+// the results do not depend on the order in which rows were flagged.
 #include "ptk_device.h"
 
 namespace ptk {
 
 namespace {
 
-// Sum over the wavefront; the butterfly gives every lane the same bits.
-__device__ __forceinline__ double wsum(double v) {
+// Sum over a segment of SEG lanes; the butterfly gives every lane the same
+// bits, and the same bits wherever the segment sits in the wavefront.
+template <int SEG>
+__device__ __forceinline__ double ssum(double v) {
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    for (int off = SEG / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, SEG);
     return v;
 }
 
 // Reflect one chunk of rows [d | x] (one per lane, zero rows allowed) into
-// the triangle rc (column-distributed, see above).
-template <int JMAX>
+// the segment's triangle rc; e is the lane's index within its segment.
+template <int JMAX, int SEG>
 __device__ __forceinline__ void ls_merge(double (&rc)[JMAX], double (&d)[JMAX], double &x,
-                                         int jn, int lane) {
+                                         int jn, int e) {
 #pragma unroll
     for (int j = 0; j < JMAX; ++j) {
         if (j >= jn) break;
         const double dj = d[j];
-        const double sig = wsum(dj * dj);
-        if (sig == 0.0) continue;              // nothing to annihilate in column j
-        const double alpha = __shfl(rc[j], j, kWave);
+        const double sig = ssum<SEG>(dj * dj);
+        const bool skip = !(sig > 0.0);        // nothing to annihilate in column j
+        const double alpha = __shfl(rc[j], j, SEG);
         const double mu = sqrt(alpha * alpha + sig);
         const double beta = alpha >= 0.0 ? -mu : mu;
         const double v0 = alpha - beta;        // |alpha| + mu: no cancellation
-        const double vtv = v0 * v0 + sig;
+        const double vtv = skip ? 1.0 : v0 * v0 + sig;
 #pragma unroll
         for (int q = j + 1; q < JMAX; ++q) {
             if (q >= jn) break;
-            const double s = wsum(dj * d[q]);
-            const double rjq = __shfl(rc[j], q, kWave);
-            const double f = 2.0 * (v0 * rjq + s) / vtv;
-            if (lane == q) rc[j] = rjq - f * v0;
+            const double s = ssum<SEG>(dj * d[q]);
+            const double rjq = __shfl(rc[j], q, SEG);
+            const double f = skip ? 0.0 : 2.0 * (v0 * rjq + s) / vtv;
+            if (e == q) rc[j] = rjq - f * v0;
             d[q] = __builtin_fma(-f, dj, d[q]);
         }
         {
-            const double s = wsum(dj * x);
-            const double rjz = __shfl(rc[j], jn, kWave);
-            const double f = 2.0 * (v0 * rjz + s) / vtv;
-            if (lane == jn) rc[j] = rjz - f * v0;
+            const double s = ssum<SEG>(dj * x);
+            const double rjz = __shfl(rc[j], jn, SEG);
+            const double f = skip ? 0.0 : 2.0 * (v0 * rjz + s) / vtv;
+            if (e == jn) rc[j] = rjz - f * v0;
             x = __builtin_fma(-f, dj, x);
         }
-        if (lane == j) rc[j] = beta;
+        if (e == j && !skip) rc[j] = beta;
         d[j] = 0.0;
     }
 }
 
-// R a = z; lane q < jn returns a_q.
-template <int JMAX>
-__device__ __forceinline__ double ls_back(const double (&rc)[JMAX], int jn, int lane) {
+// R a = z; lane q < jn of the segment returns a_q.
+template <int JMAX, int SEG>
+__device__ __forceinline__ double ls_back(const double (&rc)[JMAX], int jn, int e) {
     double aq = 0.0;
 #pragma unroll
     for (int j = JMAX - 1; j >= 0; --j) {
         if (j >= jn) continue;
-        const double t = wsum((lane > j && lane < jn) ? rc[j] * aq : 0.0);
-        const double zj = __shfl(rc[j], jn, kWave);
-        const double rjj = __shfl(rc[j], j, kWave);
+        const double t = ssum<SEG>((e > j && e < jn) ? rc[j] * aq : 0.0);
+        const double zj = __shfl(rc[j], jn, SEG);
+        const double rjj = __shfl(rc[j], j, SEG);
         const double aj = (zj - t) / rjj;
-        if (lane == j) aq = aj;
+        if (e == j) aq = aj;
     }
     return aq;
 }
 
-// delta (FP64) and value of entry pos of the row, or zeros past its end.
+// Initial triangle: diag I (sqrt(lambda) I, or 0), z = 0.
 template <int JMAX>
-__device__ __forceinline__ void chunk_rows(const ResolveArgs &a, int64_t pos, int64_t end,
-                                           float *arow, int lane, double (&d)[JMAX],
-                                           double &x) {
-    const bool valid = pos < end;
-    load_rows_generic<JMAX>(a, pos, valid, arow, lane);   // lane-private LDS
-    delta_generic<JMAX>(a, arow, lane, d);
+__device__ __forceinline__ void ls_init(double (&rc)[JMAX], double diag, int jn, int e) {
 #pragma unroll
-    for (int j = 0; j < JMAX; ++j)
-        if (!valid || j >= a.jn) d[j] = 0.0;
+    for (int p = 0; p < JMAX; ++p) rc[p] = (p == e && e < jn) ? diag : 0.0;
+}
+
+// delta (FP64) and value of the entry at pos, or zeros when !valid. NS, JS:
+// an unrolled shape (N, J) of the row-system kernels, or 0 for the generic
+// contraction. lds: the lane-private factor rows of this wavefront.
+template <int JMAX, int NS, int JS>
+__device__ __forceinline__ void entry_delta(const LsArgs &a, int64_t pos, bool valid,
+                                            float *lds, int lane, double (&d)[JMAX],
+                                            double &x) {
+    if constexpr (NS > 0) {
+        constexpr int NO = NS - 1;
+        constexpr int U = fast_depth(NS, JS);
+        double ain[U][JS];
+        load_rows_fast<NO, JS, U, double>(a, pos, valid, lds, lane, ain);
+        double out[JS];
+        delta_fast<NO, JS, U, double>(a.gp, lds, lane, ain, out);
+#pragma unroll
+        for (int j = 0; j < JMAX; ++j) d[j] = (valid && j < JS) ? out[j] : 0.0;
+    } else {
+        load_rows_generic<JMAX>(a, pos, valid, lds, lane);
+        delta_generic<JMAX>(a, lds, lane, d);
+#pragma unroll
+        for (int j = 0; j < JMAX; ++j)
+            if (!valid || j >= a.jn) d[j] = 0.0;
+    }
     x = valid ? (double)a.val[pos] : 0.0;
 }
 
-// Initial triangle of one wavefront: sqrt(lambda) I (or 0 for the helpers of
-// a heavy row), z = 0.
-template <int JMAX>
-__device__ __forceinline__ void ls_init(double (&rc)[JMAX], double diag, int jn, int lane) {
-#pragma unroll
-    for (int p = 0; p < JMAX; ++p) rc[p] = (p == lane && lane < jn) ? diag : 0.0;
-}
-
-// Write the stored (float) row, count the result; returns the stored value
-// of a_lane as a double (0 past jn), or NaN in every lane if not finite.
-__device__ __forceinline__ double ls_store(const ResolveArgs &a, int64_t i, double aq,
-                                           int lane, int64_t cnt) {
-    const bool fin = (lane >= a.jn) || isfinite(aq);
-    const bool all = __all(fin);
-    if (lane == 0) {
+// Count a solved row; write it if its result is finite (all lanes e < jn of
+// the segment). Returns the stored value of a_e as a double (0 for e >= jn),
+// or NaN when the row was left unsolved.
+template <int SEG>
+__device__ __forceinline__ double ls_store(const LsArgs &a, int64_t i, double aq, int e,
+                                           int lane, bool has, int64_t cnt) {
+    const bool fin = !has || e >= a.jn || isfinite(aq);
+    const unsigned long long m = __ballot(fin);
+    const int base = lane - e;
+    const unsigned long long seg =
+        SEG == 64 ? ~0ull : (((1ull << SEG) - 1ull) << base);
+    const bool all = (m & seg) == seg;
+    if (has && e == 0) {
         atomicAdd(&a.stats[all ? 1 : 0], 1);
         atomicMax(&a.stats[2], (int32_t)(cnt < INT32_MAX ? cnt : INT32_MAX));
     }
     if (!all) return __builtin_nan("");
     const float af = (float)aq;
-    if (lane < a.jn) a.A[i * a.jn + lane] = af;
-    return lane < a.jn ? (double)af : 0.0;
-}
-
-// Sum over the chunks c = first, first + step, ... of the row of p (p - 2x),
-// p = a^T delta with a_j held by lane j (af).
-template <int JMAX>
-__device__ __forceinline__ double ls_error(const ResolveArgs &a, int64_t r0, int64_t r1,
-                                           int64_t first, int64_t step, double af,
-                                           float *arow, int lane) {
-    double acc = 0.0;
-    for (int64_t c0 = r0 + first * kWave; c0 < r1; c0 += step * kWave) {
-        double d[JMAX], x;
-        chunk_rows<JMAX>(a, c0 + lane, r1, arow, lane, d, x);
-        double p = 0.0;
-#pragma unroll
-        for (int j = 0; j < JMAX; ++j)
-            if (j < a.jn) p = __builtin_fma(__shfl(af, j, kWave), d[j], p);
-        acc += wsum(p * (p - 2.0 * x));
-    }
-    return acc;
+    if (has && e < a.jn) a.A[i * a.jn + e] = af;
+    return e < a.jn ? (double)af : 0.0;
 }
 
 }  // namespace
 
-// W wavefronts per workgroup; dynamic LDS: W * (sum_k J_k) * 64 floats of
-// factor rows, then W * JMAX * (JMAX + 1) doubles of triangles, then W + 1
-// doubles of partial errors.
-template <int JMAX, int W>
-__global__ __launch_bounds__(kWave *W) void k_resolve(ResolveArgs a) {
+template <int JMAX, int NS, int JS>
+__global__ __launch_bounds__(kWave) void k_ls(LsArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
-    int sumj = 0;
-    for (int k = 0; k < a.nother; ++k) sumj += a.jk[k];
-    const int lane = threadIdx.x % kWave;
-    const int w = threadIdx.x / kWave;
-    float *arow = (float *)s_dyn + (size_t)w * sumj * kWave;
-    double *s_tri = (double *)(s_dyn + (((size_t)W * sumj * kWave * 4 + 15) / 16) * 16);
-    double *s_err = s_tri + (size_t)W * JMAX * (JMAX + 1);
-    const double sl = sqrt(a.lambda);
+    float *lds = (float *)s_dyn;
+    const int lane = threadIdx.x;
     const int jn = a.jn;
+    const double sl = sqrt(a.lambda);
+    const int64_t gw = blockIdx.x, nw = gridDim.x;
+    const SolveFlags &f = a.f;
+    const int64_t L = f.task_len;
 
-    // heavy rows: one workgroup per row
-    const int nheavy = a.cnt[1];
-    for (int h = blockIdx.x; h < nheavy; h += gridDim.x) {
-        const int64_t i = a.list[a.cap - 1 - h];
-        const int64_t r0 = a.rowptr[i], r1 = a.rowptr[i + 1];
+    // (1) tasks of heavy rows: a triangle per task
+    const int64_t ntask = min((int64_t)f.cnt[3], f.tcap);
+    for (int64_t t = gw; t < ntask; t += nw) {
+        const int h = f.htask[t];
+        if (h < 0) continue;
+        const int64_t i = f.hrow[h];
+        const int64_t q = t - f.hoff[h];
+        const int64_t r1row = a.rowptr[i + 1];
+        const int64_t r0 = a.rowptr[i] + q * L;
+        const int64_t r1 = min(r0 + L, r1row);
         double rc[JMAX];
-        ls_init<JMAX>(rc, w == 0 ? sl : 0.0, jn, lane);
-        for (int64_t c0 = r0 + (int64_t)w * kWave; c0 < r1; c0 += (int64_t)W * kWave) {
+        ls_init<JMAX>(rc, q == 0 ? sl : 0.0, jn, lane);
+        for (int64_t c0 = r0; c0 < r1; c0 += kWave) {
             double d[JMAX], x;
-            chunk_rows<JMAX>(a, c0 + lane, r1, arow, lane, d, x);
-            ls_merge<JMAX>(rc, d, x, jn, lane);
+            entry_delta<JMAX, NS, JS>(a, c0 + lane, c0 + lane < r1, lds, lane, d, x);
+            ls_merge<JMAX, kWave>(rc, d, x, jn, lane);
         }
-        // helpers hand their triangles over, row p of [R | z] at s_tri[w][p][*]
-        double *mine = s_tri + (size_t)w * JMAX * (JMAX + 1);
-        if (w > 0 && lane <= jn) {
+        double *tri = a.tri + t * (int64_t)jn * (jn + 1);
+        if (lane <= jn) {
 #pragma unroll
             for (int p = 0; p < JMAX; ++p)
-                if (p < jn) mine[p * (JMAX + 1) + lane] = rc[p];
+                if (p < jn) tri[p * (jn + 1) + lane] = rc[p];
         }
-        __syncthreads();
-        double aq = 0.0;
-        if (w == 0) {
-            for (int v = 1; v < W; ++v) {
-                const double *t = s_tri + (size_t)v * JMAX * (JMAX + 1);
-                double d[JMAX], x = 0.0;
-#pragma unroll
-                for (int q = 0; q < JMAX; ++q)
-                    d[q] = (lane < jn && q < jn) ? t[lane * (JMAX + 1) + q] : 0.0;
-                if (lane < jn) x = t[lane * (JMAX + 1) + jn];
-                ls_merge<JMAX>(rc, d, x, jn, lane);
-            }
-            aq = ls_back<JMAX>(rc, jn, lane);
-            const double af = ls_store(a, i, aq, lane, r1 - r0);
-            if (lane < JMAX) s_tri[lane] = af;        // hand the stored row over
-        }
-        __syncthreads();
-        if (a.rsse) {
-            const double af = lane < JMAX ? s_tri[lane] : 0.0;
-            double e = 0.0;
-            if (!isnan(af) && !isnan(s_tri[0]))
-                e = ls_error<JMAX>(a, r0, r1, w, W, af, arow, lane);
-            else
-                e = __builtin_nan("");
-            if (lane == 0) s_err[w] = e;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                double t = 0.0;
-                for (int v = 0; v < W; ++v) t += s_err[v];
-                a.rsse[i] = t;
-            }
-        }
-        __syncthreads();
     }
 
-    // light rows: one wavefront per row
-    const int nlight = a.cnt[0];
-    for (int t = blockIdx.x * W + w; t < nlight; t += gridDim.x * W) {
-        const int64_t i = a.list[t];
+    // (2) single rows: a row per wavefront, error term in a second pass
+    const int64_t nsingle = f.cnt[1];
+    for (int64_t s = gw; s < nsingle; s += nw) {
+        const int64_t i = f.list[f.cap - 1 - s];
         const int64_t r0 = a.rowptr[i], r1 = a.rowptr[i + 1];
         double rc[JMAX];
         ls_init<JMAX>(rc, sl, jn, lane);
         for (int64_t c0 = r0; c0 < r1; c0 += kWave) {
             double d[JMAX], x;
-            chunk_rows<JMAX>(a, c0 + lane, r1, arow, lane, d, x);
-            ls_merge<JMAX>(rc, d, x, jn, lane);
+            entry_delta<JMAX, NS, JS>(a, c0 + lane, c0 + lane < r1, lds, lane, d, x);
+            ls_merge<JMAX, kWave>(rc, d, x, jn, lane);
         }
-        const double aq = ls_back<JMAX>(rc, jn, lane);
-        const double af = ls_store(a, i, aq, lane, r1 - r0);
+        const double af = ls_store<kWave>(a, i, ls_back<JMAX, kWave>(rc, jn, lane), lane,
+                                          lane, true, r1 - r0);
         if (a.rsse) {
-            const double e = isnan(__shfl(af, 0, kWave))
-                                 ? __builtin_nan("")
-                                 : ls_error<JMAX>(a, r0, r1, 0, 1, af, arow, lane);
-            if (lane == 0) a.rsse[i] = e;
+            double acc = 0.0;
+            if (isnan(__shfl(af, 0, kWave))) {
+                acc = __builtin_nan("");
+            } else {
+                for (int64_t c0 = r0; c0 < r1; c0 += kWave) {
+                    double d[JMAX], x;
+                    entry_delta<JMAX, NS, JS>(a, c0 + lane, c0 + lane < r1, lds, lane, d, x);
+                    double pr = 0.0;
+#pragma unroll
+                    for (int j = 0; j < JMAX; ++j)
+                        if (j < jn) pr = __builtin_fma(__shfl(af, j, kWave), d[j], pr);
+                    acc += ssum<kWave>(pr * (pr - 2.0 * x));
+                }
+            }
+            if (lane == 0) a.rsse[i] = acc;
         }
+    }
+
+    // (3) packed rows: four per wavefront, 16 lanes each
+    if (f.pack) {
+        constexpr int SEG = kLsPack;
+        const int64_t npack = f.cnt[0];
+        const int slot = lane / SEG, e = lane % SEG;
+        for (int64_t g = gw; g * 4 < npack; g += nw) {
+            const int64_t t = g * 4 + slot;
+            const bool has = t < npack;
+            const int64_t i = has ? f.list[t] : 0;
+            const int64_t r0 = has ? a.rowptr[i] : 0, r1 = has ? a.rowptr[i + 1] : 0;
+            double d[JMAX], x;
+            entry_delta<JMAX, NS, JS>(a, r0 + e, r0 + e < r1, lds, lane, d, x);
+            double d0[JMAX];
+#pragma unroll
+            for (int j = 0; j < JMAX; ++j) d0[j] = d[j];
+            const double x0 = x;
+            double rc[JMAX];
+            ls_init<JMAX>(rc, sl, jn, e);
+            ls_merge<JMAX, SEG>(rc, d, x, jn, e);
+            const double af = ls_store<SEG>(a, i, ls_back<JMAX, SEG>(rc, jn, e), e, lane, has,
+                                            r1 - r0);
+            if (a.rsse) {
+                double pr = 0.0;
+#pragma unroll
+                for (int j = 0; j < JMAX; ++j)
+                    if (j < jn) pr = __builtin_fma(__shfl(af, j, SEG), d0[j], pr);
+                const double acc = ssum<SEG>(pr * (pr - 2.0 * x0));
+                if (has && e == 0) a.rsse[i] = acc;     // NaN when unsolved
+            }
+        }
+    }
+}
+
+// Merge the task triangles of every heavy row (W wavefronts per row, in task
+// order) and back-substitute.
+template <int JMAX, int W>
+__global__ __launch_bounds__(kWave *W) void k_ls_merge(LsArgs a) {
+    __shared__ double s_tri[W][JMAX][JMAX + 1];
+    const int lane = threadIdx.x % kWave;
+    const int w = threadIdx.x / kWave;
+    const int jn = a.jn;
+    const SolveFlags &f = a.f;
+    const int64_t nheavy = min((int64_t)f.cnt[2], f.hcap);
+    for (int64_t h = blockIdx.x; h < nheavy; h += gridDim.x) {
+        const int64_t i = f.hrow[h];
+        if (i < 0) continue;
+        const int64_t cnt = a.rowptr[i + 1] - a.rowptr[i];
+        const int64_t t0 = f.hoff[h];
+        const int64_t nt = (cnt + f.task_len - 1) / f.task_len;
+        double rc[JMAX];
+        ls_init<JMAX>(rc, 0.0, jn, lane);
+        for (int64_t k = w; k < nt; k += W) {
+            const double *tri = a.tri + (t0 + k) * (int64_t)jn * (jn + 1);
+            double d[JMAX], x = 0.0;
+#pragma unroll
+            for (int q = 0; q < JMAX; ++q)
+                d[q] = (lane < jn && q < jn) ? tri[lane * (jn + 1) + q] : 0.0;
+            if (lane < jn) x = tri[lane * (jn + 1) + jn];
+            ls_merge<JMAX, kWave>(rc, d, x, jn, lane);
+        }
+        if (w > 0 && lane <= jn) {
+#pragma unroll
+            for (int p = 0; p < JMAX; ++p)
+                if (p < jn) s_tri[w][p][lane] = rc[p];
+        }
+        __syncthreads();
+        if (w == 0) {
+            for (int v = 1; v < W; ++v) {
+                double d[JMAX], x = 0.0;
+#pragma unroll
+                for (int q = 0; q < JMAX; ++q)
+                    d[q] = (lane < jn && q < jn) ? s_tri[v][lane][q] : 0.0;
+                if (lane < jn) x = s_tri[v][lane][jn];
+                ls_merge<JMAX, kWave>(rc, d, x, jn, lane);
+            }
+            (void)ls_store<kWave>(a, i, ls_back<JMAX, kWave>(rc, jn, lane), lane, lane, true,
+                                  cnt);
+        }
+        __syncthreads();
     }
 }
 
 namespace {
 
-template <int JMAX, int W>
-size_t resolve_lds(int sumj) {
-    return (((size_t)W * sumj * kWave * 4 + 15) / 16) * 16 +
-           (size_t)W * JMAX * (JMAX + 1) * 8 + (W + 1) * 8;
-}
-
-template <int JMAX>
-hipError_t launch_resolve_j(const ResolveArgs &a, int num_cu, hipStream_t st) {
+size_t ls_lds(const LsArgs &a, int N, bool fast) {
+    if (fast) {
+        const int J = a.jn;
+        const int nout = (N - 1) - fast_depth(N, J);
+        return (size_t)(nout > 0 ? nout : 1) * J * kWave * 4;
+    }
     int sumj = 0;
     for (int k = 0; k < a.nother; ++k) sumj += a.jk[k];
-    const dim3 grid((unsigned)(2 * num_cu));
-    const size_t l4 = resolve_lds<JMAX, 4>(sumj), l2 = resolve_lds<JMAX, 2>(sumj),
-                 l1 = resolve_lds<JMAX, 1>(sumj);
-    if (l4 <= 64 * 1024)
-        hipLaunchKernelGGL((k_resolve<JMAX, 4>), grid, dim3(4 * kWave), l4, st, a);
-    else if (l2 <= 64 * 1024)
-        hipLaunchKernelGGL((k_resolve<JMAX, 2>), grid, dim3(2 * kWave), l2, st, a);
-    else
-        hipLaunchKernelGGL((k_resolve<JMAX, 1>), grid, dim3(kWave), l1, st, a);
+    return (size_t)sumj * kWave * 4;
+}
+
+template <int JMAX, int NS, int JS>
+hipError_t launch_ls_t(const LsArgs &a, size_t lds, int num_cu, hipStream_t st) {
+    hipLaunchKernelGGL((k_ls<JMAX, NS, JS>), dim3((unsigned)(16 * num_cu)), dim3(kWave),
+                       lds, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    constexpr int W = JMAX <= 16 ? 8 : 4;
+    hipLaunchKernelGGL((k_ls_merge<JMAX, W>), dim3((unsigned)(2 * num_cu)), dim3(kWave * W),
+                       0, st, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_resolve(const ResolveArgs &a, int num_cu, hipStream_t st) {
-    const int jn = a.jn;
-    if (jn <= 4) return launch_resolve_j<4>(a, num_cu, st);
-    if (jn <= 8) return launch_resolve_j<8>(a, num_cu, st);
-    if (jn <= 16) return launch_resolve_j<16>(a, num_cu, st);
-    return launch_resolve_j<32>(a, num_cu, st);
+hipError_t launch_ls(const LsArgs &a, int N, bool equal_fast, int num_cu, hipStream_t st) {
+    const int J = a.jn;
+    const size_t lds = ls_lds(a, N, equal_fast);
+    if (equal_fast) {
+#define PTK_X(n_, j_) \
+    if (N == n_ && J == j_) return launch_ls_t<j_, n_, j_>(a, lds, num_cu, st);
+        PTK_X(3, 3) PTK_X(3, 4) PTK_X(3, 5) PTK_X(3, 7) PTK_X(3, 8) PTK_X(3, 9)
+        PTK_X(3, 10) PTK_X(3, 11) PTK_X(3, 16) PTK_X(4, 3) PTK_X(4, 5) PTK_X(4, 8)
+        PTK_X(4, 10) PTK_X(5, 3) PTK_X(5, 5) PTK_X(5, 8)
+#undef PTK_X
+    }
+    if (J <= 4) return launch_ls_t<4, 0, 0>(a, lds, num_cu, st);
+    if (J <= 8) return launch_ls_t<8, 0, 0>(a, lds, num_cu, st);
+    if (J <= 16) return launch_ls_t<16, 0, 0>(a, lds, num_cu, st);
+    return launch_ls_t<32, 0, 0>(a, lds, num_cu, st);
 }
 
 }  // namespace ptk

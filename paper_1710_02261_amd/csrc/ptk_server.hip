@@ -109,6 +109,11 @@ ptk_status sfail(ptk_server *sv, ptk_status s, const std::string &msg) {
     return s;
 }
 
+// Least-squares lists of a group of q fold-in rows over P entries: counters
+// [4], the row list [q], heavy rows and first tasks [2q], tasks [tcap].
+int64_t ls_tcap(int64_t P) { return 2 * (P / kLsTaskLen) + 1; }
+int64_t ls_ints(int64_t q, int64_t P) { return 4 + 3 * q + ls_tcap(P); }
+
 size_t request_bytes(const ptk_server *sv, const Request &r) {
     const int N = sv->s.N;
     if (r.kind == 1) return align_up((size_t)r.count * (4 * N + 4)) + 2 * kAlign;
@@ -117,7 +122,7 @@ size_t request_bytes(const ptk_server *sv, const Request &r) {
     const size_t P = (size_t)((r.count + kSeg - 1) / kSeg * kSeg);
     const size_t chunks = P / kSeg;
     return P * (4 * (N - 1) + 8) + J * 4 + E * 8 + chunks * 2 * E * 8 + chunks * 12 +
-           16 + 12 + 9 * kAlign;
+           16 + ls_ints(1, (int64_t)P) * 4 + 9 * kAlign;
 }
 
 // Bump allocator over a slot's arena (same offsets in staging and device).
@@ -143,7 +148,7 @@ hipError_t launch_batch(ptk_server *sv, Slot &sl) {
         std::vector<size_t> ri;         // indices into sl.reqs
         int64_t P = 0;
         size_t o_oidx = 0, o_val = 0, o_rows = 0, o_rowptr = 0, o_split = 0;
-        size_t o_ls = 0;                // least-squares counters [2] + list [q]
+        size_t o_ls = 0;                // least-squares lists (ls_ints)
         size_t o_bbuf = 0, o_part = 0, o_out = 0;
         int32_t nsplit = 0;
     };
@@ -174,7 +179,7 @@ hipError_t launch_batch(ptk_server *sv, Slot &sl) {
         g.o_rows = L.take((size_t)g.P * 4);
         g.o_rowptr = L.take((size_t)(q + 2) * 8);
         g.o_split = L.take((size_t)(g.P / kSeg + 1) * 12);
-        g.o_ls = L.take((size_t)(q + 2) * 4);
+        g.o_ls = L.take((size_t)ls_ints(q, g.P) * 4);
     }
     const size_t o_pidx = L.take((size_t)N * M * 4);
     const size_t in_end = L.off;
@@ -228,8 +233,7 @@ hipError_t launch_batch(ptk_server *sv, Slot &sl) {
         rowptr[q] = pos;
         rowptr[q + 1] = pos;
         int32_t *ls = (int32_t *)(H + g.o_ls);
-        ls[0] = 0;                      // no row flagged yet
-        ls[1] = 0;
+        for (int k = 0; k < 4; ++k) ls[k] = 0;      // no row flagged yet
     }
     {
         int32_t *pidx = (int32_t *)(H + o_pidx);
@@ -281,16 +285,26 @@ hipError_t launch_batch(ptk_server *sv, Slot &sl) {
         if (e == hipSuccess)
             e = launch_merge(a.part, (const int32_t *)(D + g.o_split), g.nsplit, a.E, a.bbuf,
                              sl.st);
+        // rows whose Cholesky solve would be inaccurate go to the
+        // least-squares form; the triangles of their tasks reuse part (free
+        // after the merge: (P / kSeg + 1) * 2 * E doubles >= ls_tcap(P) * J * (J + 1))
         SolveFlags f{};
-        f.cnt = (int32_t *)(D + g.o_ls);
-        f.list = f.cnt + 2;
+        int32_t *ls = (int32_t *)(D + g.o_ls);
+        f.cnt = ls;
+        f.list = ls + 4;
         f.cap = q;
+        f.hrow = ls + 4 + q;
+        f.hoff = ls + 4 + 2 * q;
+        f.htask = ls + 4 + 3 * q;
+        f.hcap = q;
+        f.tcap = ls_tcap(g.P);
+        f.task_len = kLsTaskLen;
+        f.pack = J < kLsPack;
         f.cond_limit = c->opt.cond_limit > 0.0 ? c->opt.cond_limit : kCondLimitDefault;
         if (e == hipSuccess)
             e = launch_solve(a.bbuf, a.rowptr, q, J, sv->opt.lambda, out, f, sl.st);
         if (e == hipSuccess) {
-            // rows whose Cholesky solve would be inaccurate: least-squares form
-            ResolveArgs r{};
+            LsArgs r{};
             r.gp = a.gp;
             for (int k = 0; k < N - 1; ++k) {
                 r.fac[k] = a.fac[k];
@@ -302,14 +316,13 @@ hipError_t launch_batch(ptk_server *sv, Slot &sl) {
             r.jn = J;
             r.val = a.val;
             r.rowptr = a.rowptr;
-            r.list = f.list;
-            r.cnt = f.cnt;
-            r.cap = q;
+            r.f = f;
+            r.tri = a.part;
             r.lambda = sv->opt.lambda;
             r.A = out;
             r.rsse = nullptr;
             r.stats = sl.bad;
-            e = launch_resolve(r, c->num_cu, sl.st);
+            e = launch_ls(r, N, sv->fast[n], c->num_cu, sl.st);
         }
     }
     if (e == hipSuccess && M > 0) {

@@ -12,17 +12,38 @@
 // per row); cond(S) lies within a factor J of it either way. A row whose
 // factorisation breaks down, or whose tr(S^-1) exceeds the limit, is not
 // written: it is flagged and handed to the least-squares solve of
-// ptk_resolve.hip, which works from the entries and needs no formed B_i.
+// ptk_resolve.hip, which works from the entries and needs no formed B_i
+// (the lists it fills are described with SolveFlags).
 #include "ptk_internal.h"
 
 namespace ptk {
 
-// Hand row i over to the least-squares solve (one caller per row).
-__device__ __forceinline__ void flag_row(const SolveFlags &f, int64_t i, int64_t cnt) {
-    if (cnt <= kLsLight)
+// Hand row i over to the least-squares solve (one caller per row). Returns
+// whether that solve supplies the row's error term (packed and single rows).
+__device__ __forceinline__ bool flag_row(const SolveFlags &f, int64_t i, int64_t cnt) {
+    if (f.pack && cnt <= kLsPack) {
         f.list[atomicAdd(&f.cnt[0], 1)] = (int32_t)i;
-    else
+        return true;
+    }
+    if (cnt <= f.task_len || !f.hrow) {
         f.list[f.cap - 1 - atomicAdd(&f.cnt[1], 1)] = (int32_t)i;
+        return true;
+    }
+    const int64_t nt = (cnt + f.task_len - 1) / f.task_len;
+    const int64_t h = atomicAdd(&f.cnt[2], 1);
+    const int64_t t0 = atomicAdd(&f.cnt[3], (int32_t)nt);
+    if (h < f.hcap && t0 + nt <= f.tcap) {
+        f.hrow[h] = (int32_t)i;
+        f.hoff[h] = (int32_t)t0;
+        for (int64_t t = t0; t < t0 + nt; ++t) f.htask[t] = (int32_t)h;
+        return false;
+    }
+    // no room for its tasks: the reservation is voided and the row goes to
+    // the single list (one wavefront for the whole row: slower, same result)
+    if (h < f.hcap) f.hrow[h] = -1;
+    for (int64_t t = t0; t < t0 + nt && t < f.tcap; ++t) f.htask[t] = -1;
+    f.list[f.cap - 1 - atomicAdd(&f.cnt[1], 1)] = (int32_t)i;
+    return true;
 }
 
 // Merge the partial systems of rows that cross work-range boundaries:
@@ -137,11 +158,9 @@ __global__ void k_solve(const double *__restrict__ bbuf,
         }
     }
     const bool flag = !ok || !(tr <= f.cond_limit);
-    if (f.rflag) f.rflag[i] = flag;
-    if (flag) {
-        flag_row(f, i, cnt);
-        return;
-    }
+    const bool own_error = flag && flag_row(f, i, cnt);
+    if (f.rflag) f.rflag[i] = own_error;
+    if (flag) return;
     double *y = m + T * bs;                // rhs c, overwritten by y then a
     for (int r = 0; r < J; ++r) {          // L y = c
         double s = y[r * bs];
@@ -254,8 +273,8 @@ __global__ __launch_bounds__(256) void k_solve_grp(const double *__restrict__ bb
     }
     const bool flag = !ok || !(tr <= f.cond_limit);      // uniform within the group
     if (l == 0) {
-        if (f.rflag) f.rflag[i] = flag;
-        if (flag) flag_row(f, i, cnt);
+        const bool own_error = flag && flag_row(f, i, cnt);
+        if (f.rflag) f.rflag[i] = own_error;
     }
     if (!flag && l < J) A[i * J + l] = (float)a;
 }
@@ -332,11 +351,9 @@ __global__ __launch_bounds__(kWave) void k_solve_row(const double *__restrict__ 
         tr = __builtin_fma(mkk, ss, tr);
     }
     const bool flag = !ok || !(tr <= f.cond_limit);
-    if (f.rflag) f.rflag[i] = flag;
-    if (flag) {
-        flag_row(f, i, cnt);
-        return;
-    }
+    const bool own_error = flag && flag_row(f, i, cnt);
+    if (f.rflag) f.rflag[i] = own_error;
+    if (flag) return;
     // L y = c, then L^T a = y (L_rk at (k, r) of the upper triangle)
 #pragma unroll
     for (int r = 0; r < J; ++r) {
@@ -393,8 +410,8 @@ hipError_t launch_solve(const double *bbuf, const int64_t *rowptr, int64_t I,
 //     sum_Omega x^2 + sum_i (a_i^T B_i a_i - 2 a_i^T c_i)
 // with a_i the stored (float32) row. A row solved by the least-squares path
 // (marked in rflag) adds rsse[i] instead: the same term, summed from its
-// entries' deltas, since its formed B_i is the inaccurate part. Per-block
-// partial sums, FP64.
+// entries' deltas. (Heavy flagged rows keep the identity, evaluated with
+// their accurate a_i.) Per-block partial sums, FP64.
 __global__ __launch_bounds__(256) void k_row_sse(const double *__restrict__ bbuf,
                                                  const int64_t *__restrict__ rowptr,
                                                  const float *__restrict__ A,
