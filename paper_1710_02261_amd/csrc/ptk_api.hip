@@ -133,9 +133,8 @@ void free_modes(ptk_ctx *c) {
     c->part_cap = 0;
     dfree(c->ls_hrow);
     dfree(c->ls_hoff);
-    dfree(c->ls_htask);
     dfree(c->ls_tri);
-    c->ls_hrow = c->ls_hoff = c->ls_htask = nullptr;
+    c->ls_hrow = c->ls_hoff = nullptr;
     c->ls_tri = nullptr;
     c->ls_hcap = c->ls_tcap = 0;
     c->nnz = -1;
@@ -356,7 +355,6 @@ ptk_status update_mode_impl(ptk_ctx *c, int n, double lambda, int role = 0,
     f.cap = c->max_rows;
     f.hrow = c->ls_hrow;
     f.hoff = c->ls_hoff;
-    f.htask = c->ls_htask;
     f.hcap = c->ls_hcap;
     f.tcap = c->ls_tcap;
     f.task_len = kLsTaskLen;
@@ -869,7 +867,7 @@ ptk_status ptk_create(ptk_ctx **out, int32_t N, const int64_t *dims_host,
     if (e == hipSuccess) e = dalloc(&c->lslist, (size_t)max_rows);
     if (e == hipSuccess) e = dalloc(&c->rflag, (size_t)max_rows);
     if (e == hipSuccess) e = dalloc(&c->rsse, (size_t)max_rows);
-    if (e == hipSuccess) e = dalloc(&c->fold_ls, 8 + kFoldTasks);
+    if (e == hipSuccess) e = dalloc(&c->fold_ls, 8);
     if (e == hipSuccess) e = dalloc(&c->xsq, 1);
     if (e == hipSuccess) e = dalloc(&c->scal, 4);
     if (e == hipSuccess) e = dalloc(&c->iter_ctr, 1);
@@ -1124,11 +1122,15 @@ ptk_status ptk_set_observed(ptk_ctx *c, int64_t nnz, const int32_t *idx,
     {
         int jmax = 1;
         for (int n = 0; n < s.N; ++n) jmax = std::max(jmax, (int)s.ranks[n]);
-        c->ls_hcap = std::min<int64_t>({nnz / kLsTaskLen + 1, c->max_rows, kLsMaxTasks});
-        c->ls_tcap = std::min<int64_t>(2 * (nnz / kLsTaskLen) + 1, kLsMaxTasks);
+        // every row may be heavy; tasks up to 2 nnz / task_len, within a
+        // memory budget for their triangles (rows beyond it take one
+        // wavefront each)
+        c->ls_hcap = c->max_rows;
+        c->ls_tcap = std::max<int64_t>(
+            1, std::min<int64_t>(2 * (nnz / kLsTaskLen) + 1,
+                                 (int64_t)(kLsTriBytes / (sizeof(double) * jmax * (jmax + 1)))));
         HIPCHK(c, dalloc(&c->ls_hrow, (size_t)c->ls_hcap));
         HIPCHK(c, dalloc(&c->ls_hoff, (size_t)c->ls_hcap));
-        HIPCHK(c, dalloc(&c->ls_htask, (size_t)c->ls_tcap));
         HIPCHK(c, dalloc(&c->ls_tri, (size_t)c->ls_tcap * jmax * (jmax + 1)));
     }
     // sum of x^2 for the error identity of the fused pass
@@ -1464,9 +1466,9 @@ constexpr int64_t kFoldMaxChunks = 1024;
 namespace {
 
 // Device buffers of one fold-in: the row system, the partial systems of at
-// most max_chunks work ranges (reused for the least-squares tasks'
-// triangles), the row pointers, the merge list, and the least-squares lists
-// (8 + tasks ints).
+// most max_chunks work ranges (reused for the triangles of at most `tasks`
+// least-squares tasks), the row pointers, the merge list, and the
+// least-squares counters and lists (8 ints).
 struct FoldBufs {
     double *bbuf;
     double *part;
@@ -1528,7 +1530,7 @@ ptk_status fold_in_impl(ptk_ctx *c, int32_t n, int64_t k, const int32_t *idx,
     }));
     if (nchunks > 1) HIPCHK(c, launch_merge(b.part, b.split, 1, E, b.bbuf, c->st));
     // the row's least-squares solve, if the Cholesky solve flags it: tasks
-    // long enough that at most b.tasks - 1 are needed, their triangles in
+    // long enough that at most b.tasks are needed, their triangles in
     // part (free after the merge)
     SolveFlags f{};
     f.cnt = b.ls;
@@ -1536,11 +1538,10 @@ ptk_status fold_in_impl(ptk_ctx *c, int32_t n, int64_t k, const int32_t *idx,
     f.cap = 1;
     f.hrow = b.ls + 5;
     f.hoff = b.ls + 6;
-    f.htask = b.ls + 8;
     f.hcap = 1;
     f.tcap = b.tasks;
     f.task_len = (int32_t)std::max<int64_t>(
-        kLsTaskLen, round_up((k + b.tasks - 2) / (b.tasks - 1), kWave));
+        kLsTaskLen, round_up((k + b.tasks - 1) / b.tasks, kWave));
     f.pack = J < kLsPack;
     f.cond_limit = c->opt.cond_limit > 0.0 ? c->opt.cond_limit : kCondLimitDefault;
     HIPCHK(c, timed(c, "fold_solve", [&] {

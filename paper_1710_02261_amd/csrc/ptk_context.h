@@ -106,18 +106,18 @@ struct ptk_ctx {
     int32_t *bad = nullptr;      // ctr + 0
     // rows handed to the least-squares solve: the list (max I_n), a flag byte
     // per row, the rows' error terms (last mode of a fused-error iteration);
-    // heavy rows, their first tasks, the tasks and their triangles (sized at
+    // heavy rows, their first tasks and the tasks' triangles (sized at
     // ptk_set_observed, see SolveFlags)
     int32_t *lslist = nullptr;
     uint8_t *rflag = nullptr;
     double *rsse = nullptr;
     int64_t max_rows = 0;
-    int32_t *ls_hrow = nullptr, *ls_hoff = nullptr, *ls_htask = nullptr;
+    int32_t *ls_hrow = nullptr, *ls_hoff = nullptr;
     double *ls_tri = nullptr;
     int64_t ls_hcap = 0, ls_tcap = 0;
     int64_t last_not_pd = 0, last_ls_rows = 0, last_ls_max = 0;
-    // fold-in: counters [4], list [1], heavy row and first task [2], spare,
-    // tasks [kFoldTasks]; its triangles go to fold_part
+    // fold-in: counters [4], list [1], heavy row and first task [2], spare;
+    // its least-squares triangles go to fold_part
     int32_t *fold_ls = nullptr;
     int32_t last_iters = 0;      // iterations the last ptk_iterate ran
     double *host = nullptr;      // pinned results

@@ -152,26 +152,27 @@ hipError_t launch_merge(const double *part, const int32_t *split, int32_t nsplit
 // cond_limit. They are sorted by length into three lists:
 //  * packed: rows of at most kLsPack entries (with pack set), four per
 //    wavefront; list[0, cnt[0]);
-//  * single: other rows of at most task_len entries, one wavefront each;
-//    list[cap - 1 - k], k < cnt[1];
+//  * single: other rows of at most 64 entries (and rows whose tasks find no
+//    room), one wavefront each; list[cap - 1 - k], k < cnt[1];
 //  * heavy: longer rows, cut into tasks of task_len entries (any wavefront
-//    takes any task) whose triangles a second kernel merges: hrow[h] / hoff[h]
-//    (first task), h < cnt[2]; htask[t] = h, t < cnt[3].
-// Capacities: cap >= rows. A heavy row whose tasks find no room in hcap /
-// tcap goes to the single list instead (with hcap >= nnz / task_len + 1 and
-// tcap >= 2 nnz / task_len + 1 every heavy row finds room). rflag (optional,
-// one byte per row) marks the flagged rows whose error term the
-// least-squares kernel supplies (packed and single rows).
+//    takes any task) whose triangles a second kernel merges. cnt[2], cnt[3]
+//    form one 64-bit counter (tasks in the low word, rows in the high word)
+//    that a row advances by (1 << 32) + its tasks in one atomic, so hoff[h],
+//    the first task of heavy row h = hrow[h] (-1: no room, skipped), grows
+//    with h and a task finds its row by binary search.
+// Capacities: cap and hcap >= rows; tcap tasks (tri holds tcap triangles).
+// rflag (optional, one byte per row) marks the flagged rows whose error term
+// the least-squares kernel supplies (packed and single rows).
 constexpr int kLsPack = 16;
-constexpr int32_t kLsTaskLen = 1024;
-constexpr int64_t kLsMaxTasks = 65536;
+constexpr int32_t kLsTaskLen = 64;
+constexpr size_t kLsTriBytes = size_t(256) << 20;
 constexpr double kCondLimitDefault = 1e9;
 struct SolveFlags {
     uint8_t *rflag;
-    int32_t *cnt;
+    int32_t *cnt;                     // [4], 8-byte aligned
     int32_t *list;
     int64_t cap;
-    int32_t *hrow, *hoff, *htask;
+    int32_t *hrow, *hoff;
     int64_t hcap, tcap;
     int32_t task_len;
     int32_t pack;

@@ -22,11 +22,12 @@
 // Segments are whole wavefronts, or 16-lane quarters for the packed rows.
 //
 // Work: k_ls takes, with every wavefront on its own, (1) the tasks of the
-// heavy rows: task_len entries each, reduced to a triangle in memory (the
-// first task of a row starts from sqrt(lambda) I, the others from 0); (2) the
-// single rows: a row per wavefront, solved and its error term summed in a
-// second pass; (3) the packed rows: four per wavefront, 16 lanes each, deltas
-// kept for the error term. k_ls_merge then merges the triangles of every
+// heavy rows: task_len entries each (one 64-entry chunk in a fit), reduced to
+// a triangle in memory (the first task of a row starts from sqrt(lambda) I,
+// the others from 0); (2) the single rows: a row per wavefront, solved and
+// its error term formed from the kept deltas (a second pass for a row longer
+// than one chunk); (3) the packed rows: four per wavefront, 16 lanes each,
+// deltas kept for the error term. k_ls_merge then merges the triangles of every
 // heavy row in task order (W wavefronts each merge every W-th one, then the
 // first merges the others in order) and back-substitutes. A row's result
 // depends only on its own entries, never on where it sits in the lists, so
@@ -156,6 +157,17 @@ __device__ __forceinline__ double ls_store(const LsArgs &a, int64_t i, double aq
 
 }  // namespace
 
+// Heavy row owning task t: the largest h < nheavy with hoff[h] <= t.
+__device__ __forceinline__ int64_t task_row(const SolveFlags &f, int64_t nheavy, int64_t t) {
+    int64_t lo = 0, hi = nheavy - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (f.hoff[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 template <int JMAX, int NS, int JS>
 __global__ __launch_bounds__(kWave) void k_ls(LsArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
@@ -168,11 +180,12 @@ __global__ __launch_bounds__(kWave) void k_ls(LsArgs a) {
     const int64_t L = f.task_len;
 
     // (1) tasks of heavy rows: a triangle per task
-    const int64_t ntask = min((int64_t)f.cnt[3], f.tcap);
+    const int64_t nheavy = min((int64_t)f.cnt[3], f.hcap);
+    const int64_t ntask = nheavy > 0 ? min((int64_t)f.cnt[2], f.tcap) : 0;
     for (int64_t t = gw; t < ntask; t += nw) {
-        const int h = f.htask[t];
-        if (h < 0) continue;
+        const int64_t h = task_row(f, nheavy, t);
         const int64_t i = f.hrow[h];
+        if (i < 0) continue;
         const int64_t q = t - f.hoff[h];
         const int64_t r1row = a.rowptr[i + 1];
         const int64_t r0 = a.rowptr[i] + q * L;
@@ -192,16 +205,20 @@ __global__ __launch_bounds__(kWave) void k_ls(LsArgs a) {
         }
     }
 
-    // (2) single rows: a row per wavefront, error term in a second pass
+    // (2) single rows: a row per wavefront; a row of one chunk keeps its
+    // deltas for the error term, a longer one recomputes them
     const int64_t nsingle = f.cnt[1];
     for (int64_t s = gw; s < nsingle; s += nw) {
         const int64_t i = f.list[f.cap - 1 - s];
         const int64_t r0 = a.rowptr[i], r1 = a.rowptr[i + 1];
-        double rc[JMAX];
+        double rc[JMAX], d0[JMAX], x0 = 0.0;
         ls_init<JMAX>(rc, sl, jn, lane);
         for (int64_t c0 = r0; c0 < r1; c0 += kWave) {
             double d[JMAX], x;
             entry_delta<JMAX, NS, JS>(a, c0 + lane, c0 + lane < r1, lds, lane, d, x);
+#pragma unroll
+            for (int j = 0; j < JMAX; ++j) d0[j] = d[j];
+            x0 = x;
             ls_merge<JMAX, kWave>(rc, d, x, jn, lane);
         }
         const double af = ls_store<kWave>(a, i, ls_back<JMAX, kWave>(rc, jn, lane), lane,
@@ -210,6 +227,12 @@ __global__ __launch_bounds__(kWave) void k_ls(LsArgs a) {
             double acc = 0.0;
             if (isnan(__shfl(af, 0, kWave))) {
                 acc = __builtin_nan("");
+            } else if (r1 - r0 <= kWave) {
+                double pr = 0.0;
+#pragma unroll
+                for (int j = 0; j < JMAX; ++j)
+                    if (j < jn) pr = __builtin_fma(__shfl(af, j, kWave), d0[j], pr);
+                acc = ssum<kWave>(pr * (pr - 2.0 * x0));
             } else {
                 for (int64_t c0 = r0; c0 < r1; c0 += kWave) {
                     double d[JMAX], x;
@@ -267,7 +290,7 @@ __global__ __launch_bounds__(kWave *W) void k_ls_merge(LsArgs a) {
     const int w = threadIdx.x / kWave;
     const int jn = a.jn;
     const SolveFlags &f = a.f;
-    const int64_t nheavy = min((int64_t)f.cnt[2], f.hcap);
+    const int64_t nheavy = min((int64_t)f.cnt[3], f.hcap);
     for (int64_t h = blockIdx.x; h < nheavy; h += gridDim.x) {
         const int64_t i = f.hrow[h];
         if (i < 0) continue;

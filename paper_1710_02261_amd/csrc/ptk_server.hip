@@ -110,9 +110,13 @@ ptk_status sfail(ptk_server *sv, ptk_status s, const std::string &msg) {
 }
 
 // Least-squares lists of a group of q fold-in rows over P entries: counters
-// [4], the row list [q], heavy rows and first tasks [2q], tasks [tcap].
-int64_t ls_tcap(int64_t P) { return 2 * (P / kLsTaskLen) + 1; }
-int64_t ls_ints(int64_t q, int64_t P) { return 4 + 3 * q + ls_tcap(P); }
+// [4], the row list [q], heavy rows and first tasks [2q]. Tasks of
+// kServeTaskLen entries: at most P / 64 + 1 of them, whose triangles fit in
+// the group's partial systems ((P / kSeg + 1) * 2 * E doubles, free after
+// the merge).
+constexpr int32_t kServeTaskLen = 128;
+int64_t ls_tcap(int64_t P) { return 2 * (P / kServeTaskLen) + 1; }
+int64_t ls_ints(int64_t q, int64_t) { return 4 + 3 * q; }
 
 size_t request_bytes(const ptk_server *sv, const Request &r) {
     const int N = sv->s.N;
@@ -286,8 +290,7 @@ hipError_t launch_batch(ptk_server *sv, Slot &sl) {
             e = launch_merge(a.part, (const int32_t *)(D + g.o_split), g.nsplit, a.E, a.bbuf,
                              sl.st);
         // rows whose Cholesky solve would be inaccurate go to the
-        // least-squares form; the triangles of their tasks reuse part (free
-        // after the merge: (P / kSeg + 1) * 2 * E doubles >= ls_tcap(P) * J * (J + 1))
+        // least-squares form; the triangles of their tasks reuse part
         SolveFlags f{};
         int32_t *ls = (int32_t *)(D + g.o_ls);
         f.cnt = ls;
@@ -295,10 +298,9 @@ hipError_t launch_batch(ptk_server *sv, Slot &sl) {
         f.cap = q;
         f.hrow = ls + 4 + q;
         f.hoff = ls + 4 + 2 * q;
-        f.htask = ls + 4 + 3 * q;
         f.hcap = q;
         f.tcap = ls_tcap(g.P);
-        f.task_len = kLsTaskLen;
+        f.task_len = kServeTaskLen;
         f.pack = J < kLsPack;
         f.cond_limit = c->opt.cond_limit > 0.0 ? c->opt.cond_limit : kCondLimitDefault;
         if (e == hipSuccess)

@@ -25,23 +25,20 @@ __device__ __forceinline__ bool flag_row(const SolveFlags &f, int64_t i, int64_t
         f.list[atomicAdd(&f.cnt[0], 1)] = (int32_t)i;
         return true;
     }
-    if (cnt <= f.task_len || !f.hrow) {
-        f.list[f.cap - 1 - atomicAdd(&f.cnt[1], 1)] = (int32_t)i;
-        return true;
+    if (cnt > kWave && f.hrow) {
+        const unsigned long long nt = (unsigned long long)((cnt + f.task_len - 1) / f.task_len);
+        const unsigned long long old =
+            atomicAdd((unsigned long long *)(f.cnt + 2), (1ull << 32) + nt);
+        const int64_t t0 = (int64_t)(old & 0xffffffffull);
+        const int64_t h = (int64_t)(old >> 32);
+        const bool room = t0 + (int64_t)nt <= f.tcap;
+        if (h < f.hcap) {
+            f.hoff[h] = (int32_t)t0;
+            f.hrow[h] = room ? (int32_t)i : -1;
+        }
+        if (room && h < f.hcap) return false;
     }
-    const int64_t nt = (cnt + f.task_len - 1) / f.task_len;
-    const int64_t h = atomicAdd(&f.cnt[2], 1);
-    const int64_t t0 = atomicAdd(&f.cnt[3], (int32_t)nt);
-    if (h < f.hcap && t0 + nt <= f.tcap) {
-        f.hrow[h] = (int32_t)i;
-        f.hoff[h] = (int32_t)t0;
-        for (int64_t t = t0; t < t0 + nt; ++t) f.htask[t] = (int32_t)h;
-        return false;
-    }
-    // no room for its tasks: the reservation is voided and the row goes to
-    // the single list (one wavefront for the whole row: slower, same result)
-    if (h < f.hcap) f.hrow[h] = -1;
-    for (int64_t t = t0; t < t0 + nt && t < f.tcap; ++t) f.htask[t] = -1;
+    // one wavefront for the whole row
     f.list[f.cap - 1 - atomicAdd(&f.cnt[1], 1)] = (int32_t)i;
     return true;
 }
