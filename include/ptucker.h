@@ -253,6 +253,21 @@ ptk_status ptk_solve_stats(ptk_ctx *ctx, int64_t *ls_rows_host,
                            int64_t *ls_max_entries_host);
 
 /*
+ * ptk_fold_in without any allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * device allocation. Same arguments, result and errors as ptk_fold_in (same
+ * kernels); the work buffers (row system, at most 128 work-range partial
+ * systems, the merge and least-squares lists, least-squares triangles) live
+ * in a fixed 2 MiB device array of the library, one per device, held until
+ * the process ends; the call makes no hipMalloc / hipFree. Limit: k <= 2^24
+ * entries (PTK_E_INVALID beyond it). Every call on a device shares that
+ * device's array: calls that overlap on one device (other streams, other
+ * threads, other contexts) race and must be serialised by the caller.
+ */
+ptk_status ptk_fold_in_noalloc(ptk_ctx *ctx, int32_t n, int64_t k, const int32_t *idx,
+                               const float *val, double lambda, float *row_out);
+
+/*
  * Autotuner of the batching form (the GPU counterpart of the dynamic row
  * schedule of Sec. 3.4). For every mode it times the row-system kernels
  * (delta, Gram, merge) of the bound model on the observed set for several

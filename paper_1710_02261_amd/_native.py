@@ -65,6 +65,7 @@ def load_library():
         "ptk_orthogonalize": [_vp],
         "ptk_predict": [_vp, _i64, _vp, _vp],
         "ptk_fold_in": [_vp, _i32, _i64, _vp, _vp, _dbl, _vp],
+        "ptk_fold_in_noalloc": [_vp, _i32, _i64, _vp, _vp, _dbl, _vp],
         "ptk_delta": [_vp, _i32, _i64, _vp, _vp],
         "ptk_row_systems": [_vp, _i32, _vp, _vp],
         "ptk_kernel_times": [_vp, C.POINTER(_i32), C.POINTER(C.c_char_p),
@@ -294,6 +295,17 @@ class Context:
         vptr = _dev_ptr(val, torch.float32, "val") if k else _vp(0)
         self._check(self._lib.ptk_fold_in(self._h, int(n), k, iptr, vptr, float(lam),
                                           _dev_ptr(out, torch.float32, "out")))
+        return out
+
+    def fold_in_noalloc(self, n, idx, val, lam, out):
+        """ptk_fold_in_noalloc: the fold-in on the library's fixed device
+        scratch (no allocation); out is a caller-provided J_n float32 tensor."""
+        torch = _torch()
+        k = int(idx.shape[1])
+        iptr = _dev_ptr(idx, torch.int32, "idx") if k else _vp(0)
+        vptr = _dev_ptr(val, torch.float32, "val") if k else _vp(0)
+        self._check(self._lib.ptk_fold_in_noalloc(self._h, int(n), k, iptr, vptr, float(lam),
+                                                  _dev_ptr(out, torch.float32, "out")))
         return out
 
     def delta(self, n, idx):

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -22,6 +23,8 @@
 
 using namespace ptk;
 
+// device address of the scratch of ptk_fold_in_noalloc (defined with it)
+hipError_t noalloc_scratch(int device, void **out);
 
 namespace {
 
@@ -868,6 +871,7 @@ ptk_status ptk_create(ptk_ctx **out, int32_t N, const int64_t *dims_host,
     if (e == hipSuccess) e = dalloc(&c->rflag, (size_t)max_rows);
     if (e == hipSuccess) e = dalloc(&c->rsse, (size_t)max_rows);
     if (e == hipSuccess) e = dalloc(&c->fold_ls, 8);
+    if (e == hipSuccess) e = noalloc_scratch(c->device, &c->noalloc);
     if (e == hipSuccess) e = dalloc(&c->xsq, 1);
     if (e == hipSuccess) e = dalloc(&c->scal, 4);
     if (e == hipSuccess) e = dalloc(&c->iter_ctr, 1);
@@ -1577,6 +1581,74 @@ ptk_status fold_in_impl(ptk_ctx *c, int32_t n, int64_t k, const int32_t *idx,
 }
 
 }  // namespace
+
+// Scratch of ptk_fold_in_noalloc: a file-scope device array, one per device
+// for the life of the process. Host code never passes its name to a kernel:
+// the device address comes from hipGetSymbolAddress, once per device, at
+// ptk_create (noalloc_scratch), and is kept in the context.
+constexpr int64_t kNoAllocChunks = 128;         // work ranges of the Gram pass
+constexpr int64_t kNoAllocTasks = 129;          // least-squares tasks
+constexpr int64_t kNoAllocMaxEntries = int64_t(1) << 24;
+constexpr size_t kNoAllocAlign = 256;
+constexpr size_t na_up(size_t x) { return (x + kNoAllocAlign - 1) / kNoAllocAlign * kNoAllocAlign; }
+constexpr size_t kNaBbuf = 0;
+constexpr size_t kNaPart = kNaBbuf + na_up(sizeof(double) * sys_entries(kMaxJ));
+constexpr size_t kNaPartDoubles =
+    std::max<size_t>((size_t)kNoAllocChunks * 2 * sys_entries(kMaxJ),
+                     (size_t)kNoAllocTasks * kMaxJ * (kMaxJ + 1));
+constexpr size_t kNaRowptr = kNaPart + na_up(sizeof(double) * kNaPartDoubles);
+constexpr size_t kNaSplit = kNaRowptr + na_up(2 * sizeof(int64_t));
+constexpr size_t kNaLs = kNaSplit + na_up(3 * sizeof(int32_t));
+constexpr size_t kNaEnd = kNaLs + na_up(8 * sizeof(int32_t));
+constexpr size_t kNoAllocBytes = size_t(2) << 20;
+static_assert(kNaEnd <= kNoAllocBytes, "no-allocation scratch layout");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of this device's scratch (the current device), looked up
+// once per device.
+hipError_t noalloc_scratch(int device, void **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+extern "C" ptk_status ptk_fold_in_noalloc(ptk_ctx *c, int32_t n, int64_t k,
+                                          const int32_t *idx, const float *val,
+                                          double lambda, float *row_out) {
+    if (!c) return PTK_E_INVALID;
+    ptk_status s = fold_check(c, n, k, idx, val, lambda, row_out);
+    if (s != PTK_OK) return s;
+    if (k > kNoAllocMaxEntries)
+        return fail(c, PTK_E_INVALID,
+                    "ptk_fold_in_noalloc: k = %lld entries exceeds its limit of %lld",
+                    (long long)k, (long long)kNoAllocMaxEntries);
+    if (!c->noalloc)
+        return fail(c, PTK_E_STATE, "ptk_fold_in_noalloc: no scratch for this device");
+    unsigned char *base = (unsigned char *)c->noalloc;
+    const FoldBufs b{(double *)(base + kNaBbuf), (double *)(base + kNaPart), kNoAllocChunks,
+                     (int64_t *)(base + kNaRowptr), (int32_t *)(base + kNaSplit),
+                     (int32_t *)(base + kNaLs), kNoAllocTasks};
+    // timing events would be created on demand: none in this call
+    const int32_t profile = c->opt.profile;
+    c->opt.profile = 0;
+    s = fold_in_impl(c, n, k, idx, val, lambda, row_out, b);
+    c->opt.profile = profile;
+    return s;
+}
 
 extern "C" ptk_status ptk_fold_in(ptk_ctx *c, int32_t n, int64_t k, const int32_t *idx,
                                   const float *val, double lambda, float *row_out) {

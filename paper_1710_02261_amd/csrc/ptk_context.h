@@ -119,6 +119,7 @@ struct ptk_ctx {
     // fold-in: counters [4], list [1], heavy row and first task [2], spare;
     // its least-squares triangles go to fold_part
     int32_t *fold_ls = nullptr;
+    void *noalloc = nullptr;     // this device's scratch of ptk_fold_in_noalloc
     int32_t last_iters = 0;      // iterations the last ptk_iterate ran
     double *host = nullptr;      // pinned results
     size_t host_cap = 0;
