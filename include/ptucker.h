@@ -149,7 +149,7 @@ typedef struct ptk_options {
                                [sqrt(lambda) I ; Delta] from the row's
                                entries, deltas recomputed in FP64. That form
                                needs no formed B_i and never breaks down for
-                               lambda > 0. 0 = the default, 1e9; 1 sends
+                               lambda > 0. 0 = the default, 1e10; 1 sends
                                every non-empty row to the least-squares form.
                                Negative or not finite: PTK_E_INVALID.        */
 } ptk_options;

@@ -367,6 +367,9 @@ ptk_status update_mode_impl(ptk_ctx *c, int n, double lambda, int role = 0,
         return launch_solve(c->bbuf, m.rowptr, c->s.dims[n], c->s.ranks[n], lambda,
                             c->fac[n], f, c->st);
     }));
+    HIPCHK(c, timed(c, "solve_ls", [&] {
+        return launch_ls_lists(m.rowptr, c->s.dims[n], f, c->st);
+    }));
     LsArgs r{};
     HIPCHK(c, ls_core(c, n, role, &r.gp));
     int t = 0, off = 0;
@@ -1537,6 +1540,7 @@ ptk_status fold_in_impl(ptk_ctx *c, int32_t n, int64_t k, const int32_t *idx,
     // long enough that at most b.tasks are needed, their triangles in
     // part (free after the merge)
     SolveFlags f{};
+    f.rflag = (uint8_t *)(b.ls + 7);
     f.cnt = b.ls;
     f.list = b.ls + 4;
     f.cap = 1;
@@ -1551,6 +1555,7 @@ ptk_status fold_in_impl(ptk_ctx *c, int32_t n, int64_t k, const int32_t *idx,
     HIPCHK(c, timed(c, "fold_solve", [&] {
         return launch_solve(b.bbuf, b.rowptr, 1, J, lambda, row_out, f, c->st);
     }));
+    HIPCHK(c, launch_ls_lists(b.rowptr, 1, f, c->st));
     LsArgs r{};
     if (ar == kArithF64) {
         r.gp = c->gp[n];

@@ -116,8 +116,8 @@ struct ptk_ctx {
     double *ls_tri = nullptr;
     int64_t ls_hcap = 0, ls_tcap = 0;
     int64_t last_not_pd = 0, last_ls_rows = 0, last_ls_max = 0;
-    // fold-in: counters [4], list [1], heavy row and first task [2], spare;
-    // its least-squares triangles go to fold_part
+    // fold-in: counters [4], list [1], heavy row and first task [2], the
+    // row's flag byte; its least-squares triangles go to fold_part
     int32_t *fold_ls = nullptr;
     void *noalloc = nullptr;     // this device's scratch of ptk_fold_in_noalloc
     int32_t last_iters = 0;      // iterations the last ptk_iterate ran

@@ -149,7 +149,11 @@ hipError_t launch_merge(const double *part, const int32_t *split, int32_t nsplit
 // Rows the Cholesky solve hands to the least-squares solve (ptk_resolve.hip):
 // those whose factorisation broke down or whose scaled condition estimate
 // tr((D^-1/2 M D^-1/2)^-1), M = B_i + lambda I, D = diag(M), exceeds
-// cond_limit. They are sorted by length into three lists:
+// cond_limit. The solve kernel sets rflag[i] (one byte per row) to 1 for
+// them and to 0 for the rest; k_ls_lists then sorts the flagged rows by
+// length into three lists and rewrites their byte to kLsOwnError (packed and
+// single rows, whose error term the least-squares kernel supplies) or
+// kLsIdentity (heavy rows):
 //  * packed: rows of at most kLsPack entries (with pack set), four per
 //    wavefront; list[0, cnt[0]);
 //  * single: other rows of at most 64 entries (and rows whose tasks find no
@@ -160,13 +164,13 @@ hipError_t launch_merge(const double *part, const int32_t *split, int32_t nsplit
 //    that a row advances by (1 << 32) + its tasks in one atomic, so hoff[h],
 //    the first task of heavy row h = hrow[h] (-1: no room, skipped), grows
 //    with h and a task finds its row by binary search.
-// Capacities: cap and hcap >= rows; tcap tasks (tri holds tcap triangles).
-// rflag (optional, one byte per row) marks the flagged rows whose error term
-// the least-squares kernel supplies (packed and single rows).
+// Capacities: cap and hcap >= rows; tcap tasks (the triangles hold tcap).
 constexpr int kLsPack = 16;
 constexpr int32_t kLsTaskLen = 64;
 constexpr size_t kLsTriBytes = size_t(256) << 20;
-constexpr double kCondLimitDefault = 1e9;
+constexpr double kCondLimitDefault = 1e10;
+constexpr uint8_t kLsOwnError = 2;
+constexpr uint8_t kLsIdentity = 3;
 struct SolveFlags {
     uint8_t *rflag;
     int32_t *cnt;                     // [4], 8-byte aligned
@@ -181,6 +185,9 @@ struct SolveFlags {
 hipError_t launch_solve(const double *bbuf, const int64_t *rowptr, int64_t I,
                         int J, double lambda, float *A, const SolveFlags &f,
                         hipStream_t st);
+// the lists of the flagged rows (after launch_solve)
+hipError_t launch_ls_lists(const int64_t *rowptr, int64_t I, const SolveFlags &f,
+                           hipStream_t st);
 
 // Arguments of the least-squares row solve of the flagged rows (the entries
 // of mode n in grouped order, as for the row-system kernels).
@@ -208,8 +215,8 @@ struct LsArgs {
 // equal_fast: the (N, J) of an unrolled delta kernel with all ranks J
 hipError_t launch_ls(const LsArgs &a, int N, bool equal_fast, int num_cu,
                      hipStream_t st);
-// rflag / rsse (optional): rows marked in rflag add rsse[i] instead of the
-// identity of their row system.
+// rflag / rsse (optional): rows marked kLsOwnError in rflag add rsse[i]
+// instead of the identity of their row system.
 hipError_t launch_row_sse(const double *bbuf, const int64_t *rowptr, const float *A,
                           int64_t I, int J, const uint8_t *rflag, const double *rsse,
                           double *partial, int nblocks, hipStream_t st);

@@ -28,8 +28,8 @@
 // its error term formed from the kept deltas (a second pass for a row longer
 // than one chunk); (3) the packed rows: four per wavefront, 16 lanes each,
 // deltas kept for the error term. k_ls_merge then merges the triangles of every
-// heavy row in task order (W wavefronts each merge every W-th one, then the
-// first merges the others in order) and back-substitutes. A row's result
+// heavy row (streams of 16 or 64 lanes each merge every NS-th task, then a
+// fixed pairwise tree) and back-substitutes. A row's result
 // depends only on its own entries, never on where it sits in the lists, so
 // the results do not depend on the order in which rows were flagged.
 #include "ptk_device.h"
@@ -62,20 +62,20 @@ __device__ __forceinline__ void ls_merge(double (&rc)[JMAX], double (&d)[JMAX], 
         const double mu = sqrt(alpha * alpha + sig);
         const double beta = alpha >= 0.0 ? -mu : mu;
         const double v0 = alpha - beta;        // |alpha| + mu: no cancellation
-        const double vtv = skip ? 1.0 : v0 * v0 + sig;
+        const double tau = skip ? 0.0 : 2.0 / (v0 * v0 + sig);   // 2 / v^T v
 #pragma unroll
         for (int q = j + 1; q < JMAX; ++q) {
             if (q >= jn) break;
             const double s = ssum<SEG>(dj * d[q]);
             const double rjq = __shfl(rc[j], q, SEG);
-            const double f = skip ? 0.0 : 2.0 * (v0 * rjq + s) / vtv;
+            const double f = tau * (v0 * rjq + s);
             if (e == q) rc[j] = rjq - f * v0;
             d[q] = __builtin_fma(-f, dj, d[q]);
         }
         {
             const double s = ssum<SEG>(dj * x);
             const double rjz = __shfl(rc[j], jn, SEG);
-            const double f = skip ? 0.0 : 2.0 * (v0 * rjz + s) / vtv;
+            const double f = tau * (v0 * rjz + s);
             if (e == jn) rc[j] = rjz - f * v0;
             x = __builtin_fma(-f, dj, x);
         }
@@ -133,12 +133,32 @@ __device__ __forceinline__ void entry_delta(const LsArgs &a, int64_t pos, bool v
     x = valid ? (double)a.val[pos] : 0.0;
 }
 
+// Per-wavefront counts of the rows solved here, flushed with one atomic each
+// at the end of a kernel.
+struct LsStats {
+    int32_t ok = 0, bad = 0, maxcnt = 0;
+    __device__ void flush(int32_t *stats, int lane) {
+        int32_t o = ok, b = bad, m = maxcnt;
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            o += __shfl_xor(o, off, kWave);
+            b += __shfl_xor(b, off, kWave);
+            m = max(m, __shfl_xor(m, off, kWave));
+        }
+        if (lane == 0) {
+            if (o) atomicAdd(&stats[1], o);
+            if (b) atomicAdd(&stats[0], b);
+            if (m) atomicMax(&stats[2], m);
+        }
+    }
+};
+
 // Count a solved row; write it if its result is finite (all lanes e < jn of
 // the segment). Returns the stored value of a_e as a double (0 for e >= jn),
 // or NaN when the row was left unsolved.
 template <int SEG>
 __device__ __forceinline__ double ls_store(const LsArgs &a, int64_t i, double aq, int e,
-                                           int lane, bool has, int64_t cnt) {
+                                           int lane, bool has, int64_t cnt, LsStats &st) {
     const bool fin = !has || e >= a.jn || isfinite(aq);
     const unsigned long long m = __ballot(fin);
     const int base = lane - e;
@@ -146,8 +166,9 @@ __device__ __forceinline__ double ls_store(const LsArgs &a, int64_t i, double aq
         SEG == 64 ? ~0ull : (((1ull << SEG) - 1ull) << base);
     const bool all = (m & seg) == seg;
     if (has && e == 0) {
-        atomicAdd(&a.stats[all ? 1 : 0], 1);
-        atomicMax(&a.stats[2], (int32_t)(cnt < INT32_MAX ? cnt : INT32_MAX));
+        if (all) ++st.ok;
+        else ++st.bad;
+        st.maxcnt = max(st.maxcnt, (int32_t)(cnt < INT32_MAX ? cnt : INT32_MAX));
     }
     if (!all) return __builtin_nan("");
     const float af = (float)aq;
@@ -168,6 +189,53 @@ __device__ __forceinline__ int64_t task_row(const SolveFlags &f, int64_t nheavy,
     return lo;
 }
 
+// Sort the flagged rows (rflag[i] == 1) into the packed, single and heavy
+// lists; one atomic per wavefront and list for the first two (ballot and
+// prefix count within the wavefront), one per row for the rare heavy rows.
+__global__ __launch_bounds__(256) void k_ls_lists(const int64_t *__restrict__ rowptr,
+                                                  int64_t I, SolveFlags f) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x % kWave;
+    const bool flagged = i < I && f.rflag[i] == 1;
+    const int64_t cnt = flagged ? rowptr[i + 1] - rowptr[i] : 0;
+    const bool packed = flagged && f.pack && cnt <= kLsPack;
+    bool heavy = flagged && !packed && cnt > kWave && f.hrow;
+    if (heavy) {
+        const unsigned long long nt = (unsigned long long)((cnt + f.task_len - 1) / f.task_len);
+        const unsigned long long old =
+            atomicAdd((unsigned long long *)(f.cnt + 2), (1ull << 32) + nt);
+        const int64_t t0 = (int64_t)(old & 0xffffffffull);
+        const int64_t h = (int64_t)(old >> 32);
+        const bool room = t0 + (int64_t)nt <= f.tcap && h < f.hcap;
+        if (h < f.hcap) {
+            f.hoff[h] = (int32_t)t0;
+            f.hrow[h] = room ? (int32_t)i : -1;
+        }
+        heavy = room;
+    }
+    const bool single = flagged && !packed && !heavy;   // also heavy rows without room
+    const unsigned long long mp = __ballot(packed), ms = __ballot(single);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int32_t bp = 0, bs = 0;
+    if (lane == 0) {
+        if (mp) bp = atomicAdd(&f.cnt[0], (int32_t)__popcll(mp));
+        if (ms) bs = atomicAdd(&f.cnt[1], (int32_t)__popcll(ms));
+    }
+    bp = __shfl(bp, 0, kWave);
+    bs = __shfl(bs, 0, kWave);
+    if (packed) f.list[bp + __popcll(mp & below)] = (int32_t)i;
+    if (single) f.list[f.cap - 1 - (bs + __popcll(ms & below))] = (int32_t)i;
+    if (flagged) f.rflag[i] = heavy ? kLsIdentity : kLsOwnError;
+}
+
+hipError_t launch_ls_lists(const int64_t *rowptr, int64_t I, const SolveFlags &f,
+                           hipStream_t st) {
+    if (I <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ls_lists, dim3((unsigned)((I + 255) / 256)), dim3(256), 0, st, rowptr,
+                       I, f);
+    return hipGetLastError();
+}
+
 template <int JMAX, int NS, int JS>
 __global__ __launch_bounds__(kWave) void k_ls(LsArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
@@ -178,6 +246,7 @@ __global__ __launch_bounds__(kWave) void k_ls(LsArgs a) {
     const int64_t gw = blockIdx.x, nw = gridDim.x;
     const SolveFlags &f = a.f;
     const int64_t L = f.task_len;
+    LsStats st;
 
     // (1) tasks of heavy rows: a triangle per task
     const int64_t nheavy = min((int64_t)f.cnt[3], f.hcap);
@@ -222,7 +291,7 @@ __global__ __launch_bounds__(kWave) void k_ls(LsArgs a) {
             ls_merge<JMAX, kWave>(rc, d, x, jn, lane);
         }
         const double af = ls_store<kWave>(a, i, ls_back<JMAX, kWave>(rc, jn, lane), lane,
-                                          lane, true, r1 - r0);
+                                          lane, true, r1 - r0, st);
         if (a.rsse) {
             double acc = 0.0;
             if (isnan(__shfl(af, 0, kWave))) {
@@ -268,7 +337,7 @@ __global__ __launch_bounds__(kWave) void k_ls(LsArgs a) {
             ls_init<JMAX>(rc, sl, jn, e);
             ls_merge<JMAX, SEG>(rc, d, x, jn, e);
             const double af = ls_store<SEG>(a, i, ls_back<JMAX, SEG>(rc, jn, e), e, lane, has,
-                                            r1 - r0);
+                                            r1 - r0, st);
             if (a.rsse) {
                 double pr = 0.0;
 #pragma unroll
@@ -279,17 +348,27 @@ __global__ __launch_bounds__(kWave) void k_ls(LsArgs a) {
             }
         }
     }
+    st.flush(a.stats, lane);
 }
 
-// Merge the task triangles of every heavy row (W wavefronts per row, in task
-// order) and back-substitute.
-template <int JMAX, int W>
+// Merge the task triangles of every heavy row and back-substitute. The
+// workgroup's W wavefronts are cut into segments of SEG lanes (16 when
+// J_n < 16), NS = W * 64 / SEG streams in all; stream s merges tasks s,
+// s + NS, ... in order, then the streams' triangles are merged pairwise in a
+// fixed tree through LDS (stream s takes s + 1, s + 2, s + 4, ...), and
+// stream 0 back-substitutes.
+template <int JMAX, int W, int SEG>
 __global__ __launch_bounds__(kWave *W) void k_ls_merge(LsArgs a) {
-    __shared__ double s_tri[W][JMAX][JMAX + 1];
+    constexpr int NSEG = kWave / SEG;
+    constexpr int NS = W * NSEG;
+    __shared__ double s_tri[NS][JMAX][JMAX + 1];
     const int lane = threadIdx.x % kWave;
     const int w = threadIdx.x / kWave;
+    const int e = lane % SEG;
+    const int stream = w * NSEG + lane / SEG;
     const int jn = a.jn;
     const SolveFlags &f = a.f;
+    LsStats st;
     const int64_t nheavy = min((int64_t)f.cnt[3], f.hcap);
     for (int64_t h = blockIdx.x; h < nheavy; h += gridDim.x) {
         const int64_t i = f.hrow[h];
@@ -298,36 +377,39 @@ __global__ __launch_bounds__(kWave *W) void k_ls_merge(LsArgs a) {
         const int64_t t0 = f.hoff[h];
         const int64_t nt = (cnt + f.task_len - 1) / f.task_len;
         double rc[JMAX];
-        ls_init<JMAX>(rc, 0.0, jn, lane);
-        for (int64_t k = w; k < nt; k += W) {
+        ls_init<JMAX>(rc, 0.0, jn, e);
+        for (int64_t k = stream; k < nt; k += NS) {
             const double *tri = a.tri + (t0 + k) * (int64_t)jn * (jn + 1);
             double d[JMAX], x = 0.0;
 #pragma unroll
             for (int q = 0; q < JMAX; ++q)
-                d[q] = (lane < jn && q < jn) ? tri[lane * (jn + 1) + q] : 0.0;
-            if (lane < jn) x = tri[lane * (jn + 1) + jn];
-            ls_merge<JMAX, kWave>(rc, d, x, jn, lane);
+                d[q] = (e < jn && q < jn) ? tri[e * (jn + 1) + q] : 0.0;
+            if (e < jn) x = tri[e * (jn + 1) + jn];
+            ls_merge<JMAX, SEG>(rc, d, x, jn, e);
         }
-        if (w > 0 && lane <= jn) {
+        // pairwise tree over the streams: row p of [R | z] at s_tri[stream][p]
+        for (int step = 1; step < NS; step *= 2) {
+            if (e <= jn) {
 #pragma unroll
-            for (int p = 0; p < JMAX; ++p)
-                if (p < jn) s_tri[w][p][lane] = rc[p];
-        }
-        __syncthreads();
-        if (w == 0) {
-            for (int v = 1; v < W; ++v) {
+                for (int p = 0; p < JMAX; ++p)
+                    if (p < jn) s_tri[stream][p][e] = rc[p];
+            }
+            __syncthreads();
+            if (stream % (2 * step) == 0 && stream + step < NS) {
                 double d[JMAX], x = 0.0;
 #pragma unroll
                 for (int q = 0; q < JMAX; ++q)
-                    d[q] = (lane < jn && q < jn) ? s_tri[v][lane][q] : 0.0;
-                if (lane < jn) x = s_tri[v][lane][jn];
-                ls_merge<JMAX, kWave>(rc, d, x, jn, lane);
+                    d[q] = (e < jn && q < jn) ? s_tri[stream + step][e][q] : 0.0;
+                if (e < jn) x = s_tri[stream + step][e][jn];
+                ls_merge<JMAX, SEG>(rc, d, x, jn, e);
             }
-            (void)ls_store<kWave>(a, i, ls_back<JMAX, kWave>(rc, jn, lane), lane, lane, true,
-                                  cnt);
+            __syncthreads();
         }
+        if (w == 0 && lane < SEG)
+            (void)ls_store<SEG>(a, i, ls_back<JMAX, SEG>(rc, jn, e), e, lane, true, cnt, st);
         __syncthreads();
     }
+    if (w == 0) st.flush(a.stats, lane);
 }
 
 namespace {
@@ -349,9 +431,18 @@ hipError_t launch_ls_t(const LsArgs &a, size_t lds, int num_cu, hipStream_t st) 
                        lds, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // LDS of the merge: W * 64 / SEG triangles of JMAX x (JMAX + 1) doubles
+    if constexpr (JMAX <= 16) {
+        constexpr int WS = JMAX <= 11 ? 8 : 4;
+        if (a.jn < kLsPack) {
+            hipLaunchKernelGGL((k_ls_merge<JMAX, WS, kLsPack>), dim3((unsigned)(2 * num_cu)),
+                               dim3(kWave * WS), 0, st, a);
+            return hipGetLastError();
+        }
+    }
     constexpr int W = JMAX <= 16 ? 8 : 4;
-    hipLaunchKernelGGL((k_ls_merge<JMAX, W>), dim3((unsigned)(2 * num_cu)), dim3(kWave * W),
-                       0, st, a);
+    hipLaunchKernelGGL((k_ls_merge<JMAX, W, kWave>), dim3((unsigned)(2 * num_cu)),
+                       dim3(kWave * W), 0, st, a);
     return hipGetLastError();
 }
 

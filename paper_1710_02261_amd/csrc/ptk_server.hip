@@ -110,13 +110,14 @@ ptk_status sfail(ptk_server *sv, ptk_status s, const std::string &msg) {
 }
 
 // Least-squares lists of a group of q fold-in rows over P entries: counters
-// [4], the row list [q], heavy rows and first tasks [2q]. Tasks of
+// [4], the row list [q], heavy rows and first tasks [2q], a flag byte per
+// row. Tasks of
 // kServeTaskLen entries: at most P / 64 + 1 of them, whose triangles fit in
 // the group's partial systems ((P / kSeg + 1) * 2 * E doubles, free after
 // the merge).
 constexpr int32_t kServeTaskLen = 128;
 int64_t ls_tcap(int64_t P) { return 2 * (P / kServeTaskLen) + 1; }
-int64_t ls_ints(int64_t q, int64_t) { return 4 + 3 * q; }
+int64_t ls_ints(int64_t q, int64_t) { return 4 + 3 * q + (q + 3) / 4; }
 
 size_t request_bytes(const ptk_server *sv, const Request &r) {
     const int N = sv->s.N;
@@ -293,6 +294,7 @@ hipError_t launch_batch(ptk_server *sv, Slot &sl) {
         // least-squares form; the triangles of their tasks reuse part
         SolveFlags f{};
         int32_t *ls = (int32_t *)(D + g.o_ls);
+        f.rflag = (uint8_t *)(ls + 4 + 3 * q);
         f.cnt = ls;
         f.list = ls + 4;
         f.cap = q;
@@ -305,6 +307,7 @@ hipError_t launch_batch(ptk_server *sv, Slot &sl) {
         f.cond_limit = c->opt.cond_limit > 0.0 ? c->opt.cond_limit : kCondLimitDefault;
         if (e == hipSuccess)
             e = launch_solve(a.bbuf, a.rowptr, q, J, sv->opt.lambda, out, f, sl.st);
+        if (e == hipSuccess) e = launch_ls_lists(a.rowptr, q, f, sl.st);
         if (e == hipSuccess) {
             LsArgs r{};
             r.gp = a.gp;

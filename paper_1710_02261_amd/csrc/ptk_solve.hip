@@ -11,37 +11,11 @@
 // from the factor, (M^-1)_kk = ||L^-1 e_k||^2 (about J^3/6 more multiply-adds
 // per row); cond(S) lies within a factor J of it either way. A row whose
 // factorisation breaks down, or whose tr(S^-1) exceeds the limit, is not
-// written: it is flagged and handed to the least-squares solve of
-// ptk_resolve.hip, which works from the entries and needs no formed B_i
-// (the lists it fills are described with SolveFlags).
+// written: it is flagged (rflag[i] = 1) for the least-squares solve of
+// ptk_resolve.hip, which works from the entries and needs no formed B_i.
 #include "ptk_internal.h"
 
 namespace ptk {
-
-// Hand row i over to the least-squares solve (one caller per row). Returns
-// whether that solve supplies the row's error term (packed and single rows).
-__device__ __forceinline__ bool flag_row(const SolveFlags &f, int64_t i, int64_t cnt) {
-    if (f.pack && cnt <= kLsPack) {
-        f.list[atomicAdd(&f.cnt[0], 1)] = (int32_t)i;
-        return true;
-    }
-    if (cnt > kWave && f.hrow) {
-        const unsigned long long nt = (unsigned long long)((cnt + f.task_len - 1) / f.task_len);
-        const unsigned long long old =
-            atomicAdd((unsigned long long *)(f.cnt + 2), (1ull << 32) + nt);
-        const int64_t t0 = (int64_t)(old & 0xffffffffull);
-        const int64_t h = (int64_t)(old >> 32);
-        const bool room = t0 + (int64_t)nt <= f.tcap;
-        if (h < f.hcap) {
-            f.hoff[h] = (int32_t)t0;
-            f.hrow[h] = room ? (int32_t)i : -1;
-        }
-        if (room && h < f.hcap) return false;
-    }
-    // one wavefront for the whole row
-    f.list[f.cap - 1 - atomicAdd(&f.cnt[1], 1)] = (int32_t)i;
-    return true;
-}
 
 // Merge the partial systems of rows that cross work-range boundaries:
 // split[3*s + {0,1,2}] = (row, first range, last range). The first range
@@ -106,7 +80,7 @@ __global__ void k_solve(const double *__restrict__ bbuf,
     const int64_t cnt = rowptr[i + 1] - rowptr[i];
     if (cnt == 0) {                        // no entry: B = 0, c = 0 -> a = 0
         for (int p = 0; p < J; ++p) arow[p] = 0.0f;
-        if (f.rflag) f.rflag[i] = 0;
+        f.rflag[i] = 0;
         return;
     }
     const int T = J * (J + 1) / 2;
@@ -155,8 +129,7 @@ __global__ void k_solve(const double *__restrict__ bbuf,
         }
     }
     const bool flag = !ok || !(tr <= f.cond_limit);
-    const bool own_error = flag && flag_row(f, i, cnt);
-    if (f.rflag) f.rflag[i] = own_error;
+    f.rflag[i] = flag;
     if (flag) return;
     double *y = m + T * bs;                // rhs c, overwritten by y then a
     for (int r = 0; r < J; ++r) {          // L y = c
@@ -197,7 +170,7 @@ __global__ __launch_bounds__(256) void k_solve_grp(const double *__restrict__ bb
         // nothing to solve; the group leaves together, so no shuffle below
         // reads its lanes
         if (empty && l < J) A[i * J + l] = 0.0f;   // no entry: B = 0, c = 0 -> a = 0
-        if (empty && l == 0 && f.rflag) f.rflag[i] = 0;
+        if (empty && l == 0) f.rflag[i] = 0;
         return;
     }
     double b[J];
@@ -269,10 +242,7 @@ __global__ __launch_bounds__(256) void k_solve_grp(const double *__restrict__ bb
         if (l == r) a = ar;
     }
     const bool flag = !ok || !(tr <= f.cond_limit);      // uniform within the group
-    if (l == 0) {
-        const bool own_error = flag && flag_row(f, i, cnt);
-        if (f.rflag) f.rflag[i] = own_error;
-    }
+    if (l == 0) f.rflag[i] = flag;
     if (!flag && l < J) A[i * J + l] = (float)a;
 }
 
@@ -297,7 +267,7 @@ __global__ __launch_bounds__(kWave) void k_solve_row(const double *__restrict__ 
     if (cnt == 0) {                            // no entry: B = 0, c = 0 -> a = 0
 #pragma unroll
         for (int k = 0; k < J; ++k) arow[k] = 0.0f;
-        if (f.rflag) f.rflag[i] = 0;
+        f.rflag[i] = 0;
         return;
     }
     const double *sys = bbuf + i * E;
@@ -348,8 +318,7 @@ __global__ __launch_bounds__(kWave) void k_solve_row(const double *__restrict__ 
         tr = __builtin_fma(mkk, ss, tr);
     }
     const bool flag = !ok || !(tr <= f.cond_limit);
-    const bool own_error = flag && flag_row(f, i, cnt);
-    if (f.rflag) f.rflag[i] = own_error;
+    f.rflag[i] = flag;
     if (flag) return;
     // L y = c, then L^T a = y (L_rk at (k, r) of the upper triangle)
 #pragma unroll
@@ -406,8 +375,8 @@ hipError_t launch_solve(const double *bbuf, const int64_t *rowptr, int64_t I,
 // the squared error of eq. "reconfull" after the sweep is
 //     sum_Omega x^2 + sum_i (a_i^T B_i a_i - 2 a_i^T c_i)
 // with a_i the stored (float32) row. A row solved by the least-squares path
-// (marked in rflag) adds rsse[i] instead: the same term, summed from its
-// entries' deltas. (Heavy flagged rows keep the identity, evaluated with
+// with its own error term (rflag[i] == kLsOwnError) adds rsse[i] instead:
+// the same term, summed from its entries' deltas. (Heavy flagged rows keep the identity, evaluated with
 // their accurate a_i.) Per-block partial sums, FP64.
 __global__ __launch_bounds__(256) void k_row_sse(const double *__restrict__ bbuf,
                                                  const int64_t *__restrict__ rowptr,
@@ -423,7 +392,7 @@ __global__ __launch_bounds__(256) void k_row_sse(const double *__restrict__ bbuf
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I;
          i += (int64_t)gridDim.x * blockDim.x) {
         if (rowptr[i] == rowptr[i + 1]) continue;
-        if (rflag && rflag[i]) {
+        if (rflag && rflag[i] == kLsOwnError) {
             acc += rsse[i];
             continue;
         }
@@ -466,7 +435,7 @@ __global__ __launch_bounds__(256) void k_row_sse_grp(const double *__restrict__ 
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G; i < I; i += stride) {
         if (l >= J || rowptr[i] == rowptr[i + 1]) continue;
-        if (rflag && rflag[i]) {
+        if (rflag && rflag[i] == kLsOwnError) {
             if (l == 0) acc += rsse[i];
             continue;
         }

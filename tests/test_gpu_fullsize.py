@@ -102,10 +102,11 @@ def sample_rows(counts, chunk, rng, heavy=2):
     return picks
 
 
-def worst_conditioned(p, G, A, n, csr, rng, k=12, pool=1500):
-    """The k rows of a random pool of rows with 1..J entries whose
-    B + lambda I (formed from oracle deltas) has the largest 2-norm
-    condition number, with those numbers."""
+def worst_conditioned(p, G, A, n, csr, rng, k=12, pool=1500, near=1e10):
+    """From a random pool of rows with 1..J entries: the k whose B + lambda I
+    (formed from oracle deltas) has the largest 2-norm condition number, and
+    the k whose condition is nearest (in log) to `near`, the default limit
+    between the Cholesky and least-squares solves; with those numbers."""
     order, rp, counts = csr
     J = p.ranks[n]
     light = np.flatnonzero((counts > 0) & (counts <= J))
@@ -119,8 +120,10 @@ def worst_conditioned(p, G, A, n, csr, rng, k=12, pool=1500):
         big = sv[0] ** 2 + p.lam
         conds.append(big / p.lam if len(sv) < J else big / (sv[-1] ** 2 + p.lam))
     conds = np.array(conds)
-    top = np.argsort(conds)[::-1][:k]
-    return [int(cand[t]) for t in top], conds[top]
+    top = list(np.argsort(conds)[::-1][:k])
+    band = [t for t in np.argsort(np.abs(np.log(conds / near))) if t not in top][:k]
+    pick = np.array(top + band, dtype=np.int64)
+    return [int(cand[t]) for t in pick], conds[pick]
 
 
 def check_mode(p, ctx, fac, n, rows, label, cond=None):
@@ -148,7 +151,7 @@ def check_mode(p, ctx, fac, n, rows, label, cond=None):
            ", ".join("%d (%d entries, err %.3g)" % (rows[w], counts[rows[w]], err[w])
                      for w in worst)))
     if cond is not None:
-        log("%s mode %d: cond of the worst-conditioned rows %s" % (
+        log("%s mode %d: cond of the worst-conditioned rows and of rows near the limit %s" % (
             label, n, ", ".join("%.2g" % c for c in cond)))
     assert err.max() <= BAR, (label, n, rows[np.argmax(err)], err.max())
     return err
