@@ -369,6 +369,54 @@ def sweeps(args):
         "table": table, "command": command_line()}), flush=True)
 
 
+def approx_trace(args, p, idx, val, core, fac0, use_graph):
+    """Time K single iterations (each its own ptk_iterate call, bracketed by
+    synchronisations) of three runs from the same start: no removal, the
+    Approx variant with the dense row-system kernels (sparse_limit < 0), and
+    the Approx variant with the sparse-core switch; record the non-zero core
+    cells each iteration starts from. The first call of a run also captures
+    its graph."""
+    import torch
+    import paper_1710_02261_amd as ptk
+    rate = args.approx_rate if args.approx_rate > 0 else 0.2
+    runs = [("plain", 0.0, -1.0), ("approx_dense", rate, -1.0),
+            ("approx_sparse", rate, args.sparse_limit)]
+    res = {}
+    cells = int(core.numel())
+    for name, r, lim in runs:
+        fac = [f.clone() for f in fac0]
+        core_run = core.clone()
+        ctx = ptk.Context(p.dims, p.ranks)
+        ctx.set_options(fuse_error=1, profile=0, use_graph=use_graph, approx_rate=r,
+                        sparse_limit=lim)
+        ctx.set_observed(idx, val)
+        ctx.bind_model(core_run, fac)
+        if not args.no_autotune:
+            ctx.autotune(None)
+        ms, nz, sse = [], [], []
+        for t in range(args.approx_trace):
+            nz.append(int(torch.count_nonzero(core_run)))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s, _ = ctx.iterate(1, p.lam, strict=False)
+            torch.cuda.synchronize()
+            ms.append(1e3 * (time.perf_counter() - t0))
+            sse.append(float(s[0]))
+            log("%s iteration %d: %.2f ms, non-zero cells %d (%.3f), rmse %.6g" % (
+                name, t, ms[-1], nz[-1], nz[-1] / cells, np.sqrt(max(s[0], 0.0) / p.nnz)))
+        ctx.close()
+        res[name] = {"ms": ms, "nonzero_cells": nz,
+                     "rmse": [float(np.sqrt(max(x, 0.0) / p.nnz)) for x in sse]}
+    out = {"approx_trace": res, "approx_rate": rate, "core_cells": cells,
+           "sparse_limit": args.sparse_limit,
+           "config": {"workload": WORKLOADS[args.workload], "nnz": p.nnz,
+                      "ranks": list(p.ranks), "dims": list(p.dims)},
+           "note": "ms per iteration by host clock around one ptk_iterate call each "
+                   "(graph replay); the first call of each run includes the capture",
+           "command": command_line()}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -391,6 +439,14 @@ def main():
     ap.add_argument("--no-variant", action="store_true")
     ap.add_argument("--approx-rate", type=float, default=0.0,
                     help="Approx variant: core cells removed per iteration (0 = off)")
+    ap.add_argument("--sparse-limit", type=float, default=0.0,
+                    help="Approx variant: non-zero core fraction at or below which "
+                         "delta is summed over the non-zero cells (0 = library "
+                         "default, negative = never)")
+    ap.add_argument("--approx-trace", type=int, default=0, metavar="K",
+                    help="print ms and non-zero core cells of each of K single "
+                         "iterations: no removal, Approx with the dense kernels, "
+                         "Approx with the sparse-core switch; one JSON line, exit")
     ap.add_argument("--fp64-ceiling", action="store_true",
                     help="print the sustained FP64 rates of the GPU (FMA loop, "
                          "matrix cores, both) as one JSON line and exit")
@@ -455,13 +511,17 @@ def main():
     N, J = p.N, p.ranks[0]
 
     use_graph = 0 if args.no_graph else 1
+    if args.approx_trace:
+        approx_trace(args, p, idx, val, core, fac0, use_graph)
+        return
 
     def run(prec, cache=0, approx=0.0):
         fac = [f.clone() for f in fac0]
         core_run = core.clone()           # the Approx removal edits the core
         ctx = ptk.Context(p.dims, p.ranks)
         ctx.set_options(precision=PREC_NAMES[prec], fuse_error=1, profile=0,
-                        use_graph=use_graph, pair_cache=cache, approx_rate=approx)
+                        use_graph=use_graph, pair_cache=cache, approx_rate=approx,
+                        sparse_limit=args.sparse_limit)
         torch.cuda.synchronize()
         ts = time.perf_counter()
         ctx.set_observed(idx, val)
@@ -490,7 +550,8 @@ def main():
         _, rmse_direct, _ = ctx.recon_error(p.lam)
         # second pass with per-kernel HIP events on the library's stream
         ctx.set_options(precision=PREC_NAMES[prec], fuse_error=1, profile=1,
-                        use_graph=use_graph, pair_cache=cache, approx_rate=approx)
+                        use_graph=use_graph, pair_cache=cache, approx_rate=approx,
+                        sparse_limit=args.sparse_limit)
         ctx.reset_timers()
         ctx.iterate(args.steps, p.lam, strict=False)
         times = ctx.kernel_times()

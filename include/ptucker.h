@@ -152,6 +152,20 @@ typedef struct ptk_options {
                                lambda > 0. 0 = the default, 1e10; 1 sends
                                every non-empty row to the least-squares form.
                                Negative or not finite: PTK_E_INVALID.        */
+    double sparse_limit;    /* Approx variant (approx_rate > 0) inside
+                               ptk_iterate: at the start of every iteration
+                               the non-zero cells of the bound core are listed
+                               per mode (Sec. 3.3: after the removals most
+                               cells are zero), and when their number is at
+                               most sparse_limit * prod J_n the FP64 row
+                               systems take delta (eq. "delta") as a sum over
+                               the listed cells instead of the dense
+                               contraction. Same result up to rounding order;
+                               the switch is taken on the device, so it needs
+                               no synchronisation. 0 = the default, 0.2;
+                               negative = never; above 1 or not finite:
+                               PTK_E_INVALID. Extra device memory with
+                               approx_rate > 0: 16 * N * prod J_n bytes.      */
 } ptk_options;
 
 /*
@@ -251,6 +265,18 @@ ptk_status ptk_not_pd_count(ptk_ctx *ctx, int64_t *count_host);
  */
 ptk_status ptk_solve_stats(ptk_ctx *ctx, int64_t *ls_rows_host,
                            int64_t *ls_max_entries_host);
+
+/*
+ * Sparse core of the Approx variant (ptk_options.sparse_limit) in the last
+ * iteration of the last ptk_iterate: the non-zero cells of the bound core
+ * that iteration started from, and a bit mask of the modes (bit n = mode n)
+ * whose row systems summed delta over those cells only. Waits for the
+ * context's stream. When that iteration listed no cells (approx_rate = 0,
+ * sparse_limit < 0, a shape without the kernel, or no ptk_iterate yet):
+ * -1 and 0.
+ */
+ptk_status ptk_approx_stats(ptk_ctx *ctx, int64_t *nonzero_cells_host,
+                            int32_t *sparse_modes_host);
 
 /*
  * ptk_fold_in without any allocation, for callers that cannot allocate:

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "ptk_approx.h"
+#include "ptk_sparse.h"
 #include "ptk_context.h"
 #include "ptk_internal.h"
 #include "ptk_slice.h"
@@ -103,6 +104,12 @@ void free_approx(ptk_ctx *c) {
     dfree(c->ap_uw);
     dfree(c->ap_tbuf);
     dfree(c->ap_delta);
+    dfree(c->sp_count);
+    dfree(c->sp_cstart);
+    dfree(c->sp_use);
+    dfree(c->sp_recs);
+    c->sp_count = c->sp_cstart = c->sp_use = nullptr;
+    c->sp_recs = nullptr;
     c->ap_resid = c->ap_part = c->ap_R = c->ap_uw = c->ap_tbuf = c->ap_delta = nullptr;
     c->ap_removed = nullptr;
     c->ap_slices = 0;
@@ -272,6 +279,30 @@ MfmaArgs mfma_args(const ptk_ctx *c, int n) {
     return a;
 }
 
+// Cell lists of the sparse core (Approx variant).
+SparseArgs sparse_args(const ptk_ctx *c) {
+    SparseArgs sa{};
+    sa.N = c->s.N;
+    sa.J = c->s.ranks[0];
+    sa.cells = c->core_cells;
+    sa.rec = c->core_cells + 1;
+    sa.count = c->sp_count;
+    sa.cstart = c->sp_cstart;
+    sa.recs = c->sp_recs;
+    sa.use = c->sp_use;
+    sa.limit = c->opt.sparse_limit > 0.0 ? c->opt.sparse_limit : kSparseLimitDefault;
+    return sa;
+}
+
+SparseMode sparse_mode(const ptk_ctx *c, int n) {
+    SparseMode sm{};
+    const int J = c->s.ranks[0];
+    sm.use = c->sp_use + n;
+    sm.cstart = c->sp_cstart + (int64_t)n * (J + 1);
+    sm.recs = c->sp_recs + (int64_t)n * (c->core_cells + 1) * 4;
+    return sm;
+}
+
 // B_i, c_i for every row of mode n into bbuf (delta + Gram kernel, merge).
 ptk_status systems(ptk_ctx *c, int n, int role = 0) {
     const ModeData &m = c->md[n];
@@ -320,11 +351,20 @@ ptk_status systems(ptk_ctx *c, int n, int role = 0) {
         a.dstore = c->ap_delta;
         c->ap_stored = true;
     }
+    // Approx variant on a sparse core: both kernels are launched and the
+    // device-side switch of the mode lets one of them run
+    const bool sparse = c->sp_live && arith_of(c, n) == kArithF64;
+    if (sparse) a.skip_if = c->sp_use + n;
     HIPCHK(c, timed(c, "gram", [&] {
         if (two)
             return launch_gram2(a, c->s.N, c->s.ranks[n], arith_of(c, n), m.nchunks, c->st);
         return launch_gram(a, c->s, n, arith_of(c, n), m.nchunks, m.fast, c->st);
     }));
+    if (sparse)
+        HIPCHK(c, timed(c, "gram_sparse", [&] {
+            return launch_gram_sparse(a, c->s.N, c->s.ranks[n], sparse_mode(c, n), m.nchunks,
+                                      c->st);
+        }));
     HIPCHK(c, timed(c, "merge", [&] {
         return launch_merge(c->part, m.split, m.nsplit, a.E, c->bbuf, c->st);
     }));
@@ -633,6 +673,13 @@ ptk_status ensure_approx(ptk_ctx *c) {
         if (need <= 0.25 * (double)free_b)
             HIPCHK(c, dalloc(&c->ap_delta, (size_t)J * std::max<int64_t>(c->nnz, 1)));
     }
+    if (sparse_available(N, J)) {
+        HIPCHK(c, dalloc(&c->sp_count, (size_t)N * J));
+        HIPCHK(c, dalloc(&c->sp_cstart, (size_t)N * (J + 1)));
+        HIPCHK(c, dalloc(&c->sp_use, (size_t)N));
+        HIPCHK(c, hipMemsetAsync(c->sp_use, 0, (size_t)N * sizeof(int32_t), c->st));
+        HIPCHK(c, dalloc(&c->sp_recs, (size_t)N * (c->core_cells + 1) * 4));
+    }
     HIPCHK(c, dalloc(&c->ap_resid, (size_t)c->nnz + 64));
     HIPCHK(c, dalloc(&c->ap_part, (size_t)approx_part_doubles(c->s, (int32_t)ranges)));
     HIPCHK(c, dalloc(&c->ap_R, (size_t)c->core_cells));
@@ -750,13 +797,26 @@ ptk_status iteration_body(ptk_ctx *c, double lambda) {
     // residuals (when the partial errors group by that mode)
     c->ap_stored = false;
     HIPCHK(c, zero_lists(c));
+    // Approx variant: lists of the core's non-zero cells as it stands after
+    // the last removal, and the switch to the sparse-core kernels
+    c->sp_live = false;
+    if (c->opt.approx_rate > 0.0 && c->sp_recs && c->opt.sparse_limit >= 0.0) {
+        const SparseArgs sa = sparse_args(c);
+        HIPCHK(c, timed(c, "sparse_lists", [&] { return launch_sparse_lists(c->core, sa, c->st); }));
+        c->sp_live = true;
+    }
+    c->sp_lists = c->sp_live;
     for (int n = 0; n < N; ++n) {
         c->ap_store = c->opt.approx_rate > 0.0 && n == N - 1;
         ptk_status s = update_mode_impl(c, n, lambda, cache_role(c, n),
                                         n == N - 1 && c->opt.fuse_error);
         c->ap_store = false;
-        if (s != PTK_OK) return s;
+        if (s != PTK_OK) {
+            c->sp_live = false;
+            return s;
+        }
     }
+    c->sp_live = false;
     HIPCHK(c, timed(c, "error", [&]() -> hipError_t {
         if (c->opt.fuse_error) {
             // from the last mode's row systems, still in bbuf
@@ -968,6 +1028,8 @@ ptk_status ptk_set_options(ptk_ctx *c, const ptk_options *o) {
         return fail(c, PTK_E_UNSUPPORTED, "no Approx kernels for this shape");
     if (!(o->cond_limit >= 0.0) || !std::isfinite(o->cond_limit))
         return fail(c, PTK_E_INVALID, "cond_limit must be finite and >= 0");
+    if (!(o->sparse_limit <= 1.0) || !std::isfinite(o->sparse_limit))
+        return fail(c, PTK_E_INVALID, "sparse_limit must be finite and <= 1");
     c->opt = *o;
     c->epoch++;
     return PTK_OK;
@@ -1802,6 +1864,29 @@ extern "C" ptk_status ptk_solve_stats(ptk_ctx *c, int64_t *ls_rows, int64_t *ls_
     if (!c || !ls_rows || !ls_max) return PTK_E_INVALID;
     *ls_rows = c->last_ls_rows;
     *ls_max = c->last_ls_max;
+    return PTK_OK;
+}
+
+extern "C" ptk_status ptk_approx_stats(ptk_ctx *c, int64_t *nonzero_cells,
+                                       int32_t *sparse_modes) {
+    if (!c || !nonzero_cells || !sparse_modes) return PTK_E_INVALID;
+    *nonzero_cells = -1;
+    *sparse_modes = 0;
+    if (!c->sp_lists || c->last_iters <= 0 || !c->sp_count) return PTK_OK;
+    const int N = c->s.N, J = c->s.ranks[0];
+    std::vector<int32_t> cnt((size_t)N * J), use((size_t)N);
+    HIPCHK(c, hipMemcpyAsync(cnt.data(), c->sp_count, cnt.size() * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(use.data(), c->sp_use, use.size() * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    int64_t nz = 0;
+    for (int j = 0; j < J; ++j) nz += cnt[j];
+    int32_t mask = 0;
+    for (int n = 0; n < N; ++n)
+        if (use[n]) mask |= 1 << n;
+    *nonzero_cells = nz;
+    *sparse_modes = mask;
     return PTK_OK;
 }
 

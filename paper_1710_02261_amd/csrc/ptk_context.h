@@ -57,7 +57,7 @@ struct ptk_ctx {
     hipStream_t st = nullptr;
     int device = 0;
     int num_cu = 256;
-    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1, 0, 0.0, 0, 0.0, 0, 0.0};
+    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1, 0, 0.0, 0, 0.0, 0, 0.0, 0.0};
     int64_t nnz = -1;
     ModeData md[ptk::kMaxN];
     float *core = nullptr;
@@ -84,6 +84,13 @@ struct ptk_ctx {
     // residuals; ap_store asks systems() to keep them, ap_stored says it did
     double *ap_delta = nullptr;
     bool ap_store = false, ap_stored = false;
+    // sparse core of the Approx variant: per-mode lists of the non-zero
+    // cells and the per-mode switch (ptk_sparse.h), rebuilt at the start of
+    // every iteration; sp_live while such an iteration body is recorded
+    int32_t *sp_count = nullptr, *sp_cstart = nullptr, *sp_use = nullptr;
+    uint32_t *sp_recs = nullptr;
+    bool sp_live = false;
+    bool sp_lists = false;       // the iteration last recorded builds the lists
     int64_t part_cap = 0;
     double *red = nullptr;       // [kRedBlocks * (N + 1)] partials + scalars
     double *xsq = nullptr;       // sum of x^2 over Omega (device, 1 double)

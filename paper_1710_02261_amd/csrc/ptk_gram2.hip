@@ -71,6 +71,7 @@ __device__ __forceinline__ void delta_fast2(const void *gp_raw, const float *aou
 // KEEP: also store every entry's delta to a.dstore ([J][nnz], grouped order).
 template <int N, int J, int U, typename T, bool KEEP>
 __global__ __launch_bounds__(kWave) void k_gram_fast2(GramArgs a) {
+    if (a.skip_if && *a.skip_if) return;
     constexpr int NO = N - 1;
     constexpr int NOUT = NO - U;
     constexpr int E = sys_entries(J);

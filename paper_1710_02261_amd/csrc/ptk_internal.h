@@ -71,6 +71,9 @@ struct GramArgs {
     // optional (two-entry kernel): the delta of every entry, [jn][nnz] FP64 in
     // the grouped order, kept for the residuals of the Approx variant
     double *dstore;
+    // optional: the kernel returns at once when *skip_if != 0 (the mode's
+    // sparse-core kernel forms these row systems instead)
+    const int32_t *skip_if;
 };
 
 // Arguments of the per-entry kernels (predict, error, delta inspection).

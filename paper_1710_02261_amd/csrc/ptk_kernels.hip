@@ -82,6 +82,7 @@ hipError_t launch_permute_core(const float *G, void *gp, const Shape &s, int n,
 // ---------------------------------------------------------------------------
 template <int N, int J, int U, typename T>
 __global__ __launch_bounds__(kWave) void k_gram_fast(GramArgs a) {
+    if (a.skip_if && *a.skip_if) return;
     constexpr int NO = N - 1;
     constexpr int NOUT = NO - U;
     constexpr int E = sys_entries(J);
@@ -127,6 +128,7 @@ __global__ __launch_bounds__(kWave) void k_gram_fast(GramArgs a) {
 
 template <int JMAX>
 __global__ __launch_bounds__(kWave) void k_gram_generic(GramArgs a) {
+    if (a.skip_if && *a.skip_if) return;
     constexpr int EPL = (sys_entries(JMAX) + kWave - 1) / kWave;
     extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
     __shared__ int s_row[kWave];
