@@ -387,15 +387,18 @@ __global__ __launch_bounds__(kWave *W) void k_ls_merge(LsArgs a) {
             if (e < jn) x = tri[e * (jn + 1) + jn];
             ls_merge<JMAX, SEG>(rc, d, x, jn, e);
         }
-        // pairwise tree over the streams: row p of [R | z] at s_tri[stream][p]
-        for (int step = 1; step < NS; step *= 2) {
-            if (e <= jn) {
+        // pairwise tree over the streams that hold tasks (a stream without
+        // one holds a zero triangle, whose merge changes nothing): row p of
+        // [R | z] at s_tri[stream][p]
+        const int used = (int)min((int64_t)NS, nt);
+        for (int step = 1; step < used; step *= 2) {
+            if (e <= jn && stream < used) {
 #pragma unroll
                 for (int p = 0; p < JMAX; ++p)
                     if (p < jn) s_tri[stream][p][e] = rc[p];
             }
             __syncthreads();
-            if (stream % (2 * step) == 0 && stream + step < NS) {
+            if (stream % (2 * step) == 0 && stream + step < used) {
                 double d[JMAX], x = 0.0;
 #pragma unroll
                 for (int q = 0; q < JMAX; ++q)
