@@ -147,6 +147,14 @@ void free_modes(ptk_ctx *c) {
     c->ls_hrow = c->ls_hoff = nullptr;
     c->ls_tri = nullptr;
     c->ls_hcap = c->ls_tcap = 0;
+    dfree(c->ls_kbase);
+    dfree(c->ls_keep);
+    dfree(c->ls_kused);
+    c->ls_kbase = nullptr;
+    c->ls_keep = nullptr;
+    c->ls_kused = nullptr;
+    c->ls_kcap = 0;
+    c->keep_live = false;
     c->nnz = -1;
 }
 
@@ -306,6 +314,7 @@ SparseMode sparse_mode(const ptk_ctx *c, int n) {
 // B_i, c_i for every row of mode n into bbuf (delta + Gram kernel, merge).
 ptk_status systems(ptk_ctx *c, int n, int role = 0) {
     const ModeData &m = c->md[n];
+    c->keep_live = false;
     if (m.bf16) {
         MfmaArgs a = mfma_args(c, n);
         HIPCHK(c, timed(c, "gram_mfma", [&] {
@@ -355,6 +364,13 @@ ptk_status systems(ptk_ctx *c, int n, int role = 0) {
     // device-side switch of the mode lets one of them run
     const bool sparse = c->sp_live && arith_of(c, n) == kArithF64;
     if (sparse) a.skip_if = c->sp_use + n;
+    // the FP64 unrolled kernels (and the sparse one) keep the deltas of the
+    // rows the plan names for the least-squares solve
+    c->keep_live = c->ls_keep && arith_of(c, n) == kArithF64 && (two || m.fast);
+    if (c->keep_live) {
+        a.kbase = c->ls_kbase + c->kb_off[n];
+        a.keep = c->ls_keep;
+    }
     HIPCHK(c, timed(c, "gram", [&] {
         if (two)
             return launch_gram2(a, c->s.N, c->s.ranks[n], arith_of(c, n), m.nchunks, c->st);
@@ -432,10 +448,21 @@ ptk_status update_mode_impl(ptk_ctx *c, int n, double lambda, int role = 0,
     r.A = c->fac[n];
     r.rsse = want_rsse ? c->rsse : nullptr;
     r.stats = c->ctr;
+    if (c->keep_live) {
+        r.kbase = c->ls_kbase + c->kb_off[n];
+        r.keep = c->ls_keep;
+    }
     const bool fast = equal_ranks(c->s) && fast_available(c->s.N, c->s.ranks[n], kArithF64);
     HIPCHK(c, timed(c, "solve_ls", [&] {
         return launch_ls(r, c->s.N, fast, c->num_cu, c->st);
     }));
+    // the rows solved in least-squares form now keep their deltas in the
+    // next update of this mode
+    if (c->ls_keep)
+        HIPCHK(c, timed(c, "solve_ls", [&] {
+            return launch_keep_plan(c->rflag, m.rowptr, c->s.dims[n], c->ls_kcap,
+                                    c->ls_kbase + c->kb_off[n], c->ls_kused, c->st);
+        }));
     return PTK_OK;
 }
 
@@ -1201,6 +1228,25 @@ ptk_status ptk_set_observed(ptk_ctx *c, int64_t nnz, const int32_t *idx,
         HIPCHK(c, dalloc(&c->ls_hrow, (size_t)c->ls_hcap));
         HIPCHK(c, dalloc(&c->ls_hoff, (size_t)c->ls_hcap));
         HIPCHK(c, dalloc(&c->ls_tri, (size_t)c->ls_tcap * jmax * (jmax + 1)));
+        // deltas kept for the next update's least-squares rows: an eighth of
+        // the entries (at least 65536), within kKeepBytes; a plan per mode,
+        // empty until a mode update has flagged rows
+        int64_t rows = 0;
+        for (int n = 0; n < s.N; ++n) {
+            c->kb_off[n] = rows;
+            rows += s.dims[n];
+        }
+        c->ls_kcap = std::min<int64_t>(
+            nnz, std::min<int64_t>(std::max<int64_t>(65536, nnz / 8),
+                                   (int64_t)(kKeepBytes / (sizeof(double) * jmax))));
+        if (c->ls_kcap > 0) {
+            HIPCHK(c, dalloc(&c->ls_kbase, (size_t)rows));
+            HIPCHK(c, dalloc(&c->ls_keep, (size_t)c->ls_kcap * jmax));
+            HIPCHK(c, dalloc(&c->ls_kused, 1));
+            for (int n = 0; n < s.N; ++n)
+                HIPCHK(c, launch_keep_plan(nullptr, c->md[n].rowptr, s.dims[n], c->ls_kcap,
+                                           c->ls_kbase + c->kb_off[n], c->ls_kused, c->st));
+        }
     }
     // sum of x^2 for the error identity of the fused pass
     if (nnz > 0) {

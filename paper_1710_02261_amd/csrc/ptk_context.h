@@ -123,6 +123,16 @@ struct ptk_ctx {
     double *ls_tri = nullptr;
     int64_t ls_hcap = 0, ls_tcap = 0;
     int64_t last_not_pd = 0, last_ls_rows = 0, last_ls_max = 0;
+    // deltas kept by the row-system kernels for the least-squares rows: the
+    // plan of mode n at ls_kbase + kb_off[n] (one slot base per row, see
+    // GramArgs::kbase), the kept deltas [ls_kcap][J_max], the plan's counter;
+    // keep_live: the current mode update's row-system kernel kept them
+    int64_t *ls_kbase = nullptr;
+    int64_t kb_off[ptk::kMaxN] = {};
+    double *ls_keep = nullptr;
+    unsigned long long *ls_kused = nullptr;
+    int64_t ls_kcap = 0;
+    bool keep_live = false;
     // fold-in: counters [4], list [1], heavy row and first task [2], the
     // row's flag byte; its least-squares triangles go to fold_part
     int32_t *fold_ls = nullptr;

@@ -125,6 +125,18 @@ __global__ __launch_bounds__(kWave) void k_gram_fast2(GramArgs a) {
                 if (v1) a.dstore[(int64_t)j * a.nnz + p1] = d1[j];
             }
         }
+        if (a.kbase) {                       // deltas of least-squares rows
+            const int64_t k0 = v0 ? a.kbase[a.rows ? a.rows[p0] : 0] : kNoKeep;
+            const int64_t k1 = v1 ? a.kbase[a.rows ? a.rows[p1] : 0] : kNoKeep;
+            if (k0 != kNoKeep) {
+#pragma unroll
+                for (int j = 0; j < J; ++j) a.keep[(k0 + p0) * J + j] = d0[j];
+            }
+            if (k1 != kNoKeep) {
+#pragma unroll
+                for (int j = 0; j < J; ++j) a.keep[(k1 + p1) * J + j] = d1[j];
+            }
+        }
         __syncthreads();
         // first half: entries base .. base + 63
 #pragma unroll

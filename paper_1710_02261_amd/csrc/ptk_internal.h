@@ -74,7 +74,15 @@ struct GramArgs {
     // optional: the kernel returns at once when *skip_if != 0 (the mode's
     // sparse-core kernel forms these row systems instead)
     const int32_t *skip_if;
+    // optional: deltas kept for the least-squares solve; an entry at pos of
+    // row i with kbase[i] != kNoKeep stores its delta at keep[(kbase[i] + pos)
+    // * jn ..] (FP64, jn contiguous)
+    const int64_t *kbase;
+    double *keep;
 };
+
+// kbase value of a row whose deltas are not kept.
+constexpr int64_t kNoKeep = INT64_MIN;
 
 // Arguments of the per-entry kernels (predict, error, delta inspection).
 struct EntryArgs {
@@ -172,6 +180,7 @@ constexpr int kLsPack = 16;
 constexpr int32_t kLsTaskLen = 64;
 constexpr size_t kLsTriBytes = size_t(256) << 20;
 constexpr double kCondLimitDefault = 1e10;
+constexpr size_t kKeepBytes = size_t(512) << 20;   // kept deltas, at most
 constexpr uint8_t kLsOwnError = 2;
 constexpr uint8_t kLsIdentity = 3;
 struct SolveFlags {
@@ -214,7 +223,21 @@ struct LsArgs {
     int32_t *stats;                   // [0] rows left unsolved (result not
                                       // finite), [1] rows solved here,
                                       // [2] most entries of such a row
+    // optional: the deltas the row-system kernel of this mode update kept
+    // (GramArgs::kbase / keep); a row with kbase[i] != kNoKeep reads them
+    // instead of recomputing
+    const int64_t *kbase;
+    const double *keep;
 };
+
+// Plan of the kept deltas for the next update of a mode: every row that the
+// least-squares form solved in this one (rflag != 0) gets a run of slots,
+// one per entry, when all of them fit in kcap entries; else, and for the
+// other rows, kNoKeep. With rflag null every row gets kNoKeep. used: a
+// device counter of the library (zeroed here).
+hipError_t launch_keep_plan(const uint8_t *rflag, const int64_t *rowptr, int64_t I,
+                            int64_t kcap, int64_t *kbase, unsigned long long *used,
+                            hipStream_t st);
 // equal_fast: the (N, J) of an unrolled delta kernel with all ranks J
 hipError_t launch_ls(const LsArgs &a, int N, bool equal_fast, int num_cu,
                      hipStream_t st);

@@ -114,6 +114,13 @@ __global__ __launch_bounds__(kWave) void k_gram_fast(GramArgs a) {
         __syncthreads();
         double d[J];
         delta_fast<NO, J, U, T>(a.gp, s_aout, lane, ain, d);
+        if (a.kbase && valid) {              // deltas of least-squares rows
+            const int64_t kb = a.kbase[row];
+            if (kb != kNoKeep) {
+#pragma unroll
+                for (int j = 0; j < J; ++j) a.keep[(kb + pos) * J + j] = d[j];
+            }
+        }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < J; ++j) s_dl[j * kDlStride + lane] = d[j];

@@ -133,6 +133,26 @@ __device__ __forceinline__ void entry_delta(const LsArgs &a, int64_t pos, bool v
     x = valid ? (double)a.val[pos] : 0.0;
 }
 
+// The same from the deltas the row-system kernel kept for row i (kbase of
+// the row, kNoKeep: recompute).
+template <int JMAX, int NS, int JS>
+__device__ __forceinline__ void row_delta(const LsArgs &a, int64_t kb, int64_t pos,
+                                          bool valid, float *lds, int lane,
+                                          double (&d)[JMAX], double &x) {
+    if (kb != kNoKeep) {
+        const double *src = a.keep + (kb + pos) * a.jn;
+#pragma unroll
+        for (int j = 0; j < JMAX; ++j) d[j] = (valid && j < a.jn) ? src[j] : 0.0;
+        x = valid ? (double)a.val[pos] : 0.0;
+        return;
+    }
+    entry_delta<JMAX, NS, JS>(a, pos, valid, lds, lane, d, x);
+}
+
+__device__ __forceinline__ int64_t row_kbase(const LsArgs &a, int64_t i) {
+    return a.kbase ? a.kbase[i] : kNoKeep;
+}
+
 // Per-wavefront counts of the rows solved here, flushed with one atomic each
 // at the end of a kernel.
 struct LsStats {
@@ -259,11 +279,12 @@ __global__ __launch_bounds__(kWave) void k_ls(LsArgs a) {
         const int64_t r1row = a.rowptr[i + 1];
         const int64_t r0 = a.rowptr[i] + q * L;
         const int64_t r1 = min(r0 + L, r1row);
+        const int64_t kb = row_kbase(a, i);
         double rc[JMAX];
         ls_init<JMAX>(rc, q == 0 ? sl : 0.0, jn, lane);
         for (int64_t c0 = r0; c0 < r1; c0 += kWave) {
             double d[JMAX], x;
-            entry_delta<JMAX, NS, JS>(a, c0 + lane, c0 + lane < r1, lds, lane, d, x);
+            row_delta<JMAX, NS, JS>(a, kb, c0 + lane, c0 + lane < r1, lds, lane, d, x);
             ls_merge<JMAX, kWave>(rc, d, x, jn, lane);
         }
         double *tri = a.tri + t * (int64_t)jn * (jn + 1);
@@ -280,11 +301,12 @@ __global__ __launch_bounds__(kWave) void k_ls(LsArgs a) {
     for (int64_t s = gw; s < nsingle; s += nw) {
         const int64_t i = f.list[f.cap - 1 - s];
         const int64_t r0 = a.rowptr[i], r1 = a.rowptr[i + 1];
+        const int64_t kb = row_kbase(a, i);
         double rc[JMAX], d0[JMAX], x0 = 0.0;
         ls_init<JMAX>(rc, sl, jn, lane);
         for (int64_t c0 = r0; c0 < r1; c0 += kWave) {
             double d[JMAX], x;
-            entry_delta<JMAX, NS, JS>(a, c0 + lane, c0 + lane < r1, lds, lane, d, x);
+            row_delta<JMAX, NS, JS>(a, kb, c0 + lane, c0 + lane < r1, lds, lane, d, x);
 #pragma unroll
             for (int j = 0; j < JMAX; ++j) d0[j] = d[j];
             x0 = x;
@@ -305,7 +327,7 @@ __global__ __launch_bounds__(kWave) void k_ls(LsArgs a) {
             } else {
                 for (int64_t c0 = r0; c0 < r1; c0 += kWave) {
                     double d[JMAX], x;
-                    entry_delta<JMAX, NS, JS>(a, c0 + lane, c0 + lane < r1, lds, lane, d, x);
+                    row_delta<JMAX, NS, JS>(a, kb, c0 + lane, c0 + lane < r1, lds, lane, d, x);
                     double pr = 0.0;
 #pragma unroll
                     for (int j = 0; j < JMAX; ++j)
@@ -328,7 +350,8 @@ __global__ __launch_bounds__(kWave) void k_ls(LsArgs a) {
             const int64_t i = has ? f.list[t] : 0;
             const int64_t r0 = has ? a.rowptr[i] : 0, r1 = has ? a.rowptr[i + 1] : 0;
             double d[JMAX], x;
-            entry_delta<JMAX, NS, JS>(a, r0 + e, r0 + e < r1, lds, lane, d, x);
+            row_delta<JMAX, NS, JS>(a, has ? row_kbase(a, i) : kNoKeep, r0 + e, r0 + e < r1,
+                                    lds, lane, d, x);
             double d0[JMAX];
 #pragma unroll
             for (int j = 0; j < JMAX; ++j) d0[j] = d[j];
@@ -413,6 +436,53 @@ __global__ __launch_bounds__(kWave *W) void k_ls_merge(LsArgs a) {
         __syncthreads();
     }
     if (w == 0) st.flush(a.stats, lane);
+}
+
+// Plan of the kept deltas: slots by one atomic per wavefront (their order
+// varies, the deltas stored in them do not), then, when the rows do not all
+// fit, no row is kept, so the set of kept rows never depends on that order.
+__global__ void k_keep_zero(unsigned long long *used) { *used = 0; }
+
+__global__ __launch_bounds__(256) void k_keep_slots(const uint8_t *__restrict__ rflag,
+                                                    const int64_t *__restrict__ rowptr,
+                                                    int64_t I, int64_t *__restrict__ kbase,
+                                                    unsigned long long *used) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x % kWave;
+    const bool keep = rflag && i < I && rflag[i] != 0;
+    const int64_t cnt = keep ? rowptr[i + 1] - rowptr[i] : 0;
+    int64_t incl = cnt;                      // inclusive prefix within the wavefront
+#pragma unroll
+    for (int off = 1; off < kWave; off *= 2) {
+        const int64_t v = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += v;
+    }
+    unsigned long long base = 0;
+    if (lane == kWave - 1 && incl > 0) base = atomicAdd(used, (unsigned long long)incl);
+    base = __shfl(base, kWave - 1, kWave);
+    if (i < I) kbase[i] = keep ? (int64_t)base + (incl - cnt) - rowptr[i] : kNoKeep;
+}
+
+__global__ __launch_bounds__(256) void k_keep_check(int64_t I, int64_t kcap,
+                                                    int64_t *__restrict__ kbase,
+                                                    const unsigned long long *used) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < I && *used > (unsigned long long)kcap) kbase[i] = kNoKeep;
+}
+
+hipError_t launch_keep_plan(const uint8_t *rflag, const int64_t *rowptr, int64_t I,
+                            int64_t kcap, int64_t *kbase, unsigned long long *used,
+                            hipStream_t st) {
+    if (I <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((I + 255) / 256);
+    hipLaunchKernelGGL(k_keep_zero, dim3(1), dim3(1), 0, st, used);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_keep_slots, dim3(blocks), dim3(256), 0, st, rflag, rowptr, I, kbase,
+                       used);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_keep_check, dim3(blocks), dim3(256), 0, st, I, kcap, kbase, used);
+    return hipGetLastError();
 }
 
 namespace {

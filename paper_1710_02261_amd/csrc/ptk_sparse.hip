@@ -296,10 +296,18 @@ __global__ __launch_bounds__(kWave) void k_gram_sparse(GramArgs a, SparseMode sm
 #pragma unroll
                 for (int j = 0; j < J; ++j) a.dstore[(int64_t)j * a.nnz + pos] = d[q][j];
             }
+            const int rw = valid ? (a.rows ? a.rows[pos] : 0) : 0;
+            if (a.kbase && valid) {          // deltas of least-squares rows
+                const int64_t kb = a.kbase[rw];
+                if (kb != kNoKeep) {
+#pragma unroll
+                    for (int j = 0; j < J; ++j) a.keep[(kb + pos) * J + j] = d[q][j];
+                }
+            }
 #pragma unroll
             for (int j = 0; j < J; ++j) s_dl[j * kDlStride + lane] = d[q][j];
             s_dl[J * kDlStride + lane] = valid ? (double)a.val[pos] : 0.0;
-            s_row[lane] = valid ? (a.rows ? a.rows[pos] : 0) : 0;
+            s_row[lane] = rw;
             __syncthreads();
             sweep_tile<EPL>(a, sl, s_dl, s_row, nb, cur, chunk, cs, ce);
             __syncthreads();
