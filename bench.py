@@ -72,6 +72,71 @@ def traffic_record(launch_nnz):
     return rec.get("bytes_per_launch")
 
 
+HEADLINE_KERNEL = "void ptk::k_gram_fast2<4, 10, 1, double, false>(ptk::GramArgs)"
+COPY_KERNEL_TAG = "MulFunctor<float>"
+
+
+def traffic_summary(fetch_csv, write_csv, launches):
+    """HBM traffic of the headline kernel from two rocprofv3 --pmc runs of
+    `bench.py --no-cpu --no-variant --steps 2 --warmup 1 --copy-calibration`
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch): the last `launches`
+    dispatches of the kernel, each counter scaled by what it reads for the
+    copy kernel (256 MiB read and written). Writes TRAFFIC_FILE."""
+    import csv
+
+    def per_dispatch(path, counter):
+        vals = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                key = int(r["Dispatch_Id"])
+                name = r["Kernel_Name"]
+                old = vals.get(key, (name, 0.0))
+                vals[key] = (name, old[1] + float(r["Counter_Value"]))
+        return [vals[k] for k in sorted(vals)]
+
+    out = {"kernel": HEADLINE_KERNEL,
+           "workload": "order-4 100000^4, 1e7 entries Zipf(1.1), J=10, FP64 arithmetic, "
+                       "autotuned work ranges",
+           "kernel_sha": kernel_hash()}
+    cal = {"kernel": "torch.mul of 64 Mi float32 (reads and writes 256 MiB)"}
+    for tag, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"),
+                               ("write", write_csv, "WRITE_SIZE")):
+        rows = per_dispatch(path, counter)
+        copy = [v for n, v in rows if COPY_KERNEL_TAG in n]
+        gram = [v for n, v in rows if n == HEADLINE_KERNEL][-launches:]
+        if not copy or len(gram) < launches:
+            raise SystemExit("traffic summary: missing copy or kernel dispatches in " + path)
+        copy_kib = float(np.mean(copy))
+        scale = 262144.0 / copy_kib
+        raw = float(np.mean(gram))
+        cal[tag + "_kib_read"] = copy_kib
+        cal[tag + "_scale"] = scale
+        out[tag + "_kib_raw_avg"] = raw
+        out[tag + "_bytes_per_launch"] = raw * scale * 1024.0
+    out["bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    out["launches_averaged"] = launches
+    out["calibration"] = cal
+    out["commands"] = [
+        "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE "
+        "--kernel-trace -f csv -d $R/gpurun_out/pmc_fetch -o fetch -- python3 $R/bench.py "
+        "--no-cpu --no-variant --steps 2 --warmup 1 --copy-calibration",
+        "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE "
+        "--kernel-trace -f csv -d $R/gpurun_out/pmc_write -o write -- python3 $R/bench.py "
+        "--no-cpu --no-variant --steps 2 --warmup 1 --copy-calibration",
+        "python bench.py --traffic-summary $R/gpurun_out/pmc_fetch/fetch_counter_collection.csv "
+        "$R/gpurun_out/pmc_write/write_counter_collection.csv"]
+    out["note"] = ("R = repository root; counters per dispatch in KiB; the averaged launches "
+                   "are the last ones of the run (warm-up, timed and event-timed iterations, "
+                   "after the autotuner). FETCH_SIZE counts L2 misses, served by HBM or the "
+                   "Infinity Cache.")
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out))
+
+
 def _oracle_rate(p, G, A, v, seconds, rng):
     """Seconds per entry-iteration of the oracle on a bounded sample of the
     workload: Alg. 3 row updates of random rows per mode (sized from a
@@ -447,6 +512,9 @@ def main():
                     help="print ms and non-zero core cells of each of K single "
                          "iterations: no removal, Approx with the dense kernels, "
                          "Approx with the sparse-core switch; one JSON line, exit")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the headline kernel's HBM traffic record from two "
+                         "rocprofv3 counter runs (see traffic_summary) and exit; no GPU")
     ap.add_argument("--fp64-ceiling", action="store_true",
                     help="print the sustained FP64 rates of the GPU (FMA loop, "
                          "matrix cores, both) as one JSON line and exit")
@@ -459,6 +527,11 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="launch kernels one by one instead of replaying a graph")
     args = ap.parse_args()
+
+    if args.traffic_summary:
+        # warm-up 1 + steps 2 + the event-timed pass, one launch per mode each
+        traffic_summary(args.traffic_summary[0], args.traffic_summary[1], 5 * 4)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
