@@ -91,7 +91,8 @@ __global__ void k_mfma_frags(const float *__restrict__ G, __bf16 *__restrict__ f
 // the kernel
 // ---------------------------------------------------------------------------
 template <int N, int J, int SPLIT>
-__global__ __launch_bounds__(kWave * kMfmaWaves) void k_gram_mfma(MfmaArgs a) {
+__global__ __launch_bounds__(kWave * kMfmaWaves, (N == 3 && SPLIT == 1) ? 8 : 4) void k_gram_mfma(
+    MfmaArgs a) {
     constexpr int NO = N - 1;                 // other modes
     constexpr int NW = NO - 1;                // modes folded on the VALU
     constexpr int TILES = ipow(J, NW);
