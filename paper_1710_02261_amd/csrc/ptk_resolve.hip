@@ -49,6 +49,14 @@ __device__ __forceinline__ double ssum(double v) {
 
 // Reflect one chunk of rows [d | x] (one per lane, zero rows allowed) into
 // the segment's triangle rc; e is the lane's index within its segment.
+// Column j: v = [alpha - beta ; d_j] with beta = -sign(alpha) sqrt(alpha^2 +
+// sigma), sigma = ||d_j||^2; H = I - tau v v^T, tau = 2 / v^T v = -1 / (beta
+// v0). Applied to column q as rjq + g v0 / beta and d_q + g d_j / beta with
+// g = rjq + s / v0, s = d_j . d_q: every factor is bounded (|v0 / beta| in
+// [1, 2], |d_j / beta| <= 1, |s / v0| <= ||d_q||), so a column whose norm is
+// tiny or subnormal (the rounding left in the later columns of a chunk of
+// rank below J, which shrinks geometrically) gives no overflow, where tau
+// itself would.
 template <int JMAX, int SEG>
 __device__ __forceinline__ void ls_merge(double (&rc)[JMAX], double (&d)[JMAX], double &x,
                                          int jn, int e) {
@@ -62,22 +70,26 @@ __device__ __forceinline__ void ls_merge(double (&rc)[JMAX], double (&d)[JMAX], 
         const double mu = sqrt(alpha * alpha + sig);
         const double beta = alpha >= 0.0 ? -mu : mu;
         const double v0 = alpha - beta;        // |alpha| + mu: no cancellation
-        const double tau = skip ? 0.0 : 2.0 / (v0 * v0 + sig);   // 2 / v^T v
+        // mu >= v0 / 2 >= sqrt(sig) >= 2.2e-162 when sig > 0: finite inverses
+        const double rb = skip ? 0.0 : 1.0 / beta;
+        const double rv = skip ? 0.0 : 1.0 / v0;
+        const double vb = v0 * rb;             // in [-2, -1]
+        const double db = dj * rb;             // |.| <= 1
 #pragma unroll
         for (int q = j + 1; q < JMAX; ++q) {
             if (q >= jn) break;
             const double s = ssum<SEG>(dj * d[q]);
             const double rjq = __shfl(rc[j], q, SEG);
-            const double f = tau * (v0 * rjq + s);
-            if (e == q) rc[j] = rjq - f * v0;
-            d[q] = __builtin_fma(-f, dj, d[q]);
+            const double g = rjq + s * rv;
+            if (e == q) rc[j] = __builtin_fma(g, vb, rjq);
+            d[q] = __builtin_fma(g, db, d[q]);
         }
         {
             const double s = ssum<SEG>(dj * x);
             const double rjz = __shfl(rc[j], jn, SEG);
-            const double f = tau * (v0 * rjz + s);
-            if (e == jn) rc[j] = rjz - f * v0;
-            x = __builtin_fma(-f, dj, x);
+            const double g = rjz + s * rv;
+            if (e == jn) rc[j] = __builtin_fma(g, vb, rjz);
+            x = __builtin_fma(g, db, x);
         }
         if (e == j && !skip) rc[j] = beta;
         d[j] = 0.0;

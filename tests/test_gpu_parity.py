@@ -141,11 +141,38 @@ def test_update_with_rows_split_across_ranges(chunk):
 
 
 def test_update_fp32_arithmetic_stated_tolerance():
-    """fp32 delta arithmetic (PTK_PREC_FP32): per-row error reported, <= 1e-3."""
-    for dims, ranks, nnz in FAST[:4]:
+    """FP32 delta arithmetic (PTK_PREC_FP32) with the default solve limit: an
+    FP32 delta carries a relative error of a few 1e-8, which a row solve
+    amplifies by up to cond(B_i + lambda I); on these shapes the worst row
+    reaches about 2e-5 (measured 4e-6 .. 2.1e-5), held here to 1e-4."""
+    for dims, ranks, nnz in FAST:
         p = problem(dims, ranks, nnz, seed=6)
-        w = _check_update(p, precision=1, tol=1e-3)
+        w = _check_update(p, precision=1, tol=1e-4)
         log("fp32 arithmetic", dims, ranks, "worst per-row rel err", w)
+
+
+def test_update_fp32_arithmetic_at_1e5_with_fp64_least_squares():
+    """FP32 delta arithmetic meets 1e-5 per row when every row whose
+    condition estimate exceeds 1e3 (1e-5 over the FP32 delta error) is solved
+    in the least-squares form, whose deltas are FP64."""
+    for dims, ranks, nnz in FAST:
+        p = problem(dims, ranks, nnz, seed=6)
+        ctx, idx, val, core, fac = context(p, precision=1)
+        ctx.set_options(precision=1, cond_limit=1e3)
+        G, A, v = oracle_inputs(p)
+        worst = 0.0
+        for n in range(p.N):
+            before = [f.clone() for f in fac]
+            ctx.update_mode(n, p.lam)
+            want = oracle.update_rows(G, A, p.idx, v, n, p.lam)
+            nz = np.bincount(p.idx[n], minlength=p.dims[n]) > 0
+            err = row_rel_err(f64(fac[n])[nz], want[nz])
+            worst = max(worst, float(err.max()))
+            for f, b in zip(fac, before):
+                f.copy_(b)
+        ctx.close()
+        log("fp32 arithmetic, limit 1e3", dims, ranks, "worst", worst)
+        assert worst <= 1e-5
 
 
 def test_empty_rows_and_empty_observed_set():
@@ -176,9 +203,25 @@ def test_iterate_trajectory_c1_matches_oracle():
     log("c1 sse gpu", sse, "oracle", S)
     np.testing.assert_allclose(sse, S, rtol=1e-4)
     np.testing.assert_allclose(loss, L[:, -1], rtol=1e-4)
-    for n in range(3):
-        err = row_rel_err(f64(fac[n]), Af[n])
-        assert np.median(err) < 1e-4
+    ctx.close()
+    # iteration by iteration from the same state: the oracle replays each
+    # iteration from the GPU's factors, rounding its rows to FP32 after each
+    # mode as the library stores them; every row to 1e-5
+    ctx, idx, val, core, fac = context(p)
+    for t in range(p.iters):
+        A = [f64(f) for f in fac]
+        s1, _ = ctx.iterate(1, p.lam)
+        for n in range(p.N):
+            A = oracle.update_mode(G, A, p.idx, v, n, p.lam)
+            A[n] = A[n].astype(np.float32).astype(np.float64)
+        worst = 0.0
+        for n in range(p.N):
+            nz = np.bincount(p.idx[n], minlength=p.dims[n]) > 0
+            worst = max(worst, float(row_rel_err(f64(fac[n])[nz], A[n][nz]).max()))
+        want = oracle.sse(G, A, p.idx, v)
+        log("c1 iteration", t, "worst row", worst, "sse", s1[0], want)
+        assert worst <= 1e-5
+        assert abs(s1[0] - want) <= 1e-6 * want
     ctx.close()
 
 
@@ -392,4 +435,45 @@ def test_huge_sparse_mode_64bit_offsets():
     mask = torch.ones(I0, dtype=torch.bool, device=dev)
     mask[torch.from_numpy(used.astype(np.int64)).to(dev)] = False
     assert bool(torch.all(A0[mask] == 0))
+    ctx.close()
+
+
+def _rows_of_counts(J, counts, seed, N=3, other=40):
+    """A problem whose mode-0 row r has exactly counts[r] entries (distinct
+    random cells of the other modes), planted model and values."""
+    rng = np.random.default_rng(seed)
+    dims = (len(counts),) + (other,) * (N - 1)
+    idx = []
+    for r, c in enumerate(counts):
+        cells = set()
+        while len(cells) < c:
+            cells.add(tuple(int(x) for x in rng.integers(0, other, size=N - 1)))
+        idx.extend((r,) + cc for cc in sorted(cells))
+    p = synth.make_small(dims, (J,) * N, 10, seed=seed)
+    p.idx = np.array(idx, dtype=np.int32).T.copy()
+    p.val = rng.normal(size=p.idx.shape[1]).astype(np.float32)
+    return p
+
+
+@pytest.mark.parametrize("J", [8, 11, 16])
+def test_least_squares_rows_of_every_chunk_remainder(J):
+    """Every row through the least-squares form (cond_limit = 1): rows whose
+    last 64-entry chunk holds 1, 2, ... entries. A chunk of rank below J
+    leaves rounding in its later columns that shrinks geometrically into the
+    subnormal range after about ten columns; the reflections must stay finite
+    there (rows of 65, 129, 193 entries at J = 16 were once left unsolved)."""
+    import paper_1710_02261_amd as ptk
+    counts = [1, 2, 17, 63, 64, 65, 66, 100, 128, 129, 130, 193, 257]
+    p = _rows_of_counts(J, counts, seed=40 + J)
+    ctx, idx, val, core, fac = context(p)
+    ctx.set_options(precision=0, cond_limit=1.0)
+    ctx.update_mode(0, p.lam)                       # raises if a row is left unsolved
+    solved, most = ctx.solve_stats()
+    assert solved == len(counts) and most == max(counts)
+    G = p.core.astype(np.float64)
+    A = [a.astype(np.float64) for a in p.factors]
+    want = oracle.update_rows(G, A, p.idx, p.val.astype(np.float64), 0, p.lam)
+    err = row_rel_err(f64(fac[0]), want)
+    log("least squares J", J, dict(zip(counts, ["%.1e" % x for x in err])))
+    assert err.max() <= 1e-5
     ctx.close()
