@@ -73,6 +73,9 @@ def traffic_record(launch_nnz):
 
 
 HEADLINE_KERNEL = "void ptk::k_gram_fast2<4, 10, 1, double, false>(ptk::GramArgs)"
+# a precision form is reported with throughput when its RMSE after the run is
+# at most this much above the FP64 path's (the comparison at equal RMSE)
+USABLE_RMSE = 0.10
 COPY_KERNEL_TAG = "MulFunctor<float>"
 
 
@@ -743,30 +746,43 @@ def main():
                                             for k, t in v["times"].items()}}
             log("%s: %.2f ms/step, rmse %.6g (main %.6g)" % (
                 name, variants[name]["ms_per_step"], v["rmse"], r["rmse"]))
+        runs = {}
         for prec in PREC_NAMES:
             if prec == main_prec:
                 continue
             if prec.startswith("bf16") and not (N in (3, 4) and J in (8, 10, 16)
                                                 and len(set(p.ranks)) == 1):
                 continue
-            v = run(prec)
-            if v["diverged"]:
-                # the fit failed: no throughput is reported for it
-                variants[prec] = {"diverged": True, "status": "PTK_E_DIVERGED",
-                                  "rmse_after": v["rmse"],
-                                  "note": "error or loss not finite, or the loss rose: "
-                                          "not a usable form on this workload"}
-                log("%s: diverged (rmse %.6g), no throughput reported" % (prec, v["rmse"]))
+            runs[prec] = run(prec)
+        # a form whose fit is not within USABLE_RMSE of the FP64 path's RMSE
+        # after the same iterations (or that diverged) gets no throughput
+        rmse64 = r["rmse"] if main_prec == "f64" else runs.get("f64", {}).get("rmse")
+        for prec, v in runs.items():
+            rel64 = v["rmse"] / rmse64 - 1.0 if rmse64 else None
+            if v["diverged"] or (rel64 is not None and not (rel64 <= USABLE_RMSE)):
+                why = ("error or loss not finite, or the loss rose" if v["diverged"] else
+                       "RMSE more than %d %% above the FP64 path's" % round(100 * USABLE_RMSE))
+                variants[prec] = {"unusable": True, "diverged": bool(v["diverged"]),
+                                  "rmse_after": v["rmse"], "rmse_rel_to_f64": rel64,
+                                  "note": why + ": not a usable form on this workload, "
+                                          "no throughput reported"}
+                log("%s: unusable (rmse %.6g, %s), no throughput reported" % (prec, v["rmse"], why))
                 continue
             variants[prec] = {"value": v["value"], "ms_per_step": 1e3 * v["elapsed"] / args.steps,
                               "gram_ms": v["gram_ms"], "rmse_after": v["rmse"],
-                              "rmse_rel_to_main": v["rmse"] / r["rmse"] - 1.0}
+                              "rmse_rel_to_main": v["rmse"] / r["rmse"] - 1.0,
+                              "rmse_rel_to_f64": rel64}
             log("%s: %.2f ms/step, rmse %.6g (main %.6g)" % (
                 prec, variants[prec]["ms_per_step"], v["rmse"], r["rmse"]))
+        if main_prec != "f64" and rmse64:
+            out["rmse_rel_to_f64"] = r["rmse"] / rmse64 - 1.0
+            out["usable"] = bool(out["rmse_rel_to_f64"] <= USABLE_RMSE and not r["diverged"])
         out["variants"] = variants
         out["variants_note"] = ("same workload, init and iteration count; rmse_after = "
                                 "sqrt(SSE/nnz) by a direct FP64 pass after warmup+steps "
-                                "iterations")
+                                "iterations; a form whose RMSE is more than %d %% above the "
+                                "FP64 path's is marked unusable and gets no throughput"
+                                % round(100 * USABLE_RMSE))
     if not args.no_cpu and args.workload == "c2":
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
