@@ -230,7 +230,7 @@ ptk_status ptk_bind_model(ptk_ctx *ctx, float *core, float *const *factors_host)
 ptk_status ptk_update_mode(ptk_ctx *ctx, int32_t n, double lambda);
 
 /*
- * iters iterations of Alg. 2 (lines 3-4): modes 0..N-1 in order, then the
+ * iters iterations of Alg. 2: modes 0..N-1 in order, then the
  * reconstruction error. sse_host[t] / loss_host[t] (either may be NULL)
  * receive, after iteration t, sum over Omega of (x - x_hat)^2 (the square of
  * eq. "reconfull") and the loss of eq. "TF_PARTIAL". Every row is solved as
@@ -298,12 +298,16 @@ ptk_status ptk_fold_in_noalloc(ptk_ctx *ctx, int32_t n, int64_t k, const int32_t
  * schedule of Sec. 3.4). For every mode it times the row-system kernels
  * (delta, Gram, merge) of the bound model on the observed set for several
  * sizes of the per-wavefront work ranges (entries per range for the FP64 /
- * FP32 forms, 32-entry blocks per range for the BF16 forms) and keeps the
- * fastest; the model is not modified. cache_path (host string, may be NULL)
- * names a text file of "key value" lines keyed by order, ranks, precision,
- * entry count, mode size and the mode's row-length histogram: a hit is
- * applied without timing, a new result is appended. work_host (NULL or N
- * entries) receives the chosen sizes. Synchronises the stream.
+ * FP32 forms, 32-entry blocks per range for the BF16 forms) and, where both
+ * are compiled (FP64 arithmetic at (N, J) = (4, 10) and (5, 8)), for tiles of
+ * one and of two entries per lane, and keeps the fastest; the model is not
+ * modified. Rows are cut at any entry between ranges (their pieces are merged
+ * in range order), so there is no row-split threshold to choose. cache_path
+ * (host string, may be NULL) names a text file of "key work" or "key work
+ * two" lines keyed by order, ranks, precision, entry count, mode size and the
+ * mode's row-length histogram: a hit is applied without timing, a new result
+ * is appended. work_host (NULL or N entries) receives the chosen sizes.
+ * Synchronises the stream.
  */
 ptk_status ptk_autotune(ptk_ctx *ctx, const char *cache_path, int64_t *work_host);
 

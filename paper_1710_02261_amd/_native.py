@@ -506,6 +506,20 @@ class Server:
             self._h, int(idx.shape[1]), idx.ctypes.data_as(_vp), C.byref(t)))
         return t.value
 
+    def submit_foldin_ptr(self, n, k, idx_addr, val_addr):
+        """submit_foldin from host addresses of contiguous int32 [N][k] indices
+        and float32 [k] values (no conversion: for load generators)."""
+        t = C.c_uint64()
+        self._check(self._lib.ptk_server_submit_foldin(self._h, n, k, idx_addr, val_addr,
+                                                       C.byref(t)))
+        return t.value
+
+    def submit_predict_ptr(self, m, idx_addr):
+        """submit_predict from the host address of contiguous int32 [N][m]."""
+        t = C.c_uint64()
+        self._check(self._lib.ptk_server_submit_predict(self._h, m, idx_addr, C.byref(t)))
+        return t.value
+
     def poll(self, ticket, size):
         out = np.zeros(max(int(size), 1), dtype=np.float32)
         done, st, lat = _i32(), C.c_int(), _dbl()

@@ -355,7 +355,7 @@ ptk_status systems(ptk_ctx *c, int n, int role = 0) {
         return PTK_OK;
     }
     GramArgs a = gram_args(c, n);
-    const bool two = m.fast && gram2_available(c->s.N, c->s.ranks[n], arith_of(c, n));
+    const bool two = m.fast && m.two && gram2_available(c->s.N, c->s.ranks[n], arith_of(c, n));
     if (two && c->ap_store && c->ap_delta) {
         a.dstore = c->ap_delta;
         c->ap_stored = true;
@@ -580,7 +580,7 @@ int64_t default_work(const ptk_ctx *c, int n) {
     const int bpc = (m.slices > 1 && role != 2)
                         ? gram_slices_blocks_per_cu(c->s.ranks[n])
                     : role ? gram_cache_blocks_per_cu(c->s, n, arith_of(c, n), role)
-                    : (m.fast && gram2_available(c->s.N, c->s.ranks[n], arith_of(c, n)))
+                    : (m.fast && m.two && gram2_available(c->s.N, c->s.ranks[n], arith_of(c, n)))
                         ? gram2_blocks_per_cu(c->s.N, c->s.ranks[n], arith_of(c, n))
                         : gram_blocks_per_cu(c->s, n, arith_of(c, n), m.fast);
     const int64_t waves = (int64_t)c->num_cu * std::max(1, bpc);
@@ -812,7 +812,7 @@ ptk_status approx_step(ptk_ctx *c, double p, bool remove, bool deltas_kept = fal
     return PTK_OK;
 }
 
-// One iteration of Alg. 2 (lines 3-4) as stream-ordered kernels only: the
+// One iteration of Alg. 2 as stream-ordered kernels only: the
 // N mode updates, the error and the factor norms, stored to dres through the
 // device counter. Contains no memset, copy or synchronisation, so it can be
 // captured into a graph and replayed.
@@ -1821,7 +1821,9 @@ std::string tune_key(const ptk_ctx *c, int n) {
     return k;
 }
 
-bool tune_lookup(const char *path, const std::string &key, int64_t *value) {
+// A line is "key work" or "key work two" (two: 1 = two entries per lane,
+// 0 = one; absent = the default).
+bool tune_lookup(const char *path, const std::string &key, int64_t *value, int *two) {
     if (!path) return false;
     FILE *f = fopen(path, "r");
     if (!f) return false;
@@ -1832,7 +1834,10 @@ bool tune_lookup(const char *path, const std::string &key, int64_t *value) {
         if (!sp) continue;
         *sp = 0;
         if (key == line) {
-            *value = strtoll(sp + 1, nullptr, 10);
+            char *end = nullptr;
+            *value = strtoll(sp + 1, &end, 10);
+            *two = -1;
+            if (end && *end == ' ') *two = (int)strtol(end + 1, nullptr, 10) ? 1 : 0;
             hit = true;        // the last entry for a key wins
         }
     }
@@ -1840,11 +1845,12 @@ bool tune_lookup(const char *path, const std::string &key, int64_t *value) {
     return hit && *value > 0;
 }
 
-void tune_store(const char *path, const std::string &key, int64_t value) {
+void tune_store(const char *path, const std::string &key, int64_t value, int two) {
     if (!path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %lld\n", key.c_str(), (long long)value);
+    if (two >= 0) fprintf(f, "%s %lld %d\n", key.c_str(), (long long)value, two);
+    else fprintf(f, "%s %lld\n", key.c_str(), (long long)value);
     fclose(f);
 }
 
@@ -1861,36 +1867,47 @@ extern "C" ptk_status ptk_autotune(ptk_ctx *c, const char *cache_path, int64_t *
         ModeData &m = c->md[n];
         const std::string key = tune_key(c, n);
         int64_t best = 0;
-        if (!tune_lookup(cache_path, key, &best)) {
-            const int64_t base = default_work(c, n);
+        int best_two = -1;
+        // tile shape: one or two entries per lane, where both are compiled
+        const int role = cache_role(c, n);
+        const bool both = !m.bf16 && m.fast && role == 0 && m.slices <= 1 &&
+                          gram2_available(c->s.N, c->s.ranks[n], arith_of(c, n));
+        if (!tune_lookup(cache_path, key, &best, &best_two)) {
             const double mult[] = {0.125, 0.25, 0.5, 1.0, 2.0};
             double best_ms = 1e300;
-            const int role = cache_role(c, n);
             HIPCHK(c, permute(c, n, role));
-            for (double f : mult) {
-                int64_t w = (int64_t)(base * f);
-                w = m.bf16 ? std::max<int64_t>(w, 1) : std::max<int64_t>(round_up(w, kWave), kWave);
-                if ((s = configure_ranges(c, n, w)) != PTK_OK) break;
-                if ((s = systems(c, n, role)) != PTK_OK) break;    // warm-up
-                double ms_min = 1e300;
-                for (int rep = 0; rep < 3 && s == PTK_OK; ++rep) {
-                    HIPCHK(c, hipEventRecord(e0, c->st));
-                    s = systems(c, n, role);
-                    HIPCHK(c, hipEventRecord(e1, c->st));
-                    HIPCHK(c, hipEventSynchronize(e1));
-                    float ms = 0.f;
-                    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-                    ms_min = std::min(ms_min, (double)ms);
-                }
-                if (s != PTK_OK) break;
-                if (ms_min < best_ms) {
-                    best_ms = ms_min;
-                    best = m.bf16 ? m.blk_per_wave : m.chunk;
+            for (int two = both ? 1 : -1; two >= (both ? 0 : -1) && s == PTK_OK; --two) {
+                if (two >= 0) m.two = two != 0;
+                const int64_t base = default_work(c, n);
+                for (double f : mult) {
+                    int64_t w = (int64_t)(base * f);
+                    w = m.bf16 ? std::max<int64_t>(w, 1)
+                               : std::max<int64_t>(round_up(w, kWave), kWave);
+                    if ((s = configure_ranges(c, n, w)) != PTK_OK) break;
+                    if ((s = systems(c, n, role)) != PTK_OK) break;    // warm-up
+                    double ms_min = 1e300;
+                    for (int rep = 0; rep < 3 && s == PTK_OK; ++rep) {
+                        HIPCHK(c, hipEventRecord(e0, c->st));
+                        s = systems(c, n, role);
+                        HIPCHK(c, hipEventRecord(e1, c->st));
+                        HIPCHK(c, hipEventSynchronize(e1));
+                        float ms = 0.f;
+                        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+                        ms_min = std::min(ms_min, (double)ms);
+                    }
+                    if (s != PTK_OK) break;
+                    if (ms_min < best_ms) {
+                        best_ms = ms_min;
+                        best = m.bf16 ? m.blk_per_wave : m.chunk;
+                        best_two = two;
+                    }
                 }
             }
             if (s != PTK_OK) break;
-            tune_store(cache_path, key, best);
+            tune_store(cache_path, key, best, best_two);
         }
+        m.two = best_two != 0;
+        c->epoch++;
         s = configure_ranges(c, n, best);
         if (work_host) work_host[n] = m.bf16 ? m.blk_per_wave : m.chunk;
     }

@@ -26,6 +26,7 @@ struct ModeData {
     int32_t *split = nullptr;    // [nsplit][3]
     int32_t nsplit = 0;
     bool fast = false;
+    bool two = true;             // the two-entries-per-lane kernel where compiled (tuned)
     // generic path on a small observed set: the delta sum cut into slices
     // of the core cells (1: unsliced), sub slices per partner index, W
     // slices per workgroup

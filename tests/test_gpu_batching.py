@@ -67,9 +67,14 @@ def test_graph_replay_after_rebinding_model():
 @pytest.mark.parametrize("prec,dims,ranks", [
     (0, (80, 70, 60), (5, 5, 5)),
     (0, (20, 18, 16, 14, 12), (3, 3, 3, 3, 3)),
+    (0, (30, 28, 26, 24), (10, 10, 10, 10)),         # tile shape searched too
+    (0, (14, 13, 12, 11, 10), (8, 8, 8, 8, 8)),      # tile shape searched too
     (2, (80, 70, 60), (16, 16, 16)),
 ])
 def test_autotune_then_update_matches_oracle(prec, dims, ranks, tmp_path):
+    """The tuner picks the work-range size of every mode and, where both are
+    compiled (FP64 at (4, 10) and (5, 8)), one or two entries per lane; the
+    choice is cached ("key work [two]") and applied again from the cache."""
     p = synth.make_small(dims, ranks, 8000, seed=23, skew=1.2)
     if prec == 2:
         # integer data: the BF16 path is exact there
@@ -84,6 +89,9 @@ def test_autotune_then_update_matches_oracle(prec, dims, ranks, tmp_path):
     log("autotuned work per mode", work)
     assert all(w > 0 for w in work)
     assert os.path.getsize(cache) > 0
+    fields = [len(line.split()) for line in open(cache)]
+    both = prec == 0 and (len(dims), ranks[0]) in ((4, 10), (5, 8))
+    assert fields == [3 if both else 2] * len(dims)
     G = p.core.astype(np.float64)
     A = [a.astype(np.float64) for a in p.factors]
     v = p.val.astype(np.float64)
