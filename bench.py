@@ -545,6 +545,9 @@ def main():
                     help="keep the default work-range sizes")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch kernels one by one instead of replaying a graph")
+    ap.add_argument("--shared-units", type=int, default=0, choices=[-1, 0, 1, 2, 4, 8],
+                    help="ptk_options.shared_units (0 auto, -1 never, 1 always, "
+                         "2/4/8 always with that cap)")
     args = ap.parse_args()
 
     if args.traffic_summary:
@@ -613,7 +616,7 @@ def main():
         ctx = ptk.Context(p.dims, p.ranks)
         ctx.set_options(precision=PREC_NAMES[prec], fuse_error=1, profile=0,
                         use_graph=use_graph, pair_cache=cache, approx_rate=approx,
-                        sparse_limit=args.sparse_limit)
+                        sparse_limit=args.sparse_limit, shared_units=args.shared_units)
         torch.cuda.synchronize()
         ts = time.perf_counter()
         ctx.set_observed(idx, val)
@@ -638,12 +641,13 @@ def main():
         not_pd = ctx.not_pd_count()
         ls_rows, ls_max = ctx.solve_stats()
         core_left = int(torch.count_nonzero(core_run))
+        units = [ctx.unit_stats(n) for n in range(N)]
         # the model's error by a direct FP64 pass over all entries (untimed)
         _, rmse_direct, _ = ctx.recon_error(p.lam)
         # second pass with per-kernel HIP events on the library's stream
         ctx.set_options(precision=PREC_NAMES[prec], fuse_error=1, profile=1,
                         use_graph=use_graph, pair_cache=cache, approx_rate=approx,
-                        sparse_limit=args.sparse_limit)
+                        sparse_limit=args.sparse_limit, shared_units=args.shared_units)
         ctx.reset_timers()
         ctx.iterate(args.steps, p.lam, strict=False)
         times = ctx.kernel_times()
@@ -656,6 +660,7 @@ def main():
                 "value": p.nnz * args.steps / elapsed,
                 "rmse": float(rmse_direct), "work": work, "tune_s": tune_s,
                 "core_left": core_left, "ls_rows": ls_rows, "ls_max": ls_max,
+                "units": units,
                 "diverged": 8 in statuses,
                 "status": max(statuses, key=lambda v: v != 0),
                 "loss": [float(x) for x in loss],
@@ -676,12 +681,33 @@ def main():
                                 for k, v in sorted(r["times"].items())))
 
     avg_s = r["gram_ms"] / 1e3
+    unit_kernel = None
+    if any(on for _, on in r["units"]):
+        # shared-index units: the dominant kernel is the unit class with the
+        # most time; its work is the multiply-adds the unit form executes
+        # (J^(N-2) (J^2 + e (J + N - 3)) per unit of e entries)
+        best = None
+        for c in range(4):
+            name = "delta_units%d" % (1 << c)
+            calls, ms = r["times"].get(name, (0, 0.0))
+            if calls and (best is None or ms > best[2]):
+                best = (c, calls, ms)
+        c, calls, ms = best
+        e = 1 << c
+        per_unit = J ** (N - 2) * (J * J + e * (J + N - 3))
+        on_modes = [u for u, on in r["units"] if on]
+        unit_kernel = {"class": e, "avg_ms": ms / calls,
+                       "flops": 2.0 * per_unit * sum(u[c] for u in on_modes) / len(on_modes)}
+        avg_s = unit_kernel["avg_ms"] / 1e3
     if main_prec.startswith("bf16"):
         # matrix-core work per entry and mode: stage 1 J^N (+2x for the split
         # products), Gram J^2 (+2x); the VALU part is not counted here
         mult = 3 if main_prec == "bf16x3" else 1
         flops = 2.0 * p.nnz * mult * (J ** N + J * J)
         bound, unit = "mfma", "TFLOP/s"
+    elif unit_kernel:
+        flops = unit_kernel["flops"]
+        bound, unit = "alu", "TFLOP/s"
     else:
         flops = 2.0 * p.nnz * fma_per_nnz_mode(N, J)
         bound, unit = "alu", "TFLOP/s"
@@ -699,9 +725,13 @@ def main():
         kname = "k_gram_cache_write<%d,%d,%s>" % (N, J, "double" if main_prec == "f64"
                                                    else "float")
         traffic = None
+    if unit_kernel:
+        e = unit_kernel["class"]
+        kname = "k_delta_units<%d,%d,%d,%d>" % (N, J, e, 2 if e <= 2 else 1)
+        traffic = None
     roofline = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak, "traffic": traffic, "kernel": kname,
-                "avg_launch_ms": r["gram_ms"], "flops_per_launch": flops}
+                "avg_launch_ms": avg_s * 1e3, "flops_per_launch": flops}
     if main_prec == "f64":
         # context: what a plain loop of independent FP64 FMAs sustains here
         roofline["fma_loop_tflops"] = ptk.fp64_rates(2000)["fma_f64"]
@@ -738,6 +768,8 @@ def main():
         "loss_non_increasing": bool(all(b <= a * (1 + 1e-9)
                                         for a, b in zip(r["loss"], r["loss"][1:]))),
         "kernel_ms": {k: v[1] / max(v[0], 1) for k, v in r["times"].items()},
+        "shared_units": {"option": args.shared_units,
+                         "per_mode": [{"units_1_2_4_8": u, "on": on} for u, on in r["units"]]},
     }
     if not args.no_variant:
         variants = {}

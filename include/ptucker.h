@@ -162,10 +162,28 @@ typedef struct ptk_options {
                                the listed cells instead of the dense
                                contraction. Same result up to rounding order;
                                the switch is taken on the device, so it needs
-                               no synchronisation. 0 = the default, 0.2;
+                               no synchronisation. 0 = the default, 0.1;
                                negative = never; above 1 or not finite:
                                PTK_E_INVALID. Extra device memory with
                                approx_rate > 0: 16 * N * prod J_n bytes.      */
+    int32_t shared_units;   /* row systems (eqs. "rowB", "rowC") from shared-
+                               index units, FP64 arithmetic, equal ranks and
+                               (N, J) in {(3,16), (4,10), (5,8)}: the entries
+                               of every row are ordered by their index in the
+                               last other mode s, and consecutive entries of
+                               a row with the same i_s form units that share
+                               the core contracted with that mode's row
+                               (J^(N-1) multiply-adds per unit instead of per
+                               entry); deltas go through a J * nnz-double
+                               buffer. Same result up to rounding order. 0 =
+                               auto (per mode, when the units cut the
+                               modelled work by a tenth or more); -1 = never
+                               (rows keep the order of the input); 1 = always
+                               where available; 2, 4 or 8 = always, with
+                               units of at most that many entries. Chosen
+                               before ptk_set_observed; not used with
+                               pair_cache, approx_rate > 0 or the FP32 and
+                               BF16 forms. Other values: PTK_E_INVALID.      */
 } ptk_options;
 
 /*
@@ -277,6 +295,19 @@ ptk_status ptk_solve_stats(ptk_ctx *ctx, int64_t *ls_rows_host,
  */
 ptk_status ptk_approx_stats(ptk_ctx *ctx, int64_t *nonzero_cells_host,
                             int32_t *sparse_modes_host);
+
+/*
+ * Shared-index units of mode n (ptk_options.shared_units) built by the last
+ * ptk_set_observed: counts_host[c] receives the number of units of 2^c
+ * entries, c = 0..3 (a run of r consecutive entries of one row with the same
+ * index in the last other mode gives floor(r / emax) units of emax entries,
+ * then one unit for each set bit of r mod emax; emax is 8 at orders 3 and 4
+ * with J <= 10, else 4, or the option's cap if lower), and *on_host whether
+ * the row systems of mode n
+ * use them (1) or the fused kernels (0). All zero when no units were built.
+ * PTK_E_INVALID for n out of range, PTK_E_STATE before ptk_set_observed.
+ */
+ptk_status ptk_unit_stats(ptk_ctx *ctx, int32_t n, int64_t *counts_host, int32_t *on_host);
 
 /*
  * ptk_fold_in without any allocation, for callers that cannot allocate:

@@ -29,7 +29,8 @@ class _Options(C.Structure):
     _fields_ = [("precision", _i32), ("chunk_nnz", _i32), ("fuse_error", _i32),
                 ("profile", _i32), ("use_graph", _i32), ("pair_cache", _i32),
                 ("approx_rate", _dbl), ("delta_slices", _i32), ("tol", _dbl),
-                ("approx_form", _i32), ("cond_limit", _dbl), ("sparse_limit", _dbl)]
+                ("approx_form", _i32), ("cond_limit", _dbl), ("sparse_limit", _dbl),
+                ("shared_units", _i32)]
 
 
 class PtkError(RuntimeError):
@@ -74,6 +75,7 @@ def load_library():
         "ptk_not_pd_count": [_vp, C.POINTER(_i64)],
         "ptk_solve_stats": [_vp, C.POINTER(_i64), C.POINTER(_i64)],
         "ptk_approx_stats": [_vp, C.POINTER(_i64), C.POINTER(_i32)],
+        "ptk_unit_stats": [_vp, _i32, C.POINTER(_i64), C.POINTER(_i32)],
         "ptk_autotune": [_vp, C.c_char_p, C.POINTER(_i64)],
         "ptk_partial_error": [_vp, _vp],
         "ptk_truncate": [_vp, _dbl, C.POINTER(_i32)],
@@ -200,10 +202,10 @@ class Context:
     def set_options(self, precision=PREC_FP64_ACC, chunk_nnz=0, fuse_error=1,
                     profile=0, use_graph=1, pair_cache=0, approx_rate=0.0,
                     delta_slices=0, tol=0.0, approx_form=0, cond_limit=0.0,
-                    sparse_limit=0.0):
+                    sparse_limit=0.0, shared_units=0):
         o = _Options(precision, chunk_nnz, fuse_error, profile, use_graph, pair_cache,
                      float(approx_rate), delta_slices, float(tol), approx_form,
-                     float(cond_limit), float(sparse_limit))
+                     float(cond_limit), float(sparse_limit), shared_units)
         self._check(self._lib.ptk_set_options(self._h, C.byref(o)))
 
     def set_observed(self, idx, val):
@@ -277,6 +279,14 @@ class Context:
         a, b = _i64(), _i32()
         self._check(self._lib.ptk_approx_stats(self._h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def unit_stats(self, n):
+        """(units of 1, 2, 4, 8 entries, whether mode n's row systems use
+        them) for the shared-index units built by set_observed."""
+        cnt = (_i64 * 4)()
+        on = _i32()
+        self._check(self._lib.ptk_unit_stats(self._h, int(n), cnt, C.byref(on)))
+        return [int(x) for x in cnt], bool(on.value)
 
     def recon_error(self, lam=0.0):
         s, r, l = _dbl(), _dbl(), _dbl()

@@ -21,7 +21,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["ptk_api.hip", "ptk_kernels.hip", "ptk_cache.hip", "ptk_approx.hip",
            "ptk_gram2.hip", "ptk_slice.hip", "ptk_solve.hip", "ptk_resolve.hip",
-           "ptk_sparse.hip",
+           "ptk_sparse.hip", "ptk_units.hip",
            "ptk_data.hip",
            "ptk_sort.hip", "ptk_finalize.hip", "ptk_mfma.hip", "ptk_server.hip",
            "ptk_ceiling.hip"]

@@ -21,6 +21,7 @@
 #include "ptk_context.h"
 #include "ptk_internal.h"
 #include "ptk_slice.h"
+#include "ptk_units.h"
 
 using namespace ptk;
 
@@ -130,6 +131,7 @@ void free_modes(ptk_ctx *c) {
         dfree(m.blk_row);
         dfree(m.blk_start);
         dfree(m.blk_cnt);
+        dfree(m.units);
         m = ModeData();
     }
     dfree(c->bbuf);
@@ -138,6 +140,10 @@ void free_modes(ptk_ctx *c) {
     c->pcache = nullptr;
     dfree(c->dpart);
     c->dpart = nullptr;
+    dfree(c->dunits);
+    c->dunits = nullptr;
+    dfree(c->gph);
+    c->gph = nullptr;
     free_approx(c);
     c->bbuf = c->part = nullptr;
     c->part_cap = 0;
@@ -167,6 +173,18 @@ bool equal_ranks(const Shape &s) {
     for (int k = 1; k < s.N; ++k)
         if (s.ranks[k] != s.ranks[0]) return false;
     return true;
+}
+
+// The other mode whose index orders the entries inside the rows of mode n
+// (the last other mode, the second-fastest index of the permuted core) when
+// mode n may use shared-index units, else -1.
+int units_sub(const ptk_ctx *c, int n) {
+    const Shape &s = c->s;
+    if (c->opt.shared_units < 0 || c->opt.pair_cache || !equal_ranks(s) ||
+        c->opt.precision == PTK_PREC_BF16 || c->opt.precision == PTK_PREC_BF16X3 ||
+        !units_available(s.N, s.ranks[0]))
+        return -1;
+    return n == s.N - 1 ? s.N - 2 : s.N - 1;
 }
 
 // Role of mode n in the pair cache of a full sweep: 1 writes it (modes 2k
@@ -311,6 +329,15 @@ SparseMode sparse_mode(const ptk_ctx *c, int n) {
     return sm;
 }
 
+// Mode n forms its row systems from shared-index units: FP64 arithmetic, no
+// pair cache, no Approx variant (whose kernels keep their own deltas).
+bool units_live(const ptk_ctx *c, int n) {
+    const ModeData &m = c->md[n];
+    return m.units_on && c->dunits && m.fast && !m.bf16 && m.slices <= 1 &&
+           arith_of(c, n) == kArithF64 && cache_role(c, n) == 0 &&
+           !(c->opt.approx_rate > 0.0);
+}
+
 // B_i, c_i for every row of mode n into bbuf (delta + Gram kernel, merge).
 ptk_status systems(ptk_ctx *c, int n, int role = 0) {
     const ModeData &m = c->md[n];
@@ -355,6 +382,43 @@ ptk_status systems(ptk_ctx *c, int n, int role = 0) {
         return PTK_OK;
     }
     GramArgs a = gram_args(c, n);
+    if (units_live(c, n)) {
+        UnitArgs ua{};
+        ua.gp = a.gp;
+        for (int t = 0; t < c->s.N - 1; ++t) {
+            ua.fac[t] = a.fac[t];
+            ua.oidx[t] = a.oidx[t];
+        }
+        ua.dout = c->dunits;
+        ua.gph = c->gph;
+        if (units_passes(c->s.N, c->s.ranks[n]) > 1)
+            HIPCHK(c, timed(c, "core_passes", [&] {
+                return launch_core_passes((const double *)a.gp, c->gph, c->s.N,
+                                          c->s.ranks[n], c->st);
+            }));
+        static const char *const names[4] = {"delta_units1", "delta_units2", "delta_units4",
+                                             "delta_units8"};
+        for (int cl = 3; cl >= 0; --cl) {
+            if (m.ucount[cl] == 0) continue;
+            ua.units = m.units + m.ubase[cl];
+            ua.count = m.ucount[cl];
+            HIPCHK(c, timed(c, names[cl], [&] {
+                return launch_delta_units(ua, c->s.N, c->s.ranks[n], cl, c->st);
+            }));
+        }
+        c->keep_live = c->ls_keep != nullptr;
+        if (c->keep_live) {
+            a.kbase = c->ls_kbase + c->kb_off[n];
+            a.keep = c->ls_keep;
+        }
+        HIPCHK(c, timed(c, "gram_stored", [&] {
+            return launch_gram_stored(a, c->s.ranks[n], c->dunits, m.nchunks, c->st);
+        }));
+        HIPCHK(c, timed(c, "merge", [&] {
+            return launch_merge(c->part, m.split, m.nsplit, a.E, c->bbuf, c->st);
+        }));
+        return PTK_OK;
+    }
     const bool two = m.fast && m.two && gram2_available(c->s.N, c->s.ranks[n], arith_of(c, n));
     if (two && c->ap_store && c->ap_delta) {
         a.dstore = c->ap_delta;
@@ -586,6 +650,61 @@ int64_t default_work(const ptk_ctx *c, int n) {
     const int64_t waves = (int64_t)c->num_cu * std::max(1, bpc);
     int64_t chunk = round_up((c->nnz + waves - 1) / std::max<int64_t>(waves, 1), kWave);
     return std::max<int64_t>(chunk, kWave);
+}
+
+// Shared-index units of every mode whose rows are ordered for them, the
+// decision per mode (shared_units: 0 = by the work model, else always) and
+// the delta buffer. Called by ptk_set_observed after the grouping.
+ptk_status build_unit_lists(ptk_ctx *c) {
+    const Shape &s = c->s;
+    const int64_t nnz = c->nnz;
+    if (nnz <= 0 || units_sub(c, 0) < 0) return PTK_OK;
+    const int J = s.ranks[0];
+    const int su = c->opt.shared_units;
+    const int emax = su >= 2 ? std::min(su, units_emax(s.N, J)) : units_emax(s.N, J);
+    int32_t *work = nullptr;
+    HIPCHK(c, dalloc(&work, (size_t)units_workspace_ints(nnz)));
+    bool any = false;
+    for (int n = 0; n < s.N; ++n) {
+        ModeData &m = c->md[n];
+        hipError_t e = dalloc(&m.units, nnz + 64);
+        if (e == hipSuccess)
+            e = build_units(m.rows, m.oidx + (int64_t)(s.N - 2) * nnz, nnz, emax, work,
+                            m.units, m.ucount, c->st);
+        if (e != hipSuccess) {
+            dfree(work);
+            free_modes(c);
+            return fail(c, e == hipErrorOutOfMemory ? PTK_E_NOMEM : PTK_E_HIP,
+                        "unit lists of mode %d: %s", n, hipGetErrorString(e));
+        }
+        int64_t at = 0;
+        double f_units = 0.0;
+        for (int cl = 3; cl >= 0; --cl) {
+            m.ubase[cl] = at;
+            at += m.ucount[cl];
+            f_units += (double)m.ucount[cl] * unit_fma(s.N, J, 1 << cl);
+        }
+        f_units += (double)nnz * stored_delta_fma(J);
+        const double f_plain = (double)nnz * plain_fma_per_entry(s.N, J);
+        m.units_on = su != 0 || f_units <= 0.9 * f_plain;
+        any = any || m.units_on;
+    }
+    dfree(work);
+    int64_t cells = 1;
+    for (int n = 0; n < s.N; ++n) cells *= s.ranks[n];
+    if (any && (dalloc(&c->dunits, (size_t)nnz * J) != hipSuccess ||
+                dalloc(&c->gph, (size_t)cells) != hipSuccess)) {
+        dfree(c->dunits);
+        c->dunits = nullptr;
+        c->gph = nullptr;
+        if (su != 0) {
+            free_modes(c);
+            return fail(c, PTK_E_NOMEM, "shared-index deltas: %.2f GB of device memory",
+                        nnz * J * 8e-9);
+        }
+        for (int n = 0; n < s.N; ++n) c->md[n].units_on = false;
+    }
+    return PTK_OK;
 }
 
 // Cut mode n into wavefront work ranges of `work` entries (FP64/FP32 path,
@@ -1057,6 +1176,11 @@ ptk_status ptk_set_options(ptk_ctx *c, const ptk_options *o) {
         return fail(c, PTK_E_INVALID, "cond_limit must be finite and >= 0");
     if (!(o->sparse_limit <= 1.0) || !std::isfinite(o->sparse_limit))
         return fail(c, PTK_E_INVALID, "sparse_limit must be finite and <= 1");
+    const int su = o->shared_units;
+    if (su != -1 && su != 0 && su != 1 && su != 2 && su != 4 && su != 8)
+        return fail(c, PTK_E_INVALID, "shared_units must be -1, 0, 1, 2, 4 or 8");
+    if (su != c->opt.shared_units && c->nnz >= 0)
+        return fail(c, PTK_E_STATE, "shared_units must be set before ptk_set_observed");
     c->opt = *o;
     c->epoch++;
     return PTK_OK;
@@ -1117,7 +1241,8 @@ ptk_status ptk_set_observed(ptk_ctx *c, int64_t nnz, const int32_t *idx,
         if (e == hipSuccess && role == 2) e = dalloc(&m.cmap, nnz + 64);
         if (e == hipSuccess)
             e = build_mode_csr(idx, val, nnz, s, n, work, m.rowptr, m.rows, m.oidx,
-                               m.vals, c->st, role && nnz > 0 ? perm : nullptr);
+                               m.vals, c->st, role && nnz > 0 ? perm : nullptr,
+                               units_sub(c, n));
         if (e == hipSuccess && role == 1 && nnz > 0)
             e = launch_invert_perm(perm, nnz, inv, c->st);
         if (e == hipSuccess && role == 2 && nnz > 0)
@@ -1171,6 +1296,10 @@ ptk_status ptk_set_observed(ptk_ctx *c, int64_t nnz, const int32_t *idx,
         }
     }
     c->nnz = nnz;
+    {
+        ptk_status us = build_unit_lists(c);
+        if (us != PTK_OK) return us;
+    }
 
     // work ranges and rows that cross them
     int64_t bbuf_elems = 0;
@@ -1927,6 +2056,16 @@ extern "C" ptk_status ptk_solve_stats(ptk_ctx *c, int64_t *ls_rows, int64_t *ls_
     if (!c || !ls_rows || !ls_max) return PTK_E_INVALID;
     *ls_rows = c->last_ls_rows;
     *ls_max = c->last_ls_max;
+    return PTK_OK;
+}
+
+extern "C" ptk_status ptk_unit_stats(ptk_ctx *c, int32_t n, int64_t *counts, int32_t *on) {
+    if (!c || !counts || !on) return PTK_E_INVALID;
+    if (c->nnz < 0) return fail(c, PTK_E_STATE, "no observed set");
+    if (n < 0 || n >= c->s.N) return fail(c, PTK_E_INVALID, "mode out of range");
+    const ModeData &m = c->md[n];
+    for (int k = 0; k < 4; ++k) counts[k] = m.ucount[k];
+    *on = units_live(c, n) ? 1 : 0;
     return PTK_OK;
 }
 

@@ -36,6 +36,11 @@ struct ModeData {
     int split_bf16 = 1;          // 1: bf16 operands; 3: hi/lo split products
     int32_t *blk_row = nullptr, *blk_start = nullptr, *blk_cnt = nullptr;
     int64_t nblk = 0, blk_per_wave = 0, nwaves = 0;
+    // shared-index units: start positions [sum ucount], classes of 2^c
+    // entries at ubase[c]; on: the row systems of this mode use them
+    int32_t *units = nullptr;
+    int64_t ucount[4] = {0, 0, 0, 0}, ubase[4] = {0, 0, 0, 0};
+    bool units_on = false;
     // host copies used to recompute the work split (autotuner)
     std::vector<int64_t> rp_host;
     std::vector<int32_t> first_blk, last_blk;
@@ -58,7 +63,7 @@ struct ptk_ctx {
     hipStream_t st = nullptr;
     int device = 0;
     int num_cu = 256;
-    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1, 0, 0.0, 0, 0.0, 0, 0.0, 0.0};
+    ptk_options opt{PTK_PREC_FP64_ACC, 0, 1, 0, 1, 0, 0.0, 0, 0.0, 0, 0.0, 0.0, 0};
     int64_t nnz = -1;
     ModeData md[ptk::kMaxN];
     float *core = nullptr;
@@ -72,6 +77,8 @@ struct ptk_ctx {
     double *part = nullptr;
     double *pcache = nullptr;    // pair cache [nnz + 1][J][J]
     double *dpart = nullptr;     // slice partials of the sliced delta path
+    double *dunits = nullptr;    // deltas [nnz][J] of the shared-index units
+    double *gph = nullptr;       // pass-major copy of a permuted core (units)
     // Approx variant: residuals [nnz], slice sums, R per cell, removed count
     double *ap_resid = nullptr, *ap_part = nullptr, *ap_R = nullptr;
     int32_t *ap_removed = nullptr;

@@ -9,6 +9,8 @@
 // order inside a row, and hence every later floating-point sum, independent of
 // the launch. The other modes' indices and the values are then gathered into
 // the grouped order and the row pointers are read off the sorted keys.
+#include <algorithm>
+
 #include "ptk_internal.h"
 
 namespace ptk {
@@ -242,10 +244,18 @@ size_t sort_workspace_bytes(int64_t nnz) {
     return b;
 }
 
+__global__ void k_gather_keys(const int32_t *__restrict__ src,
+                              const int32_t *__restrict__ perm, int32_t *__restrict__ dst,
+                              int64_t nnz) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz;
+         p += (int64_t)gridDim.x * blockDim.x)
+        dst[p] = src[perm[p]];
+}
+
 hipError_t build_mode_csr(const int32_t *idx, const float *val, int64_t nnz,
                           const Shape &s, int n, void *work, int64_t *rowptr,
                           int32_t *rows, int32_t *oidx, float *vals,
-                          hipStream_t st, int32_t *perm_out) {
+                          hipStream_t st, int32_t *perm_out, int sub) {
     const int64_t I = s.dims[n];
     if (nnz == 0) {
         hipLaunchKernelGGL(k_rowptr, dim3((unsigned)((I + 1 + 255) / 256)), dim3(256), 0, st,
@@ -261,29 +271,44 @@ hipError_t build_mode_csr(const int32_t *idx, const float *val, int64_t nnz,
     int32_t *hist = valB + nnz + 64;
     int32_t *swork = hist + hist_n + 64;
 
-    int bits = 0;
-    while ((int64_t(1) << bits) < I) ++bits;
-    const int passes = bits <= 8 ? 1 : (bits + 7) / 8;
-
-    const int32_t *kin = idx + (int64_t)n * nnz;
+    const int32_t *kin = idx + (int64_t)(sub >= 0 ? sub : n) * nnz;
     const int32_t *vin = nullptr;
     int32_t *kout = keyA, *vout = valA;
     hipError_t e = hipSuccess;
-    for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nt), dim3(kRsThreads), 0, st,
-                           kin, nnz, shift, hist, nt);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = scan_exclusive(hist, hist, hist_n, swork, st)) != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nt), dim3(kRsThreads), 0,
-                           st, kin, vin, kout, vout, nnz, shift, hist, nt);
+    // stable passes over the 8-bit digits of keys below `extent`
+    auto passes = [&](int64_t extent) -> hipError_t {
+        int bits = 0;
+        while ((int64_t(1) << bits) < extent) ++bits;
+        const int np = bits <= 8 ? 1 : (bits + 7) / 8;
+        for (int p = 0; p < np; ++p) {
+            const int shift = 8 * p;
+            hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nt), dim3(kRsThreads), 0, st,
+                               kin, nnz, shift, hist, nt);
+            hipError_t r = hipGetLastError();
+            if (r != hipSuccess) return r;
+            if ((r = scan_exclusive(hist, hist, hist_n, swork, st)) != hipSuccess) return r;
+            hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nt), dim3(kRsThreads), 0,
+                               st, kin, vin, kout, vout, nnz, shift, hist, nt);
+            if ((r = hipGetLastError()) != hipSuccess) return r;
+            kin = kout;
+            vin = vout;
+            kout = (kout == keyA) ? keyB : keyA;
+            vout = (vout == valA) ? valB : valA;
+        }
+        return hipSuccess;
+    };
+    if (sub >= 0) {
+        // order by the index of mode `sub` first; the stable passes over the
+        // mode-n index below keep that order inside every row
+        if ((e = passes(s.dims[sub])) != hipSuccess) return e;
+        unsigned gb = (unsigned)std::min<int64_t>((nnz + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_gather_keys, dim3(gb), dim3(256), 0, st,
+                           idx + (int64_t)n * nnz, vin, kout, nnz);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         kin = kout;
-        vin = vout;
         kout = (kout == keyA) ? keyB : keyA;
-        vout = (vout == valA) ? valB : valA;
     }
+    if ((e = passes(I)) != hipSuccess) return e;
     // kin / vin hold the sorted keys and the permutation
     if ((e = hipMemcpyAsync(rows, kin, nnz * 4, hipMemcpyDeviceToDevice, st)) !=
         hipSuccess)
@@ -308,6 +333,139 @@ hipError_t build_mode_csr(const int32_t *idx, const float *val, int64_t nnz,
     hipLaunchKernelGGL(k_rowptr, dim3((unsigned)((I + 1 + 255) / 256)), dim3(256), 0, st,
                        rows, nnz, I, rowptr);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// unit lists of the shared-index row systems
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t run_flag(const int32_t *rows, const int32_t *sidx,
+                                            int64_t p) {
+    return p == 0 || rows[p] != rows[p - 1] || sidx[p] != sidx[p - 1];
+}
+
+__global__ void k_run_flags(const int32_t *__restrict__ rows, const int32_t *__restrict__ sidx,
+                            int64_t nnz, int32_t *__restrict__ flag) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz;
+         p += (int64_t)gridDim.x * blockDim.x)
+        flag[p] = run_flag(rows, sidx, p);
+}
+
+// start[r] = first position of run r; start[R] = nnz; *nruns = R.
+__global__ void k_run_starts(const int32_t *__restrict__ rows, const int32_t *__restrict__ sidx,
+                             int64_t nnz, const int32_t *__restrict__ rid,
+                             int32_t *__restrict__ start, int32_t *__restrict__ nruns) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t f = run_flag(rows, sidx, p);
+        if (f) start[rid[p]] = (int32_t)p;
+        if (p == nnz - 1) {
+            start[rid[p] + f] = (int32_t)nnz;
+            *nruns = rid[p] + f;
+        }
+    }
+}
+
+// Units of class c (2^c entries) in a run of len entries.
+__device__ __forceinline__ int32_t class_units(int32_t len, int c, int cmax) {
+    return c == cmax ? (len >> cmax) : ((len >> c) & 1);
+}
+
+__global__ void k_unit_counts(const int32_t *__restrict__ start, int32_t R, int cmax,
+                              int32_t *__restrict__ cnt) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t len = start[r + 1] - start[r];
+        for (int c = 0; c <= cmax; ++c) cnt[(int64_t)c * R + r] = class_units(len, c, cmax);
+    }
+}
+
+// total[c] = off[c][R-1] + units of class c in the last run
+__global__ void k_unit_totals(const int32_t *__restrict__ start, int32_t R, int cmax,
+                              const int32_t *__restrict__ off, int64_t *__restrict__ total) {
+    const int c = threadIdx.x;
+    if (c > cmax) return;
+    const int32_t len = start[R] - start[R - 1];
+    total[c] = (int64_t)off[(int64_t)c * R + R - 1] + class_units(len, c, cmax);
+}
+
+__global__ void k_unit_write(const int32_t *__restrict__ start, int32_t R, int cmax,
+                             const int32_t *__restrict__ off, const int64_t *__restrict__ base,
+                             int32_t *__restrict__ units) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        int32_t p = start[r];
+        const int32_t len = start[r + 1] - p;
+        for (int c = cmax; c >= 0; --c) {
+            const int32_t k = class_units(len, c, cmax);
+            int32_t *dst = units + base[c] + off[(int64_t)c * R + r];
+            for (int32_t q = 0; q < k; ++q) {
+                dst[q] = p;
+                p += 1 << c;
+            }
+        }
+    }
+}
+
+int64_t units_workspace_ints(int64_t nnz) {
+    // run ids, run starts, per-class counts (<= 4 classes of R <= nnz runs),
+    // the run count, class bases and scan work
+    return 2 * (nnz + 64) + 4 * (nnz + 64) + 64 + scan_work_elems(nnz) + 64;
+}
+
+hipError_t build_units(const int32_t *rows, const int32_t *sidx, int64_t nnz, int emax,
+                       int32_t *work, int32_t *units, int64_t *count, hipStream_t st) {
+    int cmax = 0;
+    while ((1 << cmax) < emax) ++cmax;
+    if (cmax > 3 || (1 << cmax) != emax) return hipErrorInvalidValue;
+    for (int c = 0; c <= 3; ++c) count[c] = 0;
+    if (nnz == 0) return hipSuccess;
+    int32_t *rid = work;
+    int32_t *start = rid + nnz + 64;
+    int32_t *cnt = start + nnz + 64;
+    int32_t *misc = cnt + 4 * (nnz + 64);            // [0]: R; [2..]: int64 totals, bases
+    int32_t *swork = misc + 64;
+    int64_t *total = (int64_t *)(misc + 2);
+    int64_t *base = total + 4;
+    const unsigned gb = (unsigned)std::min<int64_t>((nnz + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_run_flags, dim3(gb), dim3(256), 0, st, rows, sidx, nnz, rid);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = scan_exclusive(rid, rid, nnz, swork, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_run_starts, dim3(gb), dim3(256), 0, st, rows, sidx, nnz, rid, start,
+                       misc);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int32_t R = 0;
+    if ((e = hipMemcpyAsync(&R, misc, 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if (R <= 0 || R > nnz) return hipErrorInvalidValue;
+    const unsigned rb = (unsigned)std::min<int64_t>((R + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_unit_counts, dim3(rb), dim3(256), 0, st, start, R, cmax, cnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int c = 0; c <= cmax; ++c)
+        if ((e = scan_exclusive(cnt + (int64_t)c * R, cnt + (int64_t)c * R, R, swork, st)) !=
+            hipSuccess)
+            return e;
+    hipLaunchKernelGGL(k_unit_totals, dim3(1), dim3(64), 0, st, start, R, cmax, cnt, total);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int64_t ht[4] = {0, 0, 0, 0};
+    if ((e = hipMemcpyAsync(ht, total, 8 * (cmax + 1), hipMemcpyDeviceToHost, st)) !=
+        hipSuccess)
+        return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    // classes in the order cmax, ..., 0
+    int64_t hb[4] = {0, 0, 0, 0}, at = 0;
+    for (int c = cmax; c >= 0; --c) {
+        hb[c] = at;
+        at += ht[c];
+        count[c] = ht[c];
+    }
+    if (at > nnz) return hipErrorInvalidValue;
+    if ((e = hipMemcpyAsync(base, hb, 8 * 4, hipMemcpyHostToDevice, st)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_unit_write, dim3(rb), dim3(256), 0, st, start, R, cmax, cnt, base,
+                       units);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return hipStreamSynchronize(st);   // hb lives on this stack frame
 }
 
 // ---------------------------------------------------------------------------

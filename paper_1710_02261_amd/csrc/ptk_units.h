@@ -1,0 +1,58 @@
+// Row systems from shared-index units (Alg. 3 with the contraction of eq.
+// "delta" reordered): the entries of a row are grouped by their index in the
+// last other mode s, and the core contracted with that mode's row,
+// t = G x_s a^(s)_{i_s}, is formed once per unit of entries that share i_s
+// instead of once per entry. Deltas go to a buffer; a second kernel sweeps
+// them into the packed row systems in grouped order, like the other
+// row-system kernels.
+#pragma once
+
+#include "ptk_internal.h"
+
+namespace ptk {
+
+// Largest unit (entries sharing one t): 8 at orders 3 and 4 up to J = 10,
+// else 4 (register and LDS footprint).
+constexpr int units_emax(int N, int J) { return (J <= 10 && N <= 4) ? 8 : 4; }
+
+// Arguments of the unit delta kernel for one class of units.
+struct UnitArgs {
+    const void *gp;                   // FP64 permuted core of mode n
+    const void *gph;                  // the same in pass-major order (launch_core_passes)
+    const float *fac[kMaxN];          // factors of the other modes, mode order
+    const int32_t *oidx[kMaxN];       // other-mode index arrays, same order
+    const int32_t *units;             // first grouped position of each unit
+    int64_t count;                    // units in this class
+    double *dout;                     // deltas [nnz][J] in grouped order
+};
+
+// (N, J) with equal ranks and unit kernels (FP64 arithmetic).
+bool units_available(int N, int J);
+
+// Passes over delta's components of the largest unit class at (N, J) (the
+// pass-major core layout that class reads; 1 = none needed).
+int units_passes(int N, int J);
+
+// gph <- gp in pass-major order ([pass][outer][m][J / passes]); nothing when
+// units_passes(N, J) is 1. gph holds J^N doubles.
+hipError_t launch_core_passes(const double *gp, double *gph, int N, int J, hipStream_t st);
+
+// Deltas of every unit of class c (2^c entries) into a.dout.
+hipError_t launch_delta_units(const UnitArgs &a, int N, int J, int c, hipStream_t st);
+
+// Row systems of mode n from the stored deltas din ([nnz][J]), over the
+// work ranges of a (same chunks, partial slots and merge as launch_gram);
+// keeps the deltas of planned least-squares rows when a.kbase is set.
+hipError_t launch_gram_stored(const GramArgs &a, int J, const double *din, int64_t nchunks,
+                              hipStream_t st);
+
+// Multiply-adds per entry of the plain contraction and of one unit of e
+// entries (the model that decides whether a mode uses units).
+double plain_fma_per_entry(int N, int J);
+double unit_fma(int N, int J, int e);
+// Writing and reading back one entry's delta (16 J + 8 bytes of HBM traffic)
+// in multiply-add equivalents: about 5.5 FP64 multiply-adds per byte at the
+// rates these kernels sustain (27 T multiply-adds/s against 5 TB/s).
+double stored_delta_fma(int J);
+
+}  // namespace ptk

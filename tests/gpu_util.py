@@ -21,12 +21,13 @@ def to_device(p, device="cuda"):
 
 
 def context(p, precision=0, chunk_nnz=0, fuse_error=1, profile=0, bind=True,
-            pair_cache=0, delta_slices=0):
+            pair_cache=0, delta_slices=0, shared_units=0):
     import paper_1710_02261_amd as ptk
     idx, val, core, fac = to_device(p)
     ctx = ptk.Context(p.dims, p.ranks)
     ctx.set_options(precision=precision, chunk_nnz=chunk_nnz, fuse_error=fuse_error,
-                    profile=profile, pair_cache=pair_cache, delta_slices=delta_slices)
+                    profile=profile, pair_cache=pair_cache, delta_slices=delta_slices,
+                    shared_units=shared_units)
     ctx.set_observed(idx, val)
     if bind:
         ctx.bind_model(core, fac)

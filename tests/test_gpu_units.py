@@ -1,0 +1,186 @@
+"""GPU parity of the shared-index units (ptk_options.shared_units): the row
+systems (eqs. "rowB", "rowC") formed from units of consecutive entries of a
+row that share their index in the last other mode, the core contracted with
+that mode's row once per unit (eq. "delta" summed in another order).
+
+* Unit lists: per mode, the numbers of units of 1, 2, 4 and 8 entries equal
+  those of the runs of equal (i_n, i_s) counted here from the COO input
+  (exact), for the default cap and the caps 2, 4 and 8.
+* Row systems to 1e-10 and one mode update to 1e-5 per row against the
+  oracle, every unit shape, with work ranges that cut rows; the units and the
+  fused kernels give the same row systems to 1e-12.
+* Iterations in a captured graph with every row in the least-squares form
+  (cond_limit = 1), whose kept deltas then come from the stored ones: every
+  row of every iteration to 1e-5 against the oracle from the same state.
+* Auto: few repeats keep the fused kernels, many take the units; an empty
+  observed set; option refusals.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import context, f64, log, row_rel_err
+
+pytestmark = pytest.mark.gpu
+
+# (dims, J, nnz): small dims so that (row, i_s) pairs repeat, Zipf skew so
+# that run lengths spread from 1 to hundreds
+SHAPES = [((40, 30, 20), 16, 6001), ((30, 25, 20, 15), 10, 7003),
+          ((12, 11, 10, 9, 8), 8, 5005)]
+SIDS = ["%dd-J%d" % (len(d), j) for d, j, _ in SHAPES]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    import torch
+    assert torch.cuda.is_available()
+
+
+def problem(dims, J, nnz, seed):
+    return synth.make_small(dims, (J,) * len(dims), nnz, seed=seed, skew=1.1)
+
+
+def expected_units(p, n, emax):
+    """Units per class from the runs of equal (i_n, i_s), s the last mode
+    other than n: floor(r / emax) units of emax, then the bits of r % emax."""
+    N = len(p.dims)
+    s = N - 1 if n != N - 1 else N - 2
+    key = p.idx[n].astype(np.int64) * p.dims[s] + p.idx[s].astype(np.int64)
+    _, runs = np.unique(key, return_counts=True)
+    cmax = emax.bit_length() - 1
+    out = [0, 0, 0, 0]
+    out[cmax] = int((runs // emax).sum())
+    rest = runs % emax
+    for c in range(cmax):
+        out[c] = int(((rest >> c) & 1).sum())
+    return out
+
+
+@pytest.mark.parametrize("dims,J,nnz", SHAPES, ids=SIDS)
+@pytest.mark.parametrize("cap", [1, 2, 4, 8])
+def test_unit_lists_count_runs(dims, J, nnz, cap):
+    p = problem(dims, J, nnz, seed=71)
+    ctx, *_ = context(p, shared_units=cap)
+    emax = 8 if (J <= 10 and len(dims) <= 4) else 4
+    if cap > 1:
+        emax = min(emax, cap)
+    for n in range(len(dims)):
+        counts, on = ctx.unit_stats(n)
+        want = expected_units(p, n, emax)
+        assert counts == want, (n, counts, want)
+        assert on
+        assert sum((1 << c) * k for c, k in enumerate(counts)) == nnz
+    ctx.close()
+
+
+@pytest.mark.parametrize("dims,J,nnz", SHAPES, ids=SIDS)
+def test_row_systems_with_units_match_oracle(dims, J, nnz):
+    p = problem(dims, J, nnz, seed=72)
+    ctx, *_ = context(p, chunk_nnz=128, shared_units=1)
+    ref, *_ = context(p, chunk_nnz=128, shared_units=-1)
+    G = p.core.astype(np.float64)
+    A = [a.astype(np.float64) for a in p.factors]
+    val = p.val.astype(np.float64)
+    for n in range(len(dims)):
+        assert ctx.unit_stats(n)[1] and not ref.unit_stats(n)[1]
+        B, c = ctx.row_systems(n)
+        B, c = f64(B), f64(c)
+        Br, cr = ref.row_systems(n)
+        Br, cr = f64(Br), f64(cr)
+        scale = np.abs(Br).max()
+        assert np.abs(B - Br).max() <= 1e-12 * scale
+        assert np.abs(c - cr).max() <= 1e-12 * np.abs(cr).max()
+        counts = np.bincount(p.idx[n], minlength=dims[n])
+        rows = list(np.argsort(-counts)[:3]) + list(range(0, dims[n], max(1, dims[n] // 7)))
+        for i in rows:
+            Bo, co = oracle.row_system(G, A, p.idx, val, n, int(i))
+            assert np.abs(B[i] - Bo).max() <= 1e-10 * max(np.abs(Bo).max(), 1e-300), (n, i)
+            assert np.abs(c[i] - co).max() <= 1e-10 * max(np.abs(co).max(), 1e-300)
+    ctx.close()
+    ref.close()
+
+
+@pytest.mark.parametrize("dims,J,nnz", SHAPES, ids=SIDS)
+@pytest.mark.parametrize("cap,chunk", [(1, 0), (2, 64), (4, 192), (8, 64)])
+def test_update_with_units_matches_oracle(dims, J, nnz, cap, chunk):
+    p = problem(dims, J, nnz, seed=73)
+    ctx, idx, val, core, fac = context(p, chunk_nnz=chunk, shared_units=cap)
+    G = p.core.astype(np.float64)
+    A = [a.astype(np.float64) for a in p.factors]
+    v = p.val.astype(np.float64)
+    worst = 0.0
+    for n in range(p.N):
+        before = [f.clone() for f in fac]
+        ctx.update_mode(n, p.lam)
+        got = f64(fac[n])
+        want = oracle.update_rows(G, A, p.idx, v, n, p.lam)
+        empty = np.bincount(p.idx[n], minlength=p.dims[n]) == 0
+        assert np.all(got[empty] == 0.0)
+        err = row_rel_err(got[~empty], want[~empty])
+        worst = max(worst, float(err.max()))
+        assert err.max() <= 1e-5, (n, err.max())
+        for f, b in zip(fac, before):
+            f.copy_(b)
+    log("units", dims, J, "cap", cap, "chunk", chunk, "worst", worst)
+    ctx.close()
+
+
+@pytest.mark.parametrize("dims,J,nnz", SHAPES, ids=SIDS)
+def test_graph_iterations_least_squares_from_stored_deltas(dims, J, nnz):
+    """cond_limit = 1 sends every row to the least-squares form; from the
+    second iteration on its deltas are the ones the stored-delta sweep kept."""
+    p = problem(dims, J, nnz, seed=74)
+    ctx, idx, val, core, fac = context(p, shared_units=1)
+    ctx.set_options(cond_limit=1.0, use_graph=1, shared_units=1)
+    G = p.core.astype(np.float64)
+    v = p.val.astype(np.float64)
+    for t in range(3):
+        A = [f64(f) for f in fac]
+        s1, _ = ctx.iterate(1, p.lam, strict=False)
+        for n in range(p.N):
+            A = oracle.update_mode(G, A, p.idx, v, n, p.lam)
+            A[n] = A[n].astype(np.float32).astype(np.float64)
+        worst = 0.0
+        for n in range(p.N):
+            nz = np.bincount(p.idx[n], minlength=p.dims[n]) > 0
+            worst = max(worst, float(row_rel_err(f64(fac[n])[nz], A[n][nz]).max()))
+        want = oracle.sse(G, A, p.idx, v)
+        rows, _ = ctx.solve_stats()
+        log("units least squares", dims, J, "iteration", t, "worst", worst, "ls rows", rows)
+        assert rows > 0
+        assert worst <= 1e-5
+        assert abs(s1[0] - want) <= 1e-6 * want
+    ctx.close()
+
+
+def test_auto_keeps_fused_kernels_without_repeats():
+    # 4e4 entries spread over 3000^4 cells: nearly every (row, i_s) pair once
+    p = synth.make_small((3000, 3000, 3000, 3000), (10,) * 4, 40000, seed=75)
+    ctx, *_ = context(p)
+    for n in range(4):
+        counts, on = ctx.unit_stats(n)
+        assert not on and counts[0] > 0.9 * p.nnz
+    ctx.close()
+    p = problem((30, 25, 20, 15), 10, 7003, seed=75)
+    ctx, *_ = context(p)
+    assert all(ctx.unit_stats(n)[1] for n in range(4))
+    ctx.close()
+
+
+def test_empty_observed_set_and_refusals():
+    import torch
+    import paper_1710_02261_amd as ptk
+    p = problem((30, 25, 20, 15), 10, 100, seed=76)
+    ctx = ptk.Context(p.dims, p.ranks)
+    for bad in (3, 5, -2, 16):
+        with pytest.raises(ptk.PtkError):
+            ctx.set_options(shared_units=bad)
+    ctx.set_options(shared_units=1)
+    idx = torch.zeros((4, 0), dtype=torch.int32, device="cuda")
+    val = torch.zeros((0,), dtype=torch.float32, device="cuda")
+    ctx.set_observed(idx, val)
+    assert ctx.unit_stats(0) == ([0, 0, 0, 0], False)
+    with pytest.raises(ptk.PtkError):
+        ctx.set_options(shared_units=-1)            # after set_observed
+    ctx.close()
