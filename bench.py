@@ -687,17 +687,27 @@ def main():
         # most time; its work is the multiply-adds the unit form executes
         # (J^(N-2) (J^2 + e (J + N - 3)) per unit of e entries)
         best = None
-        for c in range(4):
-            name = "delta_units%d" % (1 << c)
+        on_modes = [u for u, on in r["units"] if on]
+        for c in range(5):
+            name = "delta_long" if c == 4 else "delta_units%d" % (1 << c)
             calls, ms = r["times"].get(name, (0, 0.0))
             if calls and (best is None or ms > best[2]):
                 best = (c, calls, ms)
         c, calls, ms = best
-        e = 1 << c
-        per_unit = J ** (N - 2) * (J * J + e * (J + N - 3))
-        on_modes = [u for u, on in r["units"] if on]
-        unit_kernel = {"class": e, "avg_ms": ms / calls,
-                       "flops": 2.0 * per_unit * sum(u[c] for u in on_modes) / len(on_modes)}
+        if c == 4:
+            # long runs: a table of J^N multiply-adds per run, then
+            # J^(N-1) + J^(N-2) per entry
+            fl = 0.0
+            for u in on_modes:
+                entries = p.nnz - sum(u[k] << k for k in range(4))
+                fl += u[4] * J ** N + entries * (J ** (N - 1) + J ** (N - 2))
+            unit_kernel = {"class": "long", "avg_ms": ms / calls,
+                           "flops": 2.0 * fl / len(on_modes)}
+        else:
+            e = 1 << c
+            per_unit = J ** (N - 2) * (J * J + e * (J + N - 3))
+            unit_kernel = {"class": e, "avg_ms": ms / calls,
+                           "flops": 2.0 * per_unit * sum(u[c] for u in on_modes) / len(on_modes)}
         avg_s = unit_kernel["avg_ms"] / 1e3
     if main_prec.startswith("bf16"):
         # matrix-core work per entry and mode: stage 1 J^N (+2x for the split
@@ -727,7 +737,9 @@ def main():
         traffic = None
     if unit_kernel:
         e = unit_kernel["class"]
-        kname = "k_delta_units<%d,%d,%d,%d>" % (N, J, e, 2 if e <= 2 else 1)
+        kname = ("k_run_tables<%d,%d> + k_delta_long<%d,%d>" % (N, J, N, J) if e == "long"
+                 else "k_delta_singles<%d,%d>" % (N, J) if e == 1
+                 else "k_delta_units<%d,%d,%d,...>" % (N, J, e))
         traffic = None
     roofline = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak, "traffic": traffic, "kernel": kname,
@@ -769,7 +781,8 @@ def main():
                                         for a, b in zip(r["loss"], r["loss"][1:]))),
         "kernel_ms": {k: v[1] / max(v[0], 1) for k, v in r["times"].items()},
         "shared_units": {"option": args.shared_units,
-                         "per_mode": [{"units_1_2_4_8": u, "on": on} for u, on in r["units"]]},
+                         "per_mode": [{"units_1_2_4_8_long_tasks": u, "on": on}
+                                      for u, on in r["units"]]},
     }
     if not args.no_variant:
         variants = {}

@@ -172,15 +172,19 @@ typedef struct ptk_options {
                                of every row are ordered by their index in the
                                last other mode s, and consecutive entries of
                                a row with the same i_s form units that share
-                               the core contracted with that mode's row
-                               (J^(N-1) multiply-adds per unit instead of per
-                               entry); deltas go through a J * nnz-double
+                               the core contracted with that mode's row (its
+                               J^N multiply-adds once per unit instead of once
+                               per entry); deltas go through a J * nnz-double
                                buffer. Same result up to rounding order. 0 =
                                auto (per mode, when the units cut the
                                modelled work by a tenth or more); -1 = never
                                (rows keep the order of the input); 1 = always
-                               where available; 2, 4 or 8 = always, with
-                               units of at most that many entries. Chosen
+                               where available, units of at most 2 entries;
+                               2, 4 or 8 = always, with units of at most that
+                               many entries. Runs of 64 entries or more of
+                               one row and one i_s get a table of the core
+                               contracted with that row (J^(N-1) doubles
+                               each, at most 4 GiB per mode) instead. Chosen
                                before ptk_set_observed; not used with
                                pair_cache, approx_rate > 0 or the FP32 and
                                BF16 forms. Other values: PTK_E_INVALID.      */
@@ -298,14 +302,18 @@ ptk_status ptk_approx_stats(ptk_ctx *ctx, int64_t *nonzero_cells_host,
 
 /*
  * Shared-index units of mode n (ptk_options.shared_units) built by the last
- * ptk_set_observed: counts_host[c] receives the number of units of 2^c
- * entries, c = 0..3 (a run of r consecutive entries of one row with the same
- * index in the last other mode gives floor(r / emax) units of emax entries,
- * then one unit for each set bit of r mod emax; emax is 8 at orders 3 and 4
- * with J <= 10, else 4, or the option's cap if lower), and *on_host whether
- * the row systems of mode n
- * use them (1) or the fused kernels (0). All zero when no units were built.
- * PTK_E_INVALID for n out of range, PTK_E_STATE before ptk_set_observed.
+ * ptk_set_observed. A run is a maximal sequence of grouped entries of one row
+ * with the same index in the last other mode. A run of 64 entries or more is
+ * long (it gets a table of the core contracted with that mode's row, and its
+ * entries are processed in tasks of at most 128); any other run of r entries
+ * gives floor(r / emax) units of emax entries, then one unit for each set bit
+ * of r mod emax (emax is 2, or the option's 4 or 8 where a kernel exists: 8
+ * at orders 3 and 4 with J <= 10, else 4). counts_host receives 6 values:
+ * the units of 1, 2,
+ * 4 and 8 entries, the long runs and their tasks. *on_host: whether the row
+ * systems of mode n use them (1) or the fused kernels (0). All zero when
+ * nothing was built. PTK_E_INVALID for n out of range, PTK_E_STATE before
+ * ptk_set_observed.
  */
 ptk_status ptk_unit_stats(ptk_ctx *ctx, int32_t n, int64_t *counts_host, int32_t *on_host);
 

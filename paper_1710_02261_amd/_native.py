@@ -281,9 +281,10 @@ class Context:
         return a.value, b.value
 
     def unit_stats(self, n):
-        """(units of 1, 2, 4, 8 entries, whether mode n's row systems use
-        them) for the shared-index units built by set_observed."""
-        cnt = (_i64 * 4)()
+        """([units of 1, 2, 4, 8 entries, long runs, their tasks], whether
+        mode n's row systems use them) for the shared-index units built by
+        set_observed."""
+        cnt = (_i64 * 6)()
         on = _i32()
         self._check(self._lib.ptk_unit_stats(self._h, int(n), cnt, C.byref(on)))
         return [int(x) for x in cnt], bool(on.value)

@@ -132,6 +132,10 @@ void free_modes(ptk_ctx *c) {
         dfree(m.blk_start);
         dfree(m.blk_cnt);
         dfree(m.units);
+        dfree(m.lg.run_pos);
+        dfree(m.lg.task_pos);
+        dfree(m.lg.task_len);
+        dfree(m.lg.task_run);
         m = ModeData();
     }
     dfree(c->bbuf);
@@ -144,6 +148,8 @@ void free_modes(ptk_ctx *c) {
     c->dunits = nullptr;
     dfree(c->gph);
     c->gph = nullptr;
+    dfree(c->ltab);
+    c->ltab = nullptr;
     free_approx(c);
     c->bbuf = c->part = nullptr;
     c->part_cap = 0;
@@ -398,6 +404,20 @@ ptk_status systems(ptk_ctx *c, int n, int role = 0) {
             }));
         static const char *const names[4] = {"delta_units1", "delta_units2", "delta_units4",
                                              "delta_units8"};
+        if (m.lg.n_long > 0) {
+            LongArgs la{};
+            la.gp = a.gp;
+            for (int t = 0; t < c->s.N - 1; ++t) {
+                la.fac[t] = a.fac[t];
+                la.oidx[t] = a.oidx[t];
+            }
+            la.lg = m.lg;
+            la.tab = c->ltab;
+            la.dout = c->dunits;
+            HIPCHK(c, timed(c, "delta_long", [&] {
+                return launch_long_runs(la, c->s.N, c->s.ranks[n], c->st);
+            }));
+        }
         for (int cl = 3; cl >= 0; --cl) {
             if (m.ucount[cl] == 0) continue;
             ua.units = m.units + m.ubase[cl];
@@ -641,7 +661,8 @@ int64_t default_work(const ptk_ctx *c, int n) {
         return std::max<int64_t>(1, (m.nblk + waves - 1) / std::max<int64_t>(waves, 1));
     }
     const int role = cache_role(c, n);
-    const int bpc = (m.slices > 1 && role != 2)
+    const int bpc = units_live(c, n) ? gram_stored_blocks_per_cu(c->s.ranks[n])
+                    : (m.slices > 1 && role != 2)
                         ? gram_slices_blocks_per_cu(c->s.ranks[n])
                     : role ? gram_cache_blocks_per_cu(c->s, n, arith_of(c, n), role)
                     : (m.fast && m.two && gram2_available(c->s.N, c->s.ranks[n], arith_of(c, n)))
@@ -661,46 +682,67 @@ ptk_status build_unit_lists(ptk_ctx *c) {
     if (nnz <= 0 || units_sub(c, 0) < 0) return PTK_OK;
     const int J = s.ranks[0];
     const int su = c->opt.shared_units;
-    const int emax = su >= 2 ? std::min(su, units_emax(s.N, J)) : units_emax(s.N, J);
+    const int emax = su >= 2 ? std::min(su, units_emax(s.N, J)) : kUnitsDefault;
+    int64_t inner = 1;                          // J^(N-1): one long run's table
+    for (int n = 1; n < s.N; ++n) inner *= s.ranks[n];
     int32_t *work = nullptr;
     HIPCHK(c, dalloc(&work, (size_t)units_workspace_ints(nnz)));
     bool any = false;
+    int64_t tab_need = 0;
     for (int n = 0; n < s.N; ++n) {
         ModeData &m = c->md[n];
+        UnitLong &lg = m.lg;
+        lg.cap_long = nnz / kLongRun + 1;
+        lg.cap_tasks = nnz / kLongTask + lg.cap_long + 1;
         hipError_t e = dalloc(&m.units, nnz + 64);
+        if (e == hipSuccess) e = dalloc(&lg.run_pos, (size_t)lg.cap_long);
+        if (e == hipSuccess) e = dalloc(&lg.task_pos, (size_t)lg.cap_tasks);
+        if (e == hipSuccess) e = dalloc(&lg.task_len, (size_t)lg.cap_tasks);
+        if (e == hipSuccess) e = dalloc(&lg.task_run, (size_t)lg.cap_tasks);
+        const int32_t *sidx = m.oidx + (int64_t)(s.N - 2) * nnz;
         if (e == hipSuccess)
-            e = build_units(m.rows, m.oidx + (int64_t)(s.N - 2) * nnz, nnz, emax, work,
-                            m.units, m.ucount, c->st);
+            e = build_units(m.rows, sidx, nnz, emax, kLongRun, kLongTask, work, m.units,
+                            m.ucount, &lg, c->st);
+        // tables beyond their budget: units only
+        if (e == hipSuccess && lg.n_long * inner * 8 > kLongTableBytes)
+            e = build_units(m.rows, sidx, nnz, emax, 0, kLongTask, work, m.units, m.ucount,
+                            &lg, c->st);
         if (e != hipSuccess) {
             dfree(work);
             free_modes(c);
             return fail(c, e == hipErrorOutOfMemory ? PTK_E_NOMEM : PTK_E_HIP,
                         "unit lists of mode %d: %s", n, hipGetErrorString(e));
         }
-        int64_t at = 0;
+        int64_t at = 0, in_units = 0;
         double f_units = 0.0;
         for (int cl = 3; cl >= 0; --cl) {
             m.ubase[cl] = at;
             at += m.ucount[cl];
+            in_units += m.ucount[cl] << cl;
             f_units += (double)m.ucount[cl] * unit_fma(s.N, J, 1 << cl);
         }
+        f_units += long_fma(s.N, J, (double)lg.n_long, (double)(nnz - in_units));
         f_units += (double)nnz * stored_delta_fma(J);
         const double f_plain = (double)nnz * plain_fma_per_entry(s.N, J);
         m.units_on = su != 0 || f_units <= 0.9 * f_plain;
         any = any || m.units_on;
+        if (m.units_on) tab_need = std::max(tab_need, lg.n_long * inner);
     }
     dfree(work);
     int64_t cells = 1;
     for (int n = 0; n < s.N; ++n) cells *= s.ranks[n];
     if (any && (dalloc(&c->dunits, (size_t)nnz * J) != hipSuccess ||
-                dalloc(&c->gph, (size_t)cells) != hipSuccess)) {
+                dalloc(&c->gph, (size_t)cells) != hipSuccess ||
+                (tab_need > 0 && dalloc(&c->ltab, (size_t)tab_need) != hipSuccess))) {
         dfree(c->dunits);
+        dfree(c->gph);
         c->dunits = nullptr;
         c->gph = nullptr;
+        c->ltab = nullptr;
         if (su != 0) {
             free_modes(c);
             return fail(c, PTK_E_NOMEM, "shared-index deltas: %.2f GB of device memory",
-                        nnz * J * 8e-9);
+                        (nnz * J + tab_need) * 8e-9);
         }
         for (int n = 0; n < s.N; ++n) c->md[n].units_on = false;
     }
@@ -2065,6 +2107,8 @@ extern "C" ptk_status ptk_unit_stats(ptk_ctx *c, int32_t n, int64_t *counts, int
     if (n < 0 || n >= c->s.N) return fail(c, PTK_E_INVALID, "mode out of range");
     const ModeData &m = c->md[n];
     for (int k = 0; k < 4; ++k) counts[k] = m.ucount[k];
+    counts[4] = m.lg.n_long;
+    counts[5] = m.lg.n_tasks;
     *on = units_live(c, n) ? 1 : 0;
     return PTK_OK;
 }

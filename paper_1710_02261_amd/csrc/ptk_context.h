@@ -40,6 +40,7 @@ struct ModeData {
     // entries at ubase[c]; on: the row systems of this mode use them
     int32_t *units = nullptr;
     int64_t ucount[4] = {0, 0, 0, 0}, ubase[4] = {0, 0, 0, 0};
+    UnitLong lg;                 // long runs and their tasks (device arrays)
     bool units_on = false;
     // host copies used to recompute the work split (autotuner)
     std::vector<int64_t> rp_host;
@@ -79,6 +80,7 @@ struct ptk_ctx {
     double *dpart = nullptr;     // slice partials of the sliced delta path
     double *dunits = nullptr;    // deltas [nnz][J] of the shared-index units
     double *gph = nullptr;       // pass-major copy of a permuted core (units)
+    double *ltab = nullptr;      // tables of the long runs of one mode (units)
     // Approx variant: residuals [nnz], slice sums, R per cell, removed count
     double *ap_resid = nullptr, *ap_part = nullptr, *ap_R = nullptr;
     int32_t *ap_removed = nullptr;

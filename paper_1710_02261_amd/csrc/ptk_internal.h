@@ -274,17 +274,29 @@ hipError_t build_mode_csr(const int32_t *idx, const float *val, int64_t nnz,
                           const Shape &s, int n, void *work, int64_t *rowptr,
                           int32_t *rows, int32_t *oidx, float *vals,
                           hipStream_t st, int32_t *perm_out = nullptr, int sub = -1);
-// Unit lists of the shared-index row systems (ptk_sort.hip): the runs of
-// consecutive grouped entries with the same row and the same index sidx (an
-// other mode's), each cut into units of emax entries and then at most one
-// unit each of emax/2, ..., 2, 1 entries (the binary digits of the rest).
-// units receives the start positions, classes in the order emax, ..., 1,
-// each in increasing position; count[c] is the number of units of class c
-// (2^c entries), c = 0..log2(emax). The workspace holds units_workspace_ints
-// int32 values.
+// Unit lists of the shared-index row systems (ptk_sort.hip). A run is a
+// maximal sequence of consecutive grouped entries with the same row and the
+// same index sidx (an other mode's). A run of at least lmin entries (lmin >
+// 0) is long: it is listed in lg (its first position, and tasks of at most
+// tlen consecutive entries, each naming its long run). Every other run is cut
+// into units of emax entries and then at most one unit each of emax/2, ...,
+// 2, 1 entries (the binary digits of the rest). units receives the units'
+// first positions, classes in the order emax, ..., 1, each in increasing
+// position; count[c] is the number of units of class c (2^c entries), c =
+// 0..3. The workspace holds units_workspace_ints int32 values; lg's arrays
+// hold cap_long and cap_tasks values (hipErrorInvalidValue beyond).
+struct UnitLong {
+    int32_t *run_pos = nullptr;       // [n_long] first position of each long run
+    int32_t *task_pos = nullptr;      // [n_tasks] first position of each task
+    int32_t *task_len = nullptr;      // [n_tasks] its entries (<= tlen)
+    int32_t *task_run = nullptr;      // [n_tasks] its long run
+    int64_t n_long = 0, n_tasks = 0;
+    int64_t cap_long = 0, cap_tasks = 0;
+};
 int64_t units_workspace_ints(int64_t nnz);
 hipError_t build_units(const int32_t *rows, const int32_t *sidx, int64_t nnz, int emax,
-                       int32_t *work, int32_t *units, int64_t *count, hipStream_t st);
+                       int32_t lmin, int32_t tlen, int32_t *work, int32_t *units,
+                       int64_t *count, UnitLong *lg, hipStream_t st);
 // inv[perm[i]] = i
 hipError_t launch_invert_perm(const int32_t *perm, int64_t nnz, int32_t *inv,
                               hipStream_t st);

@@ -365,38 +365,64 @@ __global__ void k_run_starts(const int32_t *__restrict__ rows, const int32_t *__
     }
 }
 
-// Units of class c (2^c entries) in a run of len entries.
-__device__ __forceinline__ int32_t class_units(int32_t len, int c, int cmax) {
-    return c == cmax ? (len >> cmax) : ((len >> c) & 1);
+// Counters of a run of len entries: q = 0..3, units of 2^q entries (none
+// above cmax); q = 4, one long run; q = 5, its tasks of at most tlen
+// entries. A run of at least lmin entries (lmin > 0) is long and has no units.
+__device__ __forceinline__ int32_t run_count(int32_t len, int q, int cmax, int32_t lmin,
+                                             int32_t tlen) {
+    const bool lng = lmin > 0 && len >= lmin;
+    if (q == 4) return lng ? 1 : 0;
+    if (q == 5) return lng ? (len + tlen - 1) / tlen : 0;
+    if (lng || q > cmax) return 0;
+    return q == cmax ? (len >> cmax) : ((len >> q) & 1);
 }
 
+constexpr int kRunCounters = 6;
+
 __global__ void k_unit_counts(const int32_t *__restrict__ start, int32_t R, int cmax,
-                              int32_t *__restrict__ cnt) {
+                              int32_t lmin, int32_t tlen, int32_t *__restrict__ cnt) {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
          r += (int64_t)gridDim.x * blockDim.x) {
         const int32_t len = start[r + 1] - start[r];
-        for (int c = 0; c <= cmax; ++c) cnt[(int64_t)c * R + r] = class_units(len, c, cmax);
+        for (int q = 0; q < kRunCounters; ++q)
+            cnt[(int64_t)q * R + r] = run_count(len, q, cmax, lmin, tlen);
     }
 }
 
-// total[c] = off[c][R-1] + units of class c in the last run
+// total[q] = off[q][R-1] + the last run's counter q
 __global__ void k_unit_totals(const int32_t *__restrict__ start, int32_t R, int cmax,
-                              const int32_t *__restrict__ off, int64_t *__restrict__ total) {
-    const int c = threadIdx.x;
-    if (c > cmax) return;
+                              int32_t lmin, int32_t tlen, const int32_t *__restrict__ off,
+                              int64_t *__restrict__ total) {
+    const int q = threadIdx.x;
+    if (q >= kRunCounters) return;
     const int32_t len = start[R] - start[R - 1];
-    total[c] = (int64_t)off[(int64_t)c * R + R - 1] + class_units(len, c, cmax);
+    total[q] = (int64_t)off[(int64_t)q * R + R - 1] + run_count(len, q, cmax, lmin, tlen);
 }
 
 __global__ void k_unit_write(const int32_t *__restrict__ start, int32_t R, int cmax,
-                             const int32_t *__restrict__ off, const int64_t *__restrict__ base,
-                             int32_t *__restrict__ units) {
+                             int32_t lmin, int32_t tlen, const int32_t *__restrict__ off,
+                             const int64_t *__restrict__ base, int32_t *__restrict__ units,
+                             UnitLong lg) {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
          r += (int64_t)gridDim.x * blockDim.x) {
         int32_t p = start[r];
         const int32_t len = start[r + 1] - p;
+        if (run_count(len, 4, cmax, lmin, tlen)) {
+            const int32_t li = off[4 * (int64_t)R + r];
+            lg.run_pos[li] = p;
+            const int32_t nt = run_count(len, 5, cmax, lmin, tlen);
+            int32_t *tp = lg.task_pos + off[5 * (int64_t)R + r];
+            int32_t *tl = lg.task_len + off[5 * (int64_t)R + r];
+            int32_t *tr = lg.task_run + off[5 * (int64_t)R + r];
+            for (int32_t q = 0; q < nt; ++q) {
+                tp[q] = p + q * tlen;
+                tl[q] = min(tlen, len - q * tlen);
+                tr[q] = li;
+            }
+            continue;
+        }
         for (int c = cmax; c >= 0; --c) {
-            const int32_t k = class_units(len, c, cmax);
+            const int32_t k = run_count(len, c, cmax, lmin, tlen);
             int32_t *dst = units + base[c] + off[(int64_t)c * R + r];
             for (int32_t q = 0; q < k; ++q) {
                 dst[q] = p;
@@ -407,25 +433,27 @@ __global__ void k_unit_write(const int32_t *__restrict__ start, int32_t R, int c
 }
 
 int64_t units_workspace_ints(int64_t nnz) {
-    // run ids, run starts, per-class counts (<= 4 classes of R <= nnz runs),
-    // the run count, class bases and scan work
-    return 2 * (nnz + 64) + 4 * (nnz + 64) + 64 + scan_work_elems(nnz) + 64;
+    // run ids, run starts, the counters of every run, the run count, totals
+    // and bases, scan work
+    return 2 * (nnz + 64) + kRunCounters * (nnz + 64) + 64 + scan_work_elems(nnz) + 64;
 }
 
 hipError_t build_units(const int32_t *rows, const int32_t *sidx, int64_t nnz, int emax,
-                       int32_t *work, int32_t *units, int64_t *count, hipStream_t st) {
+                       int32_t lmin, int32_t tlen, int32_t *work, int32_t *units,
+                       int64_t *count, UnitLong *lg, hipStream_t st) {
     int cmax = 0;
     while ((1 << cmax) < emax) ++cmax;
-    if (cmax > 3 || (1 << cmax) != emax) return hipErrorInvalidValue;
+    if (cmax > 3 || (1 << cmax) != emax || tlen <= 0) return hipErrorInvalidValue;
     for (int c = 0; c <= 3; ++c) count[c] = 0;
+    lg->n_long = lg->n_tasks = 0;
     if (nnz == 0) return hipSuccess;
     int32_t *rid = work;
     int32_t *start = rid + nnz + 64;
     int32_t *cnt = start + nnz + 64;
-    int32_t *misc = cnt + 4 * (nnz + 64);            // [0]: R; [2..]: int64 totals, bases
+    int32_t *misc = cnt + kRunCounters * (nnz + 64);   // [0]: R; [2..]: totals, bases
     int32_t *swork = misc + 64;
     int64_t *total = (int64_t *)(misc + 2);
-    int64_t *base = total + 4;
+    int64_t *base = total + kRunCounters;
     const unsigned gb = (unsigned)std::min<int64_t>((nnz + 255) / 256, 65536);
     hipLaunchKernelGGL(k_run_flags, dim3(gb), dim3(256), 0, st, rows, sidx, nnz, rid);
     hipError_t e = hipGetLastError();
@@ -439,16 +467,18 @@ hipError_t build_units(const int32_t *rows, const int32_t *sidx, int64_t nnz, in
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     if (R <= 0 || R > nnz) return hipErrorInvalidValue;
     const unsigned rb = (unsigned)std::min<int64_t>((R + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_unit_counts, dim3(rb), dim3(256), 0, st, start, R, cmax, cnt);
+    hipLaunchKernelGGL(k_unit_counts, dim3(rb), dim3(256), 0, st, start, R, cmax, lmin, tlen,
+                       cnt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    for (int c = 0; c <= cmax; ++c)
-        if ((e = scan_exclusive(cnt + (int64_t)c * R, cnt + (int64_t)c * R, R, swork, st)) !=
+    for (int q = 0; q < kRunCounters; ++q)
+        if ((e = scan_exclusive(cnt + (int64_t)q * R, cnt + (int64_t)q * R, R, swork, st)) !=
             hipSuccess)
             return e;
-    hipLaunchKernelGGL(k_unit_totals, dim3(1), dim3(64), 0, st, start, R, cmax, cnt, total);
+    hipLaunchKernelGGL(k_unit_totals, dim3(1), dim3(64), 0, st, start, R, cmax, lmin, tlen,
+                       cnt, total);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    int64_t ht[4] = {0, 0, 0, 0};
-    if ((e = hipMemcpyAsync(ht, total, 8 * (cmax + 1), hipMemcpyDeviceToHost, st)) !=
+    int64_t ht[kRunCounters] = {};
+    if ((e = hipMemcpyAsync(ht, total, 8 * kRunCounters, hipMemcpyDeviceToHost, st)) !=
         hipSuccess)
         return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
@@ -459,11 +489,13 @@ hipError_t build_units(const int32_t *rows, const int32_t *sidx, int64_t nnz, in
         at += ht[c];
         count[c] = ht[c];
     }
-    if (at > nnz) return hipErrorInvalidValue;
+    if (at > nnz || ht[4] > lg->cap_long || ht[5] > lg->cap_tasks) return hipErrorInvalidValue;
+    lg->n_long = ht[4];
+    lg->n_tasks = ht[5];
     if ((e = hipMemcpyAsync(base, hb, 8 * 4, hipMemcpyHostToDevice, st)) != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_unit_write, dim3(rb), dim3(256), 0, st, start, R, cmax, cnt, base,
-                       units);
+    hipLaunchKernelGGL(k_unit_write, dim3(rb), dim3(256), 0, st, start, R, cmax, lmin, tlen,
+                       cnt, base, units, *lg);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return hipStreamSynchronize(st);   // hb lives on this stack frame
 }

@@ -11,9 +11,14 @@
 
 namespace ptk {
 
-// Largest unit (entries sharing one t): 8 at orders 3 and 4 up to J = 10,
-// else 4 (register and LDS footprint).
+// Largest unit (entries sharing one t) with a kernel: 8 at orders 3 and 4
+// up to J = 10, else 4 (register and LDS footprint).
 constexpr int units_emax(int N, int J) { return (J <= 10 && N <= 4) ? 8 : 4; }
+// Largest unit by default: the kernels of 4 and 8 entries keep too few
+// wavefronts resident to hide the scalar loads of the core, and measured
+// slower per entry than pairs on the order-4 and order-5 workloads; long
+// runs take most of what they would save.
+constexpr int kUnitsDefault = 2;
 
 // Arguments of the unit delta kernel for one class of units.
 struct UnitArgs {
@@ -25,6 +30,27 @@ struct UnitArgs {
     int64_t count;                    // units in this class
     double *dout;                     // deltas [nnz][J] in grouped order
 };
+
+// Long runs: a run of at least kLongRun entries gets its own table
+// T[o][j] = sum_m gp[o][m][j] a^(s)[m] (J^(N-1) doubles), formed once, and
+// its entries, in tasks of at most kLongTask, read T through the scalar
+// cache instead of forming t per unit.
+constexpr int32_t kLongRun = 64;
+constexpr int32_t kLongTask = 128;
+// Tables of one mode beyond this many bytes: no long runs (units only).
+constexpr int64_t kLongTableBytes = int64_t(4) << 30;
+
+struct LongArgs {
+    const void *gp;                   // FP64 permuted core of mode n
+    const float *fac[kMaxN];          // factors of the other modes, mode order
+    const int32_t *oidx[kMaxN];       // other-mode index arrays, same order
+    UnitLong lg;                      // long runs and their tasks
+    double *tab;                      // [n_long][J^(N-2)][J]
+    double *dout;                     // deltas [nnz][J] in grouped order
+};
+
+// Tables of every long run, then the deltas of every task's entries.
+hipError_t launch_long_runs(const LongArgs &a, int N, int J, hipStream_t st);
 
 // (N, J) with equal ranks and unit kernels (FP64 arithmetic).
 bool units_available(int N, int J);
@@ -45,11 +71,16 @@ hipError_t launch_delta_units(const UnitArgs &a, int N, int J, int c, hipStream_
 // keeps the deltas of planned least-squares rows when a.kbase is set.
 hipError_t launch_gram_stored(const GramArgs &a, int J, const double *din, int64_t nchunks,
                               hipStream_t st);
+// Resident single-wave workgroups of the stored-delta sweep per CU.
+int gram_stored_blocks_per_cu(int J);
 
 // Multiply-adds per entry of the plain contraction and of one unit of e
 // entries (the model that decides whether a mode uses units).
 double plain_fma_per_entry(int N, int J);
 double unit_fma(int N, int J, int e);
+// Multiply-adds of the long-run form: one table per run, then J^(N-1) + J^(N-2)
+// per entry.
+double long_fma(int N, int J, double runs, double entries);
 // Writing and reading back one entry's delta (16 J + 8 bytes of HBM traffic)
 // in multiply-add equivalents: about 5.5 FP64 multiply-adds per byte at the
 // rates these kernels sustain (27 T multiply-adds/s against 5 TB/s).

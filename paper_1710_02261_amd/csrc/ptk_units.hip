@@ -265,6 +265,146 @@ hipError_t launch_core_passes(const double *gp, double *gph, int N, int J, hipSt
     return hipGetLastError();
 }
 
+// Tables of the long runs, two runs per lane and a slice of the outer
+// indices per workgroup row: T[r][o][j] = sum_m gp[o][m][j] a^(s)_{i_s}[m],
+// the core values read through the scalar cache as in k_delta_singles.
+template <int N, int J>
+__global__ __launch_bounds__(kWave) void k_run_tables(LongArgs a) {
+    constexpr int NO = N - 1;
+    constexpr int OUTER = ipow(J, N - 2);
+    constexpr int P = 2;
+    const int lane = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * (P * kWave) + lane;
+    int64_t run[P];
+    bool valid[P];
+    double as[P][J];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        run[p] = r0 + (int64_t)p * kWave;
+        valid[p] = run[p] < a.lg.n_long;
+        const int64_t pos = valid[p] ? a.lg.run_pos[run[p]] : 0;
+        const float *r = a.fac[NO - 1] + (int64_t)a.oidx[NO - 1][pos] * J;
+#pragma unroll
+        for (int j = 0; j < J; ++j) as[p][j] = (double)r[j];
+    }
+    cptr<double> gp = (cptr<double>)a.gp;
+    // the outer indices are cut into gridDim.y slices, one per workgroup row
+    const int o_begin = (int)((int64_t)blockIdx.y * OUTER / gridDim.y);
+    const int o_end = (int)((int64_t)(blockIdx.y + 1) * OUTER / gridDim.y);
+#pragma unroll 1
+    for (int o = o_begin; o < o_end; ++o) {
+        cptr<double> g = gp + (int64_t)o * (J * J);
+        double t[P][J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const double gv = g[j];
+#pragma unroll
+            for (int p = 0; p < P; ++p) t[p][j] = gv * as[p][0];
+        }
+#pragma unroll
+        for (int m = 1; m < J; ++m)
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const double gv = g[m * J + j];
+#pragma unroll
+                for (int p = 0; p < P; ++p) t[p][j] = __builtin_fma(gv, as[p][m], t[p][j]);
+            }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            if (!valid[p]) continue;
+            double *dst = a.tab + (run[p] * OUTER + o) * J;
+#pragma unroll
+            for (int j = 0; j < J; ++j) dst[j] = t[p][j];
+        }
+    }
+}
+
+// Deltas of a long run's task: one wavefront, two entries per lane. The
+// run's table is uniform over the wavefront and is read through the scalar
+// cache, J values per outer index, each feeding two multiply-adds; the row
+// of the fastest leading mode sits in VGPRs, the slower ones' rows in LDS
+// (read once per J outer indices).
+template <int N, int J>
+__global__ __launch_bounds__(kWave) void k_delta_long(LongArgs a) {
+    constexpr int NO = N - 1;
+    constexpr int NOUT = NO - 1;                 // leading other modes
+    constexpr int NS = NOUT - 1;                 // slow ones (LDS)
+    constexpr int OUTER = ipow(J, NOUT);
+    constexpr int OB = OUTER / J;                // outer indices of the slow modes
+    constexpr int P = 2;
+    __shared__ float s_a[(NS > 0 ? NS : 1) * J * P * kWave];   // [p][k][j][lane]
+    const int lane = threadIdx.x;
+    const int64_t task = blockIdx.x;
+    const int64_t tpos = a.lg.task_pos[task];
+    const int tlen = a.lg.task_len[task];
+    const int64_t run = a.lg.task_run[task];
+    int64_t pos[P];
+    bool valid[P];
+    double af[P][J];                             // fastest leading mode's row
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int off = lane + p * kWave;
+        valid[p] = off < tlen;
+        pos[p] = tpos + (valid[p] ? off : 0);
+        const float *r = a.fac[NOUT - 1] + (int64_t)a.oidx[NOUT - 1][pos[p]] * J;
+#pragma unroll
+        for (int j = 0; j < J; ++j) af[p][j] = (double)r[j];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const float *row = a.fac[k] + (int64_t)a.oidx[k][pos[p]] * J;
+#pragma unroll
+            for (int j = 0; j < J; ++j) s_a[((p * NS + k) * J + j) * kWave + lane] = row[j];
+        }
+    }
+    __syncthreads();
+    double c[P][J];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int j = 0; j < J; ++j) c[p][j] = 0.0;
+    cptr<double> tab = (cptr<double>)(a.tab + run * (OUTER * J));
+#pragma unroll 1
+    for (int ob = 0; ob < OB; ++ob) {
+        double ws[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) ws[p] = 1.0;
+        if constexpr (NS > 0) {
+            int d[NS > 0 ? NS : 1];
+            int rest = ob;
+#pragma unroll
+            for (int k = NS - 1; k >= 0; --k) {
+                d[k] = rest % J;
+                rest /= J;
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int k = 0; k < NS; ++k)
+                    ws[p] *= (double)s_a[((p * NS + k) * J + d[k]) * kWave + lane];
+        }
+        cptr<double> tb = tab + (int64_t)ob * (J * J);
+#pragma unroll(J <= 10 ? J : 4)
+        for (int dl = 0; dl < J; ++dl) {
+            double w[P];
+#pragma unroll
+            for (int p = 0; p < P; ++p) w[p] = ws[p] * af[p][dl];
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const double tv = tb[dl * J + j];
+#pragma unroll
+                for (int p = 0; p < P; ++p) c[p][j] = __builtin_fma(tv, w[p], c[p][j]);
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        if (!valid[p]) continue;
+        double *dst = a.dout + pos[p] * J;
+#pragma unroll
+        for (int j = 0; j < J; ++j) dst[j] = c[p][j];
+    }
+}
+
 // Row systems from stored deltas: per work range, tiles of 64 entries in
 // grouped order; the tile's deltas (64 * J contiguous doubles) are read with
 // coalesced loads into the LDS layout of sweep_tile.
@@ -379,6 +519,38 @@ hipError_t launch_delta_units(const UnitArgs &a, int N, int J, int c, hipStream_
     return hipErrorInvalidValue;
 }
 
+template <int N, int J>
+hipError_t launch_long_nj(const LongArgs &a, hipStream_t st) {
+    if (a.lg.n_long <= 0) return hipSuccess;
+    const unsigned rb = (unsigned)((a.lg.n_long + 2 * kWave - 1) / (2 * kWave));
+    // enough workgroups to fill the chip: slices of the outer indices
+    constexpr int OUTER = ipow(J, N - 2);
+    const unsigned slices = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>(OUTER, (8192 + rb - 1) / rb));
+    hipLaunchKernelGGL((k_run_tables<N, J>), dim3(rb, slices), dim3(kWave), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || a.lg.n_tasks <= 0) return e;
+    hipLaunchKernelGGL((k_delta_long<N, J>), dim3((unsigned)a.lg.n_tasks), dim3(kWave), 0, st,
+                       a);
+    return hipGetLastError();
+}
+
+hipError_t launch_long_runs(const LongArgs &a, int N, int J, hipStream_t st) {
+    if (a.lg.n_tasks >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+#define PTK_X(n_, j_) \
+    if (N == n_ && J == j_) return launch_long_nj<n_, j_>(a, st);
+    PTK_UNIT_SHAPES(PTK_X)
+#undef PTK_X
+    return hipErrorInvalidValue;
+}
+
+int gram_stored_blocks_per_cu(int J) {
+    if (J == 8) return blocks_per_cu(k_gram_stored<8>, 0);
+    if (J == 10) return blocks_per_cu(k_gram_stored<10>, 0);
+    if (J == 16) return blocks_per_cu(k_gram_stored<16>, 0);
+    return 8;
+}
+
 hipError_t launch_gram_stored(const GramArgs &a, int J, const double *din, int64_t nchunks,
                               hipStream_t st) {
     if (nchunks <= 0) return hipSuccess;
@@ -413,5 +585,12 @@ double unit_fma(int N, int J, int e) {
 }
 
 double stored_delta_fma(int J) { return 5.5 * (16.0 * J + 8.0); }
+
+double long_fma(int N, int J, double runs, double entries) {
+    double cells = 1.0, inner = 1.0;
+    for (int k = 0; k < N; ++k) cells *= J;
+    for (int k = 0; k < N - 1; ++k) inner *= J;
+    return runs * cells + entries * (inner + inner / J);
+}
 
 }  // namespace ptk

@@ -3,9 +3,11 @@ systems (eqs. "rowB", "rowC") formed from units of consecutive entries of a
 row that share their index in the last other mode, the core contracted with
 that mode's row once per unit (eq. "delta" summed in another order).
 
-* Unit lists: per mode, the numbers of units of 1, 2, 4 and 8 entries equal
-  those of the runs of equal (i_n, i_s) counted here from the COO input
-  (exact), for the default cap and the caps 2, 4 and 8.
+* Unit lists: per mode, the numbers of units of 1, 2, 4 and 8 entries, of
+  long runs (64 entries or more, whose entries read a table of the core
+  contracted with the shared row) and of their tasks equal those of the runs
+  of equal (i_n, i_s) counted here from the COO input (exact), for the
+  default cap and the caps 2, 4 and 8.
 * Row systems to 1e-10 and one mode update to 1e-5 per row against the
   oracle, every unit shape, with work ranges that cut rows; the units and the
   fused kernels give the same row systems to 1e-12.
@@ -41,17 +43,25 @@ def problem(dims, J, nnz, seed):
     return synth.make_small(dims, (J,) * len(dims), nnz, seed=seed, skew=1.1)
 
 
+LONG_RUN, LONG_TASK = 64, 128
+
+
 def expected_units(p, n, emax):
-    """Units per class from the runs of equal (i_n, i_s), s the last mode
-    other than n: floor(r / emax) units of emax, then the bits of r % emax."""
+    """Counters from the runs of equal (i_n, i_s), s the last mode other than
+    n: a run of r >= 64 entries is long (one run, ceil(r / 128) tasks); any
+    other gives floor(r / emax) units of emax, then the bits of r % emax."""
     N = len(p.dims)
     s = N - 1 if n != N - 1 else N - 2
     key = p.idx[n].astype(np.int64) * p.dims[s] + p.idx[s].astype(np.int64)
     _, runs = np.unique(key, return_counts=True)
+    lng = runs >= LONG_RUN
+    out = [0] * 6
+    out[4] = int(lng.sum())
+    out[5] = int(((runs[lng] + LONG_TASK - 1) // LONG_TASK).sum())
+    short = runs[~lng]
     cmax = emax.bit_length() - 1
-    out = [0, 0, 0, 0]
-    out[cmax] = int((runs // emax).sum())
-    rest = runs % emax
+    out[cmax] = int((short // emax).sum())
+    rest = short % emax
     for c in range(cmax):
         out[c] = int(((rest >> c) & 1).sum())
     return out
@@ -63,14 +73,18 @@ def test_unit_lists_count_runs(dims, J, nnz, cap):
     p = problem(dims, J, nnz, seed=71)
     ctx, *_ = context(p, shared_units=cap)
     emax = 8 if (J <= 10 and len(dims) <= 4) else 4
-    if cap > 1:
-        emax = min(emax, cap)
+    emax = min(emax, cap) if cap > 1 else 2
     for n in range(len(dims)):
         counts, on = ctx.unit_stats(n)
         want = expected_units(p, n, emax)
         assert counts == want, (n, counts, want)
         assert on
-        assert sum((1 << c) * k for c, k in enumerate(counts)) == nnz
+        N = len(dims)
+        s = N - 1 if n != N - 1 else N - 2
+        key = p.idx[n].astype(np.int64) * dims[s] + p.idx[s]
+        _, runs = np.unique(key, return_counts=True)
+        in_long = int(runs[runs >= LONG_RUN].sum())
+        assert sum((1 << c) * counts[c] for c in range(4)) + in_long == nnz
     ctx.close()
 
 
@@ -180,7 +194,7 @@ def test_empty_observed_set_and_refusals():
     idx = torch.zeros((4, 0), dtype=torch.int32, device="cuda")
     val = torch.zeros((0,), dtype=torch.float32, device="cuda")
     ctx.set_observed(idx, val)
-    assert ctx.unit_stats(0) == ([0, 0, 0, 0], False)
+    assert ctx.unit_stats(0) == ([0, 0, 0, 0, 0, 0], False)
     with pytest.raises(ptk.PtkError):
         ctx.set_options(shared_units=-1)            # after set_observed
     ctx.close()
