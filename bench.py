@@ -30,9 +30,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gram_c2_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "delta_singles_c2_traffic.json")
 KERNEL_SRC = [os.path.join(ROOT, "paper_1710_02261_amd", "csrc", f)
-              for f in ("ptk_kernels.hip", "ptk_gram2.hip", "ptk_device.h", "ptk_internal.h")]
+              for f in ("ptk_units.hip", "ptk_units.h", "ptk_device.h", "ptk_internal.h")]
 
 
 def command_line():
@@ -73,7 +73,7 @@ def traffic_record(launch_nnz):
     return rec.get("bytes_per_launch")
 
 
-HEADLINE_KERNEL = "void ptk::k_gram_fast2<4, 10, 1, double, false>(ptk::GramArgs)"
+HEADLINE_KERNEL = "void ptk::k_delta_singles<4, 10>(ptk::UnitArgs)"
 # a precision form is reported with throughput when its RMSE after the run is
 # at most this much above the FP64 path's (the comparison at equal RMSE)
 USABLE_RMSE = 0.10
@@ -102,7 +102,7 @@ def traffic_summary(fetch_csv, write_csv, launches):
 
     out = {"kernel": HEADLINE_KERNEL,
            "workload": "order-4 100000^4, 1e7 entries Zipf(1.1), J=10, FP64 arithmetic, "
-                       "autotuned work ranges",
+                       "shared-index units, autotuned work ranges",
            "kernel_sha": kernel_hash()}
     cal = {"kernel": "torch.mul of 64 Mi float32 (reads and writes 256 MiB)"}
     for tag, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"),
@@ -740,7 +740,8 @@ def main():
         kname = ("k_run_tables<%d,%d> + k_delta_long<%d,%d>" % (N, J, N, J) if e == "long"
                  else "k_delta_singles<%d,%d>" % (N, J) if e == 1
                  else "k_delta_units<%d,%d,%d,...>" % (N, J, e))
-        traffic = None
+        if e != 1:                 # the committed counters are of k_delta_singles
+            traffic = None
     roofline = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak, "traffic": traffic, "kernel": kname,
                 "avg_launch_ms": avg_s * 1e3, "flops_per_launch": flops}
