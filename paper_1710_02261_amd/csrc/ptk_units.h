@@ -81,9 +81,10 @@ double unit_fma(int N, int J, int e);
 // Multiply-adds of the long-run form: one table per run, then J^(N-1) + J^(N-2)
 // per entry.
 double long_fma(int N, int J, double runs, double entries);
-// Writing and reading back one entry's delta (16 J + 8 bytes of HBM traffic)
-// in multiply-add equivalents: about 5.5 FP64 multiply-adds per byte at the
-// rates these kernels sustain (27 T multiply-adds/s against 5 TB/s).
+// The stored-delta sweep of one entry (8 J + 8 bytes read) in multiply-add
+// equivalents: 15 FP64 multiply-adds per byte, the ratio of the rates
+// measured for the delta kernels (27 T multiply-adds/s) and the sweep
+// (1.8 TB/s) on the order-4 workload.
 double stored_delta_fma(int J);
 
 }  // namespace ptk

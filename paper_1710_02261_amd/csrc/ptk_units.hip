@@ -441,7 +441,43 @@ __global__ __launch_bounds__(kWave) void k_gram_stored(GramArgs a, const double 
                 for (int j = 0; j < J; ++j) a.keep[(kb + p) * J + j] = s_dl[j * kDlStride + lane];
             }
         }
-        sweep_tile<EPL>(a, sl, s_dl, s_row, nb, cur, chunk, cs, ce);
+        if (cur >= 0 && __ballot(v && row != cur) == 0) {
+            // the whole tile continues the open row: no row checks; a
+            // slot that only a few lanes use is summed by a wave reduction
+            // over the tile's entries instead of a masked pass per entry
+#pragma unroll
+            for (int t = 0; t < EPL; ++t) {
+                constexpr int kFull = E / kWave;
+                if (t < kFull) {
+                    const double *pp = s_dl + sl.p[t] * kDlStride;
+                    const double *qq = s_dl + sl.q[t] * kDlStride;
+                    double acc = sl.acc[t];
+#pragma unroll 8
+                    for (int b = 0; b < nb; ++b) acc = __builtin_fma(pp[b], qq[b], acc);
+                    sl.acc[t] = acc;
+                } else if constexpr (E - kFull * kWave <= 4) {
+#pragma unroll
+                    for (int k = 0; k < E - kFull * kWave; ++k) {
+                        const int pk = __shfl(sl.p[t], k), qk = __shfl(sl.q[t], k);
+                        double x = v ? s_dl[pk * kDlStride + lane] * s_dl[qk * kDlStride + lane]
+                                     : 0.0;
+#pragma unroll
+                        for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off);
+                        if (lane == k) sl.acc[t] += x;
+                    }
+                } else {
+                    if (sl.e[t] >= 0) {
+                        const double *pp = s_dl + sl.p[t] * kDlStride;
+                        const double *qq = s_dl + sl.q[t] * kDlStride;
+                        double acc = sl.acc[t];
+                        for (int b = 0; b < nb; ++b) acc = __builtin_fma(pp[b], qq[b], acc);
+                        sl.acc[t] = acc;
+                    }
+                }
+            }
+        } else {
+            sweep_tile<EPL>(a, sl, s_dl, s_row, nb, cur, chunk, cs, ce);
+        }
         __syncthreads();
     }
     if (cur >= 0) flush_row<EPL>(a, sl, cur, chunk, cs, ce);
@@ -584,7 +620,7 @@ double unit_fma(int N, int J, int e) {
     return outer * ((double)J * J + e * ((double)J + (N - 3)));
 }
 
-double stored_delta_fma(int J) { return 5.5 * (16.0 * J + 8.0); }
+double stored_delta_fma(int J) { return 15.0 * (8.0 * J + 8.0); }
 
 double long_fma(int N, int J, double runs, double entries) {
     double cells = 1.0, inner = 1.0;
