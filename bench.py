@@ -682,19 +682,30 @@ def main():
 
     avg_s = r["gram_ms"] / 1e3
     unit_kernel = None
-    if any(on for _, on in r["units"]):
+    if any(on for _, on in r["units"]) and not main_prec.startswith("bf16"):
         # shared-index units: the dominant kernel is the unit class with the
         # most time; its work is the multiply-adds the unit form executes
         # (J^(N-2) (J^2 + e (J + N - 3)) per unit of e entries)
         best = None
-        on_modes = [u for u, on in r["units"] if on]
-        for c in range(5):
-            name = "delta_long" if c == 4 else "delta_units%d" % (1 << c)
+        on_modes = [u for u, on in r["units"] if on == 1]
+        ix_modes = [n for n, (u, on) in enumerate(r["units"]) if on == 2]
+        for c in range(6):
+            name = ("delta_index" if c == 5 else "delta_long" if c == 4
+                    else "delta_units%d" % (1 << c))
             calls, ms = r["times"].get(name, (0, 0.0))
             if calls and (best is None or ms > best[2]):
                 best = (c, calls, ms)
         c, calls, ms = best
-        if c == 4:
+        if c == 5:
+            # index tables: I_s J^N multiply-adds for the tables of a mode,
+            # then J^(N-1) + J^(N-2) per entry
+            fl = 0.0
+            for n in ix_modes:
+                s_mode = N - 1 if n != N - 1 else N - 2
+                fl += p.dims[s_mode] * J ** N + p.nnz * (J ** (N - 1) + J ** (N - 2))
+            unit_kernel = {"class": "index", "avg_ms": ms / calls,
+                           "flops": 2.0 * fl / len(ix_modes)}
+        elif c == 4:
             # long runs: a table of J^N multiply-adds per run, then
             # J^(N-1) + J^(N-2) per entry
             fl = 0.0
@@ -737,7 +748,9 @@ def main():
         traffic = None
     if unit_kernel:
         e = unit_kernel["class"]
-        kname = ("k_run_tables<%d,%d> + k_delta_long<%d,%d>" % (N, J, N, J) if e == "long"
+        kname = ("k_run_tables<%d,%d> + k_delta_long<%d,%d,1> (index tables)" % (N, J, N, J)
+                 if e == "index"
+                 else "k_run_tables<%d,%d> + k_delta_long<%d,%d,2>" % (N, J, N, J) if e == "long"
                  else "k_delta_singles<%d,%d>" % (N, J) if e == 1
                  else "k_delta_units<%d,%d,%d,...>" % (N, J, e))
         if e != 1:                 # the committed counters are of k_delta_singles
@@ -782,7 +795,8 @@ def main():
                                         for a, b in zip(r["loss"], r["loss"][1:]))),
         "kernel_ms": {k: v[1] / max(v[0], 1) for k, v in r["times"].items()},
         "shared_units": {"option": args.shared_units,
-                         "per_mode": [{"units_1_2_4_8_long_tasks": u, "on": on}
+                         "per_mode": [{"units_1_2_4_8_long_tasks_values_tasks": u,
+                                       "form": ["fused", "units", "index tables"][on]}
                                       for u, on in r["units"]]},
     }
     if not args.no_variant:

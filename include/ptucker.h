@@ -184,7 +184,13 @@ typedef struct ptk_options {
                                many entries. Runs of 64 entries or more of
                                one row and one i_s get a table of the core
                                contracted with that row (J^(N-1) doubles
-                               each, at most 4 GiB per mode) instead. Chosen
+                               each, at most 4 GiB per mode) instead. 16 =
+                               index tables: G contracted with every row of
+                               A^(s) (I_s * J^(N-1) doubles, at most 16 GiB
+                               per mode, rebuilt at every mode update) serves
+                               every entry with that i_s whatever its row;
+                               auto takes them when the model prefers them.
+                               Chosen
                                before ptk_set_observed; not used with
                                pair_cache, approx_rate > 0 or the FP32 and
                                BF16 forms. Other values: PTK_E_INVALID.      */
@@ -301,19 +307,20 @@ ptk_status ptk_approx_stats(ptk_ctx *ctx, int64_t *nonzero_cells_host,
                             int32_t *sparse_modes_host);
 
 /*
- * Shared-index units of mode n (ptk_options.shared_units) built by the last
- * ptk_set_observed. A run is a maximal sequence of grouped entries of one row
- * with the same index in the last other mode. A run of 64 entries or more is
- * long (it gets a table of the core contracted with that mode's row, and its
- * entries are processed in tasks of at most 128); any other run of r entries
- * gives floor(r / emax) units of emax entries, then one unit for each set bit
- * of r mod emax (emax is 2, or the option's 4 or 8 where a kernel exists: 8
- * at orders 3 and 4 with J <= 10, else 4). counts_host receives 6 values:
- * the units of 1, 2,
- * 4 and 8 entries, the long runs and their tasks. *on_host: whether the row
- * systems of mode n use them (1) or the fused kernels (0). All zero when
- * nothing was built. PTK_E_INVALID for n out of range, PTK_E_STATE before
- * ptk_set_observed.
+ * Shared-index row systems of mode n (ptk_options.shared_units) as built by
+ * the last ptk_set_observed; s is the last mode other than n. A run is a
+ * maximal sequence of grouped entries of one row with the same i_s. A run of
+ * 64 entries or more is long (it gets a table of the core contracted with
+ * that row of A^(s), and its entries are processed in tasks of at most 128);
+ * any other run of r entries gives floor(r / emax) units of emax entries,
+ * then one unit for each set bit of r mod emax (emax is 2, or the option's
+ * 4 or 8 where a kernel exists: 8 at orders 3 and 4 with J <= 10, else 4).
+ * The index groups are the entries of one value of i_s whatever their row,
+ * in tasks of at most 128. counts_host receives 8 values: the units of 1, 2,
+ * 4 and 8 entries, the long runs, their tasks, the index values present and
+ * their tasks (zero where that form was not built). *on_host: the form mode
+ * n's row systems use: 0 the fused kernels, 1 units, 2 index tables.
+ * PTK_E_INVALID for n out of range, PTK_E_STATE before ptk_set_observed.
  */
 ptk_status ptk_unit_stats(ptk_ctx *ctx, int32_t n, int64_t *counts_host, int32_t *on_host);
 

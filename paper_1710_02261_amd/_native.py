@@ -281,13 +281,13 @@ class Context:
         return a.value, b.value
 
     def unit_stats(self, n):
-        """([units of 1, 2, 4, 8 entries, long runs, their tasks], whether
-        mode n's row systems use them) for the shared-index units built by
-        set_observed."""
-        cnt = (_i64 * 6)()
+        """([units of 1, 2, 4, 8 entries, long runs, their tasks, index
+        values, their tasks], path of mode n's row systems: 0 fused kernels,
+        1 units, 2 index tables) as built by set_observed."""
+        cnt = (_i64 * 8)()
         on = _i32()
         self._check(self._lib.ptk_unit_stats(self._h, int(n), cnt, C.byref(on)))
-        return [int(x) for x in cnt], bool(on.value)
+        return [int(x) for x in cnt], int(on.value)
 
     def recon_error(self, lam=0.0):
         s, r, l = _dbl(), _dbl(), _dbl()

@@ -136,6 +136,11 @@ void free_modes(ptk_ctx *c) {
         dfree(m.lg.task_pos);
         dfree(m.lg.task_len);
         dfree(m.lg.task_run);
+        dfree(m.spos);
+        dfree(m.ix.run_pos);
+        dfree(m.ix.task_pos);
+        dfree(m.ix.task_len);
+        dfree(m.ix.task_run);
         m = ModeData();
     }
     dfree(c->bbuf);
@@ -150,6 +155,8 @@ void free_modes(ptk_ctx *c) {
     c->gph = nullptr;
     dfree(c->ltab);
     c->ltab = nullptr;
+    dfree(c->itab);
+    c->itab = nullptr;
     free_approx(c);
     c->bbuf = c->part = nullptr;
     c->part_cap = 0;
@@ -339,10 +346,13 @@ SparseMode sparse_mode(const ptk_ctx *c, int n) {
 // pair cache, no Approx variant (whose kernels keep their own deltas).
 bool units_live(const ptk_ctx *c, int n) {
     const ModeData &m = c->md[n];
-    return m.units_on && c->dunits && m.fast && !m.bf16 && m.slices <= 1 &&
+    return (m.units_on || m.ix_on) && c->dunits && m.fast && !m.bf16 && m.slices <= 1 &&
            arith_of(c, n) == kArithF64 && cache_role(c, n) == 0 &&
            !(c->opt.approx_rate > 0.0);
 }
+
+// ... and from the index tables of the last other mode (units_live and ix_on).
+bool index_live(const ptk_ctx *c, int n) { return units_live(c, n) && c->md[n].ix_on; }
 
 // B_i, c_i for every row of mode n into bbuf (delta + Gram kernel, merge).
 ptk_status systems(ptk_ctx *c, int n, int role = 0) {
@@ -404,7 +414,23 @@ ptk_status systems(ptk_ctx *c, int n, int role = 0) {
             }));
         static const char *const names[4] = {"delta_units1", "delta_units2", "delta_units4",
                                              "delta_units8"};
-        if (m.lg.n_long > 0) {
+        if (m.ix_on) {
+            LongArgs la{};
+            la.gp = a.gp;
+            for (int t = 0; t < c->s.N - 1; ++t) {
+                la.fac[t] = a.fac[t];
+                la.oidx[t] = a.oidx[t];
+            }
+            la.lg = m.ix;
+            la.lg.n_long = c->s.dims[units_sub(c, n)];   // a table per index value
+            la.tab = c->itab;
+            la.dout = c->dunits;
+            la.index_tables = 1;
+            la.perm = m.spos;
+            HIPCHK(c, timed(c, "delta_index", [&] {
+                return launch_long_runs(la, c->s.N, c->s.ranks[n], kIndexTask / kWave, c->st);
+            }));
+        } else if (m.lg.n_long > 0) {
             LongArgs la{};
             la.gp = a.gp;
             for (int t = 0; t < c->s.N - 1; ++t) {
@@ -415,10 +441,10 @@ ptk_status systems(ptk_ctx *c, int n, int role = 0) {
             la.tab = c->ltab;
             la.dout = c->dunits;
             HIPCHK(c, timed(c, "delta_long", [&] {
-                return launch_long_runs(la, c->s.N, c->s.ranks[n], c->st);
+                return launch_long_runs(la, c->s.N, c->s.ranks[n], 2, c->st);
             }));
         }
-        for (int cl = 3; cl >= 0; --cl) {
+        for (int cl = 3; cl >= 0 && !m.ix_on; --cl) {
             if (m.ucount[cl] == 0) continue;
             ua.units = m.units + m.ubase[cl];
             ua.count = m.ucount[cl];
@@ -682,13 +708,13 @@ ptk_status build_unit_lists(ptk_ctx *c) {
     if (nnz <= 0 || units_sub(c, 0) < 0) return PTK_OK;
     const int J = s.ranks[0];
     const int su = c->opt.shared_units;
-    const int emax = su >= 2 ? std::min(su, units_emax(s.N, J)) : kUnitsDefault;
+    const int emax = (su >= 2 && su <= 8) ? std::min(su, units_emax(s.N, J)) : kUnitsDefault;
     int64_t inner = 1;                          // J^(N-1): one long run's table
     for (int n = 1; n < s.N; ++n) inner *= s.ranks[n];
     int32_t *work = nullptr;
     HIPCHK(c, dalloc(&work, (size_t)units_workspace_ints(nnz)));
     bool any = false;
-    int64_t tab_need = 0;
+    int64_t tab_need = 0, itab_need = 0;
     for (int n = 0; n < s.N; ++n) {
         ModeData &m = c->md[n];
         UnitLong &lg = m.lg;
@@ -724,27 +750,70 @@ ptk_status build_unit_lists(ptk_ctx *c) {
         f_units += long_fma(s.N, J, (double)lg.n_long, (double)(nnz - in_units));
         f_units += (double)nnz * stored_delta_fma(J);
         const double f_plain = (double)nnz * plain_fma_per_entry(s.N, J);
-        m.units_on = su != 0 || f_units <= 0.9 * f_plain;
-        any = any || m.units_on;
+        // index tables: entries in the order of i_s, groups of one value
+        const int sub = units_sub(c, n);
+        const int64_t Is = s.dims[sub];
+        const bool ix_fits = Is * inner * 8 <= kIndexTableBytes;
+        double f_index = 1e300;
+        if (ix_fits && su != 1 && !(su >= 2 && su <= 8)) {
+            UnitLong &ix = m.ix;
+            ix.cap_long = std::min<int64_t>(nnz, Is) + 1;
+            ix.cap_tasks = nnz / kIndexTask + ix.cap_long + 1;
+            int32_t *skeys = nullptr;
+            void *swork = nullptr;
+            e = dalloc(&m.spos, nnz + 64);
+            if (e == hipSuccess) e = dalloc(&skeys, nnz + 64);
+            if (e == hipSuccess) e = hipMalloc(&swork, sort_workspace_bytes(nnz));
+            if (e == hipSuccess) e = dalloc(&ix.run_pos, (size_t)ix.cap_long);
+            if (e == hipSuccess) e = dalloc(&ix.task_pos, (size_t)ix.cap_tasks);
+            if (e == hipSuccess) e = dalloc(&ix.task_len, (size_t)ix.cap_tasks);
+            if (e == hipSuccess) e = dalloc(&ix.task_run, (size_t)ix.cap_tasks);
+            if (e == hipSuccess) e = sort_by_key(sidx, nnz, Is, swork, skeys, m.spos, c->st);
+            int64_t none[4];
+            if (e == hipSuccess)
+                e = build_units(nullptr, skeys, nnz, 1, 1, kIndexTask, work, m.units, none,
+                                &ix, c->st);
+            if (e == hipSuccess) e = launch_task_keys(skeys, ix, c->st);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+            dfree(skeys);
+            if (swork) (void)hipFree(swork);
+            if (e != hipSuccess) {
+                dfree(work);
+                free_modes(c);
+                return fail(c, e == hipErrorOutOfMemory ? PTK_E_NOMEM : PTK_E_HIP,
+                            "index groups of mode %d: %s", n, hipGetErrorString(e));
+            }
+            f_index = (double)Is * (double)inner * J +
+                      (double)ix.n_tasks * kIndexTask * (double)(inner + inner / J) +
+                      (double)nnz * stored_delta_fma(J);
+        }
+        m.ix_on = ix_fits && (su == 16 || (su == 0 && f_index <= 0.9 * f_plain &&
+                                           f_index <= f_units));
+        m.units_on = !m.ix_on && (su != 0 || f_units <= 0.9 * f_plain);
+        any = any || m.units_on || m.ix_on;
         if (m.units_on) tab_need = std::max(tab_need, lg.n_long * inner);
+        if (m.ix_on) itab_need = std::max(itab_need, Is * inner);
     }
     dfree(work);
     int64_t cells = 1;
     for (int n = 0; n < s.N; ++n) cells *= s.ranks[n];
     if (any && (dalloc(&c->dunits, (size_t)nnz * J) != hipSuccess ||
                 dalloc(&c->gph, (size_t)cells) != hipSuccess ||
-                (tab_need > 0 && dalloc(&c->ltab, (size_t)tab_need) != hipSuccess))) {
+                (tab_need > 0 && dalloc(&c->ltab, (size_t)tab_need) != hipSuccess) ||
+                (itab_need > 0 && dalloc(&c->itab, (size_t)itab_need) != hipSuccess))) {
         dfree(c->dunits);
         dfree(c->gph);
+        dfree(c->ltab);
         c->dunits = nullptr;
         c->gph = nullptr;
         c->ltab = nullptr;
+        c->itab = nullptr;
         if (su != 0) {
             free_modes(c);
             return fail(c, PTK_E_NOMEM, "shared-index deltas: %.2f GB of device memory",
                         (nnz * J + tab_need) * 8e-9);
         }
-        for (int n = 0; n < s.N; ++n) c->md[n].units_on = false;
+        for (int n = 0; n < s.N; ++n) c->md[n].units_on = c->md[n].ix_on = false;
     }
     return PTK_OK;
 }
@@ -1219,8 +1288,8 @@ ptk_status ptk_set_options(ptk_ctx *c, const ptk_options *o) {
     if (!(o->sparse_limit <= 1.0) || !std::isfinite(o->sparse_limit))
         return fail(c, PTK_E_INVALID, "sparse_limit must be finite and <= 1");
     const int su = o->shared_units;
-    if (su != -1 && su != 0 && su != 1 && su != 2 && su != 4 && su != 8)
-        return fail(c, PTK_E_INVALID, "shared_units must be -1, 0, 1, 2, 4 or 8");
+    if (su != -1 && su != 0 && su != 1 && su != 2 && su != 4 && su != 8 && su != 16)
+        return fail(c, PTK_E_INVALID, "shared_units must be -1, 0, 1, 2, 4, 8 or 16");
     if (su != c->opt.shared_units && c->nnz >= 0)
         return fail(c, PTK_E_STATE, "shared_units must be set before ptk_set_observed");
     c->opt = *o;
@@ -2109,7 +2178,9 @@ extern "C" ptk_status ptk_unit_stats(ptk_ctx *c, int32_t n, int64_t *counts, int
     for (int k = 0; k < 4; ++k) counts[k] = m.ucount[k];
     counts[4] = m.lg.n_long;
     counts[5] = m.lg.n_tasks;
-    *on = units_live(c, n) ? 1 : 0;
+    counts[6] = m.ix.n_long;
+    counts[7] = m.ix.n_tasks;
+    *on = index_live(c, n) ? 2 : units_live(c, n) ? 1 : 0;
     return PTK_OK;
 }
 

@@ -42,6 +42,11 @@ struct ModeData {
     int64_t ucount[4] = {0, 0, 0, 0}, ubase[4] = {0, 0, 0, 0};
     UnitLong lg;                 // long runs and their tasks (device arrays)
     bool units_on = false;
+    // index tables: grouped positions in the order of i_s, the groups of one
+    // i_s value and their tasks (task_run = the value); on: this mode uses them
+    int32_t *spos = nullptr;
+    UnitLong ix;
+    bool ix_on = false;
     // host copies used to recompute the work split (autotuner)
     std::vector<int64_t> rp_host;
     std::vector<int32_t> first_blk, last_blk;
@@ -81,6 +86,7 @@ struct ptk_ctx {
     double *dunits = nullptr;    // deltas [nnz][J] of the shared-index units
     double *gph = nullptr;       // pass-major copy of a permuted core (units)
     double *ltab = nullptr;      // tables of the long runs of one mode (units)
+    double *itab = nullptr;      // index tables of one mode [I_s][J^(N-1)]
     // Approx variant: residuals [nnz], slice sums, R per cell, removed count
     double *ap_resid = nullptr, *ap_part = nullptr, *ap_R = nullptr;
     int32_t *ap_removed = nullptr;

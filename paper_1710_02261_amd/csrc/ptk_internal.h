@@ -275,8 +275,8 @@ hipError_t build_mode_csr(const int32_t *idx, const float *val, int64_t nnz,
                           int32_t *rows, int32_t *oidx, float *vals,
                           hipStream_t st, int32_t *perm_out = nullptr, int sub = -1);
 // Unit lists of the shared-index row systems (ptk_sort.hip). A run is a
-// maximal sequence of consecutive grouped entries with the same row and the
-// same index sidx (an other mode's). A run of at least lmin entries (lmin >
+// maximal sequence of consecutive grouped entries with the same row (unless
+// rows is null) and the same index sidx (an other mode's). A run of at least lmin entries (lmin >
 // 0) is long: it is listed in lg (its first position, and tasks of at most
 // tlen consecutive entries, each naming its long run). Every other run is cut
 // into units of emax entries and then at most one unit each of emax/2, ...,
@@ -293,6 +293,13 @@ struct UnitLong {
     int64_t n_long = 0, n_tasks = 0;
     int64_t cap_long = 0, cap_tasks = 0;
 };
+// Stable sort of keys (values below extent) with their positions: keys_out
+// sorted, pos_out[k] = the position of keys_out[k]. work: sort_workspace_bytes.
+hipError_t sort_by_key(const int32_t *keys, int64_t nnz, int64_t extent, void *work,
+                       int32_t *keys_out, int32_t *pos_out, hipStream_t st);
+// For runs of equal keys (build_units with rows null): task_run[t] <- the key
+// value of its run.
+hipError_t launch_task_keys(const int32_t *keys, const UnitLong &lg, hipStream_t st);
 int64_t units_workspace_ints(int64_t nnz);
 hipError_t build_units(const int32_t *rows, const int32_t *sidx, int64_t nnz, int emax,
                        int32_t lmin, int32_t tlen, int32_t *work, int32_t *units,

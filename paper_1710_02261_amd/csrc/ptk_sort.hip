@@ -338,9 +338,10 @@ hipError_t build_mode_csr(const int32_t *idx, const float *val, int64_t nnz,
 // ---------------------------------------------------------------------------
 // unit lists of the shared-index row systems
 // ---------------------------------------------------------------------------
+// rows may be null: runs of equal sidx only.
 __device__ __forceinline__ int32_t run_flag(const int32_t *rows, const int32_t *sidx,
                                             int64_t p) {
-    return p == 0 || rows[p] != rows[p - 1] || sidx[p] != sidx[p - 1];
+    return p == 0 || (rows && rows[p] != rows[p - 1]) || sidx[p] != sidx[p - 1];
 }
 
 __global__ void k_run_flags(const int32_t *__restrict__ rows, const int32_t *__restrict__ sidx,
@@ -430,6 +431,58 @@ __global__ void k_unit_write(const int32_t *__restrict__ start, int32_t R, int c
             }
         }
     }
+}
+
+hipError_t sort_by_key(const int32_t *keys, int64_t nnz, int64_t extent, void *work,
+                       int32_t *keys_out, int32_t *pos_out, hipStream_t st) {
+    if (nnz <= 0) return hipSuccess;
+    const int64_t nt = n_tiles(nnz);
+    const int64_t hist_n = nt * kRsDigits;
+    int32_t *keyA = (int32_t *)work;
+    int32_t *keyB = keyA + nnz + 64;
+    int32_t *valA = keyB + nnz + 64;
+    int32_t *valB = valA + nnz + 64;
+    int32_t *hist = valB + nnz + 64;
+    int32_t *swork = hist + hist_n + 64;
+    const int32_t *kin = keys;
+    const int32_t *vin = nullptr;
+    int32_t *kout = keyA, *vout = valA;
+    int bits = 0;
+    while ((int64_t(1) << bits) < extent) ++bits;
+    const int np = bits <= 8 ? 1 : (bits + 7) / 8;
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < np; ++q) {
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nt), dim3(kRsThreads), 0, st, kin, nnz,
+                           8 * q, hist, nt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = scan_exclusive(hist, hist, hist_n, swork, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nt), dim3(kRsThreads), 0, st, kin,
+                           vin, kout, vout, nnz, 8 * q, hist, nt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        kin = kout;
+        vin = vout;
+        kout = (kout == keyA) ? keyB : keyA;
+        vout = (vout == valA) ? valB : valA;
+    }
+    if ((e = hipMemcpyAsync(keys_out, kin, nnz * 4, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        return e;
+    return hipMemcpyAsync(pos_out, vin, nnz * 4, hipMemcpyDeviceToDevice, st);
+}
+
+// task_run[t] <- keys[run_pos[task_run[t]]]: each task names its key value.
+__global__ void k_task_keys(const int32_t *__restrict__ keys, const int32_t *__restrict__ run_pos,
+                            int32_t *__restrict__ task_run, int64_t n) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        task_run[t] = keys[run_pos[task_run[t]]];
+}
+
+hipError_t launch_task_keys(const int32_t *keys, const UnitLong &lg, hipStream_t st) {
+    if (lg.n_tasks <= 0) return hipSuccess;
+    const unsigned b = (unsigned)std::min<int64_t>((lg.n_tasks + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_task_keys, dim3(b), dim3(256), 0, st, keys, lg.run_pos, lg.task_run,
+                       lg.n_tasks);
+    return hipGetLastError();
 }
 
 int64_t units_workspace_ints(int64_t nnz) {

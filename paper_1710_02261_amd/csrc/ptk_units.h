@@ -45,12 +45,27 @@ struct LongArgs {
     const float *fac[kMaxN];          // factors of the other modes, mode order
     const int32_t *oidx[kMaxN];       // other-mode index arrays, same order
     UnitLong lg;                      // long runs and their tasks
-    double *tab;                      // [n_long][J^(N-2)][J]
+    double *tab;                      // runs: [n_long][J^(N-2)][J]; index
+                                      // tables: [J^(N-2)][n_long][J]
     double *dout;                     // deltas [nnz][J] in grouped order
+    // index tables: table r is that of index value r of mode s (n_long = I_s,
+    // run_pos unused), a task's entries are at grouped positions
+    // perm[task_pos ..], and task_run names the value
+    int32_t index_tables;
+    const int32_t *perm;
 };
 
-// Tables of every long run, then the deltas of every task's entries.
-hipError_t launch_long_runs(const LongArgs &a, int N, int J, hipStream_t st);
+// Tables of every long run (or index value), then the deltas of every task's
+// entries, P entries per lane (tasks of at most P * 64 entries).
+hipError_t launch_long_runs(const LongArgs &a, int N, int J, int P, hipStream_t st);
+
+// Index tables: a table per index value of mode s, T_v = G x_s a^(s)_v,
+// serves every entry of mode n with i_s = v, whatever its row. Entries are
+// taken in the order of i_s, in tasks of at most kIndexTask of one value
+// (two entries per lane).
+constexpr int32_t kIndexTask = 128;
+// Tables of one mode beyond this many bytes: not used.
+constexpr int64_t kIndexTableBytes = int64_t(16) << 30;
 
 // (N, J) with equal ranks and unit kernels (FP64 arithmetic).
 bool units_available(int N, int J);

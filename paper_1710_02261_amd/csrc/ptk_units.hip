@@ -282,8 +282,13 @@ __global__ __launch_bounds__(kWave) void k_run_tables(LongArgs a) {
     for (int p = 0; p < P; ++p) {
         run[p] = r0 + (int64_t)p * kWave;
         valid[p] = run[p] < a.lg.n_long;
-        const int64_t pos = valid[p] ? a.lg.run_pos[run[p]] : 0;
-        const float *r = a.fac[NO - 1] + (int64_t)a.oidx[NO - 1][pos] * J;
+        const float *r;
+        if (a.index_tables) {
+            r = a.fac[NO - 1] + (valid[p] ? run[p] : 0) * J;
+        } else {
+            const int64_t pos = valid[p] ? a.lg.run_pos[run[p]] : 0;
+            r = a.fac[NO - 1] + (int64_t)a.oidx[NO - 1][pos] * J;
+        }
 #pragma unroll
         for (int j = 0; j < J; ++j) as[p][j] = (double)r[j];
     }
@@ -312,7 +317,10 @@ __global__ __launch_bounds__(kWave) void k_run_tables(LongArgs a) {
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             if (!valid[p]) continue;
-            double *dst = a.tab + (run[p] * OUTER + o) * J;
+            // index tables [o][value][j] (coalesced over the lanes' values),
+            // run tables [run][o][j]
+            double *dst = a.index_tables ? a.tab + ((int64_t)o * a.lg.n_long + run[p]) * J
+                                         : a.tab + (run[p] * OUTER + o) * J;
 #pragma unroll
             for (int j = 0; j < J; ++j) dst[j] = t[p][j];
         }
@@ -324,14 +332,13 @@ __global__ __launch_bounds__(kWave) void k_run_tables(LongArgs a) {
 // cache, J values per outer index, each feeding two multiply-adds; the row
 // of the fastest leading mode sits in VGPRs, the slower ones' rows in LDS
 // (read once per J outer indices).
-template <int N, int J>
+template <int N, int J, int P>
 __global__ __launch_bounds__(kWave) void k_delta_long(LongArgs a) {
     constexpr int NO = N - 1;
     constexpr int NOUT = NO - 1;                 // leading other modes
     constexpr int NS = NOUT - 1;                 // slow ones (LDS)
     constexpr int OUTER = ipow(J, NOUT);
     constexpr int OB = OUTER / J;                // outer indices of the slow modes
-    constexpr int P = 2;
     __shared__ float s_a[(NS > 0 ? NS : 1) * J * P * kWave];   // [p][k][j][lane]
     const int lane = threadIdx.x;
     const int64_t task = blockIdx.x;
@@ -345,7 +352,8 @@ __global__ __launch_bounds__(kWave) void k_delta_long(LongArgs a) {
     for (int p = 0; p < P; ++p) {
         const int off = lane + p * kWave;
         valid[p] = off < tlen;
-        pos[p] = tpos + (valid[p] ? off : 0);
+        const int64_t k = tpos + (valid[p] ? off : 0);
+        pos[p] = a.perm ? (int64_t)a.perm[k] : k;
         const float *r = a.fac[NOUT - 1] + (int64_t)a.oidx[NOUT - 1][pos[p]] * J;
 #pragma unroll
         for (int j = 0; j < J; ++j) af[p][j] = (double)r[j];
@@ -362,7 +370,9 @@ __global__ __launch_bounds__(kWave) void k_delta_long(LongArgs a) {
     for (int p = 0; p < P; ++p)
 #pragma unroll
         for (int j = 0; j < J; ++j) c[p][j] = 0.0;
-    cptr<double> tab = (cptr<double>)(a.tab + run * (OUTER * J));
+    // stride of the outer index and offset of this task's table
+    const int64_t os = a.index_tables ? a.lg.n_long * J : J;
+    cptr<double> tab = (cptr<double>)(a.tab + run * (a.index_tables ? J : OUTER * J));
 #pragma unroll 1
     for (int ob = 0; ob < OB; ++ob) {
         double ws[P];
@@ -382,7 +392,7 @@ __global__ __launch_bounds__(kWave) void k_delta_long(LongArgs a) {
                 for (int k = 0; k < NS; ++k)
                     ws[p] *= (double)s_a[((p * NS + k) * J + d[k]) * kWave + lane];
         }
-        cptr<double> tb = tab + (int64_t)ob * (J * J);
+        cptr<double> tb = tab + (int64_t)ob * J * os;
 #pragma unroll(J <= 10 ? J : 4)
         for (int dl = 0; dl < J; ++dl) {
             double w[P];
@@ -390,7 +400,7 @@ __global__ __launch_bounds__(kWave) void k_delta_long(LongArgs a) {
             for (int p = 0; p < P; ++p) w[p] = ws[p] * af[p][dl];
 #pragma unroll
             for (int j = 0; j < J; ++j) {
-                const double tv = tb[dl * J + j];
+                const double tv = tb[dl * os + j];
 #pragma unroll
                 for (int p = 0; p < P; ++p) c[p][j] = __builtin_fma(tv, w[p], c[p][j]);
             }
@@ -556,7 +566,7 @@ hipError_t launch_delta_units(const UnitArgs &a, int N, int J, int c, hipStream_
 }
 
 template <int N, int J>
-hipError_t launch_long_nj(const LongArgs &a, hipStream_t st) {
+hipError_t launch_long_nj(const LongArgs &a, int P, hipStream_t st) {
     if (a.lg.n_long <= 0) return hipSuccess;
     const unsigned rb = (unsigned)((a.lg.n_long + 2 * kWave - 1) / (2 * kWave));
     // enough workgroups to fill the chip: slices of the outer indices
@@ -566,15 +576,19 @@ hipError_t launch_long_nj(const LongArgs &a, hipStream_t st) {
     hipLaunchKernelGGL((k_run_tables<N, J>), dim3(rb, slices), dim3(kWave), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.lg.n_tasks <= 0) return e;
-    hipLaunchKernelGGL((k_delta_long<N, J>), dim3((unsigned)a.lg.n_tasks), dim3(kWave), 0, st,
-                       a);
+    if (P == 1)
+        hipLaunchKernelGGL((k_delta_long<N, J, 1>), dim3((unsigned)a.lg.n_tasks), dim3(kWave),
+                           0, st, a);
+    else
+        hipLaunchKernelGGL((k_delta_long<N, J, 2>), dim3((unsigned)a.lg.n_tasks), dim3(kWave),
+                           0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_long_runs(const LongArgs &a, int N, int J, hipStream_t st) {
-    if (a.lg.n_tasks >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+hipError_t launch_long_runs(const LongArgs &a, int N, int J, int P, hipStream_t st) {
+    if (a.lg.n_tasks >= (int64_t(1) << 31) || (P != 1 && P != 2)) return hipErrorInvalidValue;
 #define PTK_X(n_, j_) \
-    if (N == n_ && J == j_) return launch_long_nj<n_, j_>(a, st);
+    if (N == n_ && J == j_) return launch_long_nj<n_, j_>(a, P, st);
     PTK_UNIT_SHAPES(PTK_X)
 #undef PTK_X
     return hipErrorInvalidValue;

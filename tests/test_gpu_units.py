@@ -14,8 +14,12 @@ that mode's row once per unit (eq. "delta" summed in another order).
 * Iterations in a captured graph with every row in the least-squares form
   (cond_limit = 1), whose kept deltas then come from the stored ones: every
   row of every iteration to 1e-5 against the oracle from the same state.
-* Auto: few repeats keep the fused kernels, many take the units; an empty
-  observed set; option refusals.
+* Index tables (G contracted with every row of A^(s), one per value of i_s):
+  groups and tasks counted exactly, row systems, updates and graph
+  iterations to the same bars.
+* Auto: the work model keeps the fused kernels when nothing repeats and
+  takes the index tables when the values of i_s repeat across rows; an
+  empty observed set; option refusals.
 """
 import numpy as np
 import pytest
@@ -77,8 +81,8 @@ def test_unit_lists_count_runs(dims, J, nnz, cap):
     for n in range(len(dims)):
         counts, on = ctx.unit_stats(n)
         want = expected_units(p, n, emax)
-        assert counts == want, (n, counts, want)
-        assert on
+        assert counts[:6] == want and counts[6:] == [0, 0], (n, counts, want)
+        assert on == 1
         N = len(dims)
         s = N - 1 if n != N - 1 else N - 2
         key = p.idx[n].astype(np.int64) * dims[s] + p.idx[s]
@@ -89,15 +93,17 @@ def test_unit_lists_count_runs(dims, J, nnz, cap):
 
 
 @pytest.mark.parametrize("dims,J,nnz", SHAPES, ids=SIDS)
-def test_row_systems_with_units_match_oracle(dims, J, nnz):
+@pytest.mark.parametrize("form", [1, 16], ids=["units", "index"])
+def test_row_systems_with_units_match_oracle(dims, J, nnz, form):
     p = problem(dims, J, nnz, seed=72)
-    ctx, *_ = context(p, chunk_nnz=128, shared_units=1)
+    ctx, *_ = context(p, chunk_nnz=128, shared_units=form)
     ref, *_ = context(p, chunk_nnz=128, shared_units=-1)
     G = p.core.astype(np.float64)
     A = [a.astype(np.float64) for a in p.factors]
     val = p.val.astype(np.float64)
     for n in range(len(dims)):
-        assert ctx.unit_stats(n)[1] and not ref.unit_stats(n)[1]
+        assert ctx.unit_stats(n)[1] == (2 if form == 16 else 1)
+        assert ref.unit_stats(n)[1] == 0
         B, c = ctx.row_systems(n)
         B, c = f64(B), f64(c)
         Br, cr = ref.row_systems(n)
@@ -116,7 +122,7 @@ def test_row_systems_with_units_match_oracle(dims, J, nnz):
 
 
 @pytest.mark.parametrize("dims,J,nnz", SHAPES, ids=SIDS)
-@pytest.mark.parametrize("cap,chunk", [(1, 0), (2, 64), (4, 192), (8, 64)])
+@pytest.mark.parametrize("cap,chunk", [(1, 0), (2, 64), (4, 192), (8, 64), (16, 0), (16, 64)])
 def test_update_with_units_matches_oracle(dims, J, nnz, cap, chunk):
     p = problem(dims, J, nnz, seed=73)
     ctx, idx, val, core, fac = context(p, chunk_nnz=chunk, shared_units=cap)
@@ -141,12 +147,13 @@ def test_update_with_units_matches_oracle(dims, J, nnz, cap, chunk):
 
 
 @pytest.mark.parametrize("dims,J,nnz", SHAPES, ids=SIDS)
-def test_graph_iterations_least_squares_from_stored_deltas(dims, J, nnz):
+@pytest.mark.parametrize("form", [1, 16], ids=["units", "index"])
+def test_graph_iterations_least_squares_from_stored_deltas(dims, J, nnz, form):
     """cond_limit = 1 sends every row to the least-squares form; from the
     second iteration on its deltas are the ones the stored-delta sweep kept."""
     p = problem(dims, J, nnz, seed=74)
-    ctx, idx, val, core, fac = context(p, shared_units=1)
-    ctx.set_options(cond_limit=1.0, use_graph=1, shared_units=1)
+    ctx, idx, val, core, fac = context(p, shared_units=form)
+    ctx.set_options(cond_limit=1.0, use_graph=1, shared_units=form)
     G = p.core.astype(np.float64)
     v = p.val.astype(np.float64)
     for t in range(3):
@@ -168,17 +175,38 @@ def test_graph_iterations_least_squares_from_stored_deltas(dims, J, nnz):
     ctx.close()
 
 
-def test_auto_keeps_fused_kernels_without_repeats():
-    # 4e4 entries spread over 3000^4 cells: nearly every (row, i_s) pair once
-    p = synth.make_small((3000, 3000, 3000, 3000), (10,) * 4, 40000, seed=75)
+def expected_index(p, n):
+    """Index groups: the values of i_s present and ceil(count / 128) tasks each."""
+    N = len(p.dims)
+    s = N - 1 if n != N - 1 else N - 2
+    _, cnt = np.unique(p.idx[s], return_counts=True)
+    return [int(cnt.size), int(((cnt + 127) // 128).sum())]
+
+
+@pytest.mark.parametrize("dims,J,nnz", SHAPES, ids=SIDS)
+def test_index_groups_count_values(dims, J, nnz):
+    p = problem(dims, J, nnz, seed=71)
+    ctx, *_ = context(p, shared_units=16)
+    for n in range(len(dims)):
+        counts, on = ctx.unit_stats(n)
+        assert on == 2
+        assert counts[6:] == expected_index(p, n), (n, counts)
+    ctx.close()
+
+
+def test_auto_picks_by_the_work_model():
+    # 4e4 entries over 10^6 values per mode: nothing repeats enough
+    p = synth.make_small((1_000_000,) * 4, (10,) * 4, 40000, seed=75)
     ctx, *_ = context(p)
     for n in range(4):
         counts, on = ctx.unit_stats(n)
-        assert not on and counts[0] > 0.9 * p.nnz
+        assert on == 0 and counts[0] > 0.9 * p.nnz
     ctx.close()
-    p = problem((30, 25, 20, 15), 10, 7003, seed=75)
+    # few repeated (row, i_s) pairs, but each i_s value serves 133 entries on
+    # average: the index tables win
+    p = synth.make_small((300, 300, 300, 300), (10,) * 4, 40000, seed=75)
     ctx, *_ = context(p)
-    assert all(ctx.unit_stats(n)[1] for n in range(4))
+    assert all(ctx.unit_stats(n)[1] == 2 for n in range(4))
     ctx.close()
 
 
@@ -187,14 +215,14 @@ def test_empty_observed_set_and_refusals():
     import paper_1710_02261_amd as ptk
     p = problem((30, 25, 20, 15), 10, 100, seed=76)
     ctx = ptk.Context(p.dims, p.ranks)
-    for bad in (3, 5, -2, 16):
+    for bad in (3, 5, -2, 32):
         with pytest.raises(ptk.PtkError):
             ctx.set_options(shared_units=bad)
     ctx.set_options(shared_units=1)
     idx = torch.zeros((4, 0), dtype=torch.int32, device="cuda")
     val = torch.zeros((0,), dtype=torch.float32, device="cuda")
     ctx.set_observed(idx, val)
-    assert ctx.unit_stats(0) == ([0, 0, 0, 0, 0, 0], False)
+    assert ctx.unit_stats(0) == ([0] * 8, 0)
     with pytest.raises(ptk.PtkError):
         ctx.set_options(shared_units=-1)            # after set_observed
     ctx.close()
