@@ -30,7 +30,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "delta_singles_c2_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "delta_index_c2_traffic.json")
 KERNEL_SRC = [os.path.join(ROOT, "paper_1710_02261_amd", "csrc", f)
               for f in ("ptk_units.hip", "ptk_units.h", "ptk_device.h", "ptk_internal.h")]
 
@@ -73,7 +73,7 @@ def traffic_record(launch_nnz):
     return rec.get("bytes_per_launch")
 
 
-HEADLINE_KERNEL = "void ptk::k_delta_singles<4, 10>(ptk::UnitArgs)"
+HEADLINE_KERNEL = "void ptk::k_delta_long<4, 10, 2>(ptk::LongArgs)"
 # a precision form is reported with throughput when its RMSE after the run is
 # at most this much above the FP64 path's (the comparison at equal RMSE)
 USABLE_RMSE = 0.10
@@ -102,7 +102,7 @@ def traffic_summary(fetch_csv, write_csv, launches):
 
     out = {"kernel": HEADLINE_KERNEL,
            "workload": "order-4 100000^4, 1e7 entries Zipf(1.1), J=10, FP64 arithmetic, "
-                       "shared-index units, autotuned work ranges",
+                       "index tables, autotuned work ranges",
            "kernel_sha": kernel_hash()}
     cal = {"kernel": "torch.mul of 64 Mi float32 (reads and writes 256 MiB)"}
     for tag, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"),
@@ -702,7 +702,8 @@ def main():
             fl = 0.0
             for n in ix_modes:
                 s_mode = N - 1 if n != N - 1 else N - 2
-                fl += p.dims[s_mode] * J ** N + p.nnz * (J ** (N - 1) + J ** (N - 2))
+                u = r["units"][n][0]
+                fl += p.dims[s_mode] * J ** N + (p.nnz - u[8]) * (J ** (N - 1) + J ** (N - 2))
             unit_kernel = {"class": "index", "avg_ms": ms / calls,
                            "flops": 2.0 * fl / len(ix_modes)}
         elif c == 4:
@@ -717,8 +718,11 @@ def main():
         else:
             e = 1 << c
             per_unit = J ** (N - 2) * (J * J + e * (J + N - 3))
+            # single-entry units also serve the small values of index modes
+            counted = [u[c] for u in on_modes] + ([r["units"][n][0][8] for n in ix_modes]
+                                                 if c == 0 else [])
             unit_kernel = {"class": e, "avg_ms": ms / calls,
-                           "flops": 2.0 * per_unit * sum(u[c] for u in on_modes) / len(on_modes)}
+                           "flops": 2.0 * per_unit * sum(counted) / max(1, len(counted))}
         avg_s = unit_kernel["avg_ms"] / 1e3
     if main_prec.startswith("bf16"):
         # matrix-core work per entry and mode: stage 1 J^N (+2x for the split
@@ -748,12 +752,12 @@ def main():
         traffic = None
     if unit_kernel:
         e = unit_kernel["class"]
-        kname = ("k_run_tables<%d,%d> + k_delta_long<%d,%d,1> (index tables)" % (N, J, N, J)
+        kname = ("k_run_tables<%d,%d> + k_delta_long<%d,%d,2> (index tables)" % (N, J, N, J)
                  if e == "index"
                  else "k_run_tables<%d,%d> + k_delta_long<%d,%d,2>" % (N, J, N, J) if e == "long"
                  else "k_delta_singles<%d,%d>" % (N, J) if e == 1
                  else "k_delta_units<%d,%d,%d,...>" % (N, J, e))
-        if e != 1:                 # the committed counters are of k_delta_singles
+        if e != "index":           # the committed counters are of k_delta_long<4,10,2>
             traffic = None
     roofline = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak, "traffic": traffic, "kernel": kname,
@@ -795,7 +799,7 @@ def main():
                                         for a, b in zip(r["loss"], r["loss"][1:]))),
         "kernel_ms": {k: v[1] / max(v[0], 1) for k, v in r["times"].items()},
         "shared_units": {"option": args.shared_units,
-                         "per_mode": [{"units_1_2_4_8_long_tasks_values_tasks": u,
+                         "per_mode": [{"units_1_2_4_8_long_tasks_values_tasks_smallunits": u,
                                        "form": ["fused", "units", "index tables"][on]}
                                       for u, on in r["units"]]},
     }

@@ -316,9 +316,11 @@ ptk_status ptk_approx_stats(ptk_ctx *ctx, int64_t *nonzero_cells_host,
  * then one unit for each set bit of r mod emax (emax is 2, or the option's
  * 4 or 8 where a kernel exists: 8 at orders 3 and 4 with J <= 10, else 4).
  * The index groups are the entries of one value of i_s whatever their row,
- * in tasks of at most 128. counts_host receives 8 values: the units of 1, 2,
- * 4 and 8 entries, the long runs, their tasks, the index values present and
- * their tasks (zero where that form was not built). *on_host: the form mode
+ * in tasks of at most 128; the entries of a value with fewer than 64 are
+ * single-entry units instead. counts_host receives 9 values: the units of 1, 2,
+ * 4 and 8 entries, the long runs, their tasks, the index values present,
+ * their tasks and the single-entry units of the small values (zero where a
+ * form was not built). *on_host: the form mode
  * n's row systems use: 0 the fused kernels, 1 units, 2 index tables.
  * PTK_E_INVALID for n out of range, PTK_E_STATE before ptk_set_observed.
  */

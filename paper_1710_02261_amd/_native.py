@@ -282,9 +282,10 @@ class Context:
 
     def unit_stats(self, n):
         """([units of 1, 2, 4, 8 entries, long runs, their tasks, index
-        values, their tasks], path of mode n's row systems: 0 fused kernels,
-        1 units, 2 index tables) as built by set_observed."""
-        cnt = (_i64 * 8)()
+        values, their tasks, single-entry units of small values], path of
+        mode n's row systems: 0 fused kernels, 1 units, 2 index tables) as
+        built by set_observed."""
+        cnt = (_i64 * 9)()
         on = _i32()
         self._check(self._lib.ptk_unit_stats(self._h, int(n), cnt, C.byref(on)))
         return [int(x) for x in cnt], int(on.value)

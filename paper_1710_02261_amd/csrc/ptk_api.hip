@@ -141,6 +141,9 @@ void free_modes(ptk_ctx *c) {
         dfree(m.ix.task_pos);
         dfree(m.ix.task_len);
         dfree(m.ix.task_run);
+        dfree(m.ix.ntask_pos);
+        dfree(m.ix.ntask_len);
+        dfree(m.ix.ntask_run);
         m = ModeData();
     }
     dfree(c->bbuf);
@@ -427,9 +430,19 @@ ptk_status systems(ptk_ctx *c, int n, int role = 0) {
             la.dout = c->dunits;
             la.index_tables = 1;
             la.perm = m.spos;
+            la.lg.n_ntasks = 0;
             HIPCHK(c, timed(c, "delta_index", [&] {
                 return launch_long_runs(la, c->s.N, c->s.ranks[n], kIndexTask / kWave, c->st);
             }));
+            if (m.ix.n_ntasks > 0) {
+                // the entries of values with fewer than kIndexTask / 2 entries
+                UnitArgs ub = ua;
+                ub.units = m.ix.ntask_pos;
+                ub.count = m.ix.n_ntasks;
+                HIPCHK(c, timed(c, "delta_units1", [&] {
+                    return launch_delta_units(ub, c->s.N, c->s.ranks[n], 0, c->st);
+                }));
+            }
         } else if (m.lg.n_long > 0) {
             LongArgs la{};
             la.gp = a.gp;
@@ -727,11 +740,11 @@ ptk_status build_unit_lists(ptk_ctx *c) {
         if (e == hipSuccess) e = dalloc(&lg.task_run, (size_t)lg.cap_tasks);
         const int32_t *sidx = m.oidx + (int64_t)(s.N - 2) * nnz;
         if (e == hipSuccess)
-            e = build_units(m.rows, sidx, nnz, emax, kLongRun, kLongTask, work, m.units,
+            e = build_units(m.rows, sidx, nnz, emax, kLongRun, kLongTask, 0, work, m.units,
                             m.ucount, &lg, c->st);
         // tables beyond their budget: units only
         if (e == hipSuccess && lg.n_long * inner * 8 > kLongTableBytes)
-            e = build_units(m.rows, sidx, nnz, emax, 0, kLongTask, work, m.units, m.ucount,
+            e = build_units(m.rows, sidx, nnz, emax, 0, kLongTask, 0, work, m.units, m.ucount,
                             &lg, c->st);
         if (e != hipSuccess) {
             dfree(work);
@@ -759,6 +772,7 @@ ptk_status build_unit_lists(ptk_ctx *c) {
             UnitLong &ix = m.ix;
             ix.cap_long = std::min<int64_t>(nnz, Is) + 1;
             ix.cap_tasks = nnz / kIndexTask + ix.cap_long + 1;
+            ix.cap_ntasks = nnz;                  // the entries of the small values
             int32_t *skeys = nullptr;
             void *swork = nullptr;
             e = dalloc(&m.spos, nnz + 64);
@@ -768,12 +782,19 @@ ptk_status build_unit_lists(ptk_ctx *c) {
             if (e == hipSuccess) e = dalloc(&ix.task_pos, (size_t)ix.cap_tasks);
             if (e == hipSuccess) e = dalloc(&ix.task_len, (size_t)ix.cap_tasks);
             if (e == hipSuccess) e = dalloc(&ix.task_run, (size_t)ix.cap_tasks);
+            if (e == hipSuccess) e = dalloc(&ix.ntask_pos, (size_t)ix.cap_ntasks);
+            if (e == hipSuccess) e = dalloc(&ix.ntask_len, (size_t)ix.cap_ntasks);
+            if (e == hipSuccess) e = dalloc(&ix.ntask_run, (size_t)ix.cap_ntasks);
             if (e == hipSuccess) e = sort_by_key(sidx, nnz, Is, swork, skeys, m.spos, c->st);
             int64_t none[4];
             if (e == hipSuccess)
-                e = build_units(nullptr, skeys, nnz, 1, 1, kIndexTask, work, m.units, none,
+                e = build_units(nullptr, skeys, nnz, 1, 1, kIndexTask, kIndexTask / 2, work,
+                                m.units, none,
                                 &ix, c->st);
             if (e == hipSuccess) e = launch_task_keys(skeys, ix, c->st);
+            // entries of values with few entries: grouped positions, for the
+            // single-entry unit kernel
+            if (e == hipSuccess) e = launch_permute_list(m.spos, ix.ntask_pos, ix.n_ntasks, c->st);
             if (e == hipSuccess) e = hipStreamSynchronize(c->st);
             dfree(skeys);
             if (swork) (void)hipFree(swork);
@@ -784,7 +805,8 @@ ptk_status build_unit_lists(ptk_ctx *c) {
                             "index groups of mode %d: %s", n, hipGetErrorString(e));
             }
             f_index = (double)Is * (double)inner * J +
-                      (double)ix.n_tasks * kIndexTask * (double)(inner + inner / J) +
+                      (double)(ix.n_tasks * kIndexTask) * (double)(inner + inner / J) +
+                      (double)ix.n_ntasks * unit_fma(s.N, J, 1) +
                       (double)nnz * stored_delta_fma(J);
         }
         m.ix_on = ix_fits && (su == 16 || (su == 0 && f_index <= 0.9 * f_plain &&
@@ -2180,6 +2202,7 @@ extern "C" ptk_status ptk_unit_stats(ptk_ctx *c, int32_t n, int64_t *counts, int
     counts[5] = m.lg.n_tasks;
     counts[6] = m.ix.n_long;
     counts[7] = m.ix.n_tasks;
+    counts[8] = m.ix.n_ntasks;
     *on = index_live(c, n) ? 2 : units_live(c, n) ? 1 : 0;
     return PTK_OK;
 }

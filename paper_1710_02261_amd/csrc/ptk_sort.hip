@@ -368,62 +368,70 @@ __global__ void k_run_starts(const int32_t *__restrict__ rows, const int32_t *__
 
 // Counters of a run of len entries: q = 0..3, units of 2^q entries (none
 // above cmax); q = 4, one long run; q = 5, its tasks of at most tlen
-// entries. A run of at least lmin entries (lmin > 0) is long and has no units.
+// entries, or q = 6, one per entry when it has fewer than wmin entries.
+// A run of at least lmin entries (lmin > 0) is long and has no units.
 __device__ __forceinline__ int32_t run_count(int32_t len, int q, int cmax, int32_t lmin,
-                                             int32_t tlen) {
+                                             int32_t tlen, int32_t wmin) {
     const bool lng = lmin > 0 && len >= lmin;
+    const bool narrow = len < wmin;
     if (q == 4) return lng ? 1 : 0;
-    if (q == 5) return lng ? (len + tlen - 1) / tlen : 0;
+    if (q == 5) return (lng && !narrow) ? (len + tlen - 1) / tlen : 0;
+    if (q == 6) return (lng && narrow) ? len : 0;
     if (lng || q > cmax) return 0;
     return q == cmax ? (len >> cmax) : ((len >> q) & 1);
 }
 
-constexpr int kRunCounters = 6;
+constexpr int kRunCounters = 7;
 
 __global__ void k_unit_counts(const int32_t *__restrict__ start, int32_t R, int cmax,
-                              int32_t lmin, int32_t tlen, int32_t *__restrict__ cnt) {
+                              int32_t lmin, int32_t tlen, int32_t wmin,
+                              int32_t *__restrict__ cnt) {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
          r += (int64_t)gridDim.x * blockDim.x) {
         const int32_t len = start[r + 1] - start[r];
         for (int q = 0; q < kRunCounters; ++q)
-            cnt[(int64_t)q * R + r] = run_count(len, q, cmax, lmin, tlen);
+            cnt[(int64_t)q * R + r] = run_count(len, q, cmax, lmin, tlen, wmin);
     }
 }
 
 // total[q] = off[q][R-1] + the last run's counter q
 __global__ void k_unit_totals(const int32_t *__restrict__ start, int32_t R, int cmax,
-                              int32_t lmin, int32_t tlen, const int32_t *__restrict__ off,
-                              int64_t *__restrict__ total) {
+                              int32_t lmin, int32_t tlen, int32_t wmin,
+                              const int32_t *__restrict__ off, int64_t *__restrict__ total) {
     const int q = threadIdx.x;
     if (q >= kRunCounters) return;
     const int32_t len = start[R] - start[R - 1];
-    total[q] = (int64_t)off[(int64_t)q * R + R - 1] + run_count(len, q, cmax, lmin, tlen);
+    total[q] =
+        (int64_t)off[(int64_t)q * R + R - 1] + run_count(len, q, cmax, lmin, tlen, wmin);
 }
 
 __global__ void k_unit_write(const int32_t *__restrict__ start, int32_t R, int cmax,
-                             int32_t lmin, int32_t tlen, const int32_t *__restrict__ off,
-                             const int64_t *__restrict__ base, int32_t *__restrict__ units,
-                             UnitLong lg) {
+                             int32_t lmin, int32_t tlen, int32_t wmin,
+                             const int32_t *__restrict__ off, const int64_t *__restrict__ base,
+                             int32_t *__restrict__ units, UnitLong lg) {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
          r += (int64_t)gridDim.x * blockDim.x) {
         int32_t p = start[r];
         const int32_t len = start[r + 1] - p;
-        if (run_count(len, 4, cmax, lmin, tlen)) {
+        if (run_count(len, 4, cmax, lmin, tlen, wmin)) {
             const int32_t li = off[4 * (int64_t)R + r];
             lg.run_pos[li] = p;
-            const int32_t nt = run_count(len, 5, cmax, lmin, tlen);
-            int32_t *tp = lg.task_pos + off[5 * (int64_t)R + r];
-            int32_t *tl = lg.task_len + off[5 * (int64_t)R + r];
-            int32_t *tr = lg.task_run + off[5 * (int64_t)R + r];
+            const bool narrow = len < wmin;
+            const int32_t w = narrow ? 1 : tlen;
+            const int32_t nt = run_count(len, narrow ? 6 : 5, cmax, lmin, tlen, wmin);
+            const int64_t o = off[(narrow ? 6 : 5) * (int64_t)R + r];
+            int32_t *tp = (narrow ? lg.ntask_pos : lg.task_pos) + o;
+            int32_t *tl = (narrow ? lg.ntask_len : lg.task_len) + o;
+            int32_t *tr = (narrow ? lg.ntask_run : lg.task_run) + o;
             for (int32_t q = 0; q < nt; ++q) {
-                tp[q] = p + q * tlen;
-                tl[q] = min(tlen, len - q * tlen);
+                tp[q] = p + q * w;
+                tl[q] = min(w, len - q * w);
                 tr[q] = li;
             }
             continue;
         }
         for (int c = cmax; c >= 0; --c) {
-            const int32_t k = run_count(len, c, cmax, lmin, tlen);
+            const int32_t k = run_count(len, c, cmax, lmin, tlen, wmin);
             int32_t *dst = units + base[c] + off[(int64_t)c * R + r];
             for (int32_t q = 0; q < k; ++q) {
                 dst[q] = p;
@@ -478,10 +486,28 @@ __global__ void k_task_keys(const int32_t *__restrict__ keys, const int32_t *__r
 }
 
 hipError_t launch_task_keys(const int32_t *keys, const UnitLong &lg, hipStream_t st) {
-    if (lg.n_tasks <= 0) return hipSuccess;
-    const unsigned b = (unsigned)std::min<int64_t>((lg.n_tasks + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_task_keys, dim3(b), dim3(256), 0, st, keys, lg.run_pos, lg.task_run,
-                       lg.n_tasks);
+    if (lg.n_tasks > 0) {
+        const unsigned b = (unsigned)std::min<int64_t>((lg.n_tasks + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_task_keys, dim3(b), dim3(256), 0, st, keys, lg.run_pos,
+                           lg.task_run, lg.n_tasks);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// list[i] <- perm[list[i]]
+__global__ void k_permute_list(const int32_t *__restrict__ perm, int32_t *__restrict__ list,
+                               int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        list[i] = perm[list[i]];
+}
+
+hipError_t launch_permute_list(const int32_t *perm, int32_t *list, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const unsigned b = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_permute_list, dim3(b), dim3(256), 0, st, perm, list, n);
     return hipGetLastError();
 }
 
@@ -492,13 +518,14 @@ int64_t units_workspace_ints(int64_t nnz) {
 }
 
 hipError_t build_units(const int32_t *rows, const int32_t *sidx, int64_t nnz, int emax,
-                       int32_t lmin, int32_t tlen, int32_t *work, int32_t *units,
+                       int32_t lmin, int32_t tlen, int32_t wmin, int32_t *work, int32_t *units,
                        int64_t *count, UnitLong *lg, hipStream_t st) {
     int cmax = 0;
     while ((1 << cmax) < emax) ++cmax;
     if (cmax > 3 || (1 << cmax) != emax || tlen <= 0) return hipErrorInvalidValue;
     for (int c = 0; c <= 3; ++c) count[c] = 0;
-    lg->n_long = lg->n_tasks = 0;
+    lg->n_long = lg->n_tasks = lg->n_ntasks = 0;
+    if (wmin > 0 && (tlen < 2 || !lg->ntask_pos)) return hipErrorInvalidValue;
     if (nnz == 0) return hipSuccess;
     int32_t *rid = work;
     int32_t *start = rid + nnz + 64;
@@ -521,14 +548,14 @@ hipError_t build_units(const int32_t *rows, const int32_t *sidx, int64_t nnz, in
     if (R <= 0 || R > nnz) return hipErrorInvalidValue;
     const unsigned rb = (unsigned)std::min<int64_t>((R + 255) / 256, 65536);
     hipLaunchKernelGGL(k_unit_counts, dim3(rb), dim3(256), 0, st, start, R, cmax, lmin, tlen,
-                       cnt);
+                       wmin, cnt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int q = 0; q < kRunCounters; ++q)
         if ((e = scan_exclusive(cnt + (int64_t)q * R, cnt + (int64_t)q * R, R, swork, st)) !=
             hipSuccess)
             return e;
     hipLaunchKernelGGL(k_unit_totals, dim3(1), dim3(64), 0, st, start, R, cmax, lmin, tlen,
-                       cnt, total);
+                       wmin, cnt, total);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     int64_t ht[kRunCounters] = {};
     if ((e = hipMemcpyAsync(ht, total, 8 * kRunCounters, hipMemcpyDeviceToHost, st)) !=
@@ -542,13 +569,15 @@ hipError_t build_units(const int32_t *rows, const int32_t *sidx, int64_t nnz, in
         at += ht[c];
         count[c] = ht[c];
     }
-    if (at > nnz || ht[4] > lg->cap_long || ht[5] > lg->cap_tasks) return hipErrorInvalidValue;
+    if (at > nnz || ht[4] > lg->cap_long || ht[5] > lg->cap_tasks || ht[6] > lg->cap_ntasks)
+        return hipErrorInvalidValue;
     lg->n_long = ht[4];
     lg->n_tasks = ht[5];
+    lg->n_ntasks = ht[6];
     if ((e = hipMemcpyAsync(base, hb, 8 * 4, hipMemcpyHostToDevice, st)) != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_unit_write, dim3(rb), dim3(256), 0, st, start, R, cmax, lmin, tlen,
-                       cnt, base, units, *lg);
+                       wmin, cnt, base, units, *lg);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return hipStreamSynchronize(st);   // hb lives on this stack frame
 }

@@ -575,18 +575,20 @@ hipError_t launch_long_nj(const LongArgs &a, int P, hipStream_t st) {
         1, std::min<int64_t>(OUTER, (8192 + rb - 1) / rb));
     hipLaunchKernelGGL((k_run_tables<N, J>), dim3(rb, slices), dim3(kWave), 0, st, a);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || a.lg.n_tasks <= 0) return e;
-    if (P == 1)
+    if (e != hipSuccess) return e;
+    if (a.lg.n_tasks > 0 && P == 1)
         hipLaunchKernelGGL((k_delta_long<N, J, 1>), dim3((unsigned)a.lg.n_tasks), dim3(kWave),
                            0, st, a);
-    else
+    else if (a.lg.n_tasks > 0)
         hipLaunchKernelGGL((k_delta_long<N, J, 2>), dim3((unsigned)a.lg.n_tasks), dim3(kWave),
                            0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_long_runs(const LongArgs &a, int N, int J, int P, hipStream_t st) {
-    if (a.lg.n_tasks >= (int64_t(1) << 31) || (P != 1 && P != 2)) return hipErrorInvalidValue;
+    if (a.lg.n_tasks >= (int64_t(1) << 31) || a.lg.n_ntasks >= (int64_t(1) << 31) ||
+        (P != 1 && P != 2))
+        return hipErrorInvalidValue;
 #define PTK_X(n_, j_) \
     if (N == n_ && J == j_) return launch_long_nj<n_, j_>(a, P, st);
     PTK_UNIT_SHAPES(PTK_X)

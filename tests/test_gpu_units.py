@@ -81,7 +81,7 @@ def test_unit_lists_count_runs(dims, J, nnz, cap):
     for n in range(len(dims)):
         counts, on = ctx.unit_stats(n)
         want = expected_units(p, n, emax)
-        assert counts[:6] == want and counts[6:] == [0, 0], (n, counts, want)
+        assert counts[:6] == want and counts[6:] == [0, 0, 0], (n, counts, want)
         assert on == 1
         N = len(dims)
         s = N - 1 if n != N - 1 else N - 2
@@ -176,11 +176,14 @@ def test_graph_iterations_least_squares_from_stored_deltas(dims, J, nnz, form):
 
 
 def expected_index(p, n):
-    """Index groups: the values of i_s present and ceil(count / 128) tasks each."""
+    """Index groups: the values of i_s present; a value with 64 entries or
+    more has ceil(count / 128) tasks, a smaller one a single-entry unit per
+    entry."""
     N = len(p.dims)
     s = N - 1 if n != N - 1 else N - 2
     _, cnt = np.unique(p.idx[s], return_counts=True)
-    return [int(cnt.size), int(((cnt + 127) // 128).sum())]
+    wide = cnt >= 64
+    return [int(cnt.size), int(((cnt[wide] + 127) // 128).sum()), int(cnt[~wide].sum())]
 
 
 @pytest.mark.parametrize("dims,J,nnz", SHAPES, ids=SIDS)
@@ -222,7 +225,7 @@ def test_empty_observed_set_and_refusals():
     idx = torch.zeros((4, 0), dtype=torch.int32, device="cuda")
     val = torch.zeros((0,), dtype=torch.float32, device="cuda")
     ctx.set_observed(idx, val)
-    assert ctx.unit_stats(0) == ([0] * 8, 0)
+    assert ctx.unit_stats(0) == ([0] * 9, 0)
     with pytest.raises(ptk.PtkError):
         ctx.set_options(shared_units=-1)            # after set_observed
     ctx.close()
