@@ -697,13 +697,13 @@ def main():
                 best = (c, calls, ms)
         c, calls, ms = best
         if c == 5:
-            # index tables: I_s J^N multiply-adds for the tables of a mode,
-            # then J^(N-1) + J^(N-2) per entry
+            # index tables (a kernel of their own, "index_tables"): the tasks
+            # apply J^(N-1) + J^(N-2) multiply-adds per entry of the values
+            # with 64 entries or more
             fl = 0.0
             for n in ix_modes:
-                s_mode = N - 1 if n != N - 1 else N - 2
                 u = r["units"][n][0]
-                fl += p.dims[s_mode] * J ** N + (p.nnz - u[8]) * (J ** (N - 1) + J ** (N - 2))
+                fl += (p.nnz - u[8]) * (J ** (N - 1) + J ** (N - 2))
             unit_kernel = {"class": "index", "avg_ms": ms / calls,
                            "flops": 2.0 * fl / len(ix_modes)}
         elif c == 4:
@@ -752,7 +752,7 @@ def main():
         traffic = None
     if unit_kernel:
         e = unit_kernel["class"]
-        kname = ("k_run_tables<%d,%d> + k_delta_long<%d,%d,2> (index tables)" % (N, J, N, J)
+        kname = ("k_delta_long<%d,%d,2> (index tables)" % (N, J)
                  if e == "index"
                  else "k_run_tables<%d,%d> + k_delta_long<%d,%d,2>" % (N, J, N, J) if e == "long"
                  else "k_delta_singles<%d,%d>" % (N, J) if e == 1

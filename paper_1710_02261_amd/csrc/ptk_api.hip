@@ -431,8 +431,11 @@ ptk_status systems(ptk_ctx *c, int n, int role = 0) {
             la.index_tables = 1;
             la.perm = m.spos;
             la.lg.n_ntasks = 0;
+            HIPCHK(c, timed(c, "index_tables", [&] {
+                return launch_run_tables(la, c->s.N, c->s.ranks[n], c->st);
+            }));
             HIPCHK(c, timed(c, "delta_index", [&] {
-                return launch_long_runs(la, c->s.N, c->s.ranks[n], kIndexTask / kWave, c->st);
+                return launch_long_tasks(la, c->s.N, c->s.ranks[n], kIndexTask / kWave, c->st);
             }));
             if (m.ix.n_ntasks > 0) {
                 // the entries of values with fewer than kIndexTask / 2 entries

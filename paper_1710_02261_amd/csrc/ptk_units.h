@@ -56,8 +56,11 @@ struct LongArgs {
 };
 
 // Tables of every long run (or index value), then the deltas of every task's
-// entries, P entries per lane (tasks of at most P * 64 entries).
+// entries, P entries per lane (tasks of at most P * 64 entries); the two
+// steps are also available apart.
 hipError_t launch_long_runs(const LongArgs &a, int N, int J, int P, hipStream_t st);
+hipError_t launch_run_tables(const LongArgs &a, int N, int J, hipStream_t st);
+hipError_t launch_long_tasks(const LongArgs &a, int N, int J, int P, hipStream_t st);
 
 // Index tables: a table per index value of mode s, T_v = G x_s a^(s)_v,
 // serves every entry of mode n with i_s = v, whatever its row. Entries are

@@ -566,7 +566,7 @@ hipError_t launch_delta_units(const UnitArgs &a, int N, int J, int c, hipStream_
 }
 
 template <int N, int J>
-hipError_t launch_long_nj(const LongArgs &a, int P, hipStream_t st) {
+hipError_t launch_tables_nj(const LongArgs &a, hipStream_t st) {
     if (a.lg.n_long <= 0) return hipSuccess;
     const unsigned rb = (unsigned)((a.lg.n_long + 2 * kWave - 1) / (2 * kWave));
     // enough workgroups to fill the chip: slices of the outer indices
@@ -574,8 +574,12 @@ hipError_t launch_long_nj(const LongArgs &a, int P, hipStream_t st) {
     const unsigned slices = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>(OUTER, (8192 + rb - 1) / rb));
     hipLaunchKernelGGL((k_run_tables<N, J>), dim3(rb, slices), dim3(kWave), 0, st, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+template <int N, int J>
+hipError_t launch_tasks_nj(const LongArgs &a, int P, hipStream_t st) {
+    if (a.lg.n_long <= 0) return hipSuccess;
     if (a.lg.n_tasks > 0 && P == 1)
         hipLaunchKernelGGL((k_delta_long<N, J, 1>), dim3((unsigned)a.lg.n_tasks), dim3(kWave),
                            0, st, a);
@@ -585,15 +589,27 @@ hipError_t launch_long_nj(const LongArgs &a, int P, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_long_runs(const LongArgs &a, int N, int J, int P, hipStream_t st) {
-    if (a.lg.n_tasks >= (int64_t(1) << 31) || a.lg.n_ntasks >= (int64_t(1) << 31) ||
-        (P != 1 && P != 2))
-        return hipErrorInvalidValue;
+hipError_t launch_run_tables(const LongArgs &a, int N, int J, hipStream_t st) {
 #define PTK_X(n_, j_) \
-    if (N == n_ && J == j_) return launch_long_nj<n_, j_>(a, P, st);
+    if (N == n_ && J == j_) return launch_tables_nj<n_, j_>(a, st);
     PTK_UNIT_SHAPES(PTK_X)
 #undef PTK_X
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_long_tasks(const LongArgs &a, int N, int J, int P, hipStream_t st) {
+    if (a.lg.n_tasks >= (int64_t(1) << 31) || (P != 1 && P != 2)) return hipErrorInvalidValue;
+#define PTK_X(n_, j_) \
+    if (N == n_ && J == j_) return launch_tasks_nj<n_, j_>(a, P, st);
+    PTK_UNIT_SHAPES(PTK_X)
+#undef PTK_X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_long_runs(const LongArgs &a, int N, int J, int P, hipStream_t st) {
+    hipError_t e = launch_run_tables(a, N, J, st);
+    if (e != hipSuccess) return e;
+    return launch_long_tasks(a, N, J, P, st);
 }
 
 int gram_stored_blocks_per_cu(int J) {
