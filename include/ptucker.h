@@ -185,12 +185,14 @@ typedef struct ptk_options {
                                one row and one i_s get a table of the core
                                contracted with that row (J^(N-1) doubles
                                each, at most 4 GiB per mode) instead. 16 =
-                               index tables: G contracted with every row of
-                               A^(s) (I_s * J^(N-1) doubles, at most 16 GiB
-                               per mode, rebuilt at every mode update) serves
-                               every entry with that i_s whatever its row;
-                               auto takes them when the model prefers them.
-                               Chosen
+                               index tables: G contracted with a row of
+                               A^(s) (J^(N-1) doubles) serves every entry
+                               with that i_s whatever its row; one table per
+                               value of i_s with 64 entries or more (at most
+                               16 GiB per mode, rebuilt at every mode
+                               update), single-entry units for the entries
+                               of the other values; auto takes them when the
+                               model prefers them. Chosen
                                before ptk_set_observed; not used with
                                pair_cache, approx_rate > 0 or the FP32 and
                                BF16 forms. Other values: PTK_E_INVALID.      */
@@ -315,13 +317,14 @@ ptk_status ptk_approx_stats(ptk_ctx *ctx, int64_t *nonzero_cells_host,
  * any other run of r entries gives floor(r / emax) units of emax entries,
  * then one unit for each set bit of r mod emax (emax is 2, or the option's
  * 4 or 8 where a kernel exists: 8 at orders 3 and 4 with J <= 10, else 4).
- * The index groups are the entries of one value of i_s whatever their row,
- * in tasks of at most 128; the entries of a value with fewer than 64 are
- * single-entry units instead. counts_host receives 9 values: the units of 1, 2,
- * 4 and 8 entries, the long runs, their tasks, the index values present,
- * their tasks and the single-entry units of the small values (zero where a
- * form was not built). *on_host: the form mode
- * n's row systems use: 0 the fused kernels, 1 units, 2 index tables.
+ * The index groups are the entries of one value of i_s whatever their row:
+ * a value with 64 entries or more gets a table and its entries are processed
+ * in tasks of at most 128; the entries of a value with fewer are single-entry
+ * units instead. counts_host receives 9 values: the units of 1, 2, 4 and 8
+ * entries, the long runs, their tasks, the index values with a table, their
+ * tasks and the single-entry units of the other values (zero where a form
+ * was not built). *on_host: the form mode n's row systems use: 0 the fused
+ * kernels, 1 units, 2 index tables.
  * PTK_E_INVALID for n out of range, PTK_E_STATE before ptk_set_observed.
  */
 ptk_status ptk_unit_stats(ptk_ctx *ctx, int32_t n, int64_t *counts_host, int32_t *on_host);

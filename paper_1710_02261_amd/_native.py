@@ -282,7 +282,8 @@ class Context:
 
     def unit_stats(self, n):
         """([units of 1, 2, 4, 8 entries, long runs, their tasks, index
-        values, their tasks, single-entry units of small values], path of
+        values with a table, their tasks, single-entry units of the other
+        values], path of
         mode n's row systems: 0 fused kernels, 1 units, 2 index tables) as
         built by set_observed."""
         cnt = (_i64 * 9)()

@@ -142,8 +142,6 @@ void free_modes(ptk_ctx *c) {
         dfree(m.ix.task_len);
         dfree(m.ix.task_run);
         dfree(m.ix.ntask_pos);
-        dfree(m.ix.ntask_len);
-        dfree(m.ix.ntask_run);
         m = ModeData();
     }
     dfree(c->bbuf);
@@ -424,8 +422,7 @@ ptk_status systems(ptk_ctx *c, int n, int role = 0) {
                 la.fac[t] = a.fac[t];
                 la.oidx[t] = a.oidx[t];
             }
-            la.lg = m.ix;
-            la.lg.n_long = c->s.dims[units_sub(c, n)];   // a table per index value
+            la.lg = m.ix;                  // a table per value with tasks
             la.tab = c->itab;
             la.dout = c->dunits;
             la.index_tables = 1;
@@ -769,7 +766,9 @@ ptk_status build_unit_lists(ptk_ctx *c) {
         // index tables: entries in the order of i_s, groups of one value
         const int sub = units_sub(c, n);
         const int64_t Is = s.dims[sub];
-        const bool ix_fits = Is * inner * 8 <= kIndexTableBytes;
+        // tables only for the values with kIndexTask / 2 entries or more
+        const int64_t wide_max = std::min<int64_t>(Is, nnz / (kIndexTask / 2));
+        const bool ix_fits = wide_max * inner * 8 <= kIndexTableBytes;
         double f_index = 1e300;
         if (ix_fits && su != 1 && !(su >= 2 && su <= 8)) {
             UnitLong &ix = m.ix;
@@ -786,15 +785,14 @@ ptk_status build_unit_lists(ptk_ctx *c) {
             if (e == hipSuccess) e = dalloc(&ix.task_len, (size_t)ix.cap_tasks);
             if (e == hipSuccess) e = dalloc(&ix.task_run, (size_t)ix.cap_tasks);
             if (e == hipSuccess) e = dalloc(&ix.ntask_pos, (size_t)ix.cap_ntasks);
-            if (e == hipSuccess) e = dalloc(&ix.ntask_len, (size_t)ix.cap_ntasks);
-            if (e == hipSuccess) e = dalloc(&ix.ntask_run, (size_t)ix.cap_ntasks);
             if (e == hipSuccess) e = sort_by_key(sidx, nnz, Is, swork, skeys, m.spos, c->st);
             int64_t none[4];
             if (e == hipSuccess)
                 e = build_units(nullptr, skeys, nnz, 1, 1, kIndexTask, kIndexTask / 2, work,
                                 m.units, none,
                                 &ix, c->st);
-            if (e == hipSuccess) e = launch_task_keys(skeys, ix, c->st);
+            // tables for the values with tasks only: run r names its value
+            if (e == hipSuccess) e = launch_run_keys(skeys, ix, c->st);
             // entries of values with few entries: grouped positions, for the
             // single-entry unit kernel
             if (e == hipSuccess) e = launch_permute_list(m.spos, ix.ntask_pos, ix.n_ntasks, c->st);
@@ -807,7 +805,7 @@ ptk_status build_unit_lists(ptk_ctx *c) {
                 return fail(c, e == hipErrorOutOfMemory ? PTK_E_NOMEM : PTK_E_HIP,
                             "index groups of mode %d: %s", n, hipGetErrorString(e));
             }
-            f_index = (double)Is * (double)inner * J +
+            f_index = (double)ix.n_long * (double)inner * J +
                       (double)(ix.n_tasks * kIndexTask) * (double)(inner + inner / J) +
                       (double)ix.n_ntasks * unit_fma(s.N, J, 1) +
                       (double)nnz * stored_delta_fma(J);
@@ -817,7 +815,7 @@ ptk_status build_unit_lists(ptk_ctx *c) {
         m.units_on = !m.ix_on && (su != 0 || f_units <= 0.9 * f_plain);
         any = any || m.units_on || m.ix_on;
         if (m.units_on) tab_need = std::max(tab_need, lg.n_long * inner);
-        if (m.ix_on) itab_need = std::max(itab_need, Is * inner);
+        if (m.ix_on) itab_need = std::max(itab_need, m.ix.n_long * inner);
     }
     dfree(work);
     int64_t cells = 1;

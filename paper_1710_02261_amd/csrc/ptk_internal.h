@@ -283,17 +283,16 @@ hipError_t build_mode_csr(const int32_t *idx, const float *val, int64_t nnz,
 // 2, 1 entries (the binary digits of the rest). units receives the units'
 // first positions, classes in the order emax, ..., 1, each in increasing
 // position; count[c] is the number of units of class c (2^c entries), c =
-// 0..3. A long run below wmin entries (wmin > 0) lists its entries one by
-// one (ntask_pos) instead of tasks. The workspace holds units_workspace_ints int32
-// values; lg's arrays hold cap_long, cap_tasks and cap_ntasks values
-// (hipErrorInvalidValue beyond).
+// 0..3. A long run below wmin entries (wmin > 0) is not listed as a run:
+// its entries are listed one by one (ntask_pos) instead. The workspace holds
+// units_workspace_ints int32 values; lg's arrays hold cap_long, cap_tasks and
+// cap_ntasks values (hipErrorInvalidValue beyond).
 struct UnitLong {
     int32_t *run_pos = nullptr;       // [n_long] first position of each long run
     int32_t *task_pos = nullptr;      // [n_tasks] first position of each task
     int32_t *task_len = nullptr;      // [n_tasks] its entries (<= tlen)
     int32_t *task_run = nullptr;      // [n_tasks] its long run
-    // the entries of the runs below wmin entries, one per "narrow task"
-    int32_t *ntask_pos = nullptr, *ntask_len = nullptr, *ntask_run = nullptr;
+    int32_t *ntask_pos = nullptr;     // [n_ntasks] the entries of runs below wmin entries
     int64_t n_long = 0, n_tasks = 0, n_ntasks = 0;
     int64_t cap_long = 0, cap_tasks = 0, cap_ntasks = 0;
 };
@@ -301,9 +300,9 @@ struct UnitLong {
 // sorted, pos_out[k] = the position of keys_out[k]. work: sort_workspace_bytes.
 hipError_t sort_by_key(const int32_t *keys, int64_t nnz, int64_t extent, void *work,
                        int32_t *keys_out, int32_t *pos_out, hipStream_t st);
-// For runs of equal keys (build_units with rows null): task_run[t] <- the key
-// value of its run.
-hipError_t launch_task_keys(const int32_t *keys, const UnitLong &lg, hipStream_t st);
+// For runs of equal keys (build_units with rows null): run_pos[r] <- the key
+// value of run r.
+hipError_t launch_run_keys(const int32_t *keys, const UnitLong &lg, hipStream_t st);
 // list[i] <- perm[list[i]] for i < n.
 hipError_t launch_permute_list(const int32_t *perm, int32_t *list, int64_t n, hipStream_t st);
 int64_t units_workspace_ints(int64_t nnz);

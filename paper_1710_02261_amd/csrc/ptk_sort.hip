@@ -367,14 +367,15 @@ __global__ void k_run_starts(const int32_t *__restrict__ rows, const int32_t *__
 }
 
 // Counters of a run of len entries: q = 0..3, units of 2^q entries (none
-// above cmax); q = 4, one long run; q = 5, its tasks of at most tlen
-// entries, or q = 6, one per entry when it has fewer than wmin entries.
-// A run of at least lmin entries (lmin > 0) is long and has no units.
+// above cmax); q = 4, one long run, and q = 5, its tasks of at most tlen
+// entries; or, for a long run of fewer than wmin entries, q = 6, one per
+// entry (and no q = 4 or 5). A run of at least lmin entries (lmin > 0) is
+// long and has no units.
 __device__ __forceinline__ int32_t run_count(int32_t len, int q, int cmax, int32_t lmin,
                                              int32_t tlen, int32_t wmin) {
     const bool lng = lmin > 0 && len >= lmin;
     const bool narrow = len < wmin;
-    if (q == 4) return lng ? 1 : 0;
+    if (q == 4) return (lng && !narrow) ? 1 : 0;
     if (q == 5) return (lng && !narrow) ? (len + tlen - 1) / tlen : 0;
     if (q == 6) return (lng && narrow) ? len : 0;
     if (lng || q > cmax) return 0;
@@ -413,20 +414,20 @@ __global__ void k_unit_write(const int32_t *__restrict__ start, int32_t R, int c
          r += (int64_t)gridDim.x * blockDim.x) {
         int32_t p = start[r];
         const int32_t len = start[r + 1] - p;
+        if (run_count(len, 6, cmax, lmin, tlen, wmin)) {       // its entries, one by one
+            int32_t *tp = lg.ntask_pos + off[6 * (int64_t)R + r];
+            for (int32_t q = 0; q < len; ++q) tp[q] = p + q;
+            continue;
+        }
         if (run_count(len, 4, cmax, lmin, tlen, wmin)) {
             const int32_t li = off[4 * (int64_t)R + r];
             lg.run_pos[li] = p;
-            const bool narrow = len < wmin;
-            const int32_t w = narrow ? 1 : tlen;
-            const int32_t nt = run_count(len, narrow ? 6 : 5, cmax, lmin, tlen, wmin);
-            const int64_t o = off[(narrow ? 6 : 5) * (int64_t)R + r];
-            int32_t *tp = (narrow ? lg.ntask_pos : lg.task_pos) + o;
-            int32_t *tl = (narrow ? lg.ntask_len : lg.task_len) + o;
-            int32_t *tr = (narrow ? lg.ntask_run : lg.task_run) + o;
+            const int32_t nt = run_count(len, 5, cmax, lmin, tlen, wmin);
+            const int64_t o = off[5 * (int64_t)R + r];
             for (int32_t q = 0; q < nt; ++q) {
-                tp[q] = p + q * w;
-                tl[q] = min(w, len - q * w);
-                tr[q] = li;
+                lg.task_pos[o + q] = p + q * tlen;
+                lg.task_len[o + q] = min(tlen, len - q * tlen);
+                lg.task_run[o + q] = li;
             }
             continue;
         }
@@ -477,23 +478,19 @@ hipError_t sort_by_key(const int32_t *keys, int64_t nnz, int64_t extent, void *w
     return hipMemcpyAsync(pos_out, vin, nnz * 4, hipMemcpyDeviceToDevice, st);
 }
 
-// task_run[t] <- keys[run_pos[task_run[t]]]: each task names its key value.
-__global__ void k_task_keys(const int32_t *__restrict__ keys, const int32_t *__restrict__ run_pos,
-                            int32_t *__restrict__ task_run, int64_t n) {
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-         t += (int64_t)gridDim.x * blockDim.x)
-        task_run[t] = keys[run_pos[task_run[t]]];
+// run_pos[r] <- keys[run_pos[r]]: each run names its key value.
+__global__ void k_run_keys(const int32_t *__restrict__ keys, int32_t *__restrict__ run_pos,
+                           int64_t n) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x)
+        run_pos[r] = keys[run_pos[r]];
 }
 
-hipError_t launch_task_keys(const int32_t *keys, const UnitLong &lg, hipStream_t st) {
-    if (lg.n_tasks > 0) {
-        const unsigned b = (unsigned)std::min<int64_t>((lg.n_tasks + 255) / 256, 65536);
-        hipLaunchKernelGGL(k_task_keys, dim3(b), dim3(256), 0, st, keys, lg.run_pos,
-                           lg.task_run, lg.n_tasks);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+hipError_t launch_run_keys(const int32_t *keys, const UnitLong &lg, hipStream_t st) {
+    if (lg.n_long <= 0) return hipSuccess;
+    const unsigned b = (unsigned)std::min<int64_t>((lg.n_long + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_run_keys, dim3(b), dim3(256), 0, st, keys, lg.run_pos, lg.n_long);
+    return hipGetLastError();
 }
 
 // list[i] <- perm[list[i]]

@@ -48,9 +48,9 @@ struct LongArgs {
     double *tab;                      // runs: [n_long][J^(N-2)][J]; index
                                       // tables: [J^(N-2)][n_long][J]
     double *dout;                     // deltas [nnz][J] in grouped order
-    // index tables: table r is that of index value r of mode s (n_long = I_s,
-    // run_pos unused), a task's entries are at grouped positions
-    // perm[task_pos ..], and task_run names the value
+    // index tables: table r is that of the index value run_pos[r] of mode s,
+    // a task's entries are at grouped positions perm[task_pos ..], and
+    // task_run names its table
     int32_t index_tables;
     const int32_t *perm;
 };

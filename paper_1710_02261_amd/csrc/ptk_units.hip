@@ -283,8 +283,8 @@ __global__ __launch_bounds__(kWave) void k_run_tables(LongArgs a) {
         run[p] = r0 + (int64_t)p * kWave;
         valid[p] = run[p] < a.lg.n_long;
         const float *r;
-        if (a.index_tables) {
-            r = a.fac[NO - 1] + (valid[p] ? run[p] : 0) * J;
+        if (a.index_tables) {             // run_pos names the value
+            r = a.fac[NO - 1] + (int64_t)(valid[p] ? a.lg.run_pos[run[p]] : 0) * J;
         } else {
             const int64_t pos = valid[p] ? a.lg.run_pos[run[p]] : 0;
             r = a.fac[NO - 1] + (int64_t)a.oidx[NO - 1][pos] * J;

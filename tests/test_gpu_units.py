@@ -14,7 +14,8 @@ that mode's row once per unit (eq. "delta" summed in another order).
 * Iterations in a captured graph with every row in the least-squares form
   (cond_limit = 1), whose kept deltas then come from the stored ones: every
   row of every iteration to 1e-5 against the oracle from the same state.
-* Index tables (G contracted with every row of A^(s), one per value of i_s):
+* Index tables (G contracted with a row of A^(s), one per value of i_s with
+  64 entries or more, single-entry units for the rest):
   groups and tasks counted exactly, row systems, updates and graph
   iterations to the same bars.
 * Auto: the work model keeps the fused kernels when nothing repeats and
@@ -176,14 +177,13 @@ def test_graph_iterations_least_squares_from_stored_deltas(dims, J, nnz, form):
 
 
 def expected_index(p, n):
-    """Index groups: the values of i_s present; a value with 64 entries or
-    more has ceil(count / 128) tasks, a smaller one a single-entry unit per
-    entry."""
+    """Index groups: a value of i_s with 64 entries or more has a table and
+    ceil(count / 128) tasks, a smaller one a single-entry unit per entry."""
     N = len(p.dims)
     s = N - 1 if n != N - 1 else N - 2
     _, cnt = np.unique(p.idx[s], return_counts=True)
     wide = cnt >= 64
-    return [int(cnt.size), int(((cnt[wide] + 127) // 128).sum()), int(cnt[~wide].sum())]
+    return [int(wide.sum()), int(((cnt[wide] + 127) // 128).sum()), int(cnt[~wide].sum())]
 
 
 @pytest.mark.parametrize("dims,J,nnz", SHAPES, ids=SIDS)
