@@ -17,7 +17,8 @@ that mode's row once per unit (eq. "delta" summed in another order).
 * Index tables (G contracted with a row of A^(s), one per value of i_s with
   64 entries or more, single-entry units for the rest):
   groups and tasks counted exactly, row systems, updates and graph
-  iterations to the same bars.
+  iterations to the same bars; a mode with no value wide enough for a
+  table.
 * Auto: the work model keeps the fused kernels when nothing repeats and
   takes the index tables when the values of i_s repeat across rows; an
   empty observed set; option refusals.
@@ -195,6 +196,33 @@ def test_index_groups_count_values(dims, J, nnz):
         assert on == 2
         assert counts[6:] == expected_index(p, n), (n, counts)
     ctx.close()
+
+
+def test_index_form_without_tables():
+    """Every value of i_s has fewer than 64 entries: no table at all, every
+    entry a single-entry unit; row systems as the fused kernels' and one
+    update against the oracle."""
+    p = problem((30, 25, 20, 15), 10, 120, seed=77)
+    ctx, idx, val, core, fac = context(p, shared_units=16)
+    ref, *_ = context(p, shared_units=-1)
+    G = p.core.astype(np.float64)
+    A = [a.astype(np.float64) for a in p.factors]
+    v = p.val.astype(np.float64)
+    for n in range(p.N):
+        counts, on = ctx.unit_stats(n)
+        assert on == 2 and counts[6:] == [0, 0, p.nnz], (n, counts)
+        B, c = ctx.row_systems(n)
+        Br, cr = ref.row_systems(n)
+        B, c, Br, cr = f64(B), f64(c), f64(Br), f64(cr)
+        assert np.abs(B - Br).max() <= 1e-12 * np.abs(Br).max()
+        assert np.abs(c - cr).max() <= 1e-12 * np.abs(cr).max()
+    ctx.update_mode(0, p.lam)
+    got = f64(fac[0])
+    want = oracle.update_rows(G, A, p.idx, v, 0, p.lam)
+    nz = np.bincount(p.idx[0], minlength=p.dims[0]) > 0
+    assert row_rel_err(got[nz], want[nz]).max() <= 1e-5
+    ctx.close()
+    ref.close()
 
 
 def test_auto_picks_by_the_work_model():
