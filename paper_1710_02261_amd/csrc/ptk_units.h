@@ -45,8 +45,7 @@ struct LongArgs {
     const float *fac[kMaxN];          // factors of the other modes, mode order
     const int32_t *oidx[kMaxN];       // other-mode index arrays, same order
     UnitLong lg;                      // long runs and their tasks
-    double *tab;                      // runs: [n_long][J^(N-2)][J]; index
-                                      // tables: [J^(N-2)][n_long][J]
+    double *tab;                      // tables [n_long][J^(N-2)][J]
     double *dout;                     // deltas [nnz][J] in grouped order
     // index tables: table r is that of the index value run_pos[r] of mode s,
     // a task's entries are at grouped positions perm[task_pos ..], and
@@ -62,10 +61,11 @@ hipError_t launch_long_runs(const LongArgs &a, int N, int J, int P, hipStream_t 
 hipError_t launch_run_tables(const LongArgs &a, int N, int J, hipStream_t st);
 hipError_t launch_long_tasks(const LongArgs &a, int N, int J, int P, hipStream_t st);
 
-// Index tables: a table per index value of mode s, T_v = G x_s a^(s)_v,
-// serves every entry of mode n with i_s = v, whatever its row. Entries are
-// taken in the order of i_s, in tasks of at most kIndexTask of one value
-// (two entries per lane).
+// Index tables: a table per index value of mode s with kIndexTask / 2
+// entries or more, T_v = G x_s a^(s)_v, serves every entry of mode n with
+// i_s = v, whatever its row. Entries are taken in the order of i_s, in tasks
+// of at most kIndexTask of one value (two entries per lane); the entries of
+// the other values are single-entry units.
 constexpr int32_t kIndexTask = 128;
 // Tables of one mode beyond this many bytes: not used.
 constexpr int64_t kIndexTableBytes = int64_t(16) << 30;

@@ -317,10 +317,9 @@ __global__ __launch_bounds__(kWave) void k_run_tables(LongArgs a) {
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             if (!valid[p]) continue;
-            // index tables [o][value][j] (coalesced over the lanes' values),
-            // run tables [run][o][j]
-            double *dst = a.index_tables ? a.tab + ((int64_t)o * a.lg.n_long + run[p]) * J
-                                         : a.tab + (run[p] * OUTER + o) * J;
+            // tables [run][o][j]: each contiguous, so that a task's scalar
+            // loads walk one block in order
+            double *dst = a.tab + (run[p] * OUTER + o) * J;
 #pragma unroll
             for (int j = 0; j < J; ++j) dst[j] = t[p][j];
         }
@@ -370,9 +369,9 @@ __global__ __launch_bounds__(kWave) void k_delta_long(LongArgs a) {
     for (int p = 0; p < P; ++p)
 #pragma unroll
         for (int j = 0; j < J; ++j) c[p][j] = 0.0;
-    // stride of the outer index and offset of this task's table
-    const int64_t os = a.index_tables ? a.lg.n_long * J : J;
-    cptr<double> tab = (cptr<double>)(a.tab + run * (a.index_tables ? J : OUTER * J));
+    // this task's table, [o][j] contiguous
+    const int64_t os = J;
+    cptr<double> tab = (cptr<double>)(a.tab + run * (OUTER * J));
 #pragma unroll 1
     for (int ob = 0; ob < OB; ++ob) {
         double ws[P];
