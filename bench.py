@@ -651,6 +651,7 @@ def main():
         ctx.reset_timers()
         ctx.iterate(args.steps, p.lam, strict=False)
         times = ctx.kernel_times()
+        core_left_end = int(torch.count_nonzero(core_run))
         ctx.close()
         gname = ("gram_mfma" if prec.startswith("bf16")
                  else "gram_cache_write" if cache else "gram")
@@ -659,7 +660,8 @@ def main():
                 "not_pd": not_pd, "gram_ms": ms / max(calls, 1),
                 "value": p.nnz * args.steps / elapsed,
                 "rmse": float(rmse_direct), "work": work, "tune_s": tune_s,
-                "core_left": core_left, "ls_rows": ls_rows, "ls_max": ls_max,
+                "core_left": core_left, "core_left_end": core_left_end,
+                "ls_rows": ls_rows, "ls_max": ls_max,
                 "units": units,
                 "diverged": 8 in statuses,
                 "status": max(statuses, key=lambda v: v != 0),
@@ -724,6 +726,27 @@ def main():
             unit_kernel = {"class": e, "avg_ms": ms / calls,
                            "flops": 2.0 * per_unit * sum(counted) / max(1, len(counted))}
         avg_s = unit_kernel["avg_ms"] / 1e3
+    # Approx runs: each mode update launches the dense and the sparse-core
+    # kernel, and the one not chosen (on the device, from the core's non-zero
+    # cells) returns at once. Non-zero cells only fall during a run, so the
+    # profiled pass used the sparse kernel throughout when the core was
+    # within the limit at its start, and the dense one throughout when it was
+    # still above it at its end; a pass that crossed has no roofline.
+    sparse_kernel = None
+    approx_mixed = False
+    if args.approx_rate > 0 and r["times"].get("gram_sparse", (0, 0.0))[0] > 0:
+        lim = 0.1 if args.sparse_limit == 0 else args.sparse_limit
+        cells = J ** N
+        nz0, nz1 = r["core_left"], r["core_left_end"]
+        if lim >= 0 and nz0 <= lim * cells:
+            calls, ms = r["times"]["gram_sparse"]
+            # one multiply-add per non-zero cell (mean of the counts at the
+            # start and end of the pass) plus the packed Gram and rhs
+            sparse_kernel = {"avg_ms": ms / calls,
+                             "flops": 2.0 * p.nnz * (0.5 * (nz0 + nz1) + J * (J + 1) // 2 + J)}
+            avg_s = sparse_kernel["avg_ms"] / 1e3
+        elif lim >= 0 and nz1 <= lim * cells:
+            approx_mixed = True
     if main_prec.startswith("bf16"):
         # matrix-core work per entry and mode: stage 1 J^N (+2x for the split
         # products), Gram J^2 (+2x); the VALU part is not counted here
@@ -732,6 +755,9 @@ def main():
         bound, unit = "mfma", "TFLOP/s"
     elif unit_kernel:
         flops = unit_kernel["flops"]
+        bound, unit = "alu", "TFLOP/s"
+    elif sparse_kernel:
+        flops = sparse_kernel["flops"]
         bound, unit = "alu", "TFLOP/s"
     else:
         flops = 2.0 * p.nnz * fma_per_nnz_mode(N, J)
@@ -759,10 +785,16 @@ def main():
                  else "k_delta_units<%d,%d,%d,...>" % (N, J, e))
         if e != "index":           # the committed counters are of k_delta_long<4,10,2>
             traffic = None
+    if sparse_kernel:
+        kname = "k_gram_sparse<%d,%d,2>" % (N, J)
+        traffic = None
     roofline = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak, "traffic": traffic, "kernel": kname,
                 "avg_launch_ms": avg_s * 1e3, "flops_per_launch": flops}
-    if main_prec == "f64":
+    if approx_mixed:
+        roofline = None
+        log("roofline: none (the core crossed the sparse limit inside the profiled pass)")
+    if roofline and main_prec == "f64":
         # context: what a plain loop of independent FP64 FMAs sustains here
         roofline["fma_loop_tflops"] = ptk.fp64_rates(2000)["fma_f64"]
 
@@ -789,6 +821,7 @@ def main():
         "pair_cache": bool(args.pair_cache),
         "approx_rate": args.approx_rate,
         "core_cells_left": r["core_left"],
+        "core_cells_left_profiled": r["core_left_end"],
         "rmse_after": r["rmse"],
         "rmse_after_fused": r["rmse_fused"],
         "not_pd_rows_timed": int(r["not_pd"]),

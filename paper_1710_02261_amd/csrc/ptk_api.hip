@@ -2135,11 +2135,18 @@ extern "C" ptk_status ptk_autotune(ptk_ctx *c, const char *cache_path, int64_t *
         const int role = cache_role(c, n);
         const bool both = !m.bf16 && m.fast && role == 0 && m.slices <= 1 &&
                           gram2_available(c->s.N, c->s.ranks[n], arith_of(c, n));
+        // Approx variant: the residuals reuse the deltas that the two-entry
+        // kernel of the last mode keeps (approx_step), which saves a full
+        // contraction per iteration that the timing here does not see; that
+        // mode keeps the two-entry kernel
+        const bool keep_two = both && c->opt.approx_rate > 0.0 && n == c->s.N - 1 &&
+                              approx_mode(c) == c->s.N - 1;
+        const int two_lo = both ? (keep_two ? 1 : 0) : -1;
         if (!tune_lookup(cache_path, key, &best, &best_two)) {
             const double mult[] = {0.125, 0.25, 0.5, 1.0, 2.0};
             double best_ms = 1e300;
             HIPCHK(c, permute(c, n, role));
-            for (int two = both ? 1 : -1; two >= (both ? 0 : -1) && s == PTK_OK; --two) {
+            for (int two = both ? 1 : -1; two >= two_lo && s == PTK_OK; --two) {
                 if (two >= 0) m.two = two != 0;
                 const int64_t base = default_work(c, n);
                 for (double f : mult) {
@@ -2169,7 +2176,7 @@ extern "C" ptk_status ptk_autotune(ptk_ctx *c, const char *cache_path, int64_t *
             if (s != PTK_OK) break;
             tune_store(cache_path, key, best, best_two);
         }
-        m.two = best_two != 0;
+        m.two = keep_two || best_two != 0;
         c->epoch++;
         s = configure_ranges(c, n, best);
         if (work_host) work_host[n] = m.bf16 ? m.blk_per_wave : m.chunk;
