@@ -836,17 +836,31 @@ def main():
                                        "form": ["fused", "units", "index tables"][on]}
                                       for u, on in r["units"]]},
     }
+    variants = {}
+    if args.approx_rate > 0:
+        # the same iterations without removal decide whether the Approx fit
+        # is usable (also under --no-variant); an unusable one gets no
+        # throughput
+        v = run(main_prec, 1 if args.pair_cache else 0, 0.0)
+        name = main_prec + " (no removal)"
+        variants[name] = {"value": v["value"],
+                          "ms_per_step": 1e3 * v["elapsed"] / args.steps,
+                          "rmse_after": v["rmse"],
+                          "rmse_rel_to_main": v["rmse"] / r["rmse"] - 1.0}
+        log("%s: %.2f ms/step, rmse %.6g (main %.6g)" % (
+            name, variants[name]["ms_per_step"], v["rmse"], r["rmse"]))
+        out["rmse_rel_to_no_removal"] = r["rmse"] / v["rmse"] - 1.0
+        out["usable"] = bool(out["rmse_rel_to_no_removal"] <= USABLE_RMSE and not r["diverged"])
+        if not out["usable"]:
+            out["value"] = None
+            out["note"] = ("the Approx fit's RMSE is more than %d %% above that of the same "
+                           "iterations without removal: not a usable fit on this workload, "
+                           "no throughput reported (ms_per_step is the time of the failed "
+                           "fit)" % round(100 * USABLE_RMSE))
+            log("approx: unusable (rmse %.6g against %.6g without removal)" % (
+                r["rmse"], v["rmse"]))
+        out["variants"] = variants
     if not args.no_variant:
-        variants = {}
-        if args.approx_rate > 0:
-            v = run(main_prec, 1 if args.pair_cache else 0, 0.0)
-            name = main_prec + " (no removal)"
-            variants[name] = {"value": v["value"],
-                              "ms_per_step": 1e3 * v["elapsed"] / args.steps,
-                              "rmse_after": v["rmse"],
-                              "rmse_rel_to_main": v["rmse"] / r["rmse"] - 1.0}
-            log("%s: %.2f ms/step, rmse %.6g (main %.6g)" % (
-                name, variants[name]["ms_per_step"], v["rmse"], r["rmse"]))
         if cache_ok:
             other = 0 if args.pair_cache else 1
             v = run(main_prec, other)

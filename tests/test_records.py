@@ -3,7 +3,8 @@ with themselves and with the counter summaries they cite (CPU only).
 
 * Every record carries the fields of a bench line: metric, value, unit,
   one GPU, synthetic data, a named workload and the command that made it.
-* Throughput records: value = entries / seconds per iteration.
+* Throughput records: value = entries / seconds per iteration, or no value
+  for a fit marked unusable, with the reason.
 * Rooflines: frac = achieved / peak with 0 < frac <= 1 against the
   published peak; achieved = flops per launch / average launch time.
 * Index-table records: the flops per launch are the task kernel's
@@ -44,8 +45,12 @@ def test_record_fields(path):
     assert r["data"] == "synthetic"
     assert r["command"].startswith("python bench.py")
     if "ms_per_step" in r and r.get("unit") == "nnz*iters/s":
-        nnz = r["config"]["nnz"]
-        assert math.isclose(r["value"], nnz / (r["ms_per_step"] * 1e-3), rel_tol=1e-6)
+        if r["value"] is None:
+            # a fit marked unusable reports no throughput, and says why
+            assert r["usable"] is False and r["note"]
+        else:
+            nnz = r["config"]["nnz"]
+            assert math.isclose(r["value"], nnz / (r["ms_per_step"] * 1e-3), rel_tol=1e-6)
 
 
 @pytest.mark.parametrize("path", RECORDS, ids=[os.path.basename(p) for p in RECORDS])
