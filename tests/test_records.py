@@ -12,6 +12,7 @@ with themselves and with the counter summaries they cite (CPU only).
   from the unit statistics the record carries.
 * The headline record's traffic is the bytes per launch of the committed
   counter summary, and its CPU baseline is the oracle's.
+* Every profile the design notes and the README cite is committed.
 """
 import glob
 import json
@@ -95,3 +96,19 @@ def test_headline_traffic_and_cpu_baseline():
                         t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"], rel_tol=1e-12)
     cb = r["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and cb["sample"]
+
+
+def test_cited_profiles_exist():
+    """Every file under profiles/ that the design notes or the README cite is
+    committed (a path followed by * names a family of records)."""
+    import re
+    missing = []
+    for doc in ("DESIGN.md", "README.md"):
+        text = open(os.path.join(ROOT, doc)).read()
+        for m in re.finditer(r"profiles/[A-Za-z0-9_.\-]+(\*?)", text):
+            if m.group(1):
+                continue
+            path = m.group(0).rstrip(".,)")
+            if not os.path.exists(os.path.join(ROOT, path)):
+                missing.append((doc, path))
+    assert not missing, missing
